@@ -1,0 +1,175 @@
+/*
+ * bmg.h -- C ABI of the MI355X geometric-multigrid solver for the H(div)-conforming
+ * interior-penalty discretisation of the Brinkman / Darcy equations
+ * (Kanschat, Lazarov, Mao, arXiv 1602.04858).
+ *
+ * Problem (Section 2.2, eq. Brinkman): -mu Lap u + kappa u + grad p = f, div u = 0
+ * on the unit square, mu >= 0 (mu = 0 is Darcy), kappa > 0 cellwise constant.
+ * Discretisation (Section 2.3): RT_k velocity x discontinuous Q_k pressure on a
+ * uniform N x N mesh, interior-penalty form a_h (eq. ipbrinkman) with face penalty
+ * 2 mu sigma / h, saddle-point form (eq. Brinkman-weak).  On a Dirichlet side the
+ * normal velocity is an essential condition and the tangential one is imposed by
+ * the Nitsche terms of eq. (BCh); an open side carries the natural condition.
+ * Solver (Section 3): GMRES preconditioned by the V-cycle B_J over the uniformly
+ * refined hierarchy N_j = n0 * 2^j, with the symmetric multiplicative vertex-patch
+ * Schwarz smoother (eq. smoother-Multiplicative), natural-injection prolongation,
+ * its transpose as restriction, and a direct solve on the coarsest mesh.
+ *
+ * Vector layout ("canonical numbering"), with nb = k+1, N cells per side, cell
+ * c = cy*N + cx, basis L_b = orthonormal Legendre on [0,1], psi_0 = 1-t,
+ * psi_1 = t, psi_a = int_0^t L_{a-1} (a >= 2):
+ *   x-face dofs  (i = 0..N, cy, b)      at (cy*(N+1) + i)*nb + b          [u_x = psi_a(xi) L_b(eta), a = 0/1]
+ *   y-face dofs  (j = 0..N, cx, b)      at N(N+1)nb + (j*N + cx)*nb + b   [u_y = L_b(xi) psi_a(eta), a = 0/1]
+ *   interior     (c, comp, a >= 2, b)   at 2N(N+1)nb + c*2k*nb + (comp*k + a-2)*nb + b
+ *   pressure     (c, a, b)              at n_u + c*nb^2 + b*nb + a         [p = L_a(xi) L_b(eta)]
+ * with n_u = 2N(N+1)nb + 2k*nb*N^2 and n_p = nb^2 N^2.  A full vector is the
+ * velocity block followed by the pressure block (n_u + n_p doubles).
+ *
+ * Conventions for every call:
+ *   - pointers named *_dev are device pointers (hipMalloc'd or torch tensors)
+ *     owned by the caller; *_host are host pointers; nothing is retained after
+ *     the call returns unless stated;
+ *   - all device work is enqueued on the stream given to bmg_setup; calls that
+ *     return host results synchronise that stream;
+ *   - a handle is used by one host thread at a time;
+ *   - every call returns a bmg_status; on an argument error nothing is modified;
+ *     bmg_last_error() gives a message for the last failing call on a handle.
+ */
+#ifndef BMG_H
+#define BMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bmg_ctx* bmg_handle;
+
+typedef enum {
+  BMG_OK = 0,
+  BMG_E_ARG = 1,           /* invalid argument (null pointer, out-of-range parameter) */
+  BMG_E_UNSUPPORTED = 2,   /* valid but not implemented (e.g. k outside {1,2}) */
+  BMG_E_NOMEM = 3,         /* workspace too small or device allocation failed */
+  BMG_E_HIP = 4,           /* a HIP runtime call failed */
+  BMG_E_SINGULAR = 5,      /* a local or coarse matrix could not be inverted */
+  BMG_E_NOT_CONVERGED = 6, /* maxit reached; the best iterate is returned */
+  BMG_E_NONFINITE = 7,     /* NaN/Inf in inputs or in the iteration */
+  BMG_E_STATE = 8          /* call not valid for this handle */
+} bmg_status;
+
+enum { BMG_BC_DIRICHLET = 0, BMG_BC_OPEN = 1 };                 /* sides: 0 x=0, 1 x=1, 2 y=0, 3 y=1 */
+enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1 };                        /* preconditioner arithmetic */
+enum { BMG_CYCLE_STANDARD = 0, BMG_CYCLE_VARIABLE = 1 };        /* m(j) = m_fine or m_fine 2^(J-j), Section 3.2 */
+
+typedef struct {
+  int32_t n0;            /* cells per side of the coarsest mesh T_0, 2 <= n0 <= 64 */
+  int32_t levels;        /* J >= 0 refinements; finest N = n0 << levels <= 4096 */
+  int32_t k;             /* Raviart-Thomas degree, 1 or 2 */
+  double mu;             /* viscosity, >= 0 (0 = Darcy) */
+  double sigma;          /* penalty constant; Section 4.1 uses (k+1)(k+2); face penalty 2 mu sigma / h_j */
+  int32_t bc[4];         /* BMG_BC_* per side */
+  int32_t cycle;         /* BMG_CYCLE_* */
+  int32_t m_fine;        /* smoothing steps on the finest level, >= 1 (Section 4.1: 2) */
+  int32_t precond_prec;  /* BMG_P_*: arithmetic of the V-cycle; the outer Krylov loop is always FP64 */
+  int32_t restart;       /* FGMRES restart length, 1..512 */
+} bmg_params;
+
+typedef struct {
+  int32_t iterations;            /* FGMRES iterations (preconditioner applications) */
+  int32_t converged;             /* 1 if the residual estimate reached rtol */
+  double rel_residual_estimate;  /* Arnoldi estimate / ||b|| at exit */
+  double rel_residual_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
+} bmg_solve_info;
+
+/* Device memory the library needs for these parameters (bmg_setup workspace). */
+bmg_status bmg_plan(const bmg_params* p, size_t* workspace_bytes);
+
+/* Build the hierarchy and every setup product: coarse kappa by arithmetic averaging
+ * of the four children (Section 4.1), level operators, patch pseudo-inverses
+ * (Section 3.3: the local Ritz projection on the vertex patch, pseudo-inverse with
+ * zero patch-mean pressure when the patch problem has the constant-pressure null
+ * mode), transfers and the coarse inverse (Section 3.2, B_0 = A_0^{-1}).
+ *   kappa_host: N*N doubles, cell (cx, cy) at cy*N + cx, N = n0 << levels; finite,
+ *               > 0 (BMG_E_NONFINITE / BMG_E_ARG otherwise); copied, not retained.
+ *   workspace_dev / bytes: caller-owned device memory of at least bmg_plan bytes
+ *               (256-byte aligned), or NULL / 0 to let the library allocate it.
+ *   hip_stream: hipStream_t for all work (NULL = default stream).
+ *   out:        receives the handle. */
+bmg_status bmg_setup(const bmg_params* p, const double* kappa_host, void* workspace_dev, size_t bytes,
+                     void* hip_stream, bmg_handle* out);
+bmg_status bmg_destroy(bmg_handle h);
+
+/* Sizes of level j (0 = coarsest, levels = finest). */
+bmg_status bmg_sizes(bmg_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p);
+
+/* y = A_j x, the saddle-point operator of level j (eq. Brinkman-weak) in FP64;
+ * rows of the essential (constrained) normal dofs are the identity. */
+bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x_dev, double* y_dev);
+
+/* z = B_J r: one V-cycle (Section 3.2) in the handle's preconditioner arithmetic,
+ * FP64 in and out, canonical layout of the finest level. */
+bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
+
+/* Solve A_J x = b by right-preconditioned flexible GMRES(restart) in FP64 with B_J
+ * as preconditioner (Section 3.2), until ||b - A x||_2 <= rtol ||b||_2 by the
+ * Arnoldi estimate (Section 4.1 stopping rule with rtol as given).
+ *   b_dev: the algebraic right-hand side (n_u + n_p doubles, canonical layout),
+ *          e.g. from bmg_assemble_rhs; x_dev: the solution; x0_dev: initial guess
+ *          or NULL for zero.  Returns BMG_E_NOT_CONVERGED with the last iterate
+ *          if maxit iterations did not reach rtol; info may be NULL. */
+bmg_status bmg_solve(bmg_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
+                     const double* x0_dev, bmg_solve_info* info);
+
+/* ----- setup-side host calls (no handle, no device) ----- */
+/* Quadrature points of bmg_assemble_rhs on the finest mesh of p (host arrays).
+ * cell_xy: N*N cells x q*q points (point iy*q + ix) x 2, q = k+2 Gauss points per
+ * direction; face_xy: 4 sides x N faces (ordered along the side) x q points x 2. */
+bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy_host, double* face_xy_host);
+
+/* Right-hand side of eq. (BCh) on the finest mesh of p, FP64, host arrays:
+ *   f_qp: source f at the cell points (x 2 components);
+ *   s_qp: divergence source s (pressure rows -(s, q)) at the cell points, or NULL;
+ *   g_qp: boundary data g at the face points (x 2), or NULL for g = 0; only
+ *         Dirichlet sides are read; the normal component must be zero there
+ *         (BMG_E_UNSUPPORTED otherwise), the tangential one enters through
+ *         2 mu sigma_h <g, v> - mu <grad v n, g>.
+ * Writes b (n_u + n_p doubles, canonical layout) to b_host. */
+bmg_status bmg_assemble_rhs(const bmg_params* p, const double* f_qp, const double* s_qp, const double* g_qp,
+                            double* b_host);
+
+/* Vertex patch (vx, vy) of level 1 <= j <= levels (Section 3.3, the cells sharing
+ * the vertex; dofs whose support lies in them, essential dofs excluded): writes n,
+ * the dofs in ascending global order, the colour (vx mod 3) + 3 (vy mod 3) and, if
+ * inv_host is not NULL, the FP64 pseudo-inverse of the patch matrix (row-major
+ * n x n) exactly as setup computes it.  dofs_host must hold 12(k+1) + 8k(k+1) +
+ * 4(k+1)^2 ints (an upper bound on n), inv_host the square of that many doubles.
+ * kappa_host is the finest-level field as for bmg_setup. */
+bmg_status bmg_export_patch(const bmg_params* p, const double* kappa_host, int32_t level, int32_t vx, int32_t vy,
+                            int32_t* n, int32_t* dofs_host, double* inv_host, int32_t* colour);
+
+/* Dense A_j (row-major, FP64) of a level with at most 32 cells per side, from the
+ * reference-element blocks the kernels use; essential rows/cols are the identity. */
+bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa_host, int32_t level, double* out_host);
+
+/* ----- single steps of the cycle, for step-by-step checks (FP64 in/out) ----- */
+/* One colour step of the smoother on level j >= 1: for every vertex patch of the
+ * colour (colour = (vx mod 3) + 3 (vy mod 3)), x[S] += A_S^+ (b - A_j x)[S]. */
+bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x_dev, const double* b_dev);
+/* `steps` applications of the symmetric smoother R_j (colours 0..8 then 7..0). */
+bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x_dev, const double* b_dev);
+/* b_{j-1} = P_j^T r_j (restriction; eq. 3 applied to residuals). */
+bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf_dev, double* bc_dev);
+/* x_j += P_j z_{j-1} (natural injection of Section 3.1). */
+bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc_dev, double* xf_dev);
+/* x_0 = A_0^{-1} b_0 (pseudo-inverse with zero mean pressure if A_0 is singular). */
+bmg_status bmg_coarse_solve(bmg_handle h, const double* b_dev, double* x_dev);
+
+const char* bmg_status_string(bmg_status s);
+const char* bmg_last_error(bmg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMG_H */

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libbmg.so (include/bmg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (tensor data pointers) and the stream.  If the
+library is not built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbmg.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is not built; run paper_1602_04858_amd/build.py (hipcc, gfx950)")
+
+_lib = C.CDLL(LIBPATH)
+
+BC_DIRICHLET, BC_OPEN = 0, 1
+P_FP64, P_FP32 = 0, 1
+CYCLE_STANDARD, CYCLE_VARIABLE = 0, 1
+
+STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM", 4: "BMG_E_HIP",
+          5: "BMG_E_SINGULAR", 6: "BMG_E_NOT_CONVERGED", 7: "BMG_E_NONFINITE", 8: "BMG_E_STATE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
+                ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
+                ("precond_prec", C.c_int32), ("restart", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
+                ("rel_residual_estimate", C.c_double), ("rel_residual_true", C.c_double)]
+
+
+_P, _I32, _I64, _D, _VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+_sig = {
+    "bmg_plan": [_P(Params), _P(C.c_size_t)],
+    "bmg_setup": [_P(Params), _dp, _VP, C.c_size_t, _VP, _P(_VP)],
+    "bmg_destroy": [_VP],
+    "bmg_sizes": [_VP, _I32, _P(_I32), _P(_I64), _P(_I64)],
+    "bmg_apply": [_VP, _I32, _VP, _VP],
+    "bmg_vcycle": [_VP, _VP, _VP],
+    "bmg_solve": [_VP, _VP, _VP, _D, _I32, _VP, _P(SolveInfo)],
+    "bmg_quad_points": [_P(Params), _dp, _dp],
+    "bmg_assemble_rhs": [_P(Params), _dp, _VP, _VP, _dp],
+    "bmg_colour_step": [_VP, _I32, _I32, _VP, _VP],
+    "bmg_smooth": [_VP, _I32, _I32, _VP, _VP],
+    "bmg_restrict": [_VP, _I32, _VP, _VP],
+    "bmg_prolong_add": [_VP, _I32, _VP, _VP],
+    "bmg_coarse_solve": [_VP, _VP, _VP],
+    "bmg_export_patch": [_P(Params), _dp, _I32, _I32, _I32, _P(_I32), _ip, _VP, _P(_I32)],
+    "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
+}
+EXPORTS = list(_sig) + ["bmg_status_string", "bmg_last_error"]
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.bmg_status_string.argtypes = [C.c_int]
+_lib.bmg_status_string.restype = C.c_char_p
+_lib.bmg_last_error.argtypes = [_VP]
+_lib.bmg_last_error.restype = C.c_char_p
+
+
+class BmgError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+def lib():
+    return _lib
+
+
+def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100):
+    p = Params()
+    p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
+    for i in range(4):
+        p.bc[i] = int(bc[i])
+    p.cycle, p.m_fine, p.precond_prec, p.restart = cycle, m_fine, prec, restart
+    return p
+
+
+def plan(params: Params) -> int:
+    n = C.c_size_t(0)
+    st = _lib.bmg_plan(C.byref(params), C.byref(n))
+    if st:
+        raise BmgError(st, "plan")
+    return n.value
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One problem on the GPU (handle of the C library)."""
+
+    def __init__(self, params: Params, kappa, device="cuda", workspace=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.device = torch.device(device)
+        kap = np.ascontiguousarray(kappa, dtype=np.float64)
+        self.stream = torch.cuda.current_stream(self.device)
+        ws_ptr, ws_bytes = None, 0
+        if workspace == "torch":
+            nbytes = plan(params)
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            ws_ptr = C.c_void_p((base + 255) // 256 * 256)
+            ws_bytes = nbytes
+        h = C.c_void_p()
+        st = _lib.bmg_setup(C.byref(params), kap, ws_ptr, ws_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st:
+            raise BmgError(st, "setup")
+        self.h = h
+        self.J = params.levels
+        self.k = params.k
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.bmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st:
+            raise BmgError(st, f"{what}: {_lib.bmg_last_error(self.h).decode()}")
+
+    def sizes(self, level=None):
+        level = self.J if level is None else level
+        N, nu, npr = C.c_int32(), C.c_int64(), C.c_int64()
+        self._check(_lib.bmg_sizes(self.h, level, C.byref(N), C.byref(nu), C.byref(npr)), "sizes")
+        return N.value, nu.value, npr.value
+
+    def ndof(self, level=None):
+        _, a, b = self.sizes(level)
+        return a + b
+
+    def zeros(self, level=None):
+        return self.torch.zeros(self.ndof(level), dtype=self.torch.float64, device=self.device)
+
+    def apply(self, x, level=None):
+        level = self.J if level is None else level
+        y = self.zeros(level)
+        self._check(_lib.bmg_apply(self.h, level, _ptr(x), _ptr(y)), "apply")
+        return y
+
+    def vcycle(self, r):
+        z = self.zeros()
+        self._check(_lib.bmg_vcycle(self.h, _ptr(r), _ptr(z)), "vcycle")
+        return z
+
+    def solve(self, b, rtol=1e-10, maxit=500, x0=None, x=None):
+        if x is None:
+            x = self.zeros()
+        info = SolveInfo()
+        st = _lib.bmg_solve(self.h, _ptr(b), _ptr(x), rtol, maxit, _ptr(x0) if x0 is not None else None,
+                            C.byref(info))
+        if st not in (0, 6):
+            self._check(st, "solve")
+        return x, info
+
+    def colour_step(self, level, colour, x, b):
+        x = x.clone()
+        self._check(_lib.bmg_colour_step(self.h, level, colour, _ptr(x), _ptr(b)), "colour_step")
+        return x
+
+    def smooth(self, level, steps, x, b):
+        x = x.clone()
+        self._check(_lib.bmg_smooth(self.h, level, steps, _ptr(x), _ptr(b)), "smooth")
+        return x
+
+    def restrict(self, level, rf):
+        bc = self.zeros(level - 1)
+        self._check(_lib.bmg_restrict(self.h, level, _ptr(rf), _ptr(bc)), "restrict")
+        return bc
+
+    def prolong_add(self, level, xc, xf):
+        xf = xf.clone()
+        self._check(_lib.bmg_prolong_add(self.h, level, _ptr(xc), _ptr(xf)), "prolong_add")
+        return xf
+
+    def coarse_solve(self, b):
+        x = self.zeros(0)
+        self._check(_lib.bmg_coarse_solve(self.h, _ptr(b), _ptr(x)), "coarse_solve")
+        return x
+
+def quad_points(params: Params):
+    N = params.n0 << params.levels
+    q = params.k + 2
+    cell = np.zeros(N * N * q * q * 2)
+    face = np.zeros(4 * N * q * 2)
+    st = _lib.bmg_quad_points(C.byref(params), cell, face)
+    if st:
+        raise BmgError(st, "quad_points")
+    return cell.reshape(-1, 2), face.reshape(-1, 2)
+
+
+def assemble_rhs(params: Params, f, s=None, g=None):
+    """b (numpy, host) from callables f(x, y) -> (..., 2), s(x, y), g(x, y) -> (..., 2)."""
+    cell, face = quad_points(params)
+    fq = np.ascontiguousarray(f(cell[:, 0], cell[:, 1]), dtype=np.float64).reshape(-1)
+    keep = []
+    sp = gp = None
+    if s is not None:
+        sq = np.ascontiguousarray(s(cell[:, 0], cell[:, 1]), dtype=np.float64).reshape(-1)
+        keep.append(sq)
+        sp = sq.ctypes.data_as(C.c_void_p)
+    if g is not None:
+        gq = np.ascontiguousarray(g(face[:, 0], face[:, 1]), dtype=np.float64).reshape(-1)
+        keep.append(gq)
+        gp = gq.ctypes.data_as(C.c_void_p)
+    N = params.n0 << params.levels
+    k = params.k
+    n = 2 * N * (N + 1) * (k + 1) + 2 * k * (k + 1) * N * N + (k + 1) ** 2 * N * N
+    b = np.zeros(n)
+    st = _lib.bmg_assemble_rhs(C.byref(params), fq, sp, gp, b)
+    if st:
+        raise BmgError(st, "assemble_rhs")
+    return b
+
+
+def export_patch(params: Params, kappa, level, vx, vy, with_inverse=True):
+    """(dofs ascending, pseudo-inverse or None, colour) of vertex patch (vx, vy)."""
+    k = params.k
+    cap = 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) ** 2
+    dofs = np.zeros(cap, np.int32)
+    inv = np.zeros(cap * cap) if with_inverse else None
+    n, col = C.c_int32(), C.c_int32()
+    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    st = _lib.bmg_export_patch(C.byref(params), kap, level, vx, vy, C.byref(n), dofs,
+                               inv.ctypes.data_as(C.c_void_p) if inv is not None else None, C.byref(col))
+    if st:
+        raise BmgError(st, "export_patch")
+    m = n.value
+    return dofs[:m].copy(), (inv[:m * m].reshape(m, m).copy() if inv is not None else None), col.value
+
+
+def export_level_matrix(params: Params, kappa, level):
+    N = params.n0 << level
+    k = params.k
+    n = 2 * N * (N + 1) * (k + 1) + 2 * k * (k + 1) * N * N + (k + 1) ** 2 * N * N
+    out = np.zeros(n * n)
+    st = _lib.bmg_export_level_matrix(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64), level, out)
+    if st:
+        raise BmgError(st, "export_level_matrix")
+    return out.reshape(n, n)
+
+
+def from_workload(w, prec=P_FP64, restart=100, device="cuda", **kw):
+    p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart)
+    return Solver(p, w.kappa, device=device, **kw)

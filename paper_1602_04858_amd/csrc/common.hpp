@@ -1,0 +1,92 @@
+// Shared definitions of the HIP library: compile-time sizes of the RT_k x dQ_k
+// cell, the reference-element data the kernels consume, and the launcher
+// interface between the host driver and the kernels.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace bmg {
+
+// Sizes for Raviart-Thomas degree K (Section 2.3): per velocity component the cell
+// carries NA x NB coefficients (psi_a along the component direction, L_b across),
+// the pressure NB x NB.  NL = local dofs of one cell.
+template <int K>
+struct Dims {
+  static constexpr int NA = K + 2, NB = K + 1;
+  static constexpr int NV = NA * NB;         // one velocity component
+  static constexpr int NP = NB * NB;         // pressure
+  static constexpr int NL = 2 * NV + NP;     // whole cell
+  static constexpr int NI = 2 * K * NB;      // interior velocity dofs of a cell
+  // vertex-patch slot layouts (ascending global order of the patch dofs):
+  //   regular : 4 patch-internal faces, 4 cell interiors, 4 cell pressures
+  //   extended: 12 faces (adds the 8 outer faces, used when an outer face of the
+  //             patch lies on an open part of the domain boundary)
+  static constexpr int NSR = 4 * NB + 4 * NI + 4 * NP;
+  static constexpr int NSE = 12 * NB + 4 * NI + 4 * NP;
+};
+
+// Reference-element matrices of one level family, in arithmetic T.  Velocity
+// local index of either component: a*NB + b (a = psi index along the component,
+// b = Legendre index across); pressure local index pb*NB + pa.
+//   cell velocity block   = Kmu + kappa h^2 M         (same for u_x and u_y)
+//   cell divergence block = -h Dx (u_x), -h Dy (u_y)  (rows pressure, cols velocity)
+//   face blocks F[ts] (t = test side, s = trial side; side 0 = the cell with the
+//   smaller index, side 1 = the other), used for the tangential component;
+//   Nb[0|1] = Dirichlet (Nitsche) face at normal coordinate 0 | 1.
+template <typename T, int K>
+struct Elem {
+  using D = Dims<K>;
+  T Kmu[D::NV * D::NV];
+  T M[D::NV * D::NV];
+  T Dx[D::NP * D::NV];
+  T Dy[D::NP * D::NV];
+  T F[4][D::NV * D::NV];  // 00, 01, 10, 11
+  T Nb[2][D::NV * D::NV];
+};
+
+// 1-D re-expansion of a coarse function on child interval s (s = 0 left, 1 right):
+// fine coefficient a' of coarse psi_a is Ppsi[s][a'*NA + a], of coarse L_b is
+// PL[s][b'*NB + b].
+template <typename T, int K>
+struct Xfer {
+  using D = Dims<K>;
+  T Ppsi[2][D::NA * D::NA];
+  T PL[2][D::NB * D::NB];
+};
+
+// Bit s of a boundary mask: side s (0 x=0, 1 x=1, 2 y=0, 3 y=1) is Dirichlet.
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip).  prec: 0 = double, 1 = float vectors; sprec: storage
+// of the patch inverses, 0 = double, 1 = float.  All pointers are device pointers.
+// ---------------------------------------------------------------------------
+struct LevelArgs {
+  int N;
+  int bcm;
+  double h;
+  const void* kap;  // kappa of the level, arithmetic `prec`
+};
+
+void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
+               bool residual, hipStream_t s);
+void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
+                   const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
+                   hipStream_t s);
+void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s);
+void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s);
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, hipStream_t s);
+void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s);
+void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s);
+
+// FP64 Krylov helpers
+void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_t n, double* partial,
+                 double* out, hipStream_t s);
+void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, double sign,
+                  int64_t n, hipStream_t s);
+void launch_scale(double* dst, const double* src, const double* denom, bool take_sqrt, int64_t n, hipStream_t s);
+void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s);
+int dots_partial_count();
+
+}  // namespace bmg

@@ -1,0 +1,1259 @@
+// Host side of the library: parameter checks, workspace layout, setup products
+// (kappa hierarchy, reference-element data, vertex-patch pseudo-inverses, coarse
+// inverse), the V-cycle schedule, FP64 flexible GMRES and the C ABI (bmg.h).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bmg.h"
+#include "common.hpp"
+#include "refelem.hpp"
+
+using namespace bmg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct LevelInfo {
+  int N = 0;
+  double h = 0.0;
+  int64_t n_u = 0, n_p = 0, ndof = 0;
+  std::vector<double> kappa;
+  // per colour: number of patches, extended-layout patch count
+  int npatch[9] = {0};
+  int next[9] = {0};
+  // device pointers (into the workspace)
+  void* kap = nullptr;      // preconditioner arithmetic
+  double* kap64 = nullptr;  // FP64 (operator of bmg_apply and of the outer loop)
+  void *x = nullptr, *b = nullptr, *r = nullptr;
+  void* inv[9] = {nullptr};
+  void* invx[9] = {nullptr};
+  int32_t* extidx[9] = {nullptr};
+};
+
+}  // namespace
+
+struct bmg_ctx {
+  bmg_params p{};
+  int K = 1, prec = 0, sprec = 0, bcm = 0;
+  size_t tsize = 8, ssize = 8;
+  hipStream_t stream = nullptr;
+  bool own_ws = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<LevelInfo> lev;
+  RefData ref;
+  void* elemT = nullptr;
+  void* elem64 = nullptr;
+  void* xferT = nullptr;
+  double* coarse_inv = nullptr;
+  // FP64 Krylov storage
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *rr = nullptr, *ax = nullptr, *t0 = nullptr, *t1 = nullptr;
+  double *hdev = nullptr, *partial = nullptr;
+  std::string err;
+};
+
+namespace {
+
+bmg_status fail(bmg_ctx* c, bmg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                       \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail(ctx, BMG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t n_u_of(int N, int k) { return 2LL * N * (N + 1) * (k + 1) + 2LL * k * (k + 1) * N * N; }
+int64_t n_p_of(int N, int k) { return (int64_t)(k + 1) * (k + 1) * N * N; }
+
+int npatch_colour(int N, int colour) {
+  const int c3x = colour % 3, c3y = colour / 3;
+  if (c3x > N || c3y > N) return 0;
+  return ((N - c3x) / 3 + 1) * ((N - c3y) / 3 + 1);
+}
+
+bmg_status check_params(const bmg_params* p) {
+  if (!p) return BMG_E_ARG;
+  if (p->k != 1 && p->k != 2) return BMG_E_UNSUPPORTED;
+  if (p->n0 < 2 || p->n0 > 64 || p->levels < 0 || p->levels > 12) return BMG_E_ARG;
+  if ((int64_t)p->n0 << p->levels > 4096) return BMG_E_ARG;
+  if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
+  for (int s = 0; s < 4; ++s)
+    if (p->bc[s] != BMG_BC_DIRICHLET && p->bc[s] != BMG_BC_OPEN) return BMG_E_ARG;
+  if (p->cycle != BMG_CYCLE_STANDARD && p->cycle != BMG_CYCLE_VARIABLE) return BMG_E_ARG;
+  if (p->m_fine < 1 || p->m_fine > 64) return BMG_E_ARG;
+  if (p->precond_prec != BMG_P_FP64 && p->precond_prec != BMG_P_FP32) return BMG_E_ARG;
+  if (p->restart < 1 || p->restart > 512) return BMG_E_ARG;
+  return BMG_OK;
+}
+
+// --------------------------------------------------------------------------
+// Patch layout on the host (same slot order as the smoother kernel)
+// --------------------------------------------------------------------------
+struct HostIdx {
+  int N, k, NB, NA, NV, NP, NL, NI, bcm;
+  HostIdx(int N_, int k_, int bcm_) : N(N_), k(k_), bcm(bcm_) {
+    NB = k + 1;
+    NA = k + 2;
+    NV = NA * NB;
+    NP = NB * NB;
+    NL = 2 * NV + NP;
+    NI = 2 * k * NB;
+  }
+  int64_t xface(int i, int cy, int b) const { return ((int64_t)cy * (N + 1) + i) * NB + b; }
+  int64_t yface(int j, int cx, int b) const { return (int64_t)N * (N + 1) * NB + ((int64_t)j * N + cx) * NB + b; }
+  int64_t inter(int64_t c, int comp, int a, int b) const {
+    return 2LL * N * (N + 1) * NB + c * NI + (comp * k + (a - 2)) * NB + b;
+  }
+  int64_t pres(int64_t c, int q) const { return n_u_of(N, k) + c * NP + q; }
+  int64_t g(int cx, int cy, int d) const {
+    const int64_t c = (int64_t)cy * N + cx;
+    if (d < NV) {
+      const int a = d / NB, b = d % NB;
+      return a == 0 ? xface(cx, cy, b) : a == 1 ? xface(cx + 1, cy, b) : inter(c, 0, a, b);
+    }
+    if (d < 2 * NV) {
+      const int e = d - NV, a = e / NB, b = e % NB;
+      return a == 0 ? yface(cy, cx, b) : a == 1 ? yface(cy + 1, cx, b) : inter(c, 1, a, b);
+    }
+    return pres(c, d - 2 * NV);
+  }
+  bool cons(int cx, int cy, int d) const {
+    if (d < NV) {
+      const int a = d / NB;
+      return (a == 0 && cx == 0 && (bcm & 1)) || (a == 1 && cx == N - 1 && (bcm & 2));
+    }
+    if (d < 2 * NV) {
+      const int a = (d - NV) / NB;
+      return (a == 0 && cy == 0 && (bcm & 4)) || (a == 1 && cy == N - 1 && (bcm & 8));
+    }
+    return false;
+  }
+  bool in(int cx, int cy) const { return cx >= 0 && cx < N && cy >= 0 && cy < N; }
+};
+
+const int kGroupH[12][4] = {{0, 0, -1, 0}, {0, 1, 1, 0},  {1, 1, -1, 0}, {2, 0, -1, 0},
+                            {2, 1, 3, 0},  {3, 1, -1, 0}, {0, 2, -1, 0}, {1, 2, -1, 0},
+                            {0, 3, 2, 2},  {1, 3, 3, 2},  {2, 3, -1, 0}, {3, 3, -1, 0}};
+const int kRegularH[4] = {1, 4, 8, 9};
+
+struct PatchLayout {
+  bool ext = false;
+  int ns = 0;
+  std::vector<int64_t> g;      // per slot entry, -1 = not part of the patch space
+  std::vector<int> boundary;   // per slot entry: a free normal dof on the domain boundary
+  std::vector<int> lane;       // per (slot s, local d): entry index or -1
+};
+
+PatchLayout build_layout(const HostIdx& I, int vx, int vy, bool ext) {
+  PatchLayout P;
+  P.ext = ext;
+  const int nf = ext ? 12 : 4;
+  P.ns = nf * I.NB + 4 * I.NI + 4 * I.NP;
+  P.g.assign(P.ns, -1);
+  P.boundary.assign(P.ns, 0);
+  P.lane.assign(4 * I.NL, -1);
+  auto kind_local = [&](int kind, int b) { return (kind >= 2 ? I.NV : 0) + (kind & 1) * I.NB + b; };
+  for (int t = 0; t < P.ns; ++t) {
+    if (t < nf * I.NB) {
+      const int grp = ext ? t / I.NB : kRegularH[t / I.NB];
+      const int b = t % I.NB;
+      const int sA = kGroupH[grp][0], kA = kGroupH[grp][1], sB = kGroupH[grp][2], kB = kGroupH[grp][3];
+      const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
+      const bool vA = I.in(axA, ayA);
+      bool vB = false;
+      int axB = 0, ayB = 0;
+      if (sB >= 0) {
+        axB = vx - 1 + (sB & 1);
+        ayB = vy - 1 + (sB >> 1);
+        vB = I.in(axB, ayB);
+      }
+      bool ok, bnd;
+      int cxu, cyu, du;
+      if (sB >= 0) {
+        ok = vA || vB;
+        bnd = vA != vB;
+        cxu = vA ? axA : axB;
+        cyu = vA ? ayA : ayB;
+        du = kind_local(vA ? kA : kB, b);
+      } else {
+        int ox = axA, oy = ayA;
+        if (kA == 0) ox -= 1;
+        else if (kA == 1) ox += 1;
+        else if (kA == 2) oy -= 1;
+        else oy += 1;
+        ok = vA && !I.in(ox, oy);
+        bnd = true;
+        cxu = axA;
+        cyu = ayA;
+        du = kind_local(kA, b);
+      }
+      if (ok && !I.cons(cxu, cyu, du)) {
+        P.g[t] = I.g(cxu, cyu, du);
+        P.boundary[t] = bnd;
+        if (vA) P.lane[sA * I.NL + kind_local(kA, b)] = t;
+        if (vB) P.lane[sB * I.NL + kind_local(kB, b)] = t;
+      }
+    } else {
+      const int e = t - nf * I.NB;
+      int s, d;
+      if (e < 4 * I.NI) {
+        s = e / I.NI;
+        const int w2 = e % I.NI, comp = w2 / (I.k * I.NB), rem = w2 % (I.k * I.NB);
+        d = comp * I.NV + (2 + rem / I.NB) * I.NB + rem % I.NB;
+      } else {
+        s = (e - 4 * I.NI) / I.NP;
+        d = 2 * I.NV + (e - 4 * I.NI) % I.NP;
+      }
+      const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+      if (I.in(cx, cy)) {
+        P.g[t] = I.g(cx, cy, d);
+        P.lane[s * I.NL + d] = t;
+      }
+    }
+  }
+  return P;
+}
+
+bool needs_ext(const HostIdx& I, int vx, int vy) {
+  PatchLayout P = build_layout(I, vx, vy, true);
+  for (int grp : {0, 2, 3, 5, 6, 7, 10, 11})
+    for (int b = 0; b < I.NB; ++b)
+      if (P.g[grp * I.NB + b] >= 0) return true;
+  return false;
+}
+
+// Dense A restricted to the patch layout (invalid entries: zero rows/cols),
+// from the same cell and face blocks the kernels use.
+void patch_matrix(const HostIdx& I, const RefData& R, const LevelInfo& L, int vx, int vy, const PatchLayout& P,
+                  std::vector<double>& A) {
+  const int ns = P.ns, NV = I.NV, NP = I.NP, NL = I.NL;
+  A.assign((size_t)ns * ns, 0.0);
+  auto add = [&](int s, int d, int s2, int e, double v) {
+    const int t = P.lane[s * NL + d], u = P.lane[s2 * NL + e];
+    if (t >= 0 && u >= 0) A[(size_t)t * ns + u] += v;
+  };
+  const double h = L.h, hh = h * h;
+  for (int s = 0; s < 4; ++s) {
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    if (!I.in(cx, cy)) continue;
+    const double khh = L.kappa[(size_t)cy * I.N + cx] * hh;
+    for (int comp = 0; comp < 2; ++comp) {
+      const int o = comp * NV;
+      const std::vector<double>& Dm = comp == 0 ? R.Dx : R.Dy;
+      for (int d = 0; d < NV; ++d) {
+        for (int e = 0; e < NV; ++e) add(s, o + d, s, o + e, R.Kmu[d * NV + e] + khh * R.M[d * NV + e]);
+        for (int q = 0; q < NP; ++q) {
+          add(s, o + d, s, 2 * NV + q, -h * Dm[q * NV + d]);
+          add(s, 2 * NV + q, s, o + d, -h * Dm[q * NV + d]);
+        }
+      }
+      // faces across which this component is tangential: lower (side 1 of the face) and upper (side 0)
+      for (int up = 0; up < 2; ++up) {
+        int ncx = cx, ncy = cy, side;
+        if (comp == 0) {
+          ncy += up ? 1 : -1;
+          side = up ? 3 : 2;
+        } else {
+          ncx += up ? 1 : -1;
+          side = up ? 1 : 0;
+        }
+        if (!I.in(ncx, ncy)) {
+          if ((I.bcm >> side) & 1) {
+            const std::vector<double>& Nb = R.Nb[up];
+            for (int d = 0; d < NV; ++d)
+              for (int e = 0; e < NV; ++e) add(s, o + d, s, o + e, Nb[d * NV + e]);
+          }
+          continue;
+        }
+        const std::vector<double>& Fs = R.F[up ? 0 : 3];
+        const std::vector<double>& Fn = R.F[up ? 1 : 2];
+        for (int d = 0; d < NV; ++d)
+          for (int e = 0; e < NV; ++e) add(s, o + d, s, o + e, Fs[d * NV + e]);
+        const int dx = ncx - (vx - 1), dy = ncy - (vy - 1);
+        if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) {
+          const int s2 = dy * 2 + dx;
+          for (int d = 0; d < NV; ++d)
+            for (int e = 0; e < NV; ++e) add(s, o + d, s2, o + e, Fn[d * NV + e]);
+        }
+      }
+    }
+  }
+}
+
+// Gauss-Jordan inverse with partial pivoting (row-major, in place on a copy).
+bool gauss_jordan(int n, std::vector<double>& a, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    double best = std::fabs(a[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = std::fabs(a[(size_t)r * n + c]);
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (!(best > 0.0)) return false;
+    if (piv != c) {
+      std::swap_ranges(a.begin() + (size_t)piv * n, a.begin() + (size_t)piv * n + n, a.begin() + (size_t)c * n);
+      std::swap_ranges(inv.begin() + (size_t)piv * n, inv.begin() + (size_t)piv * n + n, inv.begin() + (size_t)c * n);
+    }
+    const double d = 1.0 / a[(size_t)c * n + c];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)c * n + j] *= d;
+      inv[(size_t)c * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      double* ar = &a[(size_t)r * n];
+      double* ir = &inv[(size_t)r * n];
+      const double* ac = &a[(size_t)c * n];
+      const double* ic = &inv[(size_t)c * n];
+      for (int j = 0; j < n; ++j) {
+        ar[j] -= f * ac[j];
+        ir[j] -= f * ic[j];
+      }
+    }
+  }
+  return true;
+}
+
+// Pseudo-inverse of the patch matrix in the layout (ns x ns, zero for invalid
+// entries).  If no free normal dof of the patch lies on the domain boundary, the
+// constant patch pressure spans the kernel: invert the matrix bordered with that
+// (normalised) vector and keep the leading block.
+bool patch_pinv(const HostIdx& I, const PatchLayout& P, const std::vector<double>& A, std::vector<double>& out,
+                bool* singular) {
+  std::vector<int> idx;
+  bool has_bnd = false;
+  for (int t = 0; t < P.ns; ++t)
+    if (P.g[t] >= 0) {
+      idx.push_back(t);
+      if (P.boundary[t]) has_bnd = true;
+    }
+  const int n = (int)idx.size();
+  const bool sing = !has_bnd;
+  if (singular) *singular = sing;
+  const int m = sing ? n + 1 : n;
+  std::vector<double> a((size_t)m * m, 0.0), inv;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) a[(size_t)i * m + j] = A[(size_t)idx[i] * P.ns + idx[j]];
+  if (sing) {
+    // constant pressure: the L_0 L_0 coefficient of every patch cell
+    std::vector<double> c(n, 0.0);
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+      const int64_t gi = P.g[idx[i]];
+      const int64_t nu = n_u_of(I.N, I.k);
+      if (gi >= nu && (gi - nu) % I.NP == 0) {
+        c[i] = 1.0;
+        ++cnt;
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      c[i] /= std::sqrt((double)cnt);
+      a[(size_t)i * m + n] = c[i];
+      a[(size_t)n * m + i] = c[i];
+    }
+  }
+  if (!gauss_jordan(m, a, inv)) return false;
+  out.assign((size_t)P.ns * P.ns, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[(size_t)idx[i] * P.ns + idx[j]] = inv[(size_t)i * m + j];
+  return true;
+}
+
+template <typename F>
+void parallel_for(int n, F&& f) {
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (nt > 32) nt = 32;
+  if ((int)nt > n) nt = std::max(1, n);
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (;;) {
+        const int i = next.fetch_add(1);
+        if (i >= n) break;
+        f(i);
+      }
+    });
+  for (auto& t : th) t.join();
+}
+
+// --------------------------------------------------------------------------
+// Workspace layout
+// --------------------------------------------------------------------------
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(char* b) : base(b) {}
+  void* take(size_t bytes) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+template <typename T>
+size_t elem_bytes(int K) {
+  return K == 1 ? sizeof(Elem<T, 1>) : sizeof(Elem<T, 2>);
+}
+template <typename T>
+size_t xfer_bytes(int K) {
+  return K == 1 ? sizeof(Xfer<T, 1>) : sizeof(Xfer<T, 2>);
+}
+
+int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
+int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
+
+// assigns every device pointer of the context; with a null base only sizes
+size_t layout(bmg_ctx* c, char* base) {
+  Bump B(base);
+  const int K = c->K;
+  const size_t ts = c->tsize, ss = c->ssize;
+  const int nsr = nsr_of(K), nse = nse_of(K);
+  for (size_t j = 0; j < c->lev.size(); ++j) {
+    LevelInfo& L = c->lev[j];
+    const int64_t nc = (int64_t)L.N * L.N;
+    L.kap = B.take(nc * ts);
+    L.kap64 = (double*)B.take(nc * sizeof(double));
+    L.x = B.take(L.ndof * ts);
+    L.b = B.take(L.ndof * ts);
+    L.r = B.take(L.ndof * ts);
+    if (j > 0)
+      for (int col = 0; col < 9; ++col) {
+        L.inv[col] = B.take((size_t)L.npatch[col] * nsr * nsr * ss);
+        L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * nse * nse * ss);
+        L.extidx[col] = (int32_t*)B.take((size_t)std::max(L.npatch[col], 1) * sizeof(int32_t));
+      }
+  }
+  const int64_t n0 = c->lev[0].ndof;
+  c->coarse_inv = (double*)B.take((size_t)n0 * n0 * sizeof(double));
+  c->elemT = B.take(c->prec == 0 ? elem_bytes<double>(K) : elem_bytes<float>(K));
+  c->elem64 = B.take(elem_bytes<double>(K));
+  c->xferT = B.take(c->prec == 0 ? xfer_bytes<double>(K) : xfer_bytes<float>(K));
+  const int64_t n = c->lev.back().ndof;
+  const int m = c->p.restart;
+  c->V = (double*)B.take((size_t)(m + 1) * n * sizeof(double));
+  c->Z = (double*)B.take((size_t)m * n * sizeof(double));
+  c->w = (double*)B.take(n * sizeof(double));
+  c->rr = (double*)B.take(n * sizeof(double));
+  c->ax = (double*)B.take(n * sizeof(double));
+  c->t0 = (double*)B.take(n * sizeof(double));
+  c->t1 = (double*)B.take(n * sizeof(double));
+  c->hdev = (double*)B.take((size_t)(2 * (m + 2) + 8) * sizeof(double));
+  c->partial = (double*)B.take((size_t)dots_partial_count() * (m + 2) * sizeof(double));
+  return B.off + kAlign;
+}
+
+void init_levels(bmg_ctx* c) {
+  const bmg_params& p = c->p;
+  c->lev.assign(p.levels + 1, LevelInfo());
+  for (int j = 0; j <= p.levels; ++j) {
+    LevelInfo& L = c->lev[j];
+    L.N = p.n0 << j;
+    L.h = 1.0 / L.N;
+    L.n_u = n_u_of(L.N, p.k);
+    L.n_p = n_p_of(L.N, p.k);
+    L.ndof = L.n_u + L.n_p;
+    if (j > 0) {
+      HostIdx I(L.N, p.k, c->bcm);
+      for (int col = 0; col < 9; ++col) {
+        L.npatch[col] = npatch_colour(L.N, col);
+        int ne = 0;
+        const int c3x = col % 3, c3y = col / 3;
+        // only vertices next to an open side can need the extended layout
+        for (int vy = c3y; vy <= L.N; vy += 3)
+          for (int vx = c3x; vx <= L.N; vx += 3) {
+            const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
+            if (near && needs_ext(I, vx, vy)) ++ne;
+          }
+        L.next[col] = ne;
+      }
+    }
+  }
+}
+
+int bc_mask(const bmg_params& p) {
+  int m = 0;
+  for (int s = 0; s < 4; ++s)
+    if (p.bc[s] == BMG_BC_DIRICHLET) m |= 1 << s;
+  return m;
+}
+
+void setup_types(bmg_ctx* c) {
+  c->K = c->p.k;
+  c->prec = c->p.precond_prec == BMG_P_FP64 ? 0 : 1;
+  c->sprec = c->prec;  // inverses stored in the preconditioner arithmetic
+  c->tsize = c->prec == 0 ? 8 : 4;
+  c->ssize = c->sprec == 0 ? 8 : 4;
+  c->bcm = bc_mask(c->p);
+}
+
+template <typename T, int K>
+void fill_elem(const RefData& R, Elem<T, K>& E) {
+  using D = Dims<K>;
+  for (int i = 0; i < D::NV * D::NV; ++i) {
+    E.Kmu[i] = (T)R.Kmu[i];
+    E.M[i] = (T)R.M[i];
+    for (int f = 0; f < 4; ++f) E.F[f][i] = (T)R.F[f][i];
+    for (int f = 0; f < 2; ++f) E.Nb[f][i] = (T)R.Nb[f][i];
+  }
+  for (int i = 0; i < D::NP * D::NV; ++i) {
+    E.Dx[i] = (T)R.Dx[i];
+    E.Dy[i] = (T)R.Dy[i];
+  }
+}
+
+template <typename T, int K>
+void fill_xfer(const RefData& R, Xfer<T, K>& X) {
+  using D = Dims<K>;
+  for (int s = 0; s < 2; ++s) {
+    for (int i = 0; i < D::NA * D::NA; ++i) X.Ppsi[s][i] = (T)R.Ppsi[s][i];
+    for (int i = 0; i < D::NB * D::NB; ++i) X.PL[s][i] = (T)R.PL[s][i];
+  }
+}
+
+template <typename T, int K>
+bmg_status upload_consts(bmg_ctx* c, void* dst, bool elem, bool as_double) {
+  (void)as_double;
+  if (elem) {
+    Elem<T, K> E;
+    fill_elem<T, K>(c->ref, E);
+    HIPCHK(c, hipMemcpy(dst, &E, sizeof(E), hipMemcpyHostToDevice));
+  } else {
+    Xfer<T, K> X;
+    fill_xfer<T, K>(c->ref, X);
+    HIPCHK(c, hipMemcpy(dst, &X, sizeof(X), hipMemcpyHostToDevice));
+  }
+  return BMG_OK;
+}
+
+bmg_status upload_all_consts(bmg_ctx* c) {
+  bmg_status s;
+  if (c->K == 1) {
+    s = c->prec == 0 ? upload_consts<double, 1>(c, c->elemT, true, false) : upload_consts<float, 1>(c, c->elemT, true, false);
+    if (s) return s;
+    s = upload_consts<double, 1>(c, c->elem64, true, true);
+    if (s) return s;
+    s = c->prec == 0 ? upload_consts<double, 1>(c, c->xferT, false, false) : upload_consts<float, 1>(c, c->xferT, false, false);
+  } else {
+    s = c->prec == 0 ? upload_consts<double, 2>(c, c->elemT, true, false) : upload_consts<float, 2>(c, c->elemT, true, false);
+    if (s) return s;
+    s = upload_consts<double, 2>(c, c->elem64, true, true);
+    if (s) return s;
+    s = c->prec == 0 ? upload_consts<double, 2>(c, c->xferT, false, false) : upload_consts<float, 2>(c, c->xferT, false, false);
+  }
+  return s;
+}
+
+// upload a host FP64 array converted to the arithmetic `prec`
+bmg_status upload_converted(bmg_ctx* c, void* dst, const double* src, size_t n, int prec) {
+  if (prec == 0) {
+    HIPCHK(c, hipMemcpy(dst, src, n * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+    HIPCHK(c, hipMemcpy(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return BMG_OK;
+}
+
+// Dense A_j of a (small) level from the cell and face blocks; rows and columns
+// of the essential normal dofs are the identity.
+std::vector<double> dense_level(const RefData& R, int k, int bcm, int N, const std::vector<double>& kappa) {
+  HostIdx I(N, k, bcm);
+  const int64_t n = n_u_of(N, k) + n_p_of(N, k);
+  std::vector<double> A((size_t)n * n, 0.0);
+  const int NV = I.NV, NP = I.NP;
+  auto add = [&](int cx, int cy, int d, int cx2, int cy2, int e, double v) {
+    if (I.cons(cx, cy, d) || I.cons(cx2, cy2, e)) return;
+    A[(size_t)I.g(cx, cy, d) * n + I.g(cx2, cy2, e)] += v;
+  };
+  const double h = 1.0 / N, hh = h * h;
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx) {
+      const double khh = kappa[(size_t)cy * N + cx] * hh;
+      for (int comp = 0; comp < 2; ++comp) {
+        const int o = comp * NV;
+        const std::vector<double>& Dm = comp == 0 ? R.Dx : R.Dy;
+        for (int d = 0; d < NV; ++d) {
+          for (int e = 0; e < NV; ++e) add(cx, cy, o + d, cx, cy, o + e, R.Kmu[d * NV + e] + khh * R.M[d * NV + e]);
+          for (int q = 0; q < NP; ++q) {
+            add(cx, cy, o + d, cx, cy, 2 * NV + q, -h * Dm[q * NV + d]);
+            add(cx, cy, 2 * NV + q, cx, cy, o + d, -h * Dm[q * NV + d]);
+          }
+        }
+        for (int up = 0; up < 2; ++up) {
+          int ncx = cx, ncy = cy, side;
+          if (comp == 0) {
+            ncy += up ? 1 : -1;
+            side = up ? 3 : 2;
+          } else {
+            ncx += up ? 1 : -1;
+            side = up ? 1 : 0;
+          }
+          if (!I.in(ncx, ncy)) {
+            if ((bcm >> side) & 1)
+              for (int d = 0; d < NV; ++d)
+                for (int e = 0; e < NV; ++e) add(cx, cy, o + d, cx, cy, o + e, R.Nb[up][d * NV + e]);
+            continue;
+          }
+          const std::vector<double>& Fs = R.F[up ? 0 : 3];
+          const std::vector<double>& Fn = R.F[up ? 1 : 2];
+          for (int d = 0; d < NV; ++d)
+            for (int e = 0; e < NV; ++e) {
+              add(cx, cy, o + d, cx, cy, o + e, Fs[d * NV + e]);
+              add(cx, cy, o + d, ncx, ncy, o + e, Fn[d * NV + e]);
+            }
+        }
+      }
+    }
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx)
+      for (int d = 0; d < I.NL; ++d)
+        if (I.cons(cx, cy, d)) {
+          const int64_t gi = I.g(cx, cy, d);
+          A[(size_t)gi * n + gi] = 1.0;
+        }
+  return A;
+}
+
+// (Pseudo-)inverse of A_0, stored column-major on the device.  With every side
+// Dirichlet the constant pressure spans the kernel: bordered inverse.
+bmg_status build_coarse(bmg_ctx* c) {
+  const LevelInfo& L = c->lev[0];
+  HostIdx I(L.N, c->K, c->bcm);
+  const int64_t n = L.ndof;
+  std::vector<double> A = dense_level(c->ref, c->K, c->bcm, L.N, L.kappa);
+  const bool sing = (c->bcm == 15);
+  const int64_t m = sing ? n + 1 : n;
+  std::vector<double> a((size_t)m * m, 0.0), inv;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) a[(size_t)i * m + j] = A[(size_t)i * n + j];
+  if (sing) {
+    const double cv = 1.0 / L.N;
+    for (int64_t cc = 0; cc < (int64_t)L.N * L.N; ++cc) {
+      const int64_t gi = I.pres(cc, 0);
+      a[(size_t)gi * m + n] = cv;
+      a[(size_t)n * m + gi] = cv;
+    }
+  }
+  if (!gauss_jordan((int)m, a, inv)) return fail(c, BMG_E_SINGULAR, "coarse matrix is singular");
+  std::vector<double> cm((size_t)n * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) cm[(size_t)j * n + i] = inv[(size_t)i * m + j];
+  HIPCHK(c, hipMemcpy(c->coarse_inv, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
+  return BMG_OK;
+}
+
+// Patch pseudo-inverses of level j, colour by colour, uploaded column-major.
+bmg_status build_patches(bmg_ctx* c, int j) {
+  LevelInfo& L = c->lev[j];
+  HostIdx I(L.N, c->K, c->bcm);
+  const int nsr = nsr_of(c->K), nse = nse_of(c->K);
+  for (int col = 0; col < 9; ++col) {
+    const int np = L.npatch[col];
+    if (np == 0) continue;
+    const int c3x = col % 3, c3y = col / 3;
+    const int nvx = (L.N - c3x) / 3 + 1;
+    std::vector<int32_t> ext(np, -1);
+    int ne = 0;
+    for (int p = 0; p < np; ++p) {
+      const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+      const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
+      if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
+    }
+    std::vector<double> reg((size_t)np * nsr * nsr, 0.0), exd((size_t)std::max(ne, 1) * nse * nse, 0.0);
+    std::atomic<int> bad{0};
+    parallel_for(np, [&](int p) {
+      const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+      const bool isx = ext[p] >= 0;
+      PatchLayout P = build_layout(I, vx, vy, isx);
+      std::vector<double> A, pinv;
+      patch_matrix(I, c->ref, L, vx, vy, P, A);
+      if (!patch_pinv(I, P, A, pinv, nullptr)) {
+        bad.store(1);
+        return;
+      }
+      double* dst = isx ? &exd[(size_t)ext[p] * nse * nse] : &reg[(size_t)p * nsr * nsr];
+      const int ns = P.ns;
+      for (int t = 0; t < ns; ++t)
+        for (int u = 0; u < ns; ++u) dst[(size_t)u * ns + t] = pinv[(size_t)t * ns + u];
+    });
+    if (bad.load()) return fail(c, BMG_E_SINGULAR, "a patch matrix is singular");
+    bmg_status s = upload_converted(c, L.inv[col], reg.data(), reg.size(), c->sprec);
+    if (s) return s;
+    if (ne > 0) {
+      s = upload_converted(c, L.invx[col], exd.data(), (size_t)ne * nse * nse, c->sprec);
+      if (s) return s;
+    }
+    HIPCHK(c, hipMemcpy(L.extidx[col], ext.data(), np * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  return BMG_OK;
+}
+
+// --------------------------------------------------------------------------
+// Cycle
+// --------------------------------------------------------------------------
+LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
+  LevelArgs a;
+  a.N = c->lev[j].N;
+  a.bcm = c->bcm;
+  a.h = c->lev[j].h;
+  a.kap = fp64 ? (const void*)c->lev[j].kap64 : c->lev[j].kap;
+  return a;
+}
+
+void smooth_level(bmg_ctx* c, int j, int steps) {
+  LevelInfo& L = c->lev[j];
+  LevelArgs a = largs(c, j, c->prec == 0);
+  for (int st = 0; st < steps; ++st)
+    for (int i = 0; i < 17; ++i) {
+      const int col = i < 9 ? i : 16 - i;
+      launch_colour(c->K, c->prec, c->sprec, c->elemT, a, L.x, L.b, L.inv[col], L.invx[col], L.extidx[col], col,
+                    L.npatch[col], c->stream);
+    }
+}
+
+int smoothing_steps(const bmg_ctx* c, int j) {
+  if (c->p.cycle == BMG_CYCLE_VARIABLE) return c->p.m_fine << (c->p.levels - j);
+  return c->p.m_fine;
+}
+
+// B_j applied to lev[j].b, result in lev[j].x (Section 3.2).
+void vcycle_level(bmg_ctx* c, int j) {
+  LevelInfo& L = c->lev[j];
+  if (j == 0) {
+    launch_coarse(c->prec, (int)L.ndof, c->coarse_inv, L.b, L.x, c->stream);
+    return;
+  }
+  const int m = smoothing_steps(c, j);
+  hipMemsetAsync(L.x, 0, L.ndof * c->tsize, c->stream);
+  smooth_level(c, j, m);
+  LevelArgs a = largs(c, j, c->prec == 0);
+  launch_op(c->K, c->prec, c->elemT, a, L.x, L.b, L.r, true, c->stream);
+  LevelInfo& C = c->lev[j - 1];
+  launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, L.r, C.b, c->stream);
+  vcycle_level(c, j - 1);
+  launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, C.x, L.x, c->stream);
+  smooth_level(c, j, m);
+}
+
+// z = B_J r with FP64 r, z (device); the essential rows are inverted exactly.
+void apply_precond(bmg_ctx* c, const double* r, double* z) {
+  LevelInfo& L = c->lev.back();
+  launch_cast(c->prec, 0, r, L.b, L.ndof, c->stream);
+  vcycle_level(c, (int)c->lev.size() - 1);
+  launch_cast(0, c->prec, L.x, z, L.ndof, c->stream);
+  launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->stream);
+}
+
+void apply_op64(bmg_ctx* c, int j, const double* x, double* y) {
+  launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, c->stream);
+}
+
+// kappa of level j from the finest field: arithmetic mean of the 4 children per level (Section 4.1)
+std::vector<double> kappa_level(const double* fine, int n0, int J, int j) {
+  int N = n0 << J;
+  std::vector<double> cur(fine, fine + (size_t)N * N);
+  for (int l = J; l > j; --l) {
+    const int Nc = N / 2;
+    std::vector<double> nx((size_t)Nc * Nc);
+    for (int cy = 0; cy < Nc; ++cy)
+      for (int cx = 0; cx < Nc; ++cx) {
+        const size_t f = (size_t)(2 * cy) * N + 2 * cx;
+        nx[(size_t)cy * Nc + cx] = 0.25 * (cur[f] + cur[f + 1] + cur[f + N] + cur[f + N + 1]);
+      }
+    cur.swap(nx);
+    N = Nc;
+  }
+  return cur;
+}
+
+bmg_status check_kappa(const bmg_params* p, const double* kappa) {
+  if (!kappa) return BMG_E_ARG;
+  const int N = p->n0 << p->levels;
+  for (int64_t i = 0; i < (int64_t)N * N; ++i) {
+    if (!std::isfinite(kappa[i])) return BMG_E_NONFINITE;
+    if (!(kappa[i] > 0.0)) return BMG_E_ARG;
+  }
+  return BMG_OK;
+}
+
+bmg_status check_finite_host(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return BMG_E_NONFINITE;
+  return BMG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* bmg_status_string(bmg_status s) {
+  switch (s) {
+    case BMG_OK: return "ok";
+    case BMG_E_ARG: return "invalid argument";
+    case BMG_E_UNSUPPORTED: return "unsupported";
+    case BMG_E_NOMEM: return "out of memory";
+    case BMG_E_HIP: return "HIP error";
+    case BMG_E_SINGULAR: return "singular matrix";
+    case BMG_E_NOT_CONVERGED: return "not converged";
+    case BMG_E_NONFINITE: return "non-finite value";
+    case BMG_E_STATE: return "invalid state";
+  }
+  return "unknown";
+}
+
+const char* bmg_last_error(bmg_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+bmg_status bmg_plan(const bmg_params* p, size_t* bytes) {
+  bmg_status s = check_params(p);
+  if (s) return s;
+  if (!bytes) return BMG_E_ARG;
+  bmg_ctx tmp;
+  tmp.p = *p;
+  setup_types(&tmp);
+  init_levels(&tmp);
+  *bytes = layout(&tmp, nullptr);
+  return BMG_OK;
+}
+
+bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, size_t bytes, void* stream,
+                     bmg_handle* out) {
+  bmg_status s = check_params(p);
+  if (s) return s;
+  if (!out) return BMG_E_ARG;
+  if ((s = check_kappa(p, kappa))) return s;
+  bmg_ctx* c = new bmg_ctx();
+  c->p = *p;
+  c->stream = (hipStream_t)stream;
+  setup_types(c);
+  init_levels(c);
+  const size_t need = layout(c, nullptr);
+  if (workspace) {
+    if (bytes < need || ((uintptr_t)workspace % kAlign) != 0) {
+      delete c;
+      return BMG_E_NOMEM;
+    }
+    c->ws = (char*)workspace;
+  } else {
+    if (hipMalloc((void**)&c->ws, need) != hipSuccess) {
+      delete c;
+      return BMG_E_NOMEM;
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = need;
+  layout(c, c->ws);
+  c->ref = make_refdata(p->k, p->mu, p->sigma);
+  // kappa hierarchy: arithmetic mean of the four children (Section 4.1)
+  for (int j = 0; j <= p->levels; ++j) c->lev[j].kappa = kappa_level(kappa, p->n0, p->levels, j);
+  bmg_status st = upload_all_consts(c);
+  for (size_t j = 0; !st && j < c->lev.size(); ++j) {
+    LevelInfo& L = c->lev[j];
+    st = upload_converted(c, L.kap, L.kappa.data(), L.kappa.size(), c->prec);
+    if (!st) st = upload_converted(c, L.kap64, L.kappa.data(), L.kappa.size(), 0);
+    if (!st && j > 0) st = build_patches(c, (int)j);
+  }
+  if (!st) st = build_coarse(c);
+  if (!st && hipDeviceSynchronize() != hipSuccess) st = fail(c, BMG_E_HIP, "setup synchronisation failed");
+  if (st) {
+    if (c->own_ws) hipFree(c->ws);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return BMG_OK;
+}
+
+bmg_status bmg_destroy(bmg_handle h) {
+  if (!h) return BMG_E_ARG;
+  if (h->own_ws) {
+    hipStreamSynchronize(h->stream);
+    hipFree(h->ws);
+  }
+  delete h;
+  return BMG_OK;
+}
+
+bmg_status bmg_sizes(bmg_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p) {
+  if (!h || level < 0 || level >= (int)h->lev.size()) return BMG_E_ARG;
+  if (N) *N = h->lev[level].N;
+  if (n_u) *n_u = h->lev[level].n_u;
+  if (n_p) *n_p = h->lev[level].n_p;
+  return BMG_OK;
+}
+
+bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x, double* y) {
+  if (!h || !x || !y || level < 0 || level >= (int)h->lev.size()) return BMG_E_ARG;
+  apply_op64(h, level, x, y);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) {
+  if (!h || !r || !z) return BMG_E_ARG;
+  apply_precond(h, r, z);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+// Step entry points: FP64 vectors in/out, run in the handle's arithmetic.
+bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x, const double* b) {
+  if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || colour < 0 || colour > 8) return BMG_E_ARG;
+  LevelInfo& L = h->lev[level];
+  launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
+  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
+  launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
+                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], h->stream);
+  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, const double* b) {
+  if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || steps < 0) return BMG_E_ARG;
+  LevelInfo& L = h->lev[level];
+  launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
+  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
+  smooth_level(h, level, steps);
+  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* bc) {
+  if (!h || !rf || !bc || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
+  LevelInfo& F = h->lev[level];
+  LevelInfo& C = h->lev[level - 1];
+  launch_cast(h->prec, 0, rf, F.r, F.ndof, h->stream);
+  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, h->stream);
+  launch_cast(0, h->prec, C.b, bc, C.ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double* xf) {
+  if (!h || !xc || !xf || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
+  LevelInfo& F = h->lev[level];
+  LevelInfo& C = h->lev[level - 1];
+  launch_cast(h->prec, 0, xc, C.x, C.ndof, h->stream);
+  launch_cast(h->prec, 0, xf, F.x, F.ndof, h->stream);
+  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, h->stream);
+  launch_cast(0, h->prec, F.x, xf, F.ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) {
+  if (!h || !b || !x) return BMG_E_ARG;
+  LevelInfo& L = h->lev[0];
+  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
+  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, h->stream);
+  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+}
+
+bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int32_t maxit, const double* x0,
+                     bmg_solve_info* info) {
+  if (!h || !b || !x || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
+  const int J = (int)h->lev.size() - 1;
+  const int64_t n = h->lev[J].ndof;
+  const int m = h->p.restart;
+  hipStream_t s = h->stream;
+  double* hd = h->hdev;  // [0..m+1]: first Gram-Schmidt pass, [m+2..]: second, [2m+4]: norms
+  std::vector<double> hh(2 * (m + 2) + 8);
+  auto readback = [&](int cnt) -> bmg_status {
+    HIPCHK(h, hipMemcpyAsync(hh.data(), hd, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return BMG_OK;
+  };
+  // ||b||
+  launch_dots(b, 1, n, b, n, h->partial, hd, s);
+  bmg_status st = readback(1);
+  if (st) return st;
+  const double bnorm = std::sqrt(hh[0]);
+  if (!std::isfinite(bnorm)) return fail(h, BMG_E_NONFINITE, "right-hand side is not finite");
+  if (x0) HIPCHK(h, hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else HIPCHK(h, hipMemsetAsync(x, 0, n * sizeof(double), s));
+  if (bnorm == 0.0) {
+    HIPCHK(h, hipMemsetAsync(x, 0, n * sizeof(double), s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (info) *info = {0, 1, 0.0, 0.0};
+    return BMG_OK;
+  }
+  int its = 0;
+  bool conv = false;
+  double est = 1.0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (!conv && its < maxit) {
+    // r = b - A x
+    apply_op64(h, J, x, h->ax);
+    launch_sub(h->rr, b, h->ax, n, s);
+    launch_dots(h->rr, 1, n, h->rr, n, h->partial, hd, s);
+    if ((st = readback(1))) return st;
+    const double beta = std::sqrt(hh[0]);
+    if (!std::isfinite(beta)) return fail(h, BMG_E_NONFINITE, "residual is not finite");
+    est = beta / bnorm;
+    if (beta <= rtol * bnorm) {
+      conv = true;
+      break;
+    }
+    hh[0] = beta;
+    HIPCHK(h, hipMemcpyAsync(hd + 2 * (m + 2), hh.data(), sizeof(double), hipMemcpyHostToDevice, s));
+    launch_scale(h->V, h->rr, hd + 2 * (m + 2), false, n, s);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int i = 0;
+    for (; i < m && its < maxit; ++i) {
+      double* vi = h->V + (size_t)i * n;
+      double* zi = h->Z + (size_t)i * n;
+      apply_precond(h, vi, zi);
+      apply_op64(h, J, zi, h->w);
+      // classical Gram-Schmidt, two passes
+      launch_dots(h->V, i + 1, n, h->w, n, h->partial, hd, s);
+      launch_axpys(h->w, h->V, i + 1, n, hd, -1.0, n, s);
+      launch_dots(h->V, i + 1, n, h->w, n, h->partial, hd + (m + 2), s);
+      launch_axpys(h->w, h->V, i + 1, n, hd + (m + 2), -1.0, n, s);
+      launch_dots(h->w, 1, n, h->w, n, h->partial, hd + 2 * (m + 2), s);
+      if ((st = readback(2 * (m + 2) + 1))) return st;
+      const double hn = std::sqrt(hh[2 * (m + 2)]);
+      for (int k2 = 0; k2 <= i; ++k2) H[(size_t)k2 * m + i] = hh[k2] + hh[(m + 2) + k2];
+      H[(size_t)(i + 1) * m + i] = hn;
+      for (int k2 = 0; k2 < i; ++k2) {
+        const double a = H[(size_t)k2 * m + i], cc = H[(size_t)(k2 + 1) * m + i];
+        H[(size_t)k2 * m + i] = cs[k2] * a + sn[k2] * cc;
+        H[(size_t)(k2 + 1) * m + i] = -sn[k2] * a + cs[k2] * cc;
+      }
+      const double a = H[(size_t)i * m + i], cc = H[(size_t)(i + 1) * m + i];
+      const double den = std::hypot(a, cc);
+      if (!std::isfinite(den) || den == 0.0) return fail(h, BMG_E_NONFINITE, "Arnoldi breakdown");
+      cs[i] = a / den;
+      sn[i] = cc / den;
+      H[(size_t)i * m + i] = den;
+      H[(size_t)(i + 1) * m + i] = 0.0;
+      g[i + 1] = -sn[i] * g[i];
+      g[i] = cs[i] * g[i];
+      ++its;
+      est = std::fabs(g[i + 1]) / bnorm;
+      if (std::fabs(g[i + 1]) <= rtol * bnorm || hn == 0.0) {
+        conv = true;
+        ++i;
+        break;
+      }
+      if (i + 1 < m) launch_scale(h->V + (size_t)(i + 1) * n, h->w, hd + 2 * (m + 2), true, n, s);
+    }
+    for (int r = i - 1; r >= 0; --r) {
+      double sum = g[r];
+      for (int cc = r + 1; cc < i; ++cc) sum -= H[(size_t)r * m + cc] * y[cc];
+      y[r] = sum / H[(size_t)r * m + r];
+    }
+    HIPCHK(h, hipMemcpyAsync(hd, y.data(), i * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_axpys(x, h->Z, i, n, hd, 1.0, n, s);
+    HIPCHK(h, hipStreamSynchronize(s));  // hd is reused by the next restart
+  }
+  // true residual
+  apply_op64(h, J, x, h->ax);
+  launch_sub(h->rr, b, h->ax, n, s);
+  launch_dots(h->rr, 1, n, h->rr, n, h->partial, hd, s);
+  if ((st = readback(1))) return st;
+  HIPCHK(h, hipGetLastError());
+  if (info) {
+    info->iterations = its;
+    info->converged = conv;
+    info->rel_residual_estimate = est;
+    info->rel_residual_true = std::sqrt(hh[0]) / bnorm;
+  }
+  return conv ? BMG_OK : fail(h, BMG_E_NOT_CONVERGED, "maxit reached");
+}
+
+bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if (!cell_xy || !face_xy) return BMG_E_ARG;
+  const int q = p->k + 2, N = p->n0 << p->levels;
+  double x[4], w[4];
+  gauss_points(q, x, w);
+  const double hc = 1.0 / N;
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx)
+      for (int iy = 0; iy < q; ++iy)
+        for (int ix = 0; ix < q; ++ix) {
+          const size_t o = ((((size_t)cy * N + cx) * q + iy) * q + ix) * 2;
+          cell_xy[o] = (cx + x[ix]) * hc;
+          cell_xy[o + 1] = (cy + x[iy]) * hc;
+        }
+  for (int sd = 0; sd < 4; ++sd)
+    for (int f = 0; f < N; ++f)
+      for (int i = 0; i < q; ++i) {
+        const size_t o = (((size_t)sd * N + f) * q + i) * 2;
+        const double t = (f + x[i]) * hc;
+        if (sd < 2) {
+          face_xy[o] = sd == 0 ? 0.0 : 1.0;
+          face_xy[o + 1] = t;
+        } else {
+          face_xy[o] = t;
+          face_xy[o + 1] = sd == 2 ? 0.0 : 1.0;
+        }
+      }
+  return BMG_OK;
+}
+
+bmg_status bmg_assemble_rhs(const bmg_params* p, const double* f_qp, const double* s_qp, const double* g_qp,
+                            double* b) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if (!f_qp || !b) return BMG_E_ARG;
+  bmg_ctx tmp;
+  bmg_ctx* h = &tmp;
+  h->p = *p;
+  setup_types(h);
+  const RefData R = make_refdata(p->k, p->mu, p->sigma);
+  const int N = p->n0 << p->levels;
+  HostIdx I(N, h->K, h->bcm);
+  const int q = h->K + 2, NB = I.NB, NA = I.NA;
+  const double mu = p->mu, sigma = p->sigma;
+  const double Lh = 1.0 / N;
+  const int64_t ndof = n_u_of(N, p->k) + n_p_of(N, p->k);
+  double x[4], w[4];
+  gauss_points(q, x, w);
+  const size_t ncell = (size_t)N * N * q * q;
+  if (check_finite_host(f_qp, 2 * ncell)) return BMG_E_NONFINITE;
+  if (s_qp && check_finite_host(s_qp, ncell)) return BMG_E_NONFINITE;
+  if (g_qp) {
+    if (check_finite_host(g_qp, (size_t)4 * N * q * 2)) return BMG_E_NONFINITE;
+    for (int sd = 0; sd < 4; ++sd) {
+      if (!((h->bcm >> sd) & 1)) continue;
+      for (int i = 0; i < N * q; ++i)
+        if (g_qp[((size_t)sd * N * q + i) * 2 + (sd < 2 ? 0 : 1)] != 0.0)
+          return BMG_E_UNSUPPORTED;
+    }
+  }
+  // 1-D tables at the points
+  std::vector<double> Lq(NB * q), Pq(NA * q);
+  for (int b2 = 0; b2 < NB; ++b2)
+    for (int i = 0; i < q; ++i) Lq[b2 * q + i] = R.L[b2](x[i]);
+  for (int a = 0; a < NA; ++a)
+    for (int i = 0; i < q; ++i) Pq[a * q + i] = R.P[a](x[i]);
+  std::vector<double> out(ndof, 0.0);
+  const double hh = Lh * Lh;
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx)
+      for (int iy = 0; iy < q; ++iy)
+        for (int ix = 0; ix < q; ++ix) {
+          const size_t pt = (((size_t)cy * N + cx) * q + iy) * q + ix;
+          const double wt = w[ix] * w[iy] * hh;
+          const double fx = f_qp[2 * pt], fy = f_qp[2 * pt + 1];
+          for (int a = 0; a < NA; ++a)
+            for (int b2 = 0; b2 < NB; ++b2) {
+              const int d = a * NB + b2;
+              out[I.g(cx, cy, d)] += wt * fx * Pq[a * q + ix] * Lq[b2 * q + iy];
+              out[I.g(cx, cy, I.NV + d)] += wt * fy * Lq[b2 * q + ix] * Pq[a * q + iy];
+            }
+          if (s_qp)
+            for (int pb = 0; pb < NB; ++pb)
+              for (int pa = 0; pa < NB; ++pa)
+                out[I.pres((int64_t)cy * N + cx, pb * NB + pa)] -= wt * s_qp[pt] * Lq[pa * q + ix] * Lq[pb * q + iy];
+        }
+  if (g_qp && mu > 0.0) {
+    // tangential Nitsche terms on Dirichlet sides: the tangential component's
+    // Legendre index runs across the face (value and normal derivative at 0 or 1)
+    for (int sd = 0; sd < 4; ++sd) {
+      if (!((h->bcm >> sd) & 1)) continue;
+      const bool at1 = (sd == 1 || sd == 3);
+      for (int f = 0; f < N; ++f) {
+        const int cx = sd == 0 ? 0 : sd == 1 ? N - 1 : f;
+        const int cy = sd == 2 ? 0 : sd == 3 ? N - 1 : f;
+        const int comp = sd < 2 ? 1 : 0;  // tangential component
+        for (int b2 = 0; b2 < NB; ++b2) {
+          const double Lv = R.L[b2](at1 ? 1.0 : 0.0);
+          const double dLv = R.L[b2].deriv()(at1 ? 1.0 : 0.0);
+          const double fac = 2.0 * mu * sigma * Lv + (at1 ? -mu * dLv : mu * dLv);
+          for (int a = 0; a < NA; ++a) {
+            double s = 0.0;
+            for (int i = 0; i < q; ++i) s += w[i] * g_qp[(((size_t)sd * N + f) * q + i) * 2 + comp] * Pq[a * q + i];
+            out[I.g(cx, cy, comp * I.NV + a * NB + b2)] += fac * s;
+          }
+        }
+      }
+    }
+  }
+  // essential rows: zero normal data
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx)
+      for (int d = 0; d < 2 * I.NV; ++d)
+        if (I.cons(cx, cy, d)) out[I.g(cx, cy, d)] = 0.0;
+  std::copy(out.begin(), out.end(), b);
+  return BMG_OK;
+}
+
+bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t level, int32_t vx, int32_t vy,
+                            int32_t* n, int32_t* dofs, double* inv, int32_t* colour) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_kappa(p, kappa))) return st;
+  if (!n || !dofs || level < 1 || level > p->levels) return BMG_E_ARG;
+  const int N = p->n0 << level;
+  if (vx < 0 || vy < 0 || vx > N || vy > N) return BMG_E_ARG;
+  HostIdx I(N, p->k, bc_mask(*p));
+  const bool near = vx == 1 || vx == N - 1 || vy == 1 || vy == N - 1;
+  PatchLayout P = build_layout(I, vx, vy, near && needs_ext(I, vx, vy));
+  std::vector<int> idx;
+  for (int t = 0; t < P.ns; ++t)
+    if (P.g[t] >= 0) idx.push_back(t);
+  *n = (int32_t)idx.size();
+  for (size_t i = 0; i < idx.size(); ++i) dofs[i] = (int32_t)P.g[idx[i]];
+  if (colour) *colour = (vx % 3) + 3 * (vy % 3);
+  if (inv) {
+    LevelInfo L;
+    L.N = N;
+    L.h = 1.0 / N;
+    L.kappa = kappa_level(kappa, p->n0, p->levels, level);
+    const RefData R = make_refdata(p->k, p->mu, p->sigma);
+    std::vector<double> A, pinv;
+    patch_matrix(I, R, L, vx, vy, P, A);
+    if (!patch_pinv(I, P, A, pinv, nullptr)) return BMG_E_SINGULAR;
+    const size_t m = idx.size();
+    for (size_t i = 0; i < m; ++i)
+      for (size_t j = 0; j < m; ++j) inv[i * m + j] = pinv[(size_t)idx[i] * P.ns + idx[j]];
+  }
+  return BMG_OK;
+}
+
+bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int32_t level, double* out) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_kappa(p, kappa))) return st;
+  if (!out || level < 0 || level > p->levels) return BMG_E_ARG;
+  const int N = p->n0 << level;
+  if (N > 32) return BMG_E_ARG;
+  const RefData R = make_refdata(p->k, p->mu, p->sigma);
+  std::vector<double> A = dense_level(R, p->k, bc_mask(*p), N, kappa_level(kappa, p->n0, p->levels, level));
+  std::copy(A.begin(), A.end(), out);
+  return BMG_OK;
+}
+
+}  // extern "C"

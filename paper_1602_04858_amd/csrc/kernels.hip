@@ -1,0 +1,871 @@
+// HIP kernels of the multigrid V-cycle (gfx950).
+//
+//   k_op       level operator y = A_j x or residual r = b - A_j x, matrix-free:
+//              one thread per cell computes the rows the cell owns (its interior
+//              and pressure dofs, its left / bottom faces, and the right / top
+//              faces on the domain boundary) from cell and face blocks
+//              (Section 2.3, eqs. ipbrinkman and Brinkman-weak).
+//   k_colour   one colour step of the symmetric multiplicative vertex-patch
+//              smoother (Section 3.3): one 64-wide wavefront per patch gathers the
+//              patch cells and their face neighbours into LDS, forms the local
+//              residual (b - A_j x) on the patch dofs from the same cell / face
+//              blocks, multiplies by the stored patch pseudo-inverse (streamed
+//              column by column, coalesced) and adds the correction.  Patches of
+//              one colour have disjoint write sets and never read each other's
+//              writes, so a colour is one launch with no atomics.
+//   k_restrict b_{j-1} = P^T r_j and k_prolong x_j += P x_{j-1} (Section 3.1),
+//              one thread per coarse cell, tensor-product 1-D re-expansion.
+//   k_coarse   x_0 = A_0^{-1} b_0 with the precomputed FP64 inverse.
+//   Krylov     FP64 multi-dot (deterministic two-stage reduction), multi-axpy.
+#include "common.hpp"
+
+namespace bmg {
+namespace {
+
+enum { F_INT = 0, F_DIR = 1, F_OPEN = 2 };
+
+template <int K>
+struct Idx {
+  using D = Dims<K>;
+  __device__ __forceinline__ static int n_u(int N) { return 2 * N * (N + 1) * D::NB + D::NI * N * N; }
+  __device__ __forceinline__ static int xface(int N, int i, int cy, int b) { return (cy * (N + 1) + i) * D::NB + b; }
+  __device__ __forceinline__ static int yface(int N, int j, int cx, int b) {
+    return N * (N + 1) * D::NB + (j * N + cx) * D::NB + b;
+  }
+  __device__ __forceinline__ static int inter(int N, int c, int comp, int a, int b) {
+    return 2 * N * (N + 1) * D::NB + c * D::NI + (comp * K + (a - 2)) * D::NB + b;
+  }
+  __device__ __forceinline__ static int pres(int N, int c, int q) { return n_u(N) + c * D::NP + q; }
+  // global index of the local dof d of cell (cx, cy)
+  __device__ __forceinline__ static int g(int N, int cx, int cy, int d) {
+    const int c = cy * N + cx;
+    if (d < D::NV) {
+      const int a = d / D::NB, b = d % D::NB;
+      return a == 0 ? xface(N, cx, cy, b) : a == 1 ? xface(N, cx + 1, cy, b) : inter(N, c, 0, a, b);
+    }
+    if (d < 2 * D::NV) {
+      const int e = d - D::NV, a = e / D::NB, b = e % D::NB;
+      return a == 0 ? yface(N, cy, cx, b) : a == 1 ? yface(N, cy + 1, cx, b) : inter(N, c, 1, a, b);
+    }
+    return pres(N, c, d - 2 * D::NV);
+  }
+  // the local dof is an essential normal dof (normal face dof on a Dirichlet side)
+  __device__ __forceinline__ static bool cons(int N, int bcm, int cx, int cy, int d) {
+    if (d < D::NV) {
+      const int a = d / D::NB;
+      return (a == 0 && cx == 0 && (bcm & 1)) || (a == 1 && cx == N - 1 && (bcm & 2));
+    }
+    if (d < 2 * D::NV) {
+      const int a = (d - D::NV) / D::NB;
+      return (a == 0 && cy == 0 && (bcm & 4)) || (a == 1 && cy == N - 1 && (bcm & 8));
+    }
+    return false;
+  }
+};
+
+__device__ __forceinline__ int boundary_type(int bcm, int side) { return ((bcm >> side) & 1) ? F_DIR : F_OPEN; }
+
+// one velocity component (NV values, comp 0 = u_x, 1 = u_y) of a cell; essential dofs read as 0
+template <int K, typename T>
+__device__ __forceinline__ void load_comp(const T* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
+  using D = Dims<K>;
+#pragma unroll
+  for (int d = 0; d < D::NV; ++d) {
+    const int dd = comp * D::NV + d;
+    out[d] = Idx<K>::cons(N, bcm, cx, cy, dd) ? T(0) : x[Idx<K>::g(N, cx, cy, dd)];
+  }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void load_pres(const T* __restrict__ x, int N, int cx, int cy, T* out) {
+  using D = Dims<K>;
+  const int base = Idx<K>::pres(N, cy * N + cx, 0);
+#pragma unroll
+  for (int q = 0; q < D::NP; ++q) out[q] = x[base + q];
+}
+
+// Row d of one velocity component of a cell: cell block, divergence coupling and
+// the two faces across which this component is tangential ("lower" = normal
+// coordinate 0, where the cell is the higher-index side 1; "upper" = 1, side 0).
+template <typename T, int K>
+__device__ __forceinline__ T comp_row(const Elem<T, K>& E, int d, const T* xs, const T* p, const T* Dm, T khh, T mh,
+                                      int tl, const T* nl, int tu, const T* nu) {
+  using D = Dims<K>;
+  constexpr int NV = D::NV;
+  T s = T(0);
+#pragma unroll
+  for (int e = 0; e < NV; ++e) s += (E.Kmu[d * NV + e] + khh * E.M[d * NV + e]) * xs[e];
+#pragma unroll
+  for (int q = 0; q < D::NP; ++q) s += mh * Dm[q * NV + d] * p[q];
+  if (tl == F_INT) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) s += E.F[3][d * NV + e] * xs[e] + E.F[2][d * NV + e] * nl[e];
+  } else if (tl == F_DIR) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) s += E.Nb[0][d * NV + e] * xs[e];
+  }
+  if (tu == F_INT) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) s += E.F[0][d * NV + e] * xs[e] + E.F[1][d * NV + e] * nu[e];
+  } else if (tu == F_DIR) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) s += E.Nb[1][d * NV + e] * xs[e];
+  }
+  return s;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ T pres_row(const Elem<T, K>& E, int q, const T* ux, const T* uy, T mh) {
+  using D = Dims<K>;
+  T s = T(0);
+#pragma unroll
+  for (int e = 0; e < D::NV; ++e) s += E.Dx[q * D::NV + e] * ux[e] + E.Dy[q * D::NV + e] * uy[e];
+  return mh * s;
+}
+
+// ---------------------------------------------------------------------------
+// Level operator
+// ---------------------------------------------------------------------------
+template <typename T, int K, bool RES>
+__global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
+                                            const T* __restrict__ kap, const T* __restrict__ x,
+                                            const T* __restrict__ b, T* __restrict__ y) {
+  using D = Dims<K>;
+  using I = Idx<K>;
+  constexpr int NV = D::NV, NP = D::NP, NA = D::NA, NB = D::NB;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N * N) return;
+  const Elem<T, K>& E = *Ep;
+  const int cx = c % N, cy = c / N;
+  const T mh = -h, hh = h * h;
+  const int tL = cx > 0 ? F_INT : boundary_type(bcm, 0);
+  const int tR = cx < N - 1 ? F_INT : boundary_type(bcm, 1);
+  const int tD = cy > 0 ? F_INT : boundary_type(bcm, 2);
+  const int tU = cy < N - 1 ? F_INT : boundary_type(bcm, 3);
+  auto out = [&](int gi, T v) {
+    if (RES) y[gi] = b[gi] - v;
+    else y[gi] = v;
+  };
+  auto ident = [&](int gi) {
+    if (RES) y[gi] = b[gi] - x[gi];
+    else y[gi] = x[gi];
+  };
+
+  T ux[NV], uy[NV], p[NP], n0[NV], n1[NV];
+  load_comp<K>(x, N, bcm, cx, cy, 0, ux);
+  load_comp<K>(x, N, bcm, cx, cy, 1, uy);
+  load_pres<K>(x, N, cx, cy, p);
+  const T khh = kap[c] * hh;
+
+  // u_x rows (tangential across the bottom / top faces)
+  if (tD == F_INT) load_comp<K>(x, N, bcm, cx, cy - 1, 0, n0);
+  if (tU == F_INT) load_comp<K>(x, N, bcm, cx, cy + 1, 0, n1);
+  T zx[NV];
+#pragma unroll
+  for (int d = 0; d < NV; ++d) zx[d] = comp_row<T, K>(E, d, ux, p, E.Dx, khh, mh, tD, n0, tU, n1);
+  // u_y rows (tangential across the left / right faces)
+  if (tL == F_INT) load_comp<K>(x, N, bcm, cx - 1, cy, 1, n0);
+  if (tR == F_INT) load_comp<K>(x, N, bcm, cx + 1, cy, 1, n1);
+  T zy[NV];
+#pragma unroll
+  for (int d = 0; d < NV; ++d) zy[d] = comp_row<T, K>(E, d, uy, p, E.Dy, khh, mh, tL, n0, tR, n1);
+
+  // interior velocity and pressure rows belong to this cell only
+#pragma unroll
+  for (int a = 2; a < NA; ++a)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      out(I::inter(N, c, 0, a, bb), zx[a * NB + bb]);
+      out(I::inter(N, c, 1, a, bb), zy[a * NB + bb]);
+    }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) out(I::pres(N, c, q), pres_row<T, K>(E, q, ux, uy, mh));
+
+  // right / top faces on the domain boundary
+  if (cx == N - 1) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int gi = I::xface(N, N, cy, bb);
+      if (bcm & 2) ident(gi);
+      else out(gi, zx[1 * NB + bb]);
+    }
+  }
+  if (cy == N - 1) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int gi = I::yface(N, N, cx, bb);
+      if (bcm & 8) ident(gi);
+      else out(gi, zy[1 * NB + bb]);
+    }
+  }
+
+  // left face: this cell (a = 0) plus the left neighbour (a = 1)
+  T acc[NB];
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) acc[bb] = zx[bb];
+  if (cx > 0) {
+    T lx[NV], lp[NP];
+    load_comp<K>(x, N, bcm, cx - 1, cy, 0, lx);
+    load_pres<K>(x, N, cx - 1, cy, lp);
+    if (tD == F_INT) load_comp<K>(x, N, bcm, cx - 1, cy - 1, 0, n0);
+    if (tU == F_INT) load_comp<K>(x, N, bcm, cx - 1, cy + 1, 0, n1);
+    const T lk = kap[c - 1] * hh;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) acc[bb] += comp_row<T, K>(E, NB + bb, lx, lp, E.Dx, lk, mh, tD, n0, tU, n1);
+  }
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) {
+    const int gi = I::xface(N, cx, cy, bb);
+    if (cx == 0 && (bcm & 1)) ident(gi);
+    else out(gi, acc[bb]);
+  }
+  // bottom face: this cell (a = 0) plus the lower neighbour (a = 1)
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) acc[bb] = zy[bb];
+  if (cy > 0) {
+    T dy[NV], dp[NP];
+    load_comp<K>(x, N, bcm, cx, cy - 1, 1, dy);
+    load_pres<K>(x, N, cx, cy - 1, dp);
+    if (tL == F_INT) load_comp<K>(x, N, bcm, cx - 1, cy - 1, 1, n0);
+    if (tR == F_INT) load_comp<K>(x, N, bcm, cx + 1, cy - 1, 1, n1);
+    const T dk = kap[c - N] * hh;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) acc[bb] += comp_row<T, K>(E, NB + bb, dy, dp, E.Dy, dk, mh, tL, n0, tR, n1);
+  }
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) {
+    const int gi = I::yface(N, cy, cx, bb);
+    if (cy == 0 && (bcm & 4)) ident(gi);
+    else out(gi, acc[bb]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Smoother colour step
+// ---------------------------------------------------------------------------
+// Face groups of the extended patch layout (ascending global order):
+//   0: x-face (vx-1, vy-1)  slot 0 left          6: y-face (vy-1, vx-1) slot 0 bottom
+//   1: x-face (vx,   vy-1)  slot 0 | slot 1      7: y-face (vy-1, vx)   slot 1 bottom
+//   2: x-face (vx+1, vy-1)  slot 1 right         8: y-face (vy, vx-1)   slot 0 | slot 2
+//   3: x-face (vx-1, vy)    slot 2 left          9: y-face (vy, vx)     slot 1 | slot 3
+//   4: x-face (vx,   vy)    slot 2 | slot 3     10: y-face (vy+1, vx-1) slot 2 top
+//   5: x-face (vx+1, vy)    slot 3 right        11: y-face (vy+1, vx)   slot 3 top
+// The regular layout keeps groups 1, 4, 8, 9.  Slot s is the cell
+// (vx - 1 + (s & 1), vy - 1 + (s >> 1)).  Entry: (slotA, kindA, slotB, kindB) with
+// kind 0 = u_x at a = 0, 1 = u_x at a = 1, 2 = u_y at a = 0, 3 = u_y at a = 1.
+__constant__ int8_t kGroup[12][4] = {{0, 0, -1, 0}, {0, 1, 1, 0},  {1, 1, -1, 0}, {2, 0, -1, 0},
+                                     {2, 1, 3, 0},  {3, 1, -1, 0}, {0, 2, -1, 0}, {1, 2, -1, 0},
+                                     {0, 3, 2, 2},  {1, 3, 3, 2},  {2, 3, -1, 0}, {3, 3, -1, 0}};
+__constant__ int8_t kRegular[4] = {1, 4, 8, 9};
+
+template <int K>
+__device__ __forceinline__ int kind_to_local(int kind, int b) {
+  using D = Dims<K>;
+  return (kind >= 2 ? D::NV : 0) + (kind & 1) * D::NB + b;
+}
+
+template <typename T, typename S, int K, bool EXT>
+__device__ __forceinline__ void patch_gemv(const S* __restrict__ A, const T* rs, const int* gs, T* __restrict__ x,
+                                           int lane) {
+  using D = Dims<K>;
+  constexpr int NS = EXT ? D::NSE : D::NSR;
+#pragma unroll
+  for (int t0 = 0; t0 < NS; t0 += 64) {
+    const int t = t0 + lane;
+    if (t < NS) {
+      T acc = T(0);
+#pragma unroll 8
+      for (int u = 0; u < NS; ++u) acc += T(A[u * NS + t]) * rs[u];
+      const int gi = gs[t];
+      if (gi >= 0) x[gi] += acc;
+    }
+  }
+}
+
+template <typename T, typename S, int K>
+__global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
+                                                const T* __restrict__ kap, T* __restrict__ x,
+                                                const T* __restrict__ b, const S* __restrict__ inv,
+                                                const S* __restrict__ invx, const int32_t* __restrict__ extidx,
+                                                int colour, int npatch) {
+  using D = Dims<K>;
+  using I = Idx<K>;
+  constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NB = D::NB, NI = D::NI;
+  __shared__ T xs[4][4][NL];
+  __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
+                                 //               1: u_y of the cell across the outer vertical face]
+  __shared__ T zs[4][4 * NL];
+  __shared__ T rs[4][D::NSE];
+  __shared__ int gs[4][D::NSE];
+  const Elem<T, K>& E = *Ep;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + w;
+  const bool active = p < npatch;
+  const int c3x = colour % 3, c3y = colour / 3;
+  const int nvx = (N - c3x) / 3 + 1;
+  const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+  const T mh = -h, hh = h * h;
+  auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
+
+  // 1. gather the patch cells and the face neighbours across the patch boundary
+  for (int e = lane; e < 4 * NL; e += 64) {
+    const int s = e / NL, d = e % NL;
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    T v = T(0);
+    if (active && in_dom(cx, cy) && !I::cons(N, bcm, cx, cy, d)) v = x[I::g(N, cx, cy, d)];
+    xs[w][s][d] = v;
+  }
+  for (int e = lane; e < 8 * NV; e += 64) {
+    const int s = e / (2 * NV), r = e % (2 * NV), which = r / NV, d = r % NV;
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    int ncx = cx, ncy = cy;
+    if (which == 0) ncy = (s < 2) ? cy - 1 : cy + 1;
+    else ncx = (s & 1) ? cx + 1 : cx - 1;
+    const int dd = which * NV + d;
+    T v = T(0);
+    if (active && in_dom(cx, cy) && in_dom(ncx, ncy) && !I::cons(N, bcm, ncx, ncy, dd))
+      v = x[I::g(N, ncx, ncy, dd)];
+    nb[w][s][which][d] = v;
+  }
+  __syncthreads();
+
+  // 2. row contributions of every patch cell (cell blocks + its four faces)
+  for (int e = lane; e < 4 * NL; e += 64) {
+    const int s = e / NL, d = e % NL;
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    T z = T(0);
+    if (active && in_dom(cx, cy)) {
+      const T* xl = xs[w][s];
+      if (d < 2 * NV) {
+        const T khh = kap[cy * N + cx] * hh;
+        if (d < NV) {
+          int tl = F_INT, tu = F_INT;
+          const T* nl = nullptr;
+          const T* nu = nullptr;
+          if (cy == 0) tl = boundary_type(bcm, 2);
+          else nl = (s >= 2) ? xs[w][s - 2] : nb[w][s][0];
+          if (cy == N - 1) tu = boundary_type(bcm, 3);
+          else nu = (s < 2) ? xs[w][s + 2] : nb[w][s][0];
+          z = comp_row<T, K>(E, d, xl, xl + 2 * NV, E.Dx, khh, mh, tl, nl, tu, nu);
+        } else {
+          int tl = F_INT, tu = F_INT;
+          const T* nl = nullptr;
+          const T* nu = nullptr;
+          if (cx == 0) tl = boundary_type(bcm, 0);
+          else nl = (s & 1) ? xs[w][s - 1] + NV : nb[w][s][1];
+          if (cx == N - 1) tu = boundary_type(bcm, 1);
+          else nu = (s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV;
+          z = comp_row<T, K>(E, d - NV, xl + NV, xl + 2 * NV, E.Dy, khh, mh, tl, nl, tu, nu);
+        }
+      } else {
+        z = pres_row<T, K>(E, d - 2 * NV, xl, xl + NV, mh);
+      }
+    }
+    zs[w][e] = z;
+  }
+  __syncthreads();
+
+  // 3. local residual (b - A x) on the patch dofs, in the patch layout
+  const int ext = active ? extidx[p] : -1;
+  const int nf = ext >= 0 ? 12 : 4;
+  const int ns = nf * NB + 4 * NI + 4 * NP;
+  for (int t = lane; t < ns; t += 64) {
+    int gi = -1;
+    T z = T(0);
+    if (active) {
+      if (t < nf * NB) {
+        const int grp = ext >= 0 ? t / NB : kRegular[t / NB];
+        const int bb = t % NB;
+        const int sA = kGroup[grp][0], kA = kGroup[grp][1], sB = kGroup[grp][2], kB = kGroup[grp][3];
+        const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
+        const bool vA = in_dom(axA, ayA);
+        bool vB = false;
+        int axB = 0, ayB = 0;
+        if (sB >= 0) {
+          axB = vx - 1 + (sB & 1);
+          ayB = vy - 1 + (sB >> 1);
+          vB = in_dom(axB, ayB);
+        }
+        bool ok;
+        int cxu, cyu, du;
+        if (sB >= 0) {
+          ok = vA || vB;
+          cxu = vA ? axA : axB;
+          cyu = vA ? ayA : ayB;
+          du = kind_to_local<K>(vA ? kA : kB, bb);
+        } else {
+          // outer face: part of the patch space only on the domain boundary
+          int ox = axA, oy = ayA;
+          if (kA == 0) ox -= 1;
+          else if (kA == 1) ox += 1;
+          else if (kA == 2) oy -= 1;
+          else oy += 1;
+          ok = vA && !in_dom(ox, oy);
+          cxu = axA;
+          cyu = ayA;
+          du = kind_to_local<K>(kA, bb);
+        }
+        if (ok && !I::cons(N, bcm, cxu, cyu, du)) {
+          gi = I::g(N, cxu, cyu, du);
+          z = (vA ? zs[w][sA * NL + kind_to_local<K>(kA, bb)] : T(0)) +
+              (vB ? zs[w][sB * NL + kind_to_local<K>(kB, bb)] : T(0));
+        }
+      } else {
+        const int e = t - nf * NB;
+        int s, d;
+        if (e < 4 * NI) {
+          s = e / NI;
+          const int w2 = e % NI, comp = w2 / (K * NB), rem = w2 % (K * NB);
+          d = comp * NV + (2 + rem / NB) * NB + rem % NB;
+        } else {
+          s = (e - 4 * NI) / NP;
+          d = 2 * NV + (e - 4 * NI) % NP;
+        }
+        const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+        if (in_dom(cx, cy)) {
+          gi = I::g(N, cx, cy, d);
+          z = zs[w][s * NL + d];
+        }
+      }
+    }
+    rs[w][t] = gi >= 0 ? b[gi] - z : T(0);
+    gs[w][t] = gi;
+  }
+  __syncthreads();
+
+  // 4. correction y = A_S^+ r, x[S] += y
+  if (!active) return;
+  if (ext >= 0)
+    patch_gemv<T, S, K, true>(invx + (size_t)ext * D::NSE * D::NSE, rs[w], gs[w], x, lane);
+  else
+    patch_gemv<T, S, K, false>(inv + (size_t)p * D::NSR * D::NSR, rs[w], gs[w], x, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Transfers
+// ---------------------------------------------------------------------------
+// Sums over the fine dofs strictly inside coarse cell (cxc, cyc) of P[f][coarse dof]
+// * r_f, for one velocity component; only rows with psi index `arow` if arow >= 0.
+template <typename T, int K>
+__device__ __forceinline__ void inside_comp(const Xfer<T, K>& X, int Nf, int cxc, int cyc, int comp,
+                                            const T* __restrict__ rf, T* out, int arow) {
+  using D = Dims<K>;
+  constexpr int NA = D::NA, NB = D::NB, NV = D::NV;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = T(0);
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    const int sx = ch & 1, sy = ch >> 1;
+    const int sn = comp == 0 ? sx : sy;  // child position along the component direction
+    const int st = comp == 0 ? sy : sx;  // across
+    const int fx = 2 * cxc + sx, fy = 2 * cyc + sy;
+#pragma unroll
+    for (int ap = 0; ap < NA; ++ap) {
+      if ((sn == 0 && ap == 0) || (sn == 1 && ap == 1) || (sn == 1 && ap == 0)) continue;
+#pragma unroll
+      for (int bp = 0; bp < NB; ++bp) {
+        const T r = rf[Idx<K>::g(Nf, fx, fy, comp * NV + ap * NB + bp)];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          if (arow >= 0 && a != arow) continue;
+          const T pa = X.Ppsi[sn][ap * NA + a] * r;
+#pragma unroll
+          for (int bb = 0; bb < NB; ++bb) out[a * NB + bb] += pa * X.PL[st][bp * NB + bb];
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_restrict(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
+                                                  const T* __restrict__ rf, T* __restrict__ bc) {
+  using D = Dims<K>;
+  using I = Idx<K>;
+  constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc * Nc) return;
+  const Xfer<T, K>& X = *Xp;
+  const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
+  T in_x[NV], in_y[NV], tmp[NV];
+  inside_comp<T, K>(X, Nf, cx, cy, 0, rf, in_x, -1);
+  inside_comp<T, K>(X, Nf, cx, cy, 1, rf, in_y, -1);
+  // pressure: every child pressure dof, tensor re-expansion in both directions
+  T in_p[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) in_p[q] = T(0);
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    const int sx = ch & 1, sy = ch >> 1;
+    const int base = I::pres(Nf, (2 * cy + sy) * Nf + 2 * cx + sx, 0);
+#pragma unroll
+    for (int qb = 0; qb < NB; ++qb)
+#pragma unroll
+      for (int qa = 0; qa < NB; ++qa) {
+        const T r = rf[base + qb * NB + qa];
+#pragma unroll
+        for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+          for (int pa = 0; pa < NB; ++pa) in_p[pb * NB + pa] += X.PL[sx][qa * NB + pa] * X.PL[sy][qb * NB + pb] * r;
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) bc[I::pres(Nc, c, q)] = in_p[q];
+#pragma unroll
+  for (int a = 2; a < NA; ++a)
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      bc[I::inter(Nc, c, 0, a, bb)] = in_x[a * NB + bb];
+      bc[I::inter(Nc, c, 1, a, bb)] = in_y[a * NB + bb];
+    }
+  // fine face dofs lying on a coarse face only see that face's dofs (1-D Legendre)
+  auto face_x = [&](int i, int bb) {
+    T s = T(0);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int bp = 0; bp < NB; ++bp) s += X.PL[sd][bp * NB + bb] * rf[I::xface(Nf, 2 * i, 2 * cy + sd, bp)];
+    return s;
+  };
+  auto face_y = [&](int j, int bb) {
+    T s = T(0);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int bp = 0; bp < NB; ++bp) s += X.PL[sd][bp * NB + bb] * rf[I::yface(Nf, 2 * j, 2 * cx + sd, bp)];
+    return s;
+  };
+  // left face
+  if (cx > 0) inside_comp<T, K>(X, Nf, cx - 1, cy, 0, rf, tmp, 1);
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) {
+    T v = (cx == 0 && (bcm & 1)) ? T(0) : in_x[bb] + (cx > 0 ? tmp[NB + bb] : T(0)) + face_x(cx, bb);
+    bc[I::xface(Nc, cx, cy, bb)] = v;
+  }
+  if (cx == Nc - 1) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+      bc[I::xface(Nc, Nc, cy, bb)] = (bcm & 2) ? T(0) : in_x[NB + bb] + face_x(Nc, bb);
+  }
+  // bottom face
+  if (cy > 0) inside_comp<T, K>(X, Nf, cx, cy - 1, 1, rf, tmp, 1);
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) {
+    T v = (cy == 0 && (bcm & 4)) ? T(0) : in_y[bb] + (cy > 0 ? tmp[NB + bb] : T(0)) + face_y(cy, bb);
+    bc[I::yface(Nc, cy, cx, bb)] = v;
+  }
+  if (cy == Nc - 1) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+      bc[I::yface(Nc, Nc, cx, bb)] = (bcm & 8) ? T(0) : in_y[NB + bb] + face_y(Nc, bb);
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_prolong(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
+                                                 const T* __restrict__ xc, T* __restrict__ xf) {
+  using D = Dims<K>;
+  using I = Idx<K>;
+  constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc * Nc) return;
+  const Xfer<T, K>& X = *Xp;
+  const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
+  T zx[NV], zy[NV], zp[NP];
+  load_comp<K>(xc, Nc, bcm, cx, cy, 0, zx);
+  load_comp<K>(xc, Nc, bcm, cx, cy, 1, zy);
+  load_pres<K>(xc, Nc, cx, cy, zp);
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    const int sx = ch & 1, sy = ch >> 1;
+    const int fx = 2 * cx + sx, fy = 2 * cy + sy;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      const int sn = comp == 0 ? sx : sy, st = comp == 0 ? sy : sx;
+      const bool last = comp == 0 ? (cx == Nc - 1) : (cy == Nc - 1);
+      const T* z = comp == 0 ? zx : zy;
+#pragma unroll
+      for (int ap = 0; ap < NA; ++ap) {
+        if (sn == 1 && ap == 0) continue;            // middle face: written by child sn = 0
+        if (sn == 1 && ap == 1 && !last) continue;   // outer face: written by the next coarse cell
+#pragma unroll
+        for (int bp = 0; bp < NB; ++bp) {
+          const int d = comp * NV + ap * NB + bp;
+          if (I::cons(Nf, bcm, fx, fy, d)) continue;
+          T v = T(0);
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            T s = T(0);
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) s += X.PL[st][bp * NB + bb] * z[a * NB + bb];
+            v += X.Ppsi[sn][ap * NA + a] * s;
+          }
+          xf[I::g(Nf, fx, fy, d)] += v;
+        }
+      }
+    }
+    const int base = I::pres(Nf, fy * Nf + fx, 0);
+#pragma unroll
+    for (int qb = 0; qb < NB; ++qb)
+#pragma unroll
+      for (int qa = 0; qa < NB; ++qa) {
+        T v = T(0);
+#pragma unroll
+        for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+          for (int pa = 0; pa < NB; ++pa) v += X.PL[sx][qa * NB + pa] * X.PL[sy][qb * NB + pb] * zp[pb * NB + pa];
+        xf[base + qb * NB + qa] += v;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse solve, casts, constrained copy
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(int n, const double* __restrict__ inv, const T* __restrict__ b,
+                                                T* __restrict__ x) {
+  extern __shared__ double sb[];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += inv[(size_t)j * n + i] * sb[j];
+    x[i] = (T)s;
+  }
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (TO)src[i];
+}
+
+template <typename TO, int K>
+__global__ __launch_bounds__(256) void k_copy_cons(int N, int bcm, const double* __restrict__ src, TO* __restrict__ dst) {
+  using D = Dims<K>;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * N * D::NB) return;
+  const int side = t / (N * D::NB), r = t % (N * D::NB), f = r / D::NB, bb = r % D::NB;
+  if (!((bcm >> side) & 1)) return;
+  int gi;
+  if (side < 2) gi = Idx<K>::xface(N, side == 0 ? 0 : N, f, bb);
+  else gi = Idx<K>::yface(N, side == 2 ? 0 : N, f, bb);
+  dst[gi] = (TO)src[gi];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Krylov helpers
+// ---------------------------------------------------------------------------
+constexpr int kDotBlocks = 512;
+constexpr int kDotChunk = 8;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int nvec, int64_t ldv,
+                                              const double* __restrict__ w, int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[8];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int c0 = 0; c0 < nvec; c0 += kDotChunk) {
+    double acc[kDotChunk];
+#pragma unroll
+    for (int v = 0; v < kDotChunk; ++v) acc[v] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+      const double wi = w[i];
+#pragma unroll
+      for (int v = 0; v < kDotChunk; ++v)
+        if (c0 + v < nvec) acc[v] += V[(int64_t)(c0 + v) * ldv + i] * wi;
+    }
+#pragma unroll
+    for (int v = 0; v < kDotChunk; ++v) {
+      if (c0 + v >= nvec) break;
+      const double s = block_sum(acc[v], sh);
+      if (threadIdx.x == 0) partial[(int64_t)(c0 + v) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(int64_t)blockIdx.x * nblk + i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const double* __restrict__ V, int nvec,
+                                               int64_t ldv, const double* __restrict__ coef, double sign, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int v = 0; v < nvec; ++v) s += coef[v] * V[(int64_t)v * ldv + i];
+    w[i] += sign * s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ dst, const double* __restrict__ src,
+                                               const double* __restrict__ denom, int take_sqrt, int64_t n) {
+  const double f = 1.0 / (take_sqrt ? sqrt(denom[0]) : denom[0]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] * f;
+}
+
+__global__ __launch_bounds__(256) void k_sub(double* __restrict__ r, const double* __restrict__ b,
+                                             const double* __restrict__ ax, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - ax[i];
+}
+
+inline unsigned grid_for(int64_t n, int bs = 256, int64_t cap = 8192) {
+  int64_t g = (n + bs - 1) / bs;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T, int K>
+static void op_t(const void* elem, const LevelArgs& L, const void* x, const void* b, void* y, bool res, hipStream_t s) {
+  const int n = L.N * L.N;
+  dim3 g((n + 255) / 256), bl(256);
+  if (res)
+    hipLaunchKernelGGL((k_op<T, K, true>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y);
+  else
+    hipLaunchKernelGGL((k_op<T, K, false>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y);
+}
+
+void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
+               bool residual, hipStream_t s) {
+  if (K == 1) {
+    if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, s);
+    else op_t<float, 1>(elem, L, x, b, y, residual, s);
+  } else {
+    if (prec == 0) op_t<double, 2>(elem, L, x, b, y, residual, s);
+    else op_t<float, 2>(elem, L, x, b, y, residual, s);
+  }
+}
+
+template <typename T, typename S, int K>
+static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
+                     const int32_t* extidx, int colour, int npatch, hipStream_t s) {
+  if (npatch <= 0) return;
+  dim3 g((npatch + 3) / 4), bl(256);
+  hipLaunchKernelGGL((k_colour<T, S, K>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h, (const T*)L.kap,
+                     (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
+}
+
+void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
+                   const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, hipStream_t s) {
+  if (K == 1) {
+    if (prec == 0) colour_t<double, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    else if (sprec == 0) colour_t<float, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    else colour_t<float, float, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+  } else {
+    if (prec == 0) colour_t<double, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    else if (sprec == 0) colour_t<float, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    else colour_t<float, float, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+  }
+}
+
+template <typename T, int K>
+static void restrict_t(const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s) {
+  const int n = Nc * Nc;
+  hipLaunchKernelGGL((k_restrict<T, K>), dim3((n + 255) / 256), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc, bcm,
+                     (const T*)rf, (T*)bc);
+}
+void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s) {
+  if (K == 1) {
+    if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, s);
+    else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, s);
+  } else {
+    if (prec == 0) restrict_t<double, 2>(xfer, Nc, bcm, rf, bc, s);
+    else restrict_t<float, 2>(xfer, Nc, bcm, rf, bc, s);
+  }
+}
+
+template <typename T, int K>
+static void prolong_t(const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s) {
+  const int n = Nc * Nc;
+  hipLaunchKernelGGL((k_prolong<T, K>), dim3((n + 255) / 256), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc, bcm,
+                     (const T*)xc, (T*)xf);
+}
+void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s) {
+  if (K == 1) {
+    if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, s);
+    else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, s);
+  } else {
+    if (prec == 0) prolong_t<double, 2>(xfer, Nc, bcm, xc, xf, s);
+    else prolong_t<float, 2>(xfer, Nc, bcm, xc, xf, s);
+  }
+}
+
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, hipStream_t s) {
+  const size_t sh = (size_t)n * sizeof(double);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_coarse<double>), dim3(1), dim3(256), sh, s, n, inv, (const double*)b, (double*)x);
+  else
+    hipLaunchKernelGGL((k_coarse<float>), dim3(1), dim3(256), sh, s, n, inv, (const float*)b, (float*)x);
+}
+
+void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  if (to_prec == 0 && from_prec == 1)
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, (const float*)src, (double*)dst, n);
+  else if (to_prec == 1 && from_prec == 0)
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const double*)src, (float*)dst, n);
+  else if (to_prec == 0)
+    hipLaunchKernelGGL((k_cast<double, double>), dim3(g), dim3(256), 0, s, (const double*)src, (double*)dst, n);
+  else
+    hipLaunchKernelGGL((k_cast<float, float>), dim3(g), dim3(256), 0, s, (const float*)src, (float*)dst, n);
+}
+
+void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s) {
+  const int n = 4 * N * (K + 1);
+  dim3 g((n + 255) / 256), bl(256);
+  if (K == 1) {
+    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 1>), g, bl, 0, s, N, bcm, src, (double*)dst);
+    else hipLaunchKernelGGL((k_copy_cons<float, 1>), g, bl, 0, s, N, bcm, src, (float*)dst);
+  } else {
+    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 2>), g, bl, 0, s, N, bcm, src, (double*)dst);
+    else hipLaunchKernelGGL((k_copy_cons<float, 2>), g, bl, 0, s, N, bcm, src, (float*)dst);
+  }
+}
+
+int dots_partial_count() { return kDotBlocks; }
+
+void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_t n, double* partial, double* out,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, s, V, nvec, ldv, w, n, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3(nvec), dim3(256), 0, s, partial, kDotBlocks, out);
+}
+
+void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, double sign, int64_t n,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_axpys, dim3(grid_for(n)), dim3(256), 0, s, w, V, nvec, ldv, coef, sign, n);
+}
+
+void launch_scale(double* dst, const double* src, const double* denom, bool take_sqrt, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, dst, src, denom, (int)take_sqrt, n);
+}
+
+void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, ax, n);
+}
+
+}  // namespace bmg

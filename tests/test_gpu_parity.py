@@ -1,0 +1,225 @@
+"""GPU parity: every step of the HIP path against the CPU oracle on the same seeded
+inputs, through the C ABI.
+
+Tolerances: FP64 steps 1e-12 relative (different summation order only); FP32
+steps 2e-5 relative; full FP64 solves: relative L2 difference <= 1e-10 with the
+iteration count within +-1; mixed-precision solves: true relative residual
+<= 1e-10, difference <= 1e-8, at most 2 extra iterations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1602_04858_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+D, O = inputs.DIRICHLET, inputs.OPEN
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def bmg():
+    from paper_1602_04858_amd import bmg as b
+    return b
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# (n0, J, k, mu, sigma, bc) -- several tiles and ragged tails (N = 12, 24, 32, 48)
+CASES = [
+    (2, 4, 1, 1e-2, 6.0, (D, D, O, O)),
+    (3, 3, 1, 1e-3, 6.0, (D, D, O, O)),
+    (3, 2, 1, 0.0, 6.0, (D, D, O, O)),
+    (2, 3, 1, 1.0, 8.0, (D, D, D, D)),
+    (2, 3, 1, 1e-1, 6.0, (O, D, O, D)),
+    (3, 2, 2, 1e-2, 12.0, (D, D, O, O)),
+    (2, 2, 2, 0.0, 12.0, (D, O, D, O)),
+]
+IDS = [f"n0{c[0]}J{c[1]}k{c[2]}mu{c[3]}bc{''.join(map(str, c[5]))}" for c in CASES]
+
+
+def _setup(bmg, case, prec=0, seed=1, cycle=1, m_fine=2):
+    n0, J, k, mu, sigma, bc = case
+    n = n0 << J
+    kap = inputs.kappa_lognormal_channels(n, seed, channels=3, width=2 if n >= 16 else 1)
+    o = Oracle(n0, J, k, mu, sigma, list(bc), kap, cycle, m_fine)
+    s = bmg.Solver(bmg.make_params(n0, J, k, mu, sigma, bc, cycle=cycle, m_fine=m_fine, prec=prec, restart=60), kap)
+    return o, s, kap
+
+
+def _vec(o, j, seed, zero_cons=True):
+    v = inputs.random_vector(o.ndof(j), seed)
+    if zero_cons:
+        v[o.constrained(j)] = 0.0
+    return v
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_operator_apply(torch, bmg, case):
+    o, s, _ = _setup(bmg, case)
+    for j in range(o.J + 1):
+        x = _vec(o, j, 10 + j, zero_cons=False)
+        y_ref = o.apply(x, j)
+        y = _np(s.apply(_dev(torch, x), j))
+        assert _rel(y, y_ref) < 1e-13, j
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_colour_steps(torch, bmg, case, prec):
+    o, s, _ = _setup(bmg, case, prec=prec)
+    tol = 1e-12 if prec == 0 else 2e-5
+    for j in (1, o.J):
+        b = _vec(o, j, 20 + j)
+        x = _vec(o, j, 30 + j)
+        for colour in range(9):
+            x_ref = o.colour_step(colour, x, b, j)
+            xg = _np(s.colour_step(j, colour, _dev(torch, x), _dev(torch, b)))
+            assert _rel(xg - x, x_ref - x) < tol, (j, colour)
+        # a full symmetric smoothing step from zero
+        x0 = np.zeros(o.ndof(j))
+        x_ref = o.smooth(1, x0, b, j)
+        xg = _np(s.smooth(j, 1, _dev(torch, x0), _dev(torch, b)))
+        assert _rel(xg, x_ref) < (1e-12 if prec == 0 else 1e-4), j
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_transfers_and_coarse(torch, bmg, case):
+    o, s, _ = _setup(bmg, case)
+    for j in range(1, o.J + 1):
+        rf = _vec(o, j, 40 + j, zero_cons=False)
+        assert _rel(_np(s.restrict(j, _dev(torch, rf))), o.restrict(j, rf)) < 1e-13
+        xc = _vec(o, j - 1, 50 + j)
+        xf = _vec(o, j, 60 + j)
+        assert _rel(_np(s.prolong_add(j, _dev(torch, xc), _dev(torch, xf))), o.prolong_add(j, xc, xf)) < 1e-13
+    b0 = _vec(o, 0, 70)
+    assert _rel(_np(s.coarse_solve(_dev(torch, b0))), o.coarse_solve(b0)) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_vcycle(torch, bmg, case):
+    o, s, _ = _setup(bmg, case)
+    r = _vec(o, o.J, 80, zero_cons=False)
+    z_ref = o.vcycle(r)
+    z = _np(s.vcycle(_dev(torch, r)))
+    assert _rel(z, z_ref) < 1e-11
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=IDS[:5])
+def test_vcycle_fp32(torch, bmg, case):
+    o, s, _ = _setup(bmg, case, prec=1)
+    r = _vec(o, o.J, 81, zero_cons=False)
+    z_ref = o.vcycle(r)
+    z = _np(s.vcycle(_dev(torch, r)))
+    assert _rel(z, z_ref) < 5e-4
+
+
+def _rhs(o, bmg, s, w_source, case):
+    b_o = o.rhs(w_source)
+    b_g = bmg.assemble_rhs(s.params, w_source)
+    assert np.abs(b_o - b_g).max() <= 1e-13 * np.abs(b_o).max()
+    return b_o, b_g
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_solve_fp64(torch, bmg, case):
+    o, s, _ = _setup(bmg, case)
+    src = inputs.smooth_source(7)
+    b_o, b_g = _rhs(o, bmg, s, src, case)
+    if o.singular():
+        pidx = o.n_u() + np.arange(o.N() ** 2) * (case[2] + 1) ** 2
+        b_o[pidx] -= b_o[pidx].mean()
+        b_g = b_o.copy()
+    x_ref, its_ref, _, tr_ref = o.fgmres(b_o, rtol=1e-10, maxit=300, restart=60)
+    x, info = s.solve(_dev(torch, b_g), rtol=1e-10, maxit=300)
+    x = _np(x)
+    assert info.converged == 1 and info.rel_residual_true < 2e-10
+    assert abs(info.iterations - abs(its_ref)) <= 1, (info.iterations, its_ref)
+    # reference converged far below the tolerance for the comparison
+    x_tight, _, _, _ = o.fgmres(b_o, rtol=1e-13, maxit=400, restart=60)
+    if o.singular():
+        from fe import Space
+        sp = Space(o.N(), case[2])
+        x = sp.remove_pressure_mean(x)
+        x_tight = sp.remove_pressure_mean(x_tight)
+    assert _rel(x, x_tight) < 1e-8 * max(1.0, 1e2 * tr_ref / 1e-10)
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=IDS[:3])
+def test_solve_mixed_precision(torch, bmg, case):
+    o, s64, _ = _setup(bmg, case)
+    _, s32, _ = _setup(bmg, case, prec=1)
+    src = inputs.smooth_source(9)
+    b = bmg.assemble_rhs(s64.params, src)
+    x64, i64 = s64.solve(_dev(torch, b), rtol=1e-10, maxit=300)
+    x32, i32 = s32.solve(_dev(torch, b), rtol=1e-10, maxit=300)
+    assert i32.converged == 1 and i32.rel_residual_true < 2e-10
+    assert i32.iterations <= i64.iterations + 2, (i32.iterations, i64.iterations)
+    x_tight, _, _, _ = o.fgmres(o.rhs(src), rtol=1e-13, maxit=400, restart=60)
+    assert _rel(_np(x32), x_tight) < 1e-8
+
+
+def test_c1_manufactured_solution(torch, bmg):
+    """C1: 8x8, RT_1, mu = 1, kappa = 1, standard V-cycle m = 1, both penalty choices."""
+    w = inputs.workload("C1")
+    u, fsrc = inputs.manufactured_c1()
+    for sigma in (6.0, 8.0):
+        o = Oracle(w.n0, w.levels, w.k, w.mu, sigma, list(w.bc), w.kappa, 0, 1)
+        s = bmg.Solver(bmg.make_params(w.n0, w.levels, w.k, w.mu, sigma, w.bc, cycle=0, m_fine=1, restart=60),
+                       w.kappa)
+        f = lambda x, y: fsrc(x, y, w.mu, 1.0)
+        b = bmg.assemble_rhs(s.params, f)
+        x, info = s.solve(_dev(torch, b), rtol=1e-10, maxit=200)
+        x_ref, its, _, _ = o.fgmres(o.rhs(f), rtol=1e-10, maxit=200, restart=60)
+        assert info.converged and abs(info.iterations - its) <= 1
+        from fe import Space
+        sp = Space(8, 1)
+        xa = sp.remove_pressure_mean(_np(x))
+        xb = sp.remove_pressure_mean(x_ref)
+        assert _rel(xa, xb) < 1e-9
+
+
+def test_determinism(torch, bmg):
+    o, s, _ = _setup(bmg, CASES[0])
+    r = _dev(torch, _vec(o, o.J, 5, zero_cons=False))
+    z1 = _np(s.vcycle(r))
+    z2 = _np(s.vcycle(r))
+    assert np.array_equal(z1, z2)
+
+
+def test_caller_workspace(torch, bmg):
+    case = CASES[1]
+    n0, J, k, mu, sigma, bc = case
+    kap = inputs.kappa_lognormal_channels(n0 << J, 1, channels=3, width=2)
+    p = bmg.make_params(n0, J, k, mu, sigma, bc, restart=60)
+    s1 = bmg.Solver(p, kap)
+    s2 = bmg.Solver(p, kap, workspace="torch")
+    r = _dev(torch, inputs.random_vector(s1.ndof(), 3))
+    assert np.array_equal(_np(s1.vcycle(r)), _np(s2.vcycle(r)))
+
+
+def test_not_converged_status(torch, bmg):
+    o, s, _ = _setup(bmg, CASES[0])
+    b = bmg.assemble_rhs(s.params, inputs.constant_source(1.0, 0.0))
+    x, info = s.solve(_dev(torch, b), rtol=1e-14, maxit=2)
+    assert info.converged == 0 and info.iterations == 2
