@@ -1,0 +1,147 @@
+#!/usr/bin/env python
+"""Benchmark: V-cycle-preconditioned FGMRES solves of the H(div)-DG Brinkman problem.
+
+One step = one complete solve (FGMRES in FP64 to a 1e-10 relative residual, the
+V-cycle of Section 3.2 as preconditioner: level operators, colour-ordered vertex-
+patch smoother, transfers, coarse solve) of the 256 x 256, 8-level RT_1 Brinkman
+problem (mu = 1e-2, seeded log-normal kappa with channels, contrast 1e6, f = (1,0),
+no-slip left/right, open top/bottom), right-hand side already in HBM.
+
+Prints one JSON line: solves/s of the plain FP64 path, DoF*iterations/s, the
+mixed-precision (FP32 V-cycle) path beside it, the roofline of the finest-level
+smoother kernel (HIP events around its launches) and the CPU oracle timed on a
+bounded sample of the same solve.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "precond. solves/sec & DoF·iters/s to 1e-10 rel resid; mixed vs FP64, HBM %"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_solves(torch, s, b, steps, warmup, rtol):
+    x = s.zeros()
+    info = None
+    for _ in range(warmup):
+        x, info = s.solve(b, rtol=rtol, maxit=1000, x=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        x, info = s.solve(b, rtol=rtol, maxit=1000, x=x)
+        its.append(info.iterations)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return x, info, dt, its
+
+
+def cpu_baseline(w, iterations_full, sample_its):
+    """The oracle (plain FP64 CPU) on the same workload: setup untimed, then the
+    first `sample_its` FGMRES iterations timed and scaled to a full solve."""
+    from oracle import Oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    o = Oracle.from_workload(w)
+    b = o.rhs(w.source)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its, _, _ = o.fgmres(b, rtol=1e-10, maxit=sample_its, restart=100)
+    dt = time.perf_counter() - t0
+    per_it = dt / abs(its)
+    solve_s = per_it * iterations_full
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {abs(its)} FGMRES iterations of the same solve ({dt:.1f} s, setup {t_setup:.1f} s "
+                      f"untimed), scaled to the {iterations_full} iterations of the full solve",
+            "seconds_per_iteration": per_it}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-sample-its", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1602_04858_amd import bmg, inputs
+
+    w = inputs.workload("C2")
+    log(f"bench: workload C2 N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
+    p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100)
+    t0 = time.perf_counter()
+    s64 = bmg.Solver(p64, w.kappa)
+    setup64 = time.perf_counter() - t0
+    b = torch.as_tensor(bmg.assemble_rhs(p64, w.source), dtype=torch.float64, device="cuda")
+    ndof = s64.ndof()
+    log(f"bench: FP64 setup {setup64:.2f} s, ndof {ndof}")
+
+    x64, info64, dt64, its64 = timed_solves(torch, s64, b, args.steps, args.warmup, args.rtol)
+    value = args.steps / dt64
+    log(f"bench: FP64 {value:.3f} solves/s, iterations {its64}, true residual {info64.rel_residual_true:.2e}")
+
+    # roofline of the finest-level smoother kernel: events around its launches
+    J = w.levels
+    s64.kernel_timing(J, 34 * (max(its64) + 4))
+    s64.solve(b, rtol=args.rtol, maxit=1000)
+    nl, ms, by = s64.kernel_timing_read()
+    s64.kernel_timing(-1, 0)
+    avg_s = ms * 1e-3 / nl
+    achieved = by / nl / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_colour<double,double,1,1> (finest-level colour step)",
+            "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
+    log(f"bench: finest smoother {achieved:.0f} GB/s over {nl} launches, avg {avg_s * 1e6:.1f} us")
+
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "C2: 256x256 quads, 8 levels (2x2 coarsest), RT_1 x dQ_1 H(div)-DG Brinkman "
+                                  "mu=1e-2, seeded log-normal kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, "
+                                  "f=(1,0), no-slip left/right, open top/bottom; variable V-cycle m=2, "
+                                  "FP64 V-cycle inside FP64 FGMRES(100), rtol 1e-10",
+                      "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol},
+           "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
+           "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
+
+    if not args.no_mixed:
+        p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 100)
+        s32 = bmg.Solver(p32, w.kappa)
+        x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
+        err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+        out["mixed"] = {"value": args.steps / dt32, "unit": "solves/s", "precond": "fp32",
+                        "iterations": its32[-1], "true_rel_residual": info32.rel_residual_true,
+                        "rel_diff_vs_fp64": err, "speedup_vs_fp64": (args.steps / dt32) / value,
+                        "dof_iters_per_s": ndof * sum(its32) / dt32}
+        log(f"bench: FP32 precond {args.steps / dt32:.3f} solves/s, iterations {its32}, diff {err:.1e}")
+        del s32
+
+    out["roofline"] = roof
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(w, its64[-1], args.cpu_sample_its)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,15 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc_dev, do
 /* x_0 = A_0^{-1} b_0 (pseudo-inverse with zero mean pressure if A_0 is singular). */
 bmg_status bmg_coarse_solve(bmg_handle h, const double* b_dev, double* x_dev);
 
+/* ----- measurement ----- */
+/* Record HIP events around each colour launch of the smoother on `level` (>= 1),
+ * for at most max_launches launches from now on (-1 switches timing off).  The
+ * events are recorded on the handle's stream between kernels. */
+bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches);
+/* Launches timed so far, their summed duration and the bytes they had to move
+ * (stored patch pseudo-inverses + gathered and scattered vector entries). */
+bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes);
+
 const char* bmg_status_string(bmg_status s);
 const char* bmg_last_error(bmg_handle h);
 

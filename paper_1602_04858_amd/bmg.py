@@ -60,6 +60,8 @@ _sig = {
     "bmg_coarse_solve": [_VP, _VP, _VP],
     "bmg_export_patch": [_P(Params), _dp, _I32, _I32, _I32, _P(_I32), _ip, _VP, _P(_I32)],
     "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
+    "bmg_kernel_timing": [_VP, _I32, _I32],
+    "bmg_kernel_timing_read": [_VP, _P(_I32), _P(_D), _P(_D)],
 }
 EXPORTS = list(_sig) + ["bmg_status_string", "bmg_last_error"]
 for _name, _args in _sig.items():
@@ -196,6 +198,14 @@ class Solver:
         xf = xf.clone()
         self._check(_lib.bmg_prolong_add(self.h, level, _ptr(xc), _ptr(xf)), "prolong_add")
         return xf
+
+    def kernel_timing(self, level, max_launches=4096):
+        self._check(_lib.bmg_kernel_timing(self.h, level, max_launches), "kernel_timing")
+
+    def kernel_timing_read(self):
+        n, ms, by = C.c_int32(), C.c_double(), C.c_double()
+        self._check(_lib.bmg_kernel_timing_read(self.h, C.byref(n), C.byref(ms), C.byref(by)), "kernel_timing_read")
+        return n.value, ms.value, by.value
 
     def coarse_solve(self, b):
         x = self.zeros(0)

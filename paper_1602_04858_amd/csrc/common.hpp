@@ -73,7 +73,7 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
                bool residual, hipStream_t s);
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
-                   hipStream_t s);
+                   bool finest, hipStream_t s);
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s);
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s);
 void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, hipStream_t s);

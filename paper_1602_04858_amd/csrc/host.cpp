@@ -56,6 +56,11 @@ struct bmg_ctx {
   // FP64 Krylov storage
   double *V = nullptr, *Z = nullptr, *w = nullptr, *rr = nullptr, *ax = nullptr, *t0 = nullptr, *t1 = nullptr;
   double *hdev = nullptr, *partial = nullptr;
+  // optional event timing of the colour launches of one level
+  int timing_level = -1;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double timed_bytes = 0.0;
   std::string err;
 };
 
@@ -721,14 +726,35 @@ LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
   return a;
 }
 
+// Bytes one colour launch must move: every patch's stored pseudo-inverse, the
+// gathered x of its cells and of the tangential components across its outer faces,
+// kappa of its cells, b on the patch and the read-modify-write of x on the patch.
+double colour_bytes(const bmg_ctx* c, int j, int col) {
+  const LevelInfo& L = c->lev[j];
+  const int K = c->K, NB = K + 1, NI = 2 * K * NB, NP = NB * NB, NV = (K + 2) * NB;
+  const int nsr = nsr_of(K), nse = nse_of(K);
+  const double gather = 12.0 * NB + 4.0 * NI + 4.0 * NP + 8.0 * NV + 4.0;
+  const double reg = L.npatch[col] - L.next[col], ext = L.next[col];
+  return reg * ((double)nsr * nsr * c->ssize + (gather + 2.0 * nsr) * c->tsize) +
+         ext * ((double)nse * nse * c->ssize + (gather + 2.0 * nse) * c->tsize);
+}
+
 void smooth_level(bmg_ctx* c, int j, int steps) {
   LevelInfo& L = c->lev[j];
   LevelArgs a = largs(c, j, c->prec == 0);
+  const bool timed = (c->timing_level == j);
   for (int st = 0; st < steps; ++st)
     for (int i = 0; i < 17; ++i) {
       const int col = i < 9 ? i : 16 - i;
+      const bool rec = timed && c->ev_used + 2 <= c->ev.size();
+      if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
       launch_colour(c->K, c->prec, c->sprec, c->elemT, a, L.x, L.b, L.inv[col], L.invx[col], L.extidx[col], col,
-                    L.npatch[col], c->stream);
+                    L.npatch[col], j == (int)c->lev.size() - 1, c->stream);
+      if (rec) {
+        hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+        c->ev_used += 2;
+        c->timed_bytes += colour_bytes(c, j, col);
+      }
     }
 }
 
@@ -887,8 +913,39 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   return BMG_OK;
 }
 
+bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) {
+  if (!h || level < -1 || level >= (int)h->lev.size() || level == 0 || max_launches < 0 || max_launches > 1 << 20)
+    return BMG_E_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (auto e : h->ev) hipEventDestroy(e);
+  h->ev.clear();
+  h->ev_used = 0;
+  h->timed_bytes = 0.0;
+  h->timing_level = level;
+  if (level < 0) return BMG_OK;
+  h->ev.resize((size_t)2 * max_launches);
+  for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
+  return BMG_OK;
+}
+
+bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes) {
+  if (!h || !launches || !total_ms || !bytes) return BMG_E_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    float t = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&t, h->ev[i], h->ev[i + 1]));
+    ms += t;
+  }
+  *launches = (int32_t)(h->ev_used / 2);
+  *total_ms = ms;
+  *bytes = h->timed_bytes;
+  return BMG_OK;
+}
+
 bmg_status bmg_destroy(bmg_handle h) {
   if (!h) return BMG_E_ARG;
+  for (auto e : h->ev) hipEventDestroy(e);
   if (h->own_ws) {
     hipStreamSynchronize(h->stream);
     hipFree(h->ws);
@@ -926,7 +983,7 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
   launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
-                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], h->stream);
+                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1, h->stream);
   launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

@@ -282,7 +282,9 @@ __device__ __forceinline__ void patch_gemv(const S* __restrict__ A, const T* rs,
   }
 }
 
-template <typename T, typename S, int K>
+// TAG only separates the launches of the finest level (TAG = 1) from the others
+// in profiler output; the code is identical.
+template <typename T, typename S, int K, int TAG>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
@@ -763,23 +765,28 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
-                     const int32_t* extidx, int colour, int npatch, hipStream_t s) {
+                     const int32_t* extidx, int colour, int npatch, bool finest, hipStream_t s) {
   if (npatch <= 0) return;
   dim3 g((npatch + 3) / 4), bl(256);
-  hipLaunchKernelGGL((k_colour<T, S, K>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h, (const T*)L.kap,
-                     (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
+  if (finest)
+    hipLaunchKernelGGL((k_colour<T, S, K, 1>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
+  else
+    hipLaunchKernelGGL((k_colour<T, S, K, 0>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
 }
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
-                   const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, hipStream_t s) {
+                   const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
+                   hipStream_t s) {
   if (K == 1) {
-    if (prec == 0) colour_t<double, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
-    else if (sprec == 0) colour_t<float, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
-    else colour_t<float, float, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    if (prec == 0) colour_t<double, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    else if (sprec == 0) colour_t<float, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    else colour_t<float, float, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
   } else {
-    if (prec == 0) colour_t<double, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
-    else if (sprec == 0) colour_t<float, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
-    else colour_t<float, float, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, s);
+    if (prec == 0) colour_t<double, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    else if (sprec == 0) colour_t<float, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    else colour_t<float, float, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
   }
 }
 
