@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
+    ap.add_argument("--dense-coarse-max", type=int, default=16384,
+                    help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -87,7 +89,8 @@ def main():
 
     w = inputs.workload("C2")
     log(f"bench: workload C2 N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
-    p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100)
+    p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
+                          args.dense_coarse_max)
     t0 = time.perf_counter()
     s64 = bmg.Solver(p64, w.kappa)
     setup64 = time.perf_counter() - t0
@@ -125,7 +128,8 @@ def main():
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
     if not args.no_mixed:
-        p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 100)
+        p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 100,
+                              args.dense_coarse_max)
         s32 = bmg.Solver(p32, w.kappa)
         x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
         err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()

@@ -74,6 +74,9 @@ typedef struct {
   int32_t m_fine;        /* smoothing steps on the finest level, >= 1 (Section 4.1: 2) */
   int32_t precond_prec;  /* BMG_P_*: arithmetic of the V-cycle; the outer Krylov loop is always FP64 */
   int32_t restart;       /* FGMRES restart length, 1..512 */
+  int32_t dense_coarse_max; /* 0..65535: the finest level jc >= 1 with at most this many dofs has its whole
+                               sub-cycle B_jc (the same linear operator, Section 3.2) precomputed at setup
+                               and applied as one dense matrix-vector product; 0 = none */
 } bmg_params;
 
 typedef struct {

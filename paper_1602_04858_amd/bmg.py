@@ -31,7 +31,7 @@ STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM",
 class Params(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
-                ("precond_prec", C.c_int32), ("restart", C.c_int32)]
+                ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -84,12 +84,17 @@ def lib():
     return _lib
 
 
-def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100):
+DENSE_COARSE_DEFAULT = 16384
+
+
+def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
+                dense_coarse_max=0):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
         p.bc[i] = int(bc[i])
     p.cycle, p.m_fine, p.precond_prec, p.restart = cycle, m_fine, prec, restart
+    p.dense_coarse_max = dense_coarse_max
     return p
 
 
@@ -274,6 +279,6 @@ def export_level_matrix(params: Params, kappa, level):
     return out.reshape(n, n)
 
 
-def from_workload(w, prec=P_FP64, restart=100, device="cuda", **kw):
-    p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart)
+def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=DENSE_COARSE_DEFAULT, **kw):
+    p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart, dense_coarse_max)
     return Solver(p, w.kappa, device=device, **kw)

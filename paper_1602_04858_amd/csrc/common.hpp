@@ -69,14 +69,22 @@ struct LevelArgs {
   const void* kap;  // kappa of the level, arithmetic `prec`
 };
 
+// Level kernels work on nrhs vectors stored ld elements apart (grid.y = vector).
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
-               bool residual, hipStream_t s);
+               bool residual, int nrhs, int64_t ld, hipStream_t s);
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
-                   bool finest, hipStream_t s);
-void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s);
-void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s);
-void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, hipStream_t s);
+                   bool finest, int nrhs, int64_t ld, hipStream_t s);
+void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
+                     int64_t ldf, int64_t ldc, hipStream_t s);
+void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
+                    int64_t ldc, int64_t ldf, hipStream_t s);
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s);
+void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s);
+void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipStream_t s);
+// y = B x for a dense column-major n x n matrix (part: dense_part_elems(n) scratch)
+int64_t dense_part_elems(int64_t n);
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* part, void* y, hipStream_t s);
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s);
 void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s);
 

@@ -53,9 +53,21 @@ struct bmg_ctx {
   void* elem64 = nullptr;
   void* xferT = nullptr;
   double* coarse_inv = nullptr;
+  // dense operator of the coarse sub-cycle: B_jc for level jc (0 = none)
+  int jc = 0;
+  void* dense = nullptr;
+  void* dpart = nullptr;
+  // setup batch (unit vectors through the V-cycle of level jc), overlapping the Krylov storage
+  int batch_chunk = 0;
+  char* region = nullptr;
   // FP64 Krylov storage
   double *V = nullptr, *Z = nullptr, *w = nullptr, *rr = nullptr, *ax = nullptr, *t0 = nullptr, *t1 = nullptr;
   double *hdev = nullptr, *partial = nullptr;
+  // V-cycle captured as a graph (captured on a private stream, launched on `stream`)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t vgraph = nullptr;
+  hipGraphExec_t vexec = nullptr;
+  bool graph_failed = false;
   // optional event timing of the colour launches of one level
   int timing_level = -1;
   std::vector<hipEvent_t> ev;
@@ -98,6 +110,7 @@ bmg_status check_params(const bmg_params* p) {
   if (p->m_fine < 1 || p->m_fine > 64) return BMG_E_ARG;
   if (p->precond_prec != BMG_P_FP64 && p->precond_prec != BMG_P_FP32) return BMG_E_ARG;
   if (p->restart < 1 || p->restart > 512) return BMG_E_ARG;
+  if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -427,6 +440,15 @@ size_t xfer_bytes(int K) {
 int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
 int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
 
+// Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
+// dof count is at most dense_coarse_max (0 = none).
+int choose_jc(const bmg_ctx* c) {
+  int jc = 0;
+  for (int j = 1; j < (int)c->lev.size(); ++j)
+    if (c->lev[j].ndof <= (int64_t)c->p.dense_coarse_max) jc = j;
+  return jc;
+}
+
 // assigns every device pointer of the context; with a null base only sizes
 size_t layout(bmg_ctx* c, char* base) {
   Bump B(base);
@@ -450,18 +472,39 @@ size_t layout(bmg_ctx* c, char* base) {
   }
   const int64_t n0 = c->lev[0].ndof;
   c->coarse_inv = (double*)B.take((size_t)n0 * n0 * sizeof(double));
+  c->jc = choose_jc(c);
+  if (c->jc > 0) {
+    const int64_t nd = c->lev[c->jc].ndof;
+    c->dense = B.take((size_t)nd * nd * ts);
+    c->dpart = B.take((size_t)dense_part_elems(nd) * ts);
+  }
   c->elemT = B.take(c->prec == 0 ? elem_bytes<double>(K) : elem_bytes<float>(K));
   c->elem64 = B.take(elem_bytes<double>(K));
   c->xferT = B.take(c->prec == 0 ? xfer_bytes<double>(K) : xfer_bytes<float>(K));
   const int64_t n = c->lev.back().ndof;
   const int m = c->p.restart;
-  c->V = (double*)B.take((size_t)(m + 1) * n * sizeof(double));
-  c->Z = (double*)B.take((size_t)m * n * sizeof(double));
-  c->w = (double*)B.take(n * sizeof(double));
-  c->rr = (double*)B.take(n * sizeof(double));
-  c->ax = (double*)B.take(n * sizeof(double));
-  c->t0 = (double*)B.take(n * sizeof(double));
-  c->t1 = (double*)B.take(n * sizeof(double));
+  // one region shared by the Krylov vectors (solve) and the setup batch
+  const size_t kry = ((size_t)(2 * m + 4) * n + 64) * sizeof(double);
+  size_t per_col = 0;
+  for (int j = 0; j <= c->jc; ++j) per_col += 3 * (size_t)c->lev[j].ndof * ts;
+  int64_t chunk = 0;
+  if (c->jc > 0) {
+    const int64_t nd = c->lev[c->jc].ndof;
+    chunk = std::min<int64_t>(std::min<int64_t>(nd, 65535), (int64_t)(kry / per_col));
+    chunk = std::max<int64_t>(chunk, std::min<int64_t>(nd, 256));
+  }
+  c->batch_chunk = (int)chunk;
+  const size_t rbytes = std::max(kry, per_col * (size_t)chunk);
+  c->region = (char*)B.take(rbytes);
+  {
+    Bump R(c->region);
+    c->V = (double*)R.take((size_t)(m + 1) * n * sizeof(double));
+    c->Z = (double*)R.take((size_t)m * n * sizeof(double));
+    c->w = (double*)R.take(n * sizeof(double));
+    c->rr = (double*)R.take(n * sizeof(double));
+    c->ax = (double*)R.take(n * sizeof(double));
+    c->t0 = c->t1 = nullptr;
+  }
   c->hdev = (double*)B.take((size_t)(2 * (m + 2) + 8) * sizeof(double));
   c->partial = (double*)B.take((size_t)dots_partial_count() * (m + 2) * sizeof(double));
   return B.off + kAlign;
@@ -739,7 +782,7 @@ double colour_bytes(const bmg_ctx* c, int j, int col) {
          ext * ((double)nse * nse * c->ssize + (gather + 2.0 * nse) * c->tsize);
 }
 
-void smooth_level(bmg_ctx* c, int j, int steps) {
+void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs) {
   LevelInfo& L = c->lev[j];
   LevelArgs a = largs(c, j, c->prec == 0);
   const bool timed = (c->timing_level == j);
@@ -748,12 +791,12 @@ void smooth_level(bmg_ctx* c, int j, int steps) {
       const int col = i < 9 ? i : 16 - i;
       const bool rec = timed && c->ev_used + 2 <= c->ev.size();
       if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
-      launch_colour(c->K, c->prec, c->sprec, c->elemT, a, L.x, L.b, L.inv[col], L.invx[col], L.extidx[col], col,
-                    L.npatch[col], j == (int)c->lev.size() - 1, c->stream);
+      launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
+                    L.npatch[col], j == (int)c->lev.size() - 1, nrhs, L.ndof, c->stream);
       if (rec) {
         hipEventRecord(c->ev[c->ev_used + 1], c->stream);
         c->ev_used += 2;
-        c->timed_bytes += colour_bytes(c, j, col);
+        c->timed_bytes += colour_bytes(c, j, col) * nrhs;
       }
     }
 }
@@ -763,36 +806,111 @@ int smoothing_steps(const bmg_ctx* c, int j) {
   return c->p.m_fine;
 }
 
-// B_j applied to lev[j].b, result in lev[j].x (Section 3.2).
-void vcycle_level(bmg_ctx* c, int j) {
+// Vectors of every level the cycle works on (nrhs vectors each, ld = level ndof).
+struct Vecs {
+  std::vector<void*> x, b, r;
+  int nrhs = 1;
+};
+
+Vecs level_vecs(bmg_ctx* c) {
+  Vecs v;
+  for (auto& L : c->lev) {
+    v.x.push_back(L.x);
+    v.b.push_back(L.b);
+    v.r.push_back(L.r);
+  }
+  return v;
+}
+
+// B_j applied to v.b[j], result in v.x[j] (Section 3.2).  With use_dense the
+// sub-cycle of level jc is one product with its precomputed matrix.
+void vcycle_level(bmg_ctx* c, int j, const Vecs& v, bool use_dense) {
   LevelInfo& L = c->lev[j];
+  const int nr = v.nrhs;
+  if (use_dense && c->jc > 0 && j == c->jc && nr == 1) {
+    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], c->dpart, v.x[j], c->stream);
+    return;
+  }
   if (j == 0) {
-    launch_coarse(c->prec, (int)L.ndof, c->coarse_inv, L.b, L.x, c->stream);
+    launch_coarse(c->prec, (int)L.ndof, c->coarse_inv, v.b[0], v.x[0], nr, c->stream);
     return;
   }
   const int m = smoothing_steps(c, j);
-  hipMemsetAsync(L.x, 0, L.ndof * c->tsize, c->stream);
-  smooth_level(c, j, m);
+  launch_fill_zero(c->prec, v.x[j], L.ndof * nr, c->stream);
+  smooth_level(c, j, m, v.x[j], v.b[j], nr);
   LevelArgs a = largs(c, j, c->prec == 0);
-  launch_op(c->K, c->prec, c->elemT, a, L.x, L.b, L.r, true, c->stream);
+  launch_op(c->K, c->prec, c->elemT, a, v.x[j], v.b[j], v.r[j], true, nr, L.ndof, c->stream);
   LevelInfo& C = c->lev[j - 1];
-  launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, L.r, C.b, c->stream);
-  vcycle_level(c, j - 1);
-  launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, C.x, L.x, c->stream);
-  smooth_level(c, j, m);
+  launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, v.r[j], v.b[j - 1], nr, L.ndof, C.ndof, c->stream);
+  vcycle_level(c, j - 1, v, use_dense);
+  launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, v.x[j - 1], v.x[j], nr, C.ndof, L.ndof, c->stream);
+  smooth_level(c, j, m, v.x[j], v.b[j], nr);
+}
+
+// Dense B_jc: the V-cycle of level jc applied to the unit vectors, a chunk of
+// columns at a time (column-major storage).
+bmg_status build_dense(bmg_ctx* c) {
+  if (c->jc == 0) return BMG_OK;
+  const int64_t nd = c->lev[c->jc].ndof;
+  Vecs v;
+  Bump R(c->region);
+  for (int j = 0; j <= c->jc; ++j) {
+    const size_t bytes = (size_t)c->lev[j].ndof * c->batch_chunk * c->tsize;
+    v.x.push_back(R.take(bytes));
+    v.b.push_back(R.take(bytes));
+    v.r.push_back(R.take(bytes));
+  }
+  for (int64_t col0 = 0; col0 < nd; col0 += c->batch_chunk) {
+    v.nrhs = (int)std::min<int64_t>(c->batch_chunk, nd - col0);
+    launch_identity(c->prec, v.b[c->jc], nd, col0, v.nrhs, c->stream);
+    vcycle_level(c, c->jc, v, false);
+    HIPCHK(c, hipMemcpyAsync((char*)c->dense + (size_t)col0 * nd * c->tsize, v.x[c->jc],
+                             (size_t)v.nrhs * nd * c->tsize, hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return BMG_OK;
+}
+
+// Capture the finest-level V-cycle (fixed buffers) once; later cycles replay it.
+bool capture_vcycle(bmg_ctx* c) {
+  if (c->vexec) return true;
+  if (c->graph_failed) return false;
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->graph_failed = true;
+    return false;
+  }
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
+    ok = hipStreamEndCapture(c->cap_stream, &c->vgraph) == hipSuccess;
+  }
+  c->stream = user;
+  if (ok) ok = hipGraphInstantiate(&c->vexec, c->vgraph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (c->vgraph) hipGraphDestroy(c->vgraph);
+    c->vgraph = nullptr;
+    c->vexec = nullptr;
+    c->graph_failed = true;
+  }
+  return ok;
 }
 
 // z = B_J r with FP64 r, z (device); the essential rows are inverted exactly.
 void apply_precond(bmg_ctx* c, const double* r, double* z) {
   LevelInfo& L = c->lev.back();
   launch_cast(c->prec, 0, r, L.b, L.ndof, c->stream);
-  vcycle_level(c, (int)c->lev.size() - 1);
+  if (c->timing_level < 0 && capture_vcycle(c)) hipGraphLaunch(c->vexec, c->stream);
+  else vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
   launch_cast(0, c->prec, L.x, z, L.ndof, c->stream);
   launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->stream);
 }
 
 void apply_op64(bmg_ctx* c, int j, const double* x, double* y) {
-  launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, c->stream);
+  launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, 1, c->lev[j].ndof, c->stream);
 }
 
 // kappa of level j from the finest field: arithmetic mean of the 4 children per level (Section 4.1)
@@ -903,6 +1021,7 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
     if (!st && j > 0) st = build_patches(c, (int)j);
   }
   if (!st) st = build_coarse(c);
+  if (!st) st = build_dense(c);
   if (!st && hipDeviceSynchronize() != hipSuccess) st = fail(c, BMG_E_HIP, "setup synchronisation failed");
   if (st) {
     if (c->own_ws) hipFree(c->ws);
@@ -945,7 +1064,11 @@ bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total
 
 bmg_status bmg_destroy(bmg_handle h) {
   if (!h) return BMG_E_ARG;
+  hipStreamSynchronize(h->stream);
   for (auto e : h->ev) hipEventDestroy(e);
+  if (h->vexec) hipGraphExecDestroy(h->vexec);
+  if (h->vgraph) hipGraphDestroy(h->vgraph);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
   if (h->own_ws) {
     hipStreamSynchronize(h->stream);
     hipFree(h->ws);
@@ -983,7 +1106,8 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
   launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
-                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1, h->stream);
+                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1, 1,
+                L.ndof, h->stream);
   launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -994,7 +1118,7 @@ bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, con
   LevelInfo& L = h->lev[level];
   launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
   launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
-  smooth_level(h, level, steps);
+  smooth_level(h, level, steps, L.x, L.b, 1);
   launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -1005,7 +1129,7 @@ bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* b
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
   launch_cast(h->prec, 0, rf, F.r, F.ndof, h->stream);
-  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, h->stream);
+  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, 1, F.ndof, C.ndof, h->stream);
   launch_cast(0, h->prec, C.b, bc, C.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -1017,7 +1141,7 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
   LevelInfo& C = h->lev[level - 1];
   launch_cast(h->prec, 0, xc, C.x, C.ndof, h->stream);
   launch_cast(h->prec, 0, xf, F.x, F.ndof, h->stream);
-  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, h->stream);
+  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, 1, C.ndof, F.ndof, h->stream);
   launch_cast(0, h->prec, F.x, xf, F.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -1027,7 +1151,7 @@ bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) {
   if (!h || !b || !x) return BMG_E_ARG;
   LevelInfo& L = h->lev[0];
   launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
-  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, h->stream);
+  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, 1, h->stream);
   launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

@@ -129,12 +129,15 @@ __device__ __forceinline__ T pres_row(const Elem<T, K>& E, int q, const T* ux, c
 template <typename T, int K, bool RES>
 __global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                             const T* __restrict__ kap, const T* __restrict__ x,
-                                            const T* __restrict__ b, T* __restrict__ y) {
+                                            const T* __restrict__ b, T* __restrict__ y, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NV = D::NV, NP = D::NP, NA = D::NA, NB = D::NB;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N * N) return;
+  x += blockIdx.y * ld;
+  y += blockIdx.y * ld;
+  if (RES) b += blockIdx.y * ld;
   const Elem<T, K>& E = *Ep;
   const int cx = c % N, cy = c / N;
   const T mh = -h, hh = h * h;
@@ -289,10 +292,12 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
-                                                int colour, int npatch) {
+                                                int colour, int npatch, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NB = D::NB, NI = D::NI;
+  x += blockIdx.y * ld;
+  b += blockIdx.y * ld;
   __shared__ T xs[4][4][NL];
   __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
                                  //               1: u_y of the cell across the outer vertical face]
@@ -481,12 +486,15 @@ __device__ __forceinline__ void inside_comp(const Xfer<T, K>& X, int Nf, int cxc
 
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_restrict(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
-                                                  const T* __restrict__ rf, T* __restrict__ bc) {
+                                                  const T* __restrict__ rf, T* __restrict__ bc, int64_t ldf,
+                                                  int64_t ldc) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc * Nc) return;
+  rf += blockIdx.y * ldf;
+  bc += blockIdx.y * ldc;
   const Xfer<T, K>& X = *Xp;
   const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
   T in_x[NV], in_y[NV], tmp[NV];
@@ -565,12 +573,15 @@ __global__ __launch_bounds__(256) void k_restrict(const Xfer<T, K>* __restrict__
 
 template <typename T, int K>
 __global__ __launch_bounds__(256) void k_prolong(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
-                                                 const T* __restrict__ xc, T* __restrict__ xf) {
+                                                 const T* __restrict__ xc, T* __restrict__ xf, int64_t ldc,
+                                                 int64_t ldf) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= Nc * Nc) return;
+  xc += blockIdx.y * ldc;
+  xf += blockIdx.y * ldf;
   const Xfer<T, K>& X = *Xp;
   const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
   T zx[NV], zy[NV], zp[NP];
@@ -628,6 +639,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(int n, const double* __restrict__ inv, const T* __restrict__ b,
                                                 T* __restrict__ x) {
   extern __shared__ double sb[];
+  b += (int64_t)blockIdx.x * n;
+  x += (int64_t)blockIdx.x * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -635,6 +648,60 @@ __global__ __launch_bounds__(256) void k_coarse(int n, const double* __restrict_
     for (int j = 0; j < n; ++j) s += inv[(size_t)j * n + i] * sb[j];
     x[i] = (T)s;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ x, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// columns col0 .. col0 + nrhs - 1 of the identity, stored as nrhs vectors of length n
+template <typename T>
+__global__ __launch_bounds__(256) void k_identity(T* __restrict__ x, int64_t n, int64_t col0, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n, e = i % n;
+    x[i] = (e == col0 + r) ? T(1) : T(0);
+  }
+}
+
+// y = B x with B column-major n x n: block (row tile of 1024 rows, column chunk of
+// 256 columns) writes a partial sum; k_dense_sum adds the chunks in a fixed order.
+constexpr int kGemvRows = 1024, kGemvCols = 256;
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_part(const T* __restrict__ B, int64_t n, const T* __restrict__ x,
+                                                    T* __restrict__ part) {
+  __shared__ T xs[kGemvCols];
+  const int64_t r0 = (int64_t)blockIdx.x * kGemvRows, c0 = (int64_t)blockIdx.y * kGemvCols;
+  const int64_t nc = min((int64_t)kGemvCols, n - c0);
+  for (int i = threadIdx.x; i < kGemvCols; i += blockDim.x) xs[i] = (i < nc) ? x[c0 + i] : T(0);
+  __syncthreads();
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int64_t cc = 0; cc < nc; ++cc) {
+    const T* col = B + (c0 + cc) * n + r0;
+    const T xv = xs[cc];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = threadIdx.x + q * 256;
+      if (r0 + r < n) acc[q] += col[r] * xv;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = r0 + threadIdx.x + q * 256;
+    if (r < n) part[(int64_t)blockIdx.y * n + r] = acc[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_sum(const T* __restrict__ part, int nchunk, int64_t n,
+                                                   T* __restrict__ y) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T s = T(0);
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + r];
+  y[r] = s;
 }
 
 template <typename TO, typename TI>
@@ -741,93 +808,132 @@ inline unsigned grid_for(int64_t n, int bs = 256, int64_t cap = 8192) {
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename T, int K>
-static void op_t(const void* elem, const LevelArgs& L, const void* x, const void* b, void* y, bool res, hipStream_t s) {
+static void op_t(const void* elem, const LevelArgs& L, const void* x, const void* b, void* y, bool res, int nrhs,
+                 int64_t ld, hipStream_t s) {
   const int n = L.N * L.N;
-  dim3 g((n + 255) / 256), bl(256);
+  dim3 g((n + 255) / 256, nrhs), bl(256);
   if (res)
     hipLaunchKernelGGL((k_op<T, K, true>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y);
+                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y, ld);
   else
     hipLaunchKernelGGL((k_op<T, K, false>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y);
+                       (const T*)L.kap, (const T*)x, (const T*)b, (T*)y, ld);
 }
 
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
-               bool residual, hipStream_t s) {
+               bool residual, int nrhs, int64_t ld, hipStream_t s) {
   if (K == 1) {
-    if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, s);
-    else op_t<float, 1>(elem, L, x, b, y, residual, s);
+    if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
+    else op_t<float, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
   } else {
-    if (prec == 0) op_t<double, 2>(elem, L, x, b, y, residual, s);
-    else op_t<float, 2>(elem, L, x, b, y, residual, s);
+    if (prec == 0) op_t<double, 2>(elem, L, x, b, y, residual, nrhs, ld, s);
+    else op_t<float, 2>(elem, L, x, b, y, residual, nrhs, ld, s);
   }
 }
 
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
-                     const int32_t* extidx, int colour, int npatch, bool finest, hipStream_t s) {
+                     const int32_t* extidx, int colour, int npatch, bool finest, int nrhs, int64_t ld,
+                     hipStream_t s) {
   if (npatch <= 0) return;
-  dim3 g((npatch + 3) / 4), bl(256);
+  dim3 g((npatch + 3) / 4, nrhs), bl(256);
   if (finest)
     hipLaunchKernelGGL((k_colour<T, S, K, 1>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
+                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch,
+                       ld);
   else
     hipLaunchKernelGGL((k_colour<T, S, K, 0>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch);
+                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch,
+                       ld);
 }
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
-                   hipStream_t s) {
+                   int nrhs, int64_t ld, hipStream_t s) {
+#define BMG_COL(T, S, KK) colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, nrhs, ld, s)
   if (K == 1) {
-    if (prec == 0) colour_t<double, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
-    else if (sprec == 0) colour_t<float, double, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
-    else colour_t<float, float, 1>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    if (prec == 0) BMG_COL(double, double, 1);
+    else if (sprec == 0) BMG_COL(float, double, 1);
+    else BMG_COL(float, float, 1);
   } else {
-    if (prec == 0) colour_t<double, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
-    else if (sprec == 0) colour_t<float, double, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
-    else colour_t<float, float, 2>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, s);
+    if (prec == 0) BMG_COL(double, double, 2);
+    else if (sprec == 0) BMG_COL(float, double, 2);
+    else BMG_COL(float, float, 2);
+  }
+#undef BMG_COL
+}
+
+template <typename T, int K>
+static void restrict_t(const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs, int64_t ldf,
+                       int64_t ldc, hipStream_t s) {
+  const int n = Nc * Nc;
+  hipLaunchKernelGGL((k_restrict<T, K>), dim3((n + 255) / 256, nrhs), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc,
+                     bcm, (const T*)rf, (T*)bc, ldf, ldc);
+}
+void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
+                     int64_t ldf, int64_t ldc, hipStream_t s) {
+  if (K == 1) {
+    if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+  } else {
+    if (prec == 0) restrict_t<double, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    else restrict_t<float, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
   }
 }
 
 template <typename T, int K>
-static void restrict_t(const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s) {
+static void prolong_t(const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs, int64_t ldc,
+                      int64_t ldf, hipStream_t s) {
   const int n = Nc * Nc;
-  hipLaunchKernelGGL((k_restrict<T, K>), dim3((n + 255) / 256), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc, bcm,
-                     (const T*)rf, (T*)bc);
+  hipLaunchKernelGGL((k_prolong<T, K>), dim3((n + 255) / 256, nrhs), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc,
+                     bcm, (const T*)xc, (T*)xf, ldc, ldf);
 }
-void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, hipStream_t s) {
+void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
+                    int64_t ldc, int64_t ldf, hipStream_t s) {
   if (K == 1) {
-    if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, s);
-    else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, s);
+    if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
   } else {
-    if (prec == 0) restrict_t<double, 2>(xfer, Nc, bcm, rf, bc, s);
-    else restrict_t<float, 2>(xfer, Nc, bcm, rf, bc, s);
+    if (prec == 0) prolong_t<double, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    else prolong_t<float, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
   }
 }
 
-template <typename T, int K>
-static void prolong_t(const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s) {
-  const int n = Nc * Nc;
-  hipLaunchKernelGGL((k_prolong<T, K>), dim3((n + 255) / 256), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc, bcm,
-                     (const T*)xc, (T*)xf);
-}
-void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, hipStream_t s) {
-  if (K == 1) {
-    if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, s);
-    else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, s);
-  } else {
-    if (prec == 0) prolong_t<double, 2>(xfer, Nc, bcm, xc, xf, s);
-    else prolong_t<float, 2>(xfer, Nc, bcm, xc, xf, s);
-  }
-}
-
-void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, hipStream_t s) {
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s) {
   const size_t sh = (size_t)n * sizeof(double);
   if (prec == 0)
-    hipLaunchKernelGGL((k_coarse<double>), dim3(1), dim3(256), sh, s, n, inv, (const double*)b, (double*)x);
+    hipLaunchKernelGGL((k_coarse<double>), dim3(nrhs), dim3(256), sh, s, n, inv, (const double*)b, (double*)x);
   else
-    hipLaunchKernelGGL((k_coarse<float>), dim3(1), dim3(256), sh, s, n, inv, (const float*)b, (float*)x);
+    hipLaunchKernelGGL((k_coarse<float>), dim3(nrhs), dim3(256), sh, s, n, inv, (const float*)b, (float*)x);
+}
+
+void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  if (prec == 0) hipLaunchKernelGGL((k_fill<double>), dim3(g), dim3(256), 0, s, (double*)x, 0.0, n);
+  else hipLaunchKernelGGL((k_fill<float>), dim3(g), dim3(256), 0, s, (float*)x, 0.0f, n);
+}
+
+void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipStream_t s) {
+  const unsigned g = grid_for(n * nrhs);
+  if (prec == 0) hipLaunchKernelGGL((k_identity<double>), dim3(g), dim3(256), 0, s, (double*)x, n, col0, nrhs);
+  else hipLaunchKernelGGL((k_identity<float>), dim3(g), dim3(256), 0, s, (float*)x, n, col0, nrhs);
+}
+
+int64_t dense_part_elems(int64_t n) { return ((n + kGemvCols - 1) / kGemvCols) * n; }
+
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* part, void* y, hipStream_t s) {
+  const unsigned gr = (unsigned)((n + kGemvRows - 1) / kGemvRows), gc = (unsigned)((n + kGemvCols - 1) / kGemvCols);
+  if (prec == 0) {
+    hipLaunchKernelGGL((k_dense_part<double>), dim3(gr, gc), dim3(256), 0, s, (const double*)B, n, (const double*)x,
+                       (double*)part);
+    hipLaunchKernelGGL((k_dense_sum<double>), dim3((n + 255) / 256), dim3(256), 0, s, (const double*)part, (int)gc, n,
+                       (double*)y);
+  } else {
+    hipLaunchKernelGGL((k_dense_part<float>), dim3(gr, gc), dim3(256), 0, s, (const float*)B, n, (const float*)x,
+                       (float*)part);
+    hipLaunchKernelGGL((k_dense_sum<float>), dim3((n + 255) / 256), dim3(256), 0, s, (const float*)part, (int)gc, n,
+                       (float*)y);
+  }
 }
 
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s) {

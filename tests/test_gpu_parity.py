@@ -58,12 +58,13 @@ CASES = [
 IDS = [f"n0{c[0]}J{c[1]}k{c[2]}mu{c[3]}bc{''.join(map(str, c[5]))}" for c in CASES]
 
 
-def _setup(bmg, case, prec=0, seed=1, cycle=1, m_fine=2):
+def _setup(bmg, case, prec=0, seed=1, cycle=1, m_fine=2, dense=0):
     n0, J, k, mu, sigma, bc = case
     n = n0 << J
     kap = inputs.kappa_lognormal_channels(n, seed, channels=3, width=2 if n >= 16 else 1)
     o = Oracle(n0, J, k, mu, sigma, list(bc), kap, cycle, m_fine)
-    s = bmg.Solver(bmg.make_params(n0, J, k, mu, sigma, bc, cycle=cycle, m_fine=m_fine, prec=prec, restart=60), kap)
+    s = bmg.Solver(bmg.make_params(n0, J, k, mu, sigma, bc, cycle=cycle, m_fine=m_fine, prec=prec, restart=60,
+                                   dense_coarse_max=dense), kap)
     return o, s, kap
 
 
@@ -125,6 +126,18 @@ def test_vcycle(torch, bmg, case):
     assert _rel(z, z_ref) < 1e-11
 
 
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("dense", [1000, 16384])
+def test_vcycle_dense_coarse(torch, bmg, case, dense):
+    """The coarse sub-cycle applied as its precomputed dense matrix is the same operator."""
+    o, s, _ = _setup(bmg, case, dense=dense)
+    r = _vec(o, o.J, 82, zero_cons=False)
+    z_ref = o.vcycle(r)
+    for rep in range(3):   # first call captures the graph, later calls replay it
+        z = _np(s.vcycle(_dev(torch, r)))
+        assert _rel(z, z_ref) < 1e-10, rep
+
+
 @pytest.mark.parametrize("case", CASES[:5], ids=IDS[:5])
 def test_vcycle_fp32(torch, bmg, case):
     o, s, _ = _setup(bmg, case, prec=1)
@@ -142,8 +155,9 @@ def _rhs(o, bmg, s, w_source, case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
-def test_solve_fp64(torch, bmg, case):
-    o, s, _ = _setup(bmg, case)
+@pytest.mark.parametrize("dense", [0, 16384])
+def test_solve_fp64(torch, bmg, case, dense):
+    o, s, _ = _setup(bmg, case, dense=dense)
     src = inputs.smooth_source(7)
     b_o, b_g = _rhs(o, bmg, s, src, case)
     if o.singular():
@@ -166,9 +180,10 @@ def test_solve_fp64(torch, bmg, case):
 
 
 @pytest.mark.parametrize("case", CASES[:3], ids=IDS[:3])
-def test_solve_mixed_precision(torch, bmg, case):
-    o, s64, _ = _setup(bmg, case)
-    _, s32, _ = _setup(bmg, case, prec=1)
+@pytest.mark.parametrize("dense", [0, 16384])
+def test_solve_mixed_precision(torch, bmg, case, dense):
+    o, s64, _ = _setup(bmg, case, dense=dense)
+    _, s32, _ = _setup(bmg, case, prec=1, dense=dense)
     src = inputs.smooth_source(9)
     b = bmg.assemble_rhs(s64.params, src)
     x64, i64 = s64.solve(_dev(torch, b), rtol=1e-10, maxit=300)
