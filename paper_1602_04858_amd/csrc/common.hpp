@@ -82,9 +82,8 @@ void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const vo
 void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s);
 void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s);
 void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipStream_t s);
-// y = B x for a dense column-major n x n matrix (part: dense_part_elems(n) scratch)
-int64_t dense_part_elems(int64_t n);
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* part, void* y, hipStream_t s);
+// y = B x for a dense symmetric n x n matrix
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, hipStream_t s);
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s);
 void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s);
 

@@ -55,8 +55,7 @@ struct bmg_ctx {
   double* coarse_inv = nullptr;
   // dense operator of the coarse sub-cycle: B_jc for level jc (0 = none)
   int jc = 0;
-  void* dense = nullptr;
-  void* dpart = nullptr;
+  void* dense = nullptr;  // B_jc, symmetric: the column-major batch output is read by rows
   // setup batch (unit vectors through the V-cycle of level jc), overlapping the Krylov storage
   int batch_chunk = 0;
   char* region = nullptr;
@@ -476,7 +475,6 @@ size_t layout(bmg_ctx* c, char* base) {
   if (c->jc > 0) {
     const int64_t nd = c->lev[c->jc].ndof;
     c->dense = B.take((size_t)nd * nd * ts);
-    c->dpart = B.take((size_t)dense_part_elems(nd) * ts);
   }
   c->elemT = B.take(c->prec == 0 ? elem_bytes<double>(K) : elem_bytes<float>(K));
   c->elem64 = B.take(elem_bytes<double>(K));
@@ -828,7 +826,7 @@ void vcycle_level(bmg_ctx* c, int j, const Vecs& v, bool use_dense) {
   LevelInfo& L = c->lev[j];
   const int nr = v.nrhs;
   if (use_dense && c->jc > 0 && j == c->jc && nr == 1) {
-    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], c->dpart, v.x[j], c->stream);
+    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], v.x[j], c->stream);
     return;
   }
   if (j == 0) {

@@ -267,26 +267,84 @@ __device__ __forceinline__ int kind_to_local(int kind, int b) {
   return (kind >= 2 ? D::NV : 0) + (kind & 1) * D::NB + b;
 }
 
-template <typename T, typename S, int K, bool EXT>
-__device__ __forceinline__ void patch_gemv(const S* __restrict__ A, const T* rs, const int* gs, T* __restrict__ x,
-                                           int lane) {
+// Entry t of the patch layout: global index gi (-1 if not part of the patch
+// space) and the positions zA / zB of the row contributions of the patch cells
+// (slot * NL + local dof) that sum to row gi (zB >= 0 only for faces inside the patch).
+template <int K>
+__device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int N, int bcm, int& gi, int& zA,
+                                            int& zB) {
   using D = Dims<K>;
-  constexpr int NS = EXT ? D::NSE : D::NSR;
-#pragma unroll
-  for (int t0 = 0; t0 < NS; t0 += 64) {
-    const int t = t0 + lane;
-    if (t < NS) {
-      T acc = T(0);
-#pragma unroll 8
-      for (int u = 0; u < NS; ++u) acc += T(A[u * NS + t]) * rs[u];
-      const int gi = gs[t];
-      if (gi >= 0) x[gi] += acc;
+  using I = Idx<K>;
+  constexpr int NB = D::NB, NI = D::NI, NP = D::NP, NV = D::NV, NL = D::NL;
+  auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
+  gi = -1;
+  zA = -1;
+  zB = -1;
+  const int nf = ext ? 12 : 4;
+  if (t < nf * NB) {
+    const int grp = ext ? t / NB : kRegular[t / NB];
+    const int bb = t % NB;
+    const int sA = kGroup[grp][0], kA = kGroup[grp][1], sB = kGroup[grp][2], kB = kGroup[grp][3];
+    const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
+    const bool vA = in_dom(axA, ayA);
+    bool vB = false;
+    int axB = 0, ayB = 0;
+    if (sB >= 0) {
+      axB = vx - 1 + (sB & 1);
+      ayB = vy - 1 + (sB >> 1);
+      vB = in_dom(axB, ayB);
+    }
+    bool ok;
+    int cxu, cyu, du;
+    if (sB >= 0) {
+      ok = vA || vB;
+      cxu = vA ? axA : axB;
+      cyu = vA ? ayA : ayB;
+      du = kind_to_local<K>(vA ? kA : kB, bb);
+    } else {
+      // outer face: part of the patch space only on the domain boundary
+      int ox = axA, oy = ayA;
+      if (kA == 0) ox -= 1;
+      else if (kA == 1) ox += 1;
+      else if (kA == 2) oy -= 1;
+      else oy += 1;
+      ok = vA && !in_dom(ox, oy);
+      cxu = axA;
+      cyu = ayA;
+      du = kind_to_local<K>(kA, bb);
+    }
+    if (ok && !I::cons(N, bcm, cxu, cyu, du)) {
+      gi = I::g(N, cxu, cyu, du);
+      if (vA) zA = sA * NL + kind_to_local<K>(kA, bb);
+      if (vB) zB = sB * NL + kind_to_local<K>(kB, bb);
+    }
+  } else {
+    const int e = t - nf * NB;
+    int s, d;
+    if (e < 4 * NI) {
+      s = e / NI;
+      const int w2 = e % NI, comp = w2 / (K * NB), rem = w2 % (K * NB);
+      d = comp * NV + (2 + rem / NB) * NB + rem % NB;
+    } else {
+      s = (e - 4 * NI) / NP;
+      d = 2 * NV + (e - 4 * NI) % NP;
+    }
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    if (in_dom(cx, cy)) {
+      gi = I::g(N, cx, cy, d);
+      zA = s * NL + d;
     }
   }
 }
 
 // TAG only separates the launches of the finest level (TAG = 1) from the others
 // in profiler output; the code is identical.
+//
+// Latency structure: everything that does not depend on x is issued first -- the
+// element matrices are copied to LDS, the patch-inverse column of this lane is
+// prefetched into registers (RT_1, regular layout), the patch layout is decoded
+// arithmetically and b on the patch is loaded -- so the dependent chain is one
+// gather of x, the local residual in LDS, an FMA chain on registers and the store.
 template <typename T, typename S, int K, int TAG>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
@@ -295,16 +353,17 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 int colour, int npatch, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
-  constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NB = D::NB, NI = D::NI;
-  x += blockIdx.y * ld;
-  b += blockIdx.y * ld;
+  constexpr int NL = D::NL, NV = D::NV, NSR = D::NSR, NSE = D::NSE;
+  constexpr bool PF = (K == 1);
+  constexpr int NT = (NSE + 63) / 64;  // layout entries per lane
+  __shared__ Elem<T, K> Es;
   __shared__ T xs[4][4][NL];
   __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
                                  //               1: u_y of the cell across the outer vertical face]
   __shared__ T zs[4][4 * NL];
-  __shared__ T rs[4][D::NSE];
-  __shared__ int gs[4][D::NSE];
-  const Elem<T, K>& E = *Ep;
+  __shared__ T rs[4][NSE];
+  x += blockIdx.y * ld;
+  b += blockIdx.y * ld;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + w;
   const bool active = p < npatch;
@@ -313,6 +372,36 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
+
+  // 0. independent of x: layout guess, inverse prefetch, element matrices, b
+  const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
+                         (vy == N - 1 && !(bcm & 8));
+  const int ext = active ? extidx[p] : -1;
+  S areg[PF ? NSR : 1];
+  const bool pre = PF && active && !ext_guess && lane < NSR;
+  if (pre) {
+    const S* A = inv + (size_t)p * NSR * NSR;
+#pragma unroll
+    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lane];
+  }
+  {
+    const T* src = reinterpret_cast<const T*>(Ep);
+    T* dst = reinterpret_cast<T*>(&Es);
+    for (int i = threadIdx.x; i < (int)(sizeof(Elem<T, K>) / sizeof(T)); i += blockDim.x) dst[i] = src[i];
+  }
+  int gi[NT], zA[NT], zB[NT];
+  T bv[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    gi[q] = -1;
+    zA[q] = zB[q] = -1;
+    bv[q] = T(0);
+    const int t = lane + 64 * q;
+    if (active && t < (ext_guess ? NSE : NSR)) {
+      decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
+      if (gi[q] >= 0) bv[q] = b[gi[q]];
+    }
+  }
 
   // 1. gather the patch cells and the face neighbours across the patch boundary
   for (int e = lane; e < 4 * NL; e += 64) {
@@ -353,7 +442,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           else nl = (s >= 2) ? xs[w][s - 2] : nb[w][s][0];
           if (cy == N - 1) tu = boundary_type(bcm, 3);
           else nu = (s < 2) ? xs[w][s + 2] : nb[w][s][0];
-          z = comp_row<T, K>(E, d, xl, xl + 2 * NV, E.Dx, khh, mh, tl, nl, tu, nu);
+          z = comp_row<T, K>(Es, d, xl, xl + 2 * NV, Es.Dx, khh, mh, tl, nl, tu, nu);
         } else {
           int tl = F_INT, tu = F_INT;
           const T* nl = nullptr;
@@ -362,90 +451,64 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           else nl = (s & 1) ? xs[w][s - 1] + NV : nb[w][s][1];
           if (cx == N - 1) tu = boundary_type(bcm, 1);
           else nu = (s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV;
-          z = comp_row<T, K>(E, d - NV, xl + NV, xl + 2 * NV, E.Dy, khh, mh, tl, nl, tu, nu);
+          z = comp_row<T, K>(Es, d - NV, xl + NV, xl + 2 * NV, Es.Dy, khh, mh, tl, nl, tu, nu);
         }
       } else {
-        z = pres_row<T, K>(E, d - 2 * NV, xl, xl + NV, mh);
+        z = pres_row<T, K>(Es, d - 2 * NV, xl, xl + NV, mh);
       }
     }
     zs[w][e] = z;
   }
   __syncthreads();
 
-  // 3. local residual (b - A x) on the patch dofs, in the patch layout
-  const int ext = active ? extidx[p] : -1;
-  const int nf = ext >= 0 ? 12 : 4;
-  const int ns = nf * NB + 4 * NI + 4 * NP;
-  for (int t = lane; t < ns; t += 64) {
-    int gi = -1;
-    T z = T(0);
-    if (active) {
-      if (t < nf * NB) {
-        const int grp = ext >= 0 ? t / NB : kRegular[t / NB];
-        const int bb = t % NB;
-        const int sA = kGroup[grp][0], kA = kGroup[grp][1], sB = kGroup[grp][2], kB = kGroup[grp][3];
-        const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
-        const bool vA = in_dom(axA, ayA);
-        bool vB = false;
-        int axB = 0, ayB = 0;
-        if (sB >= 0) {
-          axB = vx - 1 + (sB & 1);
-          ayB = vy - 1 + (sB >> 1);
-          vB = in_dom(axB, ayB);
-        }
-        bool ok;
-        int cxu, cyu, du;
-        if (sB >= 0) {
-          ok = vA || vB;
-          cxu = vA ? axA : axB;
-          cyu = vA ? ayA : ayB;
-          du = kind_to_local<K>(vA ? kA : kB, bb);
-        } else {
-          // outer face: part of the patch space only on the domain boundary
-          int ox = axA, oy = ayA;
-          if (kA == 0) ox -= 1;
-          else if (kA == 1) ox += 1;
-          else if (kA == 2) oy -= 1;
-          else oy += 1;
-          ok = vA && !in_dom(ox, oy);
-          cxu = axA;
-          cyu = ayA;
-          du = kind_to_local<K>(kA, bb);
-        }
-        if (ok && !I::cons(N, bcm, cxu, cyu, du)) {
-          gi = I::g(N, cxu, cyu, du);
-          z = (vA ? zs[w][sA * NL + kind_to_local<K>(kA, bb)] : T(0)) +
-              (vB ? zs[w][sB * NL + kind_to_local<K>(kB, bb)] : T(0));
-        }
-      } else {
-        const int e = t - nf * NB;
-        int s, d;
-        if (e < 4 * NI) {
-          s = e / NI;
-          const int w2 = e % NI, comp = w2 / (K * NB), rem = w2 % (K * NB);
-          d = comp * NV + (2 + rem / NB) * NB + rem % NB;
-        } else {
-          s = (e - 4 * NI) / NP;
-          d = 2 * NV + (e - 4 * NI) % NP;
-        }
-        const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-        if (in_dom(cx, cy)) {
-          gi = I::g(N, cx, cy, d);
-          z = zs[w][s * NL + d];
-        }
+  // 3. local residual (b - A x) on the patch entries; the layout guess is checked
+  // against the table and decoded again on a mismatch
+  const bool is_ext = ext >= 0;
+  const int ns = is_ext ? NSE : NSR;
+  if (active && is_ext != ext_guess) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      gi[q] = -1;
+      zA[q] = zB[q] = -1;
+      bv[q] = T(0);
+      const int t = lane + 64 * q;
+      if (t < ns) {
+        decode_slot<K>(t, is_ext, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
+        if (gi[q] >= 0) bv[q] = b[gi[q]];
       }
     }
-    rs[w][t] = gi >= 0 ? b[gi] - z : T(0);
-    gs[w][t] = gi;
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int t = lane + 64 * q;
+    if (t < NSE) {
+      T r = T(0);
+      if (gi[q] >= 0) r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
+      rs[w][t] = r;
+    }
   }
   __syncthreads();
 
   // 4. correction y = A_S^+ r, x[S] += y
   if (!active) return;
-  if (ext >= 0)
-    patch_gemv<T, S, K, true>(invx + (size_t)ext * D::NSE * D::NSE, rs[w], gs[w], x, lane);
-  else
-    patch_gemv<T, S, K, false>(inv + (size_t)p * D::NSR * D::NSR, rs[w], gs[w], x, lane);
+  if (PF && !is_ext && pre) {
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
+    if (gi[0] >= 0) x[gi[0]] += acc;
+    return;
+  }
+  const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int t = lane + 64 * q;
+    if (t < ns) {
+      T acc = T(0);
+#pragma unroll 8
+      for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
+      if (gi[q] >= 0) x[gi[q]] += acc;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -666,42 +729,27 @@ __global__ __launch_bounds__(256) void k_identity(T* __restrict__ x, int64_t n, 
   }
 }
 
-// y = B x with B column-major n x n: block (row tile of 1024 rows, column chunk of
-// 256 columns) writes a partial sum; k_dense_sum adds the chunks in a fixed order.
-constexpr int kGemvRows = 1024, kGemvCols = 256;
+// y = B x for a symmetric n x n matrix stored densely: one wavefront per row,
+// four independent partial sums per lane, streamed (non-temporal) matrix loads.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_part(const T* __restrict__ B, int64_t n, const T* __restrict__ x,
-                                                    T* __restrict__ part) {
-  __shared__ T xs[kGemvCols];
-  const int64_t r0 = (int64_t)blockIdx.x * kGemvRows, c0 = (int64_t)blockIdx.y * kGemvCols;
-  const int64_t nc = min((int64_t)kGemvCols, n - c0);
-  for (int i = threadIdx.x; i < kGemvCols; i += blockDim.x) xs[i] = (i < nc) ? x[c0 + i] : T(0);
-  __syncthreads();
-  T acc[4] = {T(0), T(0), T(0), T(0)};
-  for (int64_t cc = 0; cc < nc; ++cc) {
-    const T* col = B + (c0 + cc) * n + r0;
-    const T xv = xs[cc];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t r = threadIdx.x + q * 256;
-      if (r0 + r < n) acc[q] += col[r] * xv;
-    }
+__global__ __launch_bounds__(256) void k_dense_rows(const T* __restrict__ B, int64_t n, const T* __restrict__ x,
+                                                    T* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const T* r = B + row * n;
+  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+  int64_t j = lane;
+  for (; j + 192 < n; j += 256) {
+    a0 += __builtin_nontemporal_load(r + j) * x[j];
+    a1 += __builtin_nontemporal_load(r + j + 64) * x[j + 64];
+    a2 += __builtin_nontemporal_load(r + j + 128) * x[j + 128];
+    a3 += __builtin_nontemporal_load(r + j + 192) * x[j + 192];
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t r = r0 + threadIdx.x + q * 256;
-    if (r < n) part[(int64_t)blockIdx.y * n + r] = acc[q];
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_sum(const T* __restrict__ part, int nchunk, int64_t n,
-                                                   T* __restrict__ y) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T s = T(0);
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + r];
-  y[r] = s;
+  for (; j < n; j += 64) a0 += __builtin_nontemporal_load(r + j) * x[j];
+  T s = (a0 + a1) + (a2 + a3);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) y[row] = s;
 }
 
 template <typename TO, typename TI>
@@ -919,21 +967,14 @@ void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipSt
   else hipLaunchKernelGGL((k_identity<float>), dim3(g), dim3(256), 0, s, (float*)x, n, col0, nrhs);
 }
 
-int64_t dense_part_elems(int64_t n) { return ((n + kGemvCols - 1) / kGemvCols) * n; }
-
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* part, void* y, hipStream_t s) {
-  const unsigned gr = (unsigned)((n + kGemvRows - 1) / kGemvRows), gc = (unsigned)((n + kGemvCols - 1) / kGemvCols);
-  if (prec == 0) {
-    hipLaunchKernelGGL((k_dense_part<double>), dim3(gr, gc), dim3(256), 0, s, (const double*)B, n, (const double*)x,
-                       (double*)part);
-    hipLaunchKernelGGL((k_dense_sum<double>), dim3((n + 255) / 256), dim3(256), 0, s, (const double*)part, (int)gc, n,
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 3) / 4);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_dense_rows<double>), dim3(g), dim3(256), 0, s, (const double*)B, n, (const double*)x,
                        (double*)y);
-  } else {
-    hipLaunchKernelGGL((k_dense_part<float>), dim3(gr, gc), dim3(256), 0, s, (const float*)B, n, (const float*)x,
-                       (float*)part);
-    hipLaunchKernelGGL((k_dense_sum<float>), dim3((n + 255) / 256), dim3(256), 0, s, (const float*)part, (int)gc, n,
+  else
+    hipLaunchKernelGGL((k_dense_rows<float>), dim3(g), dim3(256), 0, s, (const float*)B, n, (const float*)x,
                        (float*)y);
-  }
 }
 
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s) {
