@@ -315,8 +315,11 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
     }
     if (ok && !I::cons(N, bcm, cxu, cyu, du)) {
       gi = I::g(N, cxu, cyu, du);
-      if (vA) zA = sA * NL + kind_to_local<K>(kA, bb);
-      if (vB) zB = sB * NL + kind_to_local<K>(kB, bb);
+      // zA is always the first existing contribution, zB the second (if any)
+      const int za = vA ? sA * NL + kind_to_local<K>(kA, bb) : -1;
+      const int zb = vB ? sB * NL + kind_to_local<K>(kB, bb) : -1;
+      zA = za >= 0 ? za : zb;
+      zB = za >= 0 ? zb : -1;
     }
   } else {
     const int e = t - nf * NB;
