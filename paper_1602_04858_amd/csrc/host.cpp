@@ -67,6 +67,7 @@ struct bmg_ctx {
   hipGraph_t vgraph = nullptr;
   hipGraphExec_t vexec = nullptr;
   bool graph_failed = false;
+  bool layout_mismatch = false;  // the kernel's layout rule disagrees with the patch construction
   // optional event timing of the colour launches of one level
   int timing_level = -1;
   std::vector<hipEvent_t> ev;
@@ -247,6 +248,13 @@ bool needs_ext(const HostIdx& I, int vx, int vy) {
     for (int b = 0; b < I.NB; ++b)
       if (P.g[grp * I.NB + b] >= 0) return true;
   return false;
+}
+
+// The rule the smoother kernel uses to pick the layout without a table lookup:
+// an outer face of the patch lies on an open side.
+bool ext_rule(const HostIdx& I, int vx, int vy) {
+  return (vx == 1 && !(I.bcm & 1)) || (vx == I.N - 1 && !(I.bcm & 2)) || (vy == 1 && !(I.bcm & 4)) ||
+         (vy == I.N - 1 && !(I.bcm & 8));
 }
 
 // Dense A restricted to the patch layout (invalid entries: zero rows/cols),
@@ -528,7 +536,9 @@ void init_levels(bmg_ctx* c) {
         for (int vy = c3y; vy <= L.N; vy += 3)
           for (int vx = c3x; vx <= L.N; vx += 3) {
             const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
-            if (near && needs_ext(I, vx, vy)) ++ne;
+            const bool e = near && needs_ext(I, vx, vy);
+            if (e != ext_rule(I, vx, vy)) c->layout_mismatch = true;
+            if (e) ++ne;
           }
         L.next[col] = ne;
       }
@@ -977,6 +987,7 @@ bmg_status bmg_plan(const bmg_params* p, size_t* bytes) {
   tmp.p = *p;
   setup_types(&tmp);
   init_levels(&tmp);
+  if (tmp.layout_mismatch) return BMG_E_STATE;
   *bytes = layout(&tmp, nullptr);
   return BMG_OK;
 }
@@ -1007,6 +1018,11 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
     c->own_ws = true;
   }
   c->ws_bytes = need;
+  if (c->layout_mismatch) {
+    if (c->own_ws) hipFree(c->ws);
+    delete c;
+    return BMG_E_STATE;
+  }
   layout(c, c->ws);
   c->ref = make_refdata(p->k, p->mu, p->sigma);
   // kappa hierarchy: arithmetic mean of the four children (Section 4.1)

@@ -65,6 +65,14 @@ struct Idx {
 
 __device__ __forceinline__ int boundary_type(int bcm, int side) { return ((bcm >> side) & 1) ? F_DIR : F_OPEN; }
 
+// Workgroup barrier that orders LDS only: global loads issued before it stay in
+// flight (a full __syncthreads() would wait for every outstanding global access).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // one velocity component (NV values, comp 0 = u_x, 1 = u_y) of a cell; essential dofs read as 0
 template <int K, typename T>
 __device__ __forceinline__ void load_comp(const T* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
@@ -256,10 +264,20 @@ __global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, i
 // The regular layout keeps groups 1, 4, 8, 9.  Slot s is the cell
 // (vx - 1 + (s & 1), vy - 1 + (s >> 1)).  Entry: (slotA, kindA, slotB, kindB) with
 // kind 0 = u_x at a = 0, 1 = u_x at a = 1, 2 = u_y at a = 0, 3 = u_y at a = 1.
-__constant__ int8_t kGroup[12][4] = {{0, 0, -1, 0}, {0, 1, 1, 0},  {1, 1, -1, 0}, {2, 0, -1, 0},
-                                     {2, 1, 3, 0},  {3, 1, -1, 0}, {0, 2, -1, 0}, {1, 2, -1, 0},
-                                     {0, 3, 2, 2},  {1, 3, 3, 2},  {2, 3, -1, 0}, {3, 3, -1, 0}};
-__constant__ int8_t kRegular[4] = {1, 4, 8, 9};
+// Packed form of that table (no memory access): byte g of the three words holds
+// slotA | kindA << 2 | slotB << 4 | kindB << 6; bit g of kSingle marks groups with
+// one cell only; kRegularGroups holds the four regular groups as nibbles.
+constexpr uint32_t kGroupW0 = 0x02051400u, kGroupW1 = 0x09080736u, kGroupW2 = 0x0F0EBDACu;
+constexpr uint32_t kSingle = 0xCEDu, kRegularGroups = 0x9841u;
+
+__device__ __forceinline__ void group_info(int grp, int& sA, int& kA, int& sB, int& kB) {
+  const uint32_t wd = grp < 4 ? kGroupW0 : grp < 8 ? kGroupW1 : kGroupW2;
+  const uint32_t by = (wd >> ((grp & 3) * 8)) & 0xffu;
+  sA = by & 3;
+  kA = (by >> 2) & 3;
+  kB = (by >> 6) & 3;
+  sB = ((kSingle >> grp) & 1u) ? -1 : (int)((by >> 4) & 3);
+}
 
 template <int K>
 __device__ __forceinline__ int kind_to_local(int kind, int b) {
@@ -282,9 +300,10 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
   zB = -1;
   const int nf = ext ? 12 : 4;
   if (t < nf * NB) {
-    const int grp = ext ? t / NB : kRegular[t / NB];
+    const int grp = ext ? t / NB : (int)((kRegularGroups >> (4 * (t / NB))) & 0xfu);
     const int bb = t % NB;
-    const int sA = kGroup[grp][0], kA = kGroup[grp][1], sB = kGroup[grp][2], kB = kGroup[grp][3];
+    int sA, kA, sB, kB;
+    group_info(grp, sA, kA, sB, kB);
     const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
     const bool vA = in_dom(axA, ayA);
     bool vB = false;
@@ -367,76 +386,114 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T rs[4][NSE];
   x += blockIdx.y * ld;
   b += blockIdx.y * ld;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + w;
   const bool active = p < npatch;
+  const int pc = active ? p : npatch - 1;  // in-bounds stand-in for idle waves
   const int c3x = colour % 3, c3y = colour / 3;
   const int nvx = (N - c3x) / 3 + 1;
-  const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+  const int vx = c3x + 3 * (pc % nvx), vy = c3y + 3 * (pc / nvx);
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
 
-  // 0. independent of x: layout guess, inverse prefetch, element matrices, b
-  const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
-                         (vy == N - 1 && !(bcm & 8));
-  const int ext = active ? extidx[p] : -1;
-  S areg[PF ? NSR : 1];
-  const bool pre = PF && active && !ext_guess && lane < NSR;
-  if (pre) {
-    const S* A = inv + (size_t)p * NSR * NSR;
+  // 0. issue every load that does not depend on the correction: the gather of x
+  // (first: it is needed first), the element matrices, b on the patch, then the
+  // patch-inverse column of this lane (needed last).  The loads are unconditional
+  // (clamped in-bounds indices, masked where the value is used) so that no branch
+  // separates them from their uses; they complete in order and the later ones stay
+  // in flight through the LDS-only barriers below.
+  constexpr int NG = (4 * NL + 63) / 64, NN = (8 * NV + 63) / 64;
+  T gx[NG], gn[NN];
+  bool okx[NG], okn[NN];
 #pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lane];
-  }
-  {
-    const T* src = reinterpret_cast<const T*>(Ep);
-    T* dst = reinterpret_cast<T*>(&Es);
-    for (int i = threadIdx.x; i < (int)(sizeof(Elem<T, K>) / sizeof(T)); i += blockDim.x) dst[i] = src[i];
-  }
-  int gi[NT], zA[NT], zB[NT];
-  T bv[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    gi[q] = -1;
-    zA[q] = zB[q] = -1;
-    bv[q] = T(0);
-    const int t = lane + 64 * q;
-    if (active && t < (ext_guess ? NSE : NSR)) {
-      decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
-      if (gi[q] >= 0) bv[q] = b[gi[q]];
-    }
-  }
-
-  // 1. gather the patch cells and the face neighbours across the patch boundary
-  for (int e = lane; e < 4 * NL; e += 64) {
-    const int s = e / NL, d = e % NL;
+  for (int q = 0; q < NG; ++q) {
+    const int e = lane + 64 * q;
+    const int s = (e / NL) & 3, d = e % NL;
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    T v = T(0);
-    if (active && in_dom(cx, cy) && !I::cons(N, bcm, cx, cy, d)) v = x[I::g(N, cx, cy, d)];
-    xs[w][s][d] = v;
+    okx[q] = e < 4 * NL && in_dom(cx, cy) && !I::cons(N, bcm, cx, cy, d);
+    gx[q] = x[okx[q] ? I::g(N, cx, cy, d) : 0];
   }
-  for (int e = lane; e < 8 * NV; e += 64) {
-    const int s = e / (2 * NV), r = e % (2 * NV), which = r / NV, d = r % NV;
+#pragma unroll
+  for (int q = 0; q < NN; ++q) {
+    const int e = lane + 64 * q;
+    const int s = (e / (2 * NV)) & 3, r = e % (2 * NV), which = r / NV, d = r % NV;
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     int ncx = cx, ncy = cy;
     if (which == 0) ncy = (s < 2) ? cy - 1 : cy + 1;
     else ncx = (s & 1) ? cx + 1 : cx - 1;
     const int dd = which * NV + d;
-    T v = T(0);
-    if (active && in_dom(cx, cy) && in_dom(ncx, ncy) && !I::cons(N, bcm, ncx, ncy, dd))
-      v = x[I::g(N, ncx, ncy, dd)];
-    nb[w][s][which][d] = v;
+    okn[q] = e < 8 * NV && in_dom(cx, cy) && in_dom(ncx, ncy) && !I::cons(N, bcm, ncx, ncy, dd);
+    gn[q] = x[okn[q] ? I::g(N, ncx, ncy, dd) : 0];
   }
-  __syncthreads();
+  constexpr int NE = (int)(sizeof(Elem<T, K>) / sizeof(T)), NEQ = (NE + 255) / 256;
+  T ev[NEQ];
+  {
+    const T* src = reinterpret_cast<const T*>(Ep);
+#pragma unroll
+    for (int q = 0; q < NEQ; ++q) ev[q] = src[min((int)threadIdx.x + 256 * q, NE - 1)];
+  }
+  const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
+                         (vy == N - 1 && !(bcm & 8));
+  const int ext = active ? extidx[pc] : -1;
+  int gi[NT], zA[NT], zB[NT];
+  T bv[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int t = lane + 64 * q;
+    decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
+    if (!active || t >= (ext_guess ? NSE : NSR)) gi[q] = -1;
+    bv[q] = b[gi[q] >= 0 ? gi[q] : 0];
+  }
+  T kv[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int s = ((lane + 64 * q) / NL) & 3;
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
+  }
+  S areg[PF ? NSR : 1];
+  const bool pre = PF && active && !ext_guess && lane < NSR;
+  if (PF) {
+    const S* A = inv + (size_t)pc * NSR * NSR;
+    const int lc = lane < NSR ? lane : NSR - 1;
+#pragma unroll
+    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lc];
+  }
+
+  // 1. gathered values and element matrices to LDS
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int e = lane + 64 * q;
+    if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < NN; ++q) {
+    const int e = lane + 64 * q;
+    if (e < 8 * NV) {
+      const int s = e / (2 * NV), r = e % (2 * NV);
+      nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+    }
+  }
+  {
+    T* dst = reinterpret_cast<T*>(&Es);
+#pragma unroll
+    for (int q = 0; q < NEQ; ++q)
+      if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
+  }
+  lds_barrier();
 
   // 2. row contributions of every patch cell (cell blocks + its four faces)
-  for (int e = lane; e < 4 * NL; e += 64) {
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int e = lane + 64 * q;
+    if (e >= 4 * NL) break;
     const int s = e / NL, d = e % NL;
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     T z = T(0);
     if (active && in_dom(cx, cy)) {
       const T* xl = xs[w][s];
       if (d < 2 * NV) {
-        const T khh = kap[cy * N + cx] * hh;
+        const T khh = kv[q] * hh;
         if (d < NV) {
           int tl = F_INT, tu = F_INT;
           const T* nl = nullptr;
@@ -462,25 +519,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     }
     zs[w][e] = z;
   }
-  __syncthreads();
+  lds_barrier();
 
-  // 3. local residual (b - A x) on the patch entries; the layout guess is checked
-  // against the table and decoded again on a mismatch
-  const bool is_ext = ext >= 0;
+  // 3. local residual (b - A x) on the patch entries.  The layout follows from the
+  // vertex position (extended iff an outer face of the patch lies on an open
+  // side); setup checks this rule against the patch construction.
+  const bool is_ext = ext_guess;
   const int ns = is_ext ? NSE : NSR;
-  if (active && is_ext != ext_guess) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      gi[q] = -1;
-      zA[q] = zB[q] = -1;
-      bv[q] = T(0);
-      const int t = lane + 64 * q;
-      if (t < ns) {
-        decode_slot<K>(t, is_ext, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
-        if (gi[q] >= 0) bv[q] = b[gi[q]];
-      }
-    }
-  }
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const int t = lane + 64 * q;
@@ -490,7 +535,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       rs[w][t] = r;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // 4. correction y = A_S^+ r, x[S] += y
   if (!active) return;

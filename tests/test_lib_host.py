@@ -52,6 +52,18 @@ def test_parameter_validation(change, expect):
     assert e.value.status == expect
 
 
+@pytest.mark.parametrize("n0", [2, 3])
+def test_smoother_layout_rule_matches_patch_construction(n0):
+    """The colour kernel picks the patch layout from the vertex position alone; setup
+    (and plan) refuse with BMG_E_STATE if that rule ever disagrees with the generic
+    patch construction.  Every boundary combination, several mesh sizes."""
+    for code in range(16):
+        bc = [(code >> s) & 1 for s in range(4)]
+        for J in (1, 2, 3):
+            bmg.plan(bmg.make_params(n0, J, 1, 1e-2, 6.0, bc, restart=4))
+            bmg.plan(bmg.make_params(n0, J, 2, 1e-2, 12.0, bc, restart=4))
+
+
 def test_plan_grows_with_levels():
     sizes = [bmg.plan(bmg.make_params(2, J, 1, 1e-2, 6.0, [D, D, O, O], restart=20)) for J in (2, 3, 4)]
     assert sizes[0] < sizes[1] < sizes[2]
