@@ -446,6 +446,9 @@ size_t xfer_bytes(int K) {
 
 int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
 int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
+// stored entries of one patch pseudo-inverse: RT_1 packed upper triangle, RT_2 full
+bool packed_inv(int k) { return k == 1; }
+int64_t inv_entries(int k, int ns) { return packed_inv(k) ? (int64_t)ns * (ns + 1) / 2 : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
 // dof count is at most dense_coarse_max (0 = none).
@@ -472,8 +475,8 @@ size_t layout(bmg_ctx* c, char* base) {
     L.r = B.take(L.ndof * ts);
     if (j > 0)
       for (int col = 0; col < 9; ++col) {
-        L.inv[col] = B.take((size_t)L.npatch[col] * nsr * nsr * ss);
-        L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * nse * nse * ss);
+        L.inv[col] = B.take((size_t)L.npatch[col] * inv_entries(K, nsr) * ss);
+        L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * inv_entries(K, nse) * ss);
         L.extidx[col] = (int32_t*)B.take((size_t)std::max(L.npatch[col], 1) * sizeof(int32_t));
       }
   }
@@ -736,7 +739,9 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
       if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
     }
-    std::vector<double> reg((size_t)np * nsr * nsr, 0.0), exd((size_t)std::max(ne, 1) * nse * nse, 0.0);
+    const int64_t er = inv_entries(c->K, nsr), ee = inv_entries(c->K, nse);
+    const bool pk = packed_inv(c->K);
+    std::vector<double> reg((size_t)np * er, 0.0), exd((size_t)std::max(ne, 1) * ee, 0.0);
     std::atomic<int> bad{0};
     parallel_for(np, [&](int p) {
       const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
@@ -748,16 +753,23 @@ bmg_status build_patches(bmg_ctx* c, int j) {
         bad.store(1);
         return;
       }
-      double* dst = isx ? &exd[(size_t)ext[p] * nse * nse] : &reg[(size_t)p * nsr * nsr];
+      double* dst = isx ? &exd[(size_t)ext[p] * ee] : &reg[(size_t)p * er];
       const int ns = P.ns;
-      for (int t = 0; t < ns; ++t)
-        for (int u = 0; u < ns; ++u) dst[(size_t)u * ns + t] = pinv[(size_t)t * ns + u];
+      if (pk) {
+        // symmetric: upper triangle of (A+ + A+^T)/2, column-major packed
+        for (int cc = 0; cc < ns; ++cc)
+          for (int r = 0; r <= cc; ++r)
+            dst[(size_t)cc * (cc + 1) / 2 + r] = 0.5 * (pinv[(size_t)r * ns + cc] + pinv[(size_t)cc * ns + r]);
+      } else {
+        for (int t = 0; t < ns; ++t)
+          for (int u = 0; u < ns; ++u) dst[(size_t)u * ns + t] = pinv[(size_t)t * ns + u];
+      }
     });
     if (bad.load()) return fail(c, BMG_E_SINGULAR, "a patch matrix is singular");
     bmg_status s = upload_converted(c, L.inv[col], reg.data(), reg.size(), c->sprec);
     if (s) return s;
     if (ne > 0) {
-      s = upload_converted(c, L.invx[col], exd.data(), (size_t)ne * nse * nse, c->sprec);
+      s = upload_converted(c, L.invx[col], exd.data(), (size_t)ne * ee, c->sprec);
       if (s) return s;
     }
     HIPCHK(c, hipMemcpy(L.extidx[col], ext.data(), np * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -786,8 +798,9 @@ double colour_bytes(const bmg_ctx* c, int j, int col) {
   const int nsr = nsr_of(K), nse = nse_of(K);
   const double gather = 12.0 * NB + 4.0 * NI + 4.0 * NP + 8.0 * NV + 4.0;
   const double reg = L.npatch[col] - L.next[col], ext = L.next[col];
-  return reg * ((double)nsr * nsr * c->ssize + (gather + 2.0 * nsr) * c->tsize) +
-         ext * ((double)nse * nse * c->ssize + (gather + 2.0 * nse) * c->tsize);
+  // x on the patch is written once (its old values come with the gather)
+  return reg * ((double)inv_entries(K, nsr) * c->ssize + (gather + nsr + (packed_inv(K) ? nsr : 2.0 * nsr)) * c->tsize) +
+         ext * ((double)inv_entries(K, nse) * c->ssize + (gather + nse + (packed_inv(K) ? nse : 2.0 * nse)) * c->tsize);
 }
 
 void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs) {

@@ -376,14 +376,19 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NSR = D::NSR, NSE = D::NSE;
-  constexpr bool PF = (K == 1);
-  constexpr int NT = (NSE + 63) / 64;  // layout entries per lane
+  // RT_1: pseudo-inverses stored as packed upper triangles (symmetric), staged
+  // through LDS for the product; RT_2: full column-major blocks streamed from HBM.
+  constexpr bool PK = (K == 1);
+  constexpr int NPR = NSR * (NSR + 1) / 2, NPE = NSE * (NSE + 1) / 2;
+  constexpr int NQ = PK ? (NPE + 63) / 64 : 1;  // packed entries per lane
+  constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
   __shared__ Elem<T, K> Es;
   __shared__ T xs[4][4][NL];
   __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
                                  //               1: u_y of the cell across the outer vertical face]
   __shared__ T zs[4][4 * NL];
   __shared__ T rs[4][NSE];
+  __shared__ S aps[4][PK ? NPR : 1];
   x += blockIdx.y * ld;
   b += blockIdx.y * ld;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -395,6 +400,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   const int vx = c3x + 3 * (pc % nvx), vy = c3y + 3 * (pc / nvx);
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
+  const int ext = active ? extidx[pc] : -1;
 
   // 0. issue every load that does not depend on the correction: the gather of x
   // (first: it is needed first), the element matrices, b on the patch, then the
@@ -434,7 +440,6 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   }
   const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
                          (vy == N - 1 && !(bcm & 8));
-  const int ext = active ? extidx[pc] : -1;
   int gi[NT], zA[NT], zB[NT];
   T bv[NT];
 #pragma unroll
@@ -451,13 +456,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
   }
-  S areg[PF ? NSR : 1];
-  const bool pre = PF && active && !ext_guess && lane < NSR;
-  if (PF) {
-    const S* A = inv + (size_t)pc * NSR * NSR;
-    const int lc = lane < NSR ? lane : NSR - 1;
+  // packed inverse of this patch: entry i of the upper triangle (column-major,
+  // (r, c) with r <= c at c (c + 1) / 2 + r) in lane i mod 64
+  S apk[NQ];
+  if (PK) {
+    const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NPE : inv + (size_t)pc * NPR;
+    const int np = ext_guess ? NPE : NPR;
 #pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lc];
+    for (int q = 0; q < NQ; ++q) apk[q] = A[min(lane + 64 * q, np - 1)];
   }
 
   // 1. gathered values and element matrices to LDS
@@ -526,24 +532,54 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   // side); setup checks this rule against the patch construction.
   const bool is_ext = ext_guess;
   const int ns = is_ext ? NSE : NSR;
+  T xold[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const int t = lane + 64 * q;
+    xold[q] = T(0);
     if (t < NSE) {
       T r = T(0);
-      if (gi[q] >= 0) r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
+      if (gi[q] >= 0) {
+        r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
+        xold[q] = (&xs[w][0][0])[zA[q]];
+      }
       rs[w][t] = r;
     }
   }
+  // regular packed inverse to LDS (the extended ones are read from HBM below)
+  if (PK && !ext_guess) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+  }
   lds_barrier();
 
-  // 4. correction y = A_S^+ r, x[S] += y
+  // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
   if (!active) return;
-  if (PF && !is_ext && pre) {
-    T acc = T(0);
-#pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
-    if (gi[0] >= 0) x[gi[0]] += acc;
+  if (PK) {
+    // symmetric packed product: row t = column t (rows r <= t contiguous) plus the
+    // entries (t, c), c > t, at c (c + 1) / 2 + t
+    const int t = lane;
+    if (t < ns) {
+      T acc = T(0);
+      if (!is_ext) {
+        const S* Ap = aps[w];
+        const int ct = t * (t + 1) / 2;
+#pragma unroll 8
+        for (int u = 0; u < NSR; ++u) {
+          const int idx = u <= t ? ct + u : u * (u + 1) / 2 + t;
+          acc += T(Ap[idx]) * rs[w][u];
+        }
+      } else {
+        const S* Ap = invx + (size_t)ext * NPE;
+        const int ct = t * (t + 1) / 2;
+        for (int u = 0; u < NSE; ++u) {
+          const int idx = u <= t ? ct + u : u * (u + 1) / 2 + t;
+          acc += T(Ap[idx]) * rs[w][u];
+        }
+      }
+      if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
+    }
     return;
   }
   const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
@@ -554,7 +590,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       T acc = T(0);
 #pragma unroll 8
       for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
-      if (gi[q] >= 0) x[gi[q]] += acc;
+      if (gi[q] >= 0) x[gi[q]] = xold[q] + acc;
     }
   }
 }
