@@ -132,11 +132,16 @@ def main():
                               args.dense_coarse_max)
         s32 = bmg.Solver(p32, w.kappa)
         x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
+        s32.kernel_timing(J, 34 * (max(its32) + 4))
+        s32.solve(b, rtol=args.rtol, maxit=1000)
+        nl32, ms32, by32 = s32.kernel_timing_read()
+        s32.kernel_timing(-1, 0)
         err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
         out["mixed"] = {"value": args.steps / dt32, "unit": "solves/s", "precond": "fp32",
                         "iterations": its32[-1], "true_rel_residual": info32.rel_residual_true,
                         "rel_diff_vs_fp64": err, "speedup_vs_fp64": (args.steps / dt32) / value,
-                        "dof_iters_per_s": ndof * sum(its32) / dt32}
+                        "dof_iters_per_s": ndof * sum(its32) / dt32,
+                        "finest_smoother_gbs": by32 / (ms32 * 1e-3), "finest_smoother_avg_us": ms32 * 1e3 / nl32}
         log(f"bench: FP32 precond {args.steps / dt32:.3f} solves/s, iterations {its32}, diff {err:.1e}")
         del s32
 

@@ -74,7 +74,7 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
                bool residual, int nrhs, int64_t ld, hipStream_t s);
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
-                   bool finest, int nrhs, int64_t ld, hipStream_t s);
+                   bool finest, bool packed, int nrhs, int64_t ld, hipStream_t s);
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
                      int64_t ldf, int64_t ldc, hipStream_t s);
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,

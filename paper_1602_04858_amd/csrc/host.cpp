@@ -446,9 +446,10 @@ size_t xfer_bytes(int K) {
 
 int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
 int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
-// stored entries of one patch pseudo-inverse: RT_1 packed upper triangle, RT_2 full
-bool packed_inv(int k) { return k == 1; }
-int64_t inv_entries(int k, int ns) { return packed_inv(k) ? (int64_t)ns * (ns + 1) / 2 : (int64_t)ns * ns; }
+// Stored entries of one patch pseudo-inverse: packed upper triangle (RT_1 on levels
+// with N >= 192, where the smoother is bandwidth-bound) or full column-major block.
+bool packed_level(int k, int N) { return k == 1 && N >= 192; }
+int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns + 1) / 2 : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
 // dof count is at most dense_coarse_max (0 = none).
@@ -475,8 +476,9 @@ size_t layout(bmg_ctx* c, char* base) {
     L.r = B.take(L.ndof * ts);
     if (j > 0)
       for (int col = 0; col < 9; ++col) {
-        L.inv[col] = B.take((size_t)L.npatch[col] * inv_entries(K, nsr) * ss);
-        L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * inv_entries(K, nse) * ss);
+        const bool pk = packed_level(K, L.N);
+        L.inv[col] = B.take((size_t)L.npatch[col] * inv_entries(pk, nsr) * ss);
+        L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * inv_entries(pk, nse) * ss);
         L.extidx[col] = (int32_t*)B.take((size_t)std::max(L.npatch[col], 1) * sizeof(int32_t));
       }
   }
@@ -739,8 +741,8 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
       if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
     }
-    const int64_t er = inv_entries(c->K, nsr), ee = inv_entries(c->K, nse);
-    const bool pk = packed_inv(c->K);
+    const bool pk = packed_level(c->K, L.N);
+    const int64_t er = inv_entries(pk, nsr), ee = inv_entries(pk, nse);
     std::vector<double> reg((size_t)np * er, 0.0), exd((size_t)std::max(ne, 1) * ee, 0.0);
     std::atomic<int> bad{0};
     parallel_for(np, [&](int p) {
@@ -799,8 +801,9 @@ double colour_bytes(const bmg_ctx* c, int j, int col) {
   const double gather = 12.0 * NB + 4.0 * NI + 4.0 * NP + 8.0 * NV + 4.0;
   const double reg = L.npatch[col] - L.next[col], ext = L.next[col];
   // x on the patch is written once (its old values come with the gather)
-  return reg * ((double)inv_entries(K, nsr) * c->ssize + (gather + nsr + (packed_inv(K) ? nsr : 2.0 * nsr)) * c->tsize) +
-         ext * ((double)inv_entries(K, nse) * c->ssize + (gather + nse + (packed_inv(K) ? nse : 2.0 * nse)) * c->tsize);
+  const bool pk = packed_level(K, L.N);
+  return reg * ((double)inv_entries(pk, nsr) * c->ssize + (gather + 2.0 * nsr) * c->tsize) +
+         ext * ((double)inv_entries(pk, nse) * c->ssize + (gather + 2.0 * nse) * c->tsize);
 }
 
 void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs) {
@@ -813,7 +816,7 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs
       const bool rec = timed && c->ev_used + 2 <= c->ev.size();
       if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
       launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
-                    L.npatch[col], j == (int)c->lev.size() - 1, nrhs, L.ndof, c->stream);
+                    L.npatch[col], j == (int)c->lev.size() - 1, packed_level(c->K, L.N), nrhs, L.ndof, c->stream);
       if (rec) {
         hipEventRecord(c->ev[c->ev_used + 1], c->stream);
         c->ev_used += 2;
@@ -1133,8 +1136,8 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
   launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
-                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1, 1,
-                L.ndof, h->stream);
+                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1,
+                packed_level(h->K, L.N), 1, L.ndof, h->stream);
   launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

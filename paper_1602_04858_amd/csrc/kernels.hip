@@ -367,7 +367,7 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
 // prefetched into registers (RT_1, regular layout), the patch layout is decoded
 // arithmetically and b on the patch is loaded -- so the dependent chain is one
 // gather of x, the local residual in LDS, an FMA chain on registers and the store.
-template <typename T, typename S, int K, int TAG>
+template <typename T, typename S, int K, int TAG, bool PKD>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
@@ -376,9 +376,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NSR = D::NSR, NSE = D::NSE;
-  // RT_1: pseudo-inverses stored as packed upper triangles (symmetric), staged
-  // through LDS for the product; RT_2: full column-major blocks streamed from HBM.
-  constexpr bool PK = (K == 1);
+  // Storage of the pseudo-inverses (chosen per level by the host):
+  //   PK (RT_1, bandwidth-bound levels): packed upper triangles (symmetric), staged
+  //       through LDS for the product;
+  //   PF (RT_1, latency-bound levels): full column-major blocks, the column of this
+  //       lane prefetched into registers;
+  //   otherwise (RT_2): full blocks streamed from HBM in the product.
+  constexpr bool PK = (K == 1) && PKD;
+  constexpr bool PF = (K == 1) && !PKD;
   constexpr int NPR = NSR * (NSR + 1) / 2, NPE = NSE * (NSE + 1) / 2;
   constexpr int NQ = PK ? (NPE + 63) / 64 : 1;  // packed entries per lane
   constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                  //               1: u_y of the cell across the outer vertical face]
   __shared__ T zs[4][4 * NL];
   __shared__ T rs[4][NSE];
-  __shared__ S aps[4][PK ? NPR : 1];
+  __shared__ S aps[4][((K == 1) && PKD) ? NPR : 1];
   x += blockIdx.y * ld;
   b += blockIdx.y * ld;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -458,6 +463,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   }
   // packed inverse of this patch: entry i of the upper triangle (column-major,
   // (r, c) with r <= c at c (c + 1) / 2 + r) in lane i mod 64
+  S areg[PF ? NSR : 1];
+  const bool pre = PF && active && !ext_guess && lane < NSR;
+  if (PF) {
+    const S* A = inv + (size_t)pc * NSR * NSR;
+    const int lc = lane < NSR ? lane : NSR - 1;
+#pragma unroll
+    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lc];
+  }
   S apk[NQ];
   if (PK) {
     const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NPE : inv + (size_t)pc * NPR;
@@ -580,6 +593,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       }
       if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
     }
+    return;
+  }
+  if (PF && !is_ext && pre) {
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
+    if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
     return;
   }
   const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
@@ -965,24 +985,28 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
-                     const int32_t* extidx, int colour, int npatch, bool finest, int nrhs, int64_t ld,
-                     hipStream_t s) {
+                     const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs,
+                     int64_t ld, hipStream_t s) {
   if (npatch <= 0) return;
   dim3 g((npatch + 3) / 4, nrhs), bl(256);
-  if (finest)
-    hipLaunchKernelGGL((k_colour<T, S, K, 1>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch,
-                       ld);
-  else
-    hipLaunchKernelGGL((k_colour<T, S, K, 0>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
-                       (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch,
-                       ld);
+#define BMG_KC(TAG, PKD)                                                                                        \
+  hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h, \
+                     (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch, ld)
+  if (finest) {
+    if (packed) BMG_KC(1, true);
+    else BMG_KC(1, false);
+  } else {
+    if (packed) BMG_KC(0, true);
+    else BMG_KC(0, false);
+  }
+#undef BMG_KC
 }
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
-                   int nrhs, int64_t ld, hipStream_t s) {
-#define BMG_COL(T, S, KK) colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, nrhs, ld, s)
+                   bool packed, int nrhs, int64_t ld, hipStream_t s) {
+#define BMG_COL(T, S, KK) \
+  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, s)
   if (K == 1) {
     if (prec == 0) BMG_COL(double, double, 1);
     else if (sprec == 0) BMG_COL(float, double, 1);

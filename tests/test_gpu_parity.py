@@ -238,3 +238,48 @@ def test_not_converged_status(torch, bmg):
     b = bmg.assemble_rhs(s.params, inputs.constant_source(1.0, 0.0))
     x, info = s.solve(_dev(torch, b), rtol=1e-14, maxit=2)
     assert info.converged == 0 and info.iterations == 2
+
+
+# --------------------------------------------------------------------------
+# Full benchmark size (C2: 256 x 256, 8 levels), launch configuration of bench.py
+# (dense coarse sub-cycle on, graph replay, packed inverses on the finest level)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c2(bmg):
+    w = inputs.workload("C2")
+    o = Oracle.from_workload(w)
+    return w, o
+
+
+def test_c2_finest_colour_steps_and_vcycle(torch, bmg, c2):
+    w, o = c2
+    s = bmg.from_workload(w, restart=100)
+    j = w.levels
+    b = _vec(o, j, 91)
+    x = _vec(o, j, 92)
+    for colour in (0, 4, 8):
+        x_ref = o.colour_step(colour, x, b, j)
+        xg = _np(s.colour_step(j, colour, _dev(torch, x), _dev(torch, b)))
+        assert _rel(xg - x, x_ref - x) < 1e-12, colour
+    r = _vec(o, j, 93, zero_cons=False)
+    z_ref = o.vcycle(r)
+    for rep in range(2):
+        assert _rel(_np(s.vcycle(_dev(torch, r))), z_ref) < 1e-10, rep
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c2_solve_full_size(torch, bmg, c2, prec):
+    w, o = c2
+    s = bmg.from_workload(w, prec=prec, restart=100)
+    b = bmg.assemble_rhs(s.params, w.source)
+    x, info = s.solve(_dev(torch, b), rtol=1e-10, maxit=200)
+    x_ref, its_ref, _, tr_ref = o.fgmres(o.rhs(w.source), rtol=1e-10, maxit=200, restart=100)
+    assert info.converged == 1 and info.rel_residual_true < 2e-10
+    if prec == 0:
+        assert abs(info.iterations - its_ref) <= 1
+        assert _rel(_np(x), x_ref) < 1e-10 * max(1.0, 100 * tr_ref / 1e-10)
+    else:
+        assert info.iterations <= its_ref + 2
+        # both converged to 1e-10: compare against the reference run further down
+        x_tight, _, _, _ = o.fgmres(o.rhs(w.source), rtol=1e-13, maxit=300, restart=100)
+        assert _rel(_np(x), x_tight) < 1e-8
