@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy"],
+                    help="C2 (default, the benchmark configuration) or the 1024^2 precision study")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     args = ap.parse_args()
@@ -87,8 +89,8 @@ def main():
     import torch
     from paper_1602_04858_amd import bmg, inputs
 
-    w = inputs.workload("C2")
-    log(f"bench: workload C2 N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
+    w = inputs.workload(args.workload)
+    log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
     p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
                           args.dense_coarse_max)
     t0 = time.perf_counter()
@@ -119,34 +121,39 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "C2: 256x256 quads, 8 levels (2x2 coarsest), RT_1 x dQ_1 H(div)-DG Brinkman "
-                                  "mu=1e-2, seeded log-normal kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, "
-                                  "f=(1,0), no-slip left/right, open top/bottom; variable V-cycle m=2, "
-                                  "FP64 V-cycle inside FP64 FGMRES(100), rtol 1e-10",
+           "config": {"workload": f"{w.name}: {w.n}x{w.n} quads, {w.levels + 1} levels (2x2 coarsest), RT_1 x dQ_1 "
+                                  f"H(div)-DG {'Darcy' if w.mu == 0 else 'Brinkman'} mu={w.mu:g}, seeded log-normal "
+                                  "kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, f=(1,0), no-slip left/right, "
+                                  "open top/bottom; variable V-cycle m=2, FP64 V-cycle inside FP64 FGMRES(100), "
+                                  "rtol 1e-10",
                       "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol},
            "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
     if not args.no_mixed:
-        p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 100,
-                              args.dense_coarse_max)
-        s32 = bmg.Solver(p32, w.kappa)
-        x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
-        s32.kernel_timing(J, 34 * (max(its32) + 4))
-        s32.solve(b, rtol=args.rtol, maxit=1000)
-        nl32, ms32, by32 = s32.kernel_timing_read()
-        s32.kernel_timing(-1, 0)
-        err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
-        out["mixed"] = {"value": args.steps / dt32, "unit": "solves/s", "precond": "fp32",
+        for key, prec in (("mixed", bmg.P_FP32), ("mixed_bf16", bmg.P_BF16)):
+            p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
+                                  args.dense_coarse_max)
+            s32 = bmg.Solver(p32, w.kappa)
+            x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
+            s32.kernel_timing(J, 34 * (max(its32) + 4))
+            s32.solve(b, rtol=args.rtol, maxit=1000)
+            nl32, ms32, by32 = s32.kernel_timing_read()
+            s32.kernel_timing(-1, 0)
+            err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+            out[key] = {"value": args.steps / dt32, "unit": "solves/s",
+                        "precond": "fp32" if prec == bmg.P_FP32 else "fp32 arithmetic, bf16 patch inverses",
                         "iterations": its32[-1], "true_rel_residual": info32.rel_residual_true,
                         "rel_diff_vs_fp64": err, "speedup_vs_fp64": (args.steps / dt32) / value,
                         "dof_iters_per_s": ndof * sum(its32) / dt32,
                         "finest_smoother_gbs": by32 / (ms32 * 1e-3), "finest_smoother_avg_us": ms32 * 1e3 / nl32}
-        log(f"bench: FP32 precond {args.steps / dt32:.3f} solves/s, iterations {its32}, diff {err:.1e}")
-        del s32
+            log(f"bench: {key} {args.steps / dt32:.3f} solves/s, iterations {its32}, diff {err:.1e}, "
+                f"finest smoother {by32 / (ms32 * 1e-3) / 1e9:.0f} GB/s")
+            s32.close()
+            del s32
 
     out["roofline"] = roof
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "C2":
         log("bench: CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(w, its64[-1], args.cpu_sample_its)
     print(json.dumps(out), flush=True)

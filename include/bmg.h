@@ -60,7 +60,8 @@ typedef enum {
 } bmg_status;
 
 enum { BMG_BC_DIRICHLET = 0, BMG_BC_OPEN = 1 };                 /* sides: 0 x=0, 1 x=1, 2 y=0, 3 y=1 */
-enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1 };                        /* preconditioner arithmetic */
+enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1, BMG_P_BF16 = 2 };        /* preconditioner arithmetic: FP64; FP32;
+                                                                   FP32 with bfloat16-stored patch inverses */
 enum { BMG_CYCLE_STANDARD = 0, BMG_CYCLE_VARIABLE = 1 };        /* m(j) = m_fine or m_fine 2^(J-j), Section 3.2 */
 
 typedef struct {

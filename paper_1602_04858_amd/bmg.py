@@ -21,7 +21,7 @@ if not os.path.exists(LIBPATH):
 _lib = C.CDLL(LIBPATH)
 
 BC_DIRICHLET, BC_OPEN = 0, 1
-P_FP64, P_FP32 = 0, 1
+P_FP64, P_FP32, P_BF16 = 0, 1, 2
 CYCLE_STANDARD, CYCLE_VARIABLE = 0, 1
 
 STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM", 4: "BMG_E_HIP",

@@ -58,9 +58,17 @@ struct Xfer {
 
 // Bit s of a boundary mask: side s (0 x=0, 1 x=1, 2 y=0, 3 y=1) is Dirichlet.
 
+// bfloat16 storage of patch pseudo-inverses: the upper 16 bits of an FP32 value,
+// widened to FP32 on load (arithmetic stays FP32).
+struct bf16 {
+  uint16_t v;
+  __host__ __device__ operator float() const { return __uint_as_float((uint32_t)v << 16); }
+};
+
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip).  prec: 0 = double, 1 = float vectors; sprec: storage
-// of the patch inverses, 0 = double, 1 = float.  All pointers are device pointers.
+// of the patch inverses, 0 = double, 1 = float, 2 = bfloat16.  All pointers are
+// device pointers.
 // ---------------------------------------------------------------------------
 struct LevelArgs {
   int N;

@@ -108,7 +108,8 @@ bmg_status check_params(const bmg_params* p) {
     if (p->bc[s] != BMG_BC_DIRICHLET && p->bc[s] != BMG_BC_OPEN) return BMG_E_ARG;
   if (p->cycle != BMG_CYCLE_STANDARD && p->cycle != BMG_CYCLE_VARIABLE) return BMG_E_ARG;
   if (p->m_fine < 1 || p->m_fine > 64) return BMG_E_ARG;
-  if (p->precond_prec != BMG_P_FP64 && p->precond_prec != BMG_P_FP32) return BMG_E_ARG;
+  if (p->precond_prec != BMG_P_FP64 && p->precond_prec != BMG_P_FP32 && p->precond_prec != BMG_P_BF16)
+    return BMG_E_ARG;
   if (p->restart < 1 || p->restart > 512) return BMG_E_ARG;
   if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
   return BMG_OK;
@@ -561,9 +562,10 @@ int bc_mask(const bmg_params& p) {
 void setup_types(bmg_ctx* c) {
   c->K = c->p.k;
   c->prec = c->p.precond_prec == BMG_P_FP64 ? 0 : 1;
-  c->sprec = c->prec;  // inverses stored in the preconditioner arithmetic
+  // inverses stored in the preconditioner arithmetic, or bfloat16 with FP32 arithmetic
+  c->sprec = c->p.precond_prec == BMG_P_BF16 ? 2 : c->prec;
   c->tsize = c->prec == 0 ? 8 : 4;
-  c->ssize = c->sprec == 0 ? 8 : 4;
+  c->ssize = c->sprec == 0 ? 8 : c->sprec == 1 ? 4 : 2;
   c->bcm = bc_mask(c->p);
 }
 
@@ -624,10 +626,25 @@ bmg_status upload_all_consts(bmg_ctx* c) {
   return s;
 }
 
-// upload a host FP64 array converted to the arithmetic `prec`
+// FP64 -> bfloat16 with round-to-nearest-even (through FP32)
+uint16_t to_bf16(double d) {
+  const float f = (float)d;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan kept
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+// upload a host FP64 array converted to `prec` (0 double, 1 float, 2 bfloat16)
 bmg_status upload_converted(bmg_ctx* c, void* dst, const double* src, size_t n, int prec) {
   if (prec == 0) {
     HIPCHK(c, hipMemcpy(dst, src, n * sizeof(double), hipMemcpyHostToDevice));
+  } else if (prec == 2) {
+    std::vector<uint16_t> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = to_bf16(src[i]);
+    HIPCHK(c, hipMemcpy(dst, tmp.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice));
   } else {
     std::vector<float> tmp(n);
     for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];

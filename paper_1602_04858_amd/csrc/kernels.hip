@@ -1010,11 +1010,13 @@ void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs
   if (K == 1) {
     if (prec == 0) BMG_COL(double, double, 1);
     else if (sprec == 0) BMG_COL(float, double, 1);
-    else BMG_COL(float, float, 1);
+    else if (sprec == 1) BMG_COL(float, float, 1);
+    else BMG_COL(float, bf16, 1);
   } else {
     if (prec == 0) BMG_COL(double, double, 2);
     else if (sprec == 0) BMG_COL(float, double, 2);
-    else BMG_COL(float, float, 2);
+    else if (sprec == 1) BMG_COL(float, float, 2);
+    else BMG_COL(float, bf16, 2);
   }
 #undef BMG_COL
 }

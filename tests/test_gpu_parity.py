@@ -181,9 +181,13 @@ def test_solve_fp64(torch, bmg, case, dense):
 
 @pytest.mark.parametrize("case", CASES[:3], ids=IDS[:3])
 @pytest.mark.parametrize("dense", [0, 16384])
-def test_solve_mixed_precision(torch, bmg, case, dense):
+@pytest.mark.parametrize("prec", [1, 2])
+def test_solve_mixed_precision(torch, bmg, case, dense, prec):
+    """FP32 V-cycle (prec 1) or FP32 with bfloat16-stored patch inverses (prec 2)
+    inside FP64 FGMRES: 1e-10 true residual, <= 1e-8 from the oracle, <= 2 extra
+    iterations."""
     o, s64, _ = _setup(bmg, case, dense=dense)
-    _, s32, _ = _setup(bmg, case, prec=1, dense=dense)
+    _, s32, _ = _setup(bmg, case, prec=prec, dense=dense)
     src = inputs.smooth_source(9)
     b = bmg.assemble_rhs(s64.params, src)
     x64, i64 = s64.solve(_dev(torch, b), rtol=1e-10, maxit=300)
@@ -267,7 +271,7 @@ def test_c2_finest_colour_steps_and_vcycle(torch, bmg, c2):
         assert _rel(_np(s.vcycle(_dev(torch, r))), z_ref) < 1e-10, rep
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_c2_solve_full_size(torch, bmg, c2, prec):
     w, o = c2
     s = bmg.from_workload(w, prec=prec, restart=100)
