@@ -69,6 +69,10 @@ def lib():
             "orc_rhs": (V, [P, _dp, P, P, _dp]),
             "orc_L": (D, [I, D]), "orc_psi": (D, [I, D]),
             "orc_gauss": (V, [I, _dp, _dp]),
+            "orc_level_create": (P, [I, I, D, D, _ip, _dp]),
+            "orc_level_destroy": (V, [P]),
+            "orc_level_ndof": (I, [P]),
+            "orc_level_rows": (V, [P, I, _ip, _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -254,3 +258,25 @@ class Oracle:
         b = np.zeros(self.ndof())
         lib().orc_rhs(self.h, fq, sp_, gp_, b)
         return b
+
+
+class OracleLevel:
+    """One level without hierarchy: sampled rows of A x from the integrals."""
+
+    def __init__(self, n, k, mu, sigma, bc, kappa):
+        self.bc = np.ascontiguousarray(bc, dtype=np.int32)
+        self.h = lib().orc_level_create(n, k, mu, sigma, self.bc, _f64(kappa))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_level_destroy(self.h)
+            self.h = None
+
+    def ndof(self):
+        return lib().orc_level_ndof(self.h)
+
+    def rows(self, rows, x):
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        out = np.zeros(rows.size)
+        lib().orc_level_rows(self.h, rows.size, rows, _f64(x), out)
+        return out

@@ -418,85 +418,93 @@ void face_terms(const Level& L, const FaceSide* sides, int nsides, const double 
     }
 }
 
-void assemble(Level& L) {
+// Cell integrals of one cell: mu (grad u, grad v) + (kappa u, v) - (p, div v) - (q, div u).
+void cell_terms(const Level& L, int cx, int cy, std::vector<Trip>& t) {
   const int N = L.N, q = L.k + 2, nl = L.nloc;
   Rule r = gauss01(q);
-  std::vector<Trip> t;
-  t.reserve((size_t)N * N * nl * nl / 2);
-  // cell integrals: mu (grad u, grad v) + (kappa u, v) - (p, div v) - (q, div u)
   std::vector<BVal> bv((size_t)nl * q * q);
-  for (int cy = 0; cy < N; ++cy)
-    for (int cx = 0; cx < N; ++cx) {
-      double kap = L.kappa[cy * N + cx];
-      for (int l = 0; l < nl; ++l)
-        for (int iy = 0; iy < q; ++iy)
-          for (int ix = 0; ix < q; ++ix)
-            bv[((size_t)l * q + iy) * q + ix] = eval_fn(L, l, r.x[ix], r.x[iy], L.h);
-      for (int i = 0; i < nl; ++i)
-        for (int j = 0; j < nl; ++j) {
-          const LocalFn &fi = L.loc[i], &fj = L.loc[j];
-          double s = 0.0;
-          for (int iy = 0; iy < q; ++iy)
-            for (int ix = 0; ix < q; ++ix) {
-              const BVal& bi = bv[((size_t)i * q + iy) * q + ix];
-              const BVal& bj = bv[((size_t)j * q + iy) * q + ix];
-              double w = r.w[ix] * r.w[iy] * L.h * L.h;
-              double val = 0.0;
-              if (fi.kind < 2 && fj.kind < 2) {
-                double gg = 0.0, vv = 0.0;
-                for (int c = 0; c < 2; ++c) {
-                  vv += bi.v[c] * bj.v[c];
-                  for (int d = 0; d < 2; ++d) gg += bi.g[c][d] * bj.g[c][d];
-                }
-                val = L.mu * gg + kap * vv;
-              } else if (fi.kind == 2 && fj.kind < 2) {
-                val = -bi.p * bj.div;
-              } else if (fi.kind < 2 && fj.kind == 2) {
-                val = -bj.p * bi.div;
-              }
-              s += w * val;
+  double kap = L.kappa[cy * N + cx];
+  for (int l = 0; l < nl; ++l)
+    for (int iy = 0; iy < q; ++iy)
+      for (int ix = 0; ix < q; ++ix)
+        bv[((size_t)l * q + iy) * q + ix] = eval_fn(L, l, r.x[ix], r.x[iy], L.h);
+  for (int i = 0; i < nl; ++i)
+    for (int j = 0; j < nl; ++j) {
+      const LocalFn &fi = L.loc[i], &fj = L.loc[j];
+      double s = 0.0;
+      for (int iy = 0; iy < q; ++iy)
+        for (int ix = 0; ix < q; ++ix) {
+          const BVal& bi = bv[((size_t)i * q + iy) * q + ix];
+          const BVal& bj = bv[((size_t)j * q + iy) * q + ix];
+          double w = r.w[ix] * r.w[iy] * L.h * L.h;
+          double val = 0.0;
+          if (fi.kind < 2 && fj.kind < 2) {
+            double gg = 0.0, vv = 0.0;
+            for (int c = 0; c < 2; ++c) {
+              vv += bi.v[c] * bj.v[c];
+              for (int d = 0; d < 2; ++d) gg += bi.g[c][d] * bj.g[c][d];
             }
-          if (s != 0.0) t.push_back({global_of(L, cx, cy, i), global_of(L, cx, cy, j), s});
+            val = L.mu * gg + kap * vv;
+          } else if (fi.kind == 2 && fj.kind < 2) {
+            val = -bi.p * bj.div;
+          } else if (fi.kind < 2 && fj.kind == 2) {
+            val = -bj.p * bi.div;
+          }
+          s += w * val;
         }
+      if (s != 0.0) t.push_back({global_of(L, cx, cy, i), global_of(L, cx, cy, j), s});
     }
-  // interior faces: jump, average and penalty terms; T1 = smaller cell index
-  if (L.mu != 0.0) {
-    for (int cy = 0; cy < N; ++cy)
-      for (int i = 1; i < N; ++i) {  // vertical faces, normal +x
-        FaceSide s[2] = {{i - 1, cy, 1.0, 0.0, true}, {i, cy, 0.0, 0.0, true}};
-        double n[2] = {1.0, 0.0};
-        face_terms(L, s, 2, n, t);
-      }
-    for (int j = 1; j < N; ++j)
-      for (int cx = 0; cx < N; ++cx) {  // horizontal faces, normal +y
-        FaceSide s[2] = {{cx, j - 1, 0.0, 1.0, false}, {cx, j, 0.0, 0.0, false}};
-        double n[2] = {0.0, 1.0};
-        face_terms(L, s, 2, n, t);
-      }
-    // Dirichlet boundary faces: {v} = [v] = v, outward normal
-    for (int c = 0; c < N; ++c) {
-      if (L.bc[0] == BC_DIRICHLET) {
-        FaceSide s = {0, c, 0.0, 0.0, true};
-        double n[2] = {-1.0, 0.0};
-        face_terms(L, &s, 1, n, t);
-      }
-      if (L.bc[1] == BC_DIRICHLET) {
-        FaceSide s = {N - 1, c, 1.0, 0.0, true};
-        double n[2] = {1.0, 0.0};
-        face_terms(L, &s, 1, n, t);
-      }
-      if (L.bc[2] == BC_DIRICHLET) {
-        FaceSide s = {c, 0, 0.0, 0.0, false};
-        double n[2] = {0.0, -1.0};
-        face_terms(L, &s, 1, n, t);
-      }
-      if (L.bc[3] == BC_DIRICHLET) {
-        FaceSide s = {c, N - 1, 0.0, 1.0, false};
-        double n[2] = {0.0, 1.0};
-        face_terms(L, &s, 1, n, t);
-      }
+}
+
+// Face integrals of one face: vertical face (i, row c) if vertical, horizontal face
+// (column c, j = i) otherwise; interior faces and Dirichlet boundary faces.
+void one_face(const Level& L, bool vertical, int i, int c, std::vector<Trip>& t) {
+  const int N = L.N;
+  if (L.mu == 0.0) return;
+  if (vertical) {
+    if (i > 0 && i < N) {
+      FaceSide sd[2] = {{i - 1, c, 1.0, 0.0, true}, {i, c, 0.0, 0.0, true}};
+      double n[2] = {1.0, 0.0};
+      face_terms(L, sd, 2, n, t);
+    } else if (i == 0 && L.bc[0] == BC_DIRICHLET) {
+      FaceSide sd = {0, c, 0.0, 0.0, true};
+      double n[2] = {-1.0, 0.0};
+      face_terms(L, &sd, 1, n, t);
+    } else if (i == N && L.bc[1] == BC_DIRICHLET) {
+      FaceSide sd = {N - 1, c, 1.0, 0.0, true};
+      double n[2] = {1.0, 0.0};
+      face_terms(L, &sd, 1, n, t);
+    }
+  } else {
+    if (i > 0 && i < N) {
+      FaceSide sd[2] = {{c, i - 1, 0.0, 1.0, false}, {c, i, 0.0, 0.0, false}};
+      double n[2] = {0.0, 1.0};
+      face_terms(L, sd, 2, n, t);
+    } else if (i == 0 && L.bc[2] == BC_DIRICHLET) {
+      FaceSide sd = {c, 0, 0.0, 0.0, false};
+      double n[2] = {0.0, -1.0};
+      face_terms(L, &sd, 1, n, t);
+    } else if (i == N && L.bc[3] == BC_DIRICHLET) {
+      FaceSide sd = {c, N - 1, 0.0, 1.0, false};
+      double n[2] = {0.0, 1.0};
+      face_terms(L, &sd, 1, n, t);
     }
   }
+}
+
+void assemble(Level& L) {
+  const int N = L.N, nl = L.nloc;
+  std::vector<Trip> t;
+  t.reserve((size_t)N * N * nl * nl / 2);
+  for (int cy = 0; cy < N; ++cy)
+    for (int cx = 0; cx < N; ++cx) cell_terms(L, cx, cy, t);
+  // faces: jump, average and penalty terms (T1 = smaller cell index); Dirichlet
+  // boundary faces with {v} = [v] = v and the outward normal
+  for (int c = 0; c < N; ++c)
+    for (int i = 0; i <= N; ++i) {
+      one_face(L, true, i, c, t);
+      one_face(L, false, i, c, t);
+    }
   L.Afull = from_triplets(L.ndof, L.ndof, t);
   // essential normal condition: identity rows and columns for constrained dofs
   std::vector<Trip> te;
@@ -1075,6 +1083,67 @@ void orc_rhs(void* p, const double* f_qp, const double* s_qp, const double* g_qp
     for (int e = L.Afull.rp[i]; e < L.Afull.rp[i + 1]; ++e)
       if (L.cons[L.Afull.ci[e]]) s += L.Afull.v[e] * uc[L.Afull.ci[e]];
     b[i] = bb[i] - s;
+  }
+}
+
+// One level without hierarchy or stored matrix: rows of A x computed from the cell
+// and face integrals touching each requested row (check of large results).
+void* orc_level_create(int N, int k, double mu, double sigma, const int* bc, const double* kappa) {
+  Level* L = new Level();
+  init_level(*L, N, k, mu, sigma, bc);
+  L->kappa.assign(kappa, kappa + (size_t)N * N);
+  return L;
+}
+void orc_level_destroy(void* p) { delete static_cast<Level*>(p); }
+int orc_level_ndof(void* p) { return static_cast<Level*>(p)->ndof; }
+
+void orc_level_rows(void* p, int nrows, const int* rows, const double* x, double* out) {
+  const Level& L = *static_cast<Level*>(p);
+  const int N = L.N, nb = L.nb;
+  const int nxf = N * (N + 1) * nb, n_int = 2 * N * (N + 1) * nb;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int r = 0; r < nrows; ++r) {
+    const int g = rows[r];
+    if (L.cons[g]) {
+      out[r] = x[g];
+      continue;
+    }
+    // cells whose basis functions can couple to dof g: its support cells
+    std::vector<std::pair<int, int>> cells;
+    if (g < nxf) {
+      int f = g / nb, i = f % (N + 1), cy = f / (N + 1);
+      if (i > 0) cells.push_back({i - 1, cy});
+      if (i < N) cells.push_back({i, cy});
+    } else if (g < n_int) {
+      int f = (g - nxf) / nb, cx = f % N, j = f / N;
+      if (j > 0) cells.push_back({cx, j - 1});
+      if (j < N) cells.push_back({cx, j});
+    } else if (g < L.n_u) {
+      int c = (g - n_int) / (2 * L.k * nb);
+      cells.push_back({c % N, c / N});
+    } else {
+      int c = (g - L.n_u) / L.np;
+      cells.push_back({c % N, c / N});
+    }
+    std::vector<Trip> t;
+    std::vector<std::pair<int, int>> faces;  // (vertical?, face id)
+    for (auto& cc : cells) {
+      cell_terms(L, cc.first, cc.second, t);
+      faces.push_back({1, cc.second * (N + 1) + cc.first});
+      faces.push_back({1, cc.second * (N + 1) + cc.first + 1});
+      faces.push_back({0, cc.first * (N + 1) + cc.second});
+      faces.push_back({0, cc.first * (N + 1) + cc.second + 1});
+    }
+    std::sort(faces.begin(), faces.end());
+    faces.erase(std::unique(faces.begin(), faces.end()), faces.end());
+    for (auto& f : faces) {
+      if (f.first) one_face(L, true, f.second % (N + 1), f.second / (N + 1), t);
+      else one_face(L, false, f.second % (N + 1), f.second / (N + 1), t);
+    }
+    double s = 0.0;
+    for (auto& e : t)
+      if (e.i == g && !L.cons[e.j]) s += e.v * x[e.j];
+    out[r] = s;
   }
 }
 

@@ -287,3 +287,41 @@ def test_c2_solve_full_size(torch, bmg, c2, prec):
         # both converged to 1e-10: compare against the reference run further down
         x_tight, _, _, _ = o.fgmres(o.rhs(w.source), rtol=1e-13, maxit=300, restart=100)
         assert _rel(_np(x), x_tight) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# C3 (1024 x 1024, 10 levels): too large for the oracle's hierarchy; checked by
+# sampled operator rows from the oracle's integrals, the FP64 true residual, and
+# the mixed-precision solutions against the FP64 one
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["C3", "C3darcy"])
+def test_c3_full_size(torch, bmg, name):
+    from oracle import OracleLevel
+    w = inputs.workload(name)
+    s64 = bmg.from_workload(w, restart=60)
+    b = bmg.assemble_rhs(s64.params, w.source)
+    bd = _dev(torch, b)
+    # operator rows at full size
+    rng = np.random.default_rng(17)
+    lv = OracleLevel(w.n, w.k, w.mu, w.sigma, list(w.bc), w.kappa)
+    xr = rng.standard_normal(s64.ndof())
+    rows = rng.choice(s64.ndof(), 3000, replace=False)
+    y = _np(s64.apply(_dev(torch, xr)))
+    yr = lv.rows(rows, xr)
+    assert np.abs(y[rows] - yr).max() <= 1e-13 * np.abs(yr).max()
+    # FP64 solve
+    x64, i64 = s64.solve(bd, rtol=1e-10, maxit=300)
+    assert i64.converged == 1 and i64.rel_residual_true < 2e-10
+    x64n = _np(x64)
+    r_rows = b[rows] - lv.rows(rows, x64n)
+    assert np.abs(r_rows).max() <= 1e-8 * np.abs(b).max()
+    ref, _ = s64.solve(bd, rtol=1e-13, maxit=400)
+    ref = _np(ref)
+    del s64
+    for prec in (1, 2):
+        s = bmg.from_workload(w, prec=prec, restart=60)
+        x, info = s.solve(bd, rtol=1e-10, maxit=300)
+        assert info.converged == 1 and info.rel_residual_true < 2e-10, prec
+        assert info.iterations <= i64.iterations + 2, (prec, info.iterations, i64.iterations)
+        assert _rel(_np(x), ref) < 1e-8, prec
+        del s

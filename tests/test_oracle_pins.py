@@ -453,3 +453,18 @@ def test_standard_vs_variable_cycle_both_converge():
         b = o.rhs(w.source)
         x, its, hist, tr = o.fgmres(b, rtol=1e-10, maxit=300)
         assert its > 0 and tr < 1e-9
+
+
+@pytest.mark.parametrize("k,bc", [(1, [D, D, O, O]), (2, [D, D, D, D]), (1, [O, D, O, D])])
+def test_sampled_rows_equal_assembled_operator(k, bc):
+    """The row sampler (used to check results too large for the hierarchy) gives the
+    same rows as the assembled level operator."""
+    from oracle import OracleLevel
+    n = 16
+    kap = inputs.kappa_random_cells(n, 31, 1e-4, 1.0)
+    o = Oracle(2, 3, k, 1e-2, 6.0 * (k + 1) * (k + 2) / 6, bc, kap, 1, 2)
+    lv = OracleLevel(n, k, 1e-2, 6.0 * (k + 1) * (k + 2) / 6, bc, kap)
+    x = np.random.default_rng(4).standard_normal(o.ndof())
+    y = o.apply(x)
+    rows = np.arange(o.ndof())
+    assert np.abs(lv.rows(rows, x) - y).max() <= 1e-14 * np.abs(y).max()
