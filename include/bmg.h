@@ -117,8 +117,11 @@ bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x_dev, double* y
 bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
 
 /* Solve A_J x = b by right-preconditioned flexible GMRES(restart) in FP64 with B_J
- * as preconditioner (Section 3.2), until ||b - A x||_2 <= rtol ||b||_2 by the
- * Arnoldi estimate (Section 4.1 stopping rule with rtol as given).
+ * as preconditioner (Section 3.2), until ||b - A x||_2 <= rtol ||b||_2 (Section 4.1
+ * stopping rule with rtol as given).  A cycle ends when the Arnoldi estimate reaches
+ * rtol; the next cycle starts from the true residual, which decides convergence
+ * (iterative refinement); a cycle that fails to halve the true residual ends the
+ * solve with BMG_E_NOT_CONVERGED (attainable accuracy reached).
  *   b_dev: the algebraic right-hand side (n_u + n_p doubles, canonical layout),
  *          e.g. from bmg_assemble_rhs; x_dev: the solution; x0_dev: initial guess
  *          or NULL for zero.  Returns BMG_E_NOT_CONVERGED with the last iterate

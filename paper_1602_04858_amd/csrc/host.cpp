@@ -1236,6 +1236,11 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
   bool conv = false;
   double est = 1.0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // Each restart cycle starts from the true residual, so convergence is confirmed on
+  // ||b - A x|| itself (iterative refinement when the Arnoldi estimate has drifted
+  // from it); a cycle that does not halve the true residual ends the solve.
+  double prev_beta = -1.0;
+  bool stalled = false;
   while (!conv && its < maxit) {
     // r = b - A x
     apply_op64(h, J, x, h->ax);
@@ -1249,6 +1254,11 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       conv = true;
       break;
     }
+    if (prev_beta >= 0.0 && beta > 0.5 * prev_beta) {
+      stalled = true;
+      break;
+    }
+    prev_beta = beta;
     hh[0] = beta;
     HIPCHK(h, hipMemcpyAsync(hd + 2 * (m + 2), hh.data(), sizeof(double), hipMemcpyHostToDevice, s));
     launch_scale(h->V, h->rr, hd + 2 * (m + 2), false, n, s);
@@ -1288,8 +1298,7 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       ++its;
       est = std::fabs(g[i + 1]) / bnorm;
       if (std::fabs(g[i + 1]) <= rtol * bnorm || hn == 0.0) {
-        conv = true;
-        ++i;
+        ++i;  // confirmed on the true residual by the next cycle
         break;
       }
       if (i + 1 < m) launch_scale(h->V + (size_t)(i + 1) * n, h->w, hd + 2 * (m + 2), true, n, s);
@@ -1315,7 +1324,9 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
     info->rel_residual_estimate = est;
     info->rel_residual_true = std::sqrt(hh[0]) / bnorm;
   }
-  return conv ? BMG_OK : fail(h, BMG_E_NOT_CONVERGED, "maxit reached");
+  return conv ? BMG_OK
+              : fail(h, BMG_E_NOT_CONVERGED,
+                     stalled ? "true residual stagnates above rtol (attainable accuracy reached)" : "maxit reached");
 }
 
 bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy) {

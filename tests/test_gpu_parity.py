@@ -309,19 +309,19 @@ def test_c3_full_size(torch, bmg, name):
     y = _np(s64.apply(_dev(torch, xr)))
     yr = lv.rows(rows, xr)
     assert np.abs(y[rows] - yr).max() <= 1e-13 * np.abs(yr).max()
-    # FP64 solve
+    # FP64 solve (convergence is confirmed on the true residual)
     x64, i64 = s64.solve(bd, rtol=1e-10, maxit=300)
-    assert i64.converged == 1 and i64.rel_residual_true < 2e-10
+    assert i64.converged == 1 and i64.rel_residual_true <= 1e-10
     x64n = _np(x64)
     r_rows = b[rows] - lv.rows(rows, x64n)
     assert np.abs(r_rows).max() <= 1e-8 * np.abs(b).max()
-    ref, _ = s64.solve(bd, rtol=1e-13, maxit=400)
+    ref, iref = s64.solve(bd, rtol=1e-12, maxit=400)
     ref = _np(ref)
     del s64
     for prec in (1, 2):
         s = bmg.from_workload(w, prec=prec, restart=60)
         x, info = s.solve(bd, rtol=1e-10, maxit=300)
-        assert info.converged == 1 and info.rel_residual_true < 2e-10, prec
+        assert info.converged == 1 and info.rel_residual_true <= 1e-10, prec
         assert info.iterations <= i64.iterations + 2, (prec, info.iterations, i64.iterations)
         assert _rel(_np(x), ref) < 1e-8, prec
         del s
