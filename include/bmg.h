@@ -120,8 +120,8 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
  * as preconditioner (Section 3.2), until ||b - A x||_2 <= rtol ||b||_2 (Section 4.1
  * stopping rule with rtol as given).  A cycle ends when the Arnoldi estimate reaches
  * rtol; the next cycle starts from the true residual, which decides convergence
- * (iterative refinement); a cycle that fails to halve the true residual ends the
- * solve with BMG_E_NOT_CONVERGED (attainable accuracy reached).
+ * (iterative refinement); a cycle that reduces the true residual by less than 10%
+ * ends the solve with BMG_E_NOT_CONVERGED (attainable accuracy reached).
  *   b_dev: the algebraic right-hand side (n_u + n_p doubles, canonical layout),
  *          e.g. from bmg_assemble_rhs; x_dev: the solution; x0_dev: initial guess
  *          or NULL for zero.  Returns BMG_E_NOT_CONVERGED with the last iterate

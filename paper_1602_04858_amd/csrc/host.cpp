@@ -1238,7 +1238,7 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   // Each restart cycle starts from the true residual, so convergence is confirmed on
   // ||b - A x|| itself (iterative refinement when the Arnoldi estimate has drifted
-  // from it); a cycle that does not halve the true residual ends the solve.
+  // from it); a cycle that reduces the true residual by less than 10% ends the solve.
   double prev_beta = -1.0;
   bool stalled = false;
   while (!conv && its < maxit) {
@@ -1254,7 +1254,7 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       conv = true;
       break;
     }
-    if (prev_beta >= 0.0 && beta > 0.5 * prev_beta) {
+    if (prev_beta >= 0.0 && beta > 0.9 * prev_beta) {
       stalled = true;
       break;
     }
