@@ -79,6 +79,9 @@ def main():
                     help="C2 (default, the benchmark configuration) or the 1024^2 precision study")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known "
+                         "size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -88,6 +91,16 @@ def main():
     import numpy as np
     import torch
     from paper_1602_04858_amd import bmg, inputs
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 17  # float64 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration, 3 copies of {args.copy_calibration} MiB")
+        del src, dst
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
@@ -106,7 +119,7 @@ def main():
 
     # roofline of the finest-level smoother kernel: events around its launches
     J = w.levels
-    s64.kernel_timing(J, 34 * (max(its64) + 4))
+    s64.kernel_timing(J, 34 * (max(its64) + 4))  # launches of the finest smoother in one solve
     s64.solve(b, rtol=args.rtol, maxit=1000)
     nl, ms, by = s64.kernel_timing_read()
     s64.kernel_timing(-1, 0)

@@ -174,12 +174,15 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc_dev, do
 bmg_status bmg_coarse_solve(bmg_handle h, const double* b_dev, double* x_dev);
 
 /* ----- measurement ----- */
-/* Record HIP events around each colour launch of the smoother on `level` (>= 1),
- * for at most max_launches launches from now on (-1 switches timing off).  The
- * events are recorded on the handle's stream between kernels. */
+/* Record HIP events around the colour launches of the smoother on `level` (>= 1),
+ * for at most max_launches launches from now on (-1 switches timing off).  One
+ * event pair brackets the 17 back-to-back launches of each smoothing step (so the
+ * timed span holds the 16 short gaps between them); the events are recorded on
+ * the handle's stream, and V-cycles run without the graph while timing is on. */
 bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches);
-/* Launches timed so far, their summed duration and the bytes they had to move
- * (stored patch pseudo-inverses + gathered and scattered vector entries). */
+/* Launches timed so far, the summed duration of the bracketed spans and the bytes
+ * the launches had to move (stored patch pseudo-inverses + gathered and scattered
+ * vector entries). */
 bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes);
 
 const char* bmg_status_string(bmg_status s);

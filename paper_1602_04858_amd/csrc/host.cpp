@@ -72,6 +72,7 @@ struct bmg_ctx {
   int timing_level = -1;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
+  int64_t timed_launches = 0;
   double timed_bytes = 0.0;
   std::string err;
 };
@@ -447,10 +448,11 @@ size_t xfer_bytes(int K) {
 
 int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
 int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
-// Stored entries of one patch pseudo-inverse: packed upper triangle (RT_1 on levels
-// with N >= 192, where the smoother is bandwidth-bound) or full column-major block.
+// Stored entries of one patch pseudo-inverse: rotated symmetric block (RT_1 on levels
+// with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
+// mod n] for d = 0 .. n/2, n even) or full column-major block.
 bool packed_level(int k, int N) { return k == 1 && N >= 192; }
-int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns + 1) / 2 : (int64_t)ns * ns; }
+int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
 // dof count is at most dense_coarse_max (0 = none).
@@ -775,10 +777,12 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       double* dst = isx ? &exd[(size_t)ext[p] * ee] : &reg[(size_t)p * er];
       const int ns = P.ns;
       if (pk) {
-        // symmetric: upper triangle of (A+ + A+^T)/2, column-major packed
-        for (int cc = 0; cc < ns; ++cc)
-          for (int r = 0; r <= cc; ++r)
-            dst[(size_t)cc * (cc + 1) / 2 + r] = 0.5 * (pinv[(size_t)r * ns + cc] + pinv[(size_t)cc * ns + r]);
+        // rotated diagonals of the symmetrised (A+ + A+^T)/2
+        for (int d = 0; d <= ns / 2; ++d)
+          for (int t = 0; t < ns; ++t) {
+            const int u = (t + d) % ns;
+            dst[(size_t)d * ns + t] = 0.5 * (pinv[(size_t)t * ns + u] + pinv[(size_t)u * ns + t]);
+          }
       } else {
         for (int t = 0; t < ns; ++t)
           for (int u = 0; u < ns; ++u) dst[(size_t)u * ns + t] = pinv[(size_t)t * ns + u];
@@ -827,19 +831,23 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs
   LevelInfo& L = c->lev[j];
   LevelArgs a = largs(c, j, c->prec == 0);
   const bool timed = (c->timing_level == j);
-  for (int st = 0; st < steps; ++st)
+  for (int st = 0; st < steps; ++st) {
+    // one event pair around the 17 back-to-back launches of a smoothing step, so
+    // that no marker sits between two colour kernels
+    const bool rec = timed && c->ev_used + 2 <= c->ev.size();
+    if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
     for (int i = 0; i < 17; ++i) {
       const int col = i < 9 ? i : 16 - i;
-      const bool rec = timed && c->ev_used + 2 <= c->ev.size();
-      if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
       launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
                     L.npatch[col], j == (int)c->lev.size() - 1, packed_level(c->K, L.N), nrhs, L.ndof, c->stream);
-      if (rec) {
-        hipEventRecord(c->ev[c->ev_used + 1], c->stream);
-        c->ev_used += 2;
-        c->timed_bytes += colour_bytes(c, j, col) * nrhs;
-      }
+      if (rec) c->timed_bytes += colour_bytes(c, j, col) * nrhs;
     }
+    if (rec) {
+      hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+      c->ev_used += 2;
+      c->timed_launches += 17;
+    }
+  }
 }
 
 int smoothing_steps(const bmg_ctx* c, int j) {
@@ -1086,10 +1094,11 @@ bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) 
   for (auto e : h->ev) hipEventDestroy(e);
   h->ev.clear();
   h->ev_used = 0;
+  h->timed_launches = 0;
   h->timed_bytes = 0.0;
   h->timing_level = level;
   if (level < 0) return BMG_OK;
-  h->ev.resize((size_t)2 * max_launches);
+  h->ev.resize((size_t)2 * ((max_launches + 16) / 17));
   for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   return BMG_OK;
 }
@@ -1103,7 +1112,7 @@ bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total
     HIPCHK(h, hipEventElapsedTime(&t, h->ev[i], h->ev[i + 1]));
     ms += t;
   }
-  *launches = (int32_t)(h->ev_used / 2);
+  *launches = (int32_t)h->timed_launches;
   *total_ms = ms;
   *bytes = h->timed_bytes;
   return BMG_OK;

@@ -377,15 +377,17 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NSR = D::NSR, NSE = D::NSE;
   // Storage of the pseudo-inverses (chosen per level by the host):
-  //   PK (RT_1, bandwidth-bound levels): packed upper triangles (symmetric), staged
-  //       through LDS for the product;
+  //   PK (RT_1, bandwidth-bound levels): symmetric "rotated diagonal" blocks,
+  //       R[d n + t] = A+[t][(t + d) mod n] for d = 0 .. n/2 (n (n/2 + 1) entries,
+  //       about half the full block), staged through LDS for the product;
   //   PF (RT_1, latency-bound levels): full column-major blocks, the column of this
   //       lane prefetched into registers;
   //   otherwise (RT_2): full blocks streamed from HBM in the product.
   constexpr bool PK = (K == 1) && PKD;
   constexpr bool PF = (K == 1) && !PKD;
-  constexpr int NPR = NSR * (NSR + 1) / 2, NPE = NSE * (NSE + 1) / 2;
-  constexpr int NQ = PK ? (NPE + 63) / 64 : 1;  // packed entries per lane
+  constexpr int NPR = NSR * (NSR / 2 + 1), NPE = NSE * (NSE / 2 + 1);  // rotated entries
+  static_assert(NSR % 2 == 0 && NSE % 2 == 0, "rotated storage needs an even patch size");
+  constexpr int NQ = PK ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
   constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
   __shared__ Elem<T, K> Es;
   __shared__ T xs[4][4][NL];
@@ -461,8 +463,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
   }
-  // packed inverse of this patch: entry i of the upper triangle (column-major,
-  // (r, c) with r <= c at c (c + 1) / 2 + r) in lane i mod 64
+  // PF: this lane's column of the full inverse; PK: rotated entry i in lane i mod 64
   S areg[PF ? NSR : 1];
   const bool pre = PF && active && !ext_guess && lane < NSR;
   if (PF) {
@@ -473,10 +474,11 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   }
   S apk[NQ];
   if (PK) {
-    const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NPE : inv + (size_t)pc * NPR;
-    const int np = ext_guess ? NPE : NPR;
+    // the regular slot exists for every patch; extended patches read their own
+    // inverse from HBM in the product
+    const S* A = inv + (size_t)pc * NPR;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) apk[q] = A[min(lane + 64 * q, np - 1)];
+    for (int q = 0; q < NQ; ++q) apk[q] = A[min(lane + 64 * q, NPR - 1)];
   }
 
   // 1. gathered values and element matrices to LDS
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       rs[w][t] = r;
     }
   }
-  // regular packed inverse to LDS (the extended ones are read from HBM below)
+  // regular rotated inverse to LDS (the extended ones are read from HBM below)
   if (PK && !ext_guess) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -570,25 +572,39 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
   if (!active) return;
   if (PK) {
-    // symmetric packed product: row t = column t (rows r <= t contiguous) plus the
-    // entries (t, c), c > t, at c (c + 1) / 2 + t
+    // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
+    //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
+    // consecutive lanes read consecutive entries, so the LDS reads are conflict-free
     const int t = lane;
     if (t < ns) {
       T acc = T(0);
       if (!is_ext) {
-        const S* Ap = aps[w];
-        const int ct = t * (t + 1) / 2;
-#pragma unroll 8
-        for (int u = 0; u < NSR; ++u) {
-          const int idx = u <= t ? ct + u : u * (u + 1) / 2 + t;
-          acc += T(Ap[idx]) * rs[w][u];
+        const S* Rp = aps[w];
+#pragma unroll
+        for (int d = 0; d <= NSR / 2; ++d) {
+          int u = t + d;
+          u -= u >= NSR ? NSR : 0;
+          acc += T(Rp[d * NSR + t]) * rs[w][u];
+        }
+#pragma unroll
+        for (int d = 1; d < NSR / 2; ++d) {
+          int u = t - d;
+          u += u < 0 ? NSR : 0;
+          acc += T(Rp[d * NSR + u]) * rs[w][u];
         }
       } else {
-        const S* Ap = invx + (size_t)ext * NPE;
-        const int ct = t * (t + 1) / 2;
-        for (int u = 0; u < NSE; ++u) {
-          const int idx = u <= t ? ct + u : u * (u + 1) / 2 + t;
-          acc += T(Ap[idx]) * rs[w][u];
+        const S* Rp = invx + (size_t)ext * NPE;
+#pragma unroll 4
+        for (int d = 0; d <= NSE / 2; ++d) {
+          int u = t + d;
+          u -= u >= NSE ? NSE : 0;
+          acc += T(Rp[d * NSE + t]) * rs[w][u];
+        }
+#pragma unroll 4
+        for (int d = 1; d < NSE / 2; ++d) {
+          int u = t - d;
+          u += u < 0 ? NSE : 0;
+          acc += T(Rp[d * NSE + u]) * rs[w][u];
         }
       }
       if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
