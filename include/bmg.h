@@ -78,6 +78,9 @@ typedef struct {
   int32_t dense_coarse_max; /* 0..65535: the finest level jc >= 1 with at most this many dofs has its whole
                                sub-cycle B_jc (the same linear operator, Section 3.2) precomputed at setup
                                and applied as one dense matrix-vector product; 0 = none */
+  int32_t n_rhs;         /* right-hand sides solved together, 1..16 (0 is read as 1).  Every vector
+                            argument of a handle call then holds n_rhs columns of the level's ndof
+                            entries, column r at offset r * ndof (column-major, contiguous) */
 } bmg_params;
 
 typedef struct {
@@ -109,11 +112,11 @@ bmg_status bmg_destroy(bmg_handle h);
 bmg_status bmg_sizes(bmg_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p);
 
 /* y = A_j x, the saddle-point operator of level j (eq. Brinkman-weak) in FP64;
- * rows of the essential (constrained) normal dofs are the identity. */
+ * rows of the essential (constrained) normal dofs are the identity.  n_rhs columns. */
 bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x_dev, double* y_dev);
 
 /* z = B_J r: one V-cycle (Section 3.2) in the handle's preconditioner arithmetic,
- * FP64 in and out, canonical layout of the finest level. */
+ * FP64 in and out, canonical layout of the finest level, n_rhs columns. */
 bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
 
 /* Solve A_J x = b by right-preconditioned flexible GMRES(restart) in FP64 with B_J
@@ -122,10 +125,16 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
  * rtol; the next cycle starts from the true residual, which decides convergence
  * (iterative refinement); a cycle that reduces the true residual by less than 10%
  * ends the solve with BMG_E_NOT_CONVERGED (attainable accuracy reached).
- *   b_dev: the algebraic right-hand side (n_u + n_p doubles, canonical layout),
- *          e.g. from bmg_assemble_rhs; x_dev: the solution; x0_dev: initial guess
- *          or NULL for zero.  Returns BMG_E_NOT_CONVERGED with the last iterate
- *          if maxit iterations did not reach rtol; info may be NULL. */
+ * With n_rhs > 1 every right-hand side runs its own FGMRES (own Krylov basis,
+ * Hessenberg matrix, stopping test and iteration count); the iterations advance in
+ * lockstep so that one V-cycle launch serves all columns, and a column that has
+ * stopped is carried as zeros.  Column r gives the same iterates as a solve of b_r
+ * alone.
+ *   b_dev: the algebraic right-hand sides (n_rhs columns of n_u + n_p doubles,
+ *          canonical layout), e.g. from bmg_assemble_rhs; x_dev: the solutions;
+ *          x0_dev: initial guesses or NULL for zero.  Returns BMG_E_NOT_CONVERGED
+ *          (with the last iterates) if some column did not reach rtol within maxit
+ *          iterations; info: NULL or an array of n_rhs records, one per column. */
 bmg_status bmg_solve(bmg_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
                      const double* x0_dev, bmg_solve_info* info);
 
@@ -160,7 +169,8 @@ bmg_status bmg_export_patch(const bmg_params* p, const double* kappa_host, int32
  * reference-element blocks the kernels use; essential rows/cols are the identity. */
 bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa_host, int32_t level, double* out_host);
 
-/* ----- single steps of the cycle, for step-by-step checks (FP64 in/out) ----- */
+/* ----- single steps of the cycle, for step-by-step checks (FP64 in/out, n_rhs
+ * columns of the level's ndof entries) ----- */
 /* One colour step of the smoother on level j >= 1: for every vertex patch of the
  * colour (colour = (vx mod 3) + 3 (vy mod 3)), x[S] += A_S^+ (b - A_j x)[S]. */
 bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x_dev, const double* b_dev);

@@ -31,7 +31,8 @@ STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM",
 class Params(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
-                ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32)]
+                ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32),
+                ("n_rhs", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -88,13 +89,14 @@ DENSE_COARSE_DEFAULT = 16384
 
 
 def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
-                dense_coarse_max=0):
+                dense_coarse_max=0, n_rhs=1):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
         p.bc[i] = int(bc[i])
     p.cycle, p.m_fine, p.precond_prec, p.restart = cycle, m_fine, prec, restart
     p.dense_coarse_max = dense_coarse_max
+    p.n_rhs = n_rhs
     return p
 
 
@@ -118,6 +120,8 @@ class Solver:
         self.torch = torch
         self.params = params
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         kap = np.ascontiguousarray(kappa, dtype=np.float64)
         self.stream = torch.cuda.current_stream(self.device)
         ws_ptr, ws_bytes = None, 0
@@ -134,6 +138,7 @@ class Solver:
         self.h = h
         self.J = params.levels
         self.k = params.k
+        self.R = max(1, params.n_rhs)
 
     def close(self):
         if getattr(self, "h", None):
@@ -161,47 +166,62 @@ class Solver:
         return a + b
 
     def zeros(self, level=None):
-        return self.torch.zeros(self.ndof(level), dtype=self.torch.float64, device=self.device)
+        """Vector(s) of a level: shape (ndof,) for one right-hand side, (n_rhs, ndof) otherwise."""
+        n = self.ndof(level)
+        shape = (n,) if self.R == 1 else (self.R, n)
+        return self.torch.zeros(shape, dtype=self.torch.float64, device=self.device)
+
+    def _vec(self, t, level=None):
+        """Pointer to t after checking that it holds n_rhs FP64 columns of the level on the device."""
+        n = self.ndof(level)
+        if (t.dtype != self.torch.float64 or t.device != self.device or not t.is_contiguous()
+                or t.numel() != self.R * n):
+            raise ValueError(f"expected a contiguous float64 tensor of {self.R} x {n} entries on {self.device}, "
+                             f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+        return _ptr(t)
 
     def apply(self, x, level=None):
         level = self.J if level is None else level
         y = self.zeros(level)
-        self._check(_lib.bmg_apply(self.h, level, _ptr(x), _ptr(y)), "apply")
+        self._check(_lib.bmg_apply(self.h, level, self._vec(x, level), _ptr(y)), "apply")
         return y
 
     def vcycle(self, r):
         z = self.zeros()
-        self._check(_lib.bmg_vcycle(self.h, _ptr(r), _ptr(z)), "vcycle")
+        self._check(_lib.bmg_vcycle(self.h, self._vec(r), _ptr(z)), "vcycle")
         return z
 
     def solve(self, b, rtol=1e-10, maxit=500, x0=None, x=None):
+        """x, info: one SolveInfo for one right-hand side, a list of n_rhs otherwise."""
         if x is None:
             x = self.zeros()
-        info = SolveInfo()
-        st = _lib.bmg_solve(self.h, _ptr(b), _ptr(x), rtol, maxit, _ptr(x0) if x0 is not None else None,
-                            C.byref(info))
+        infos = (SolveInfo * self.R)()
+        st = _lib.bmg_solve(self.h, self._vec(b), self._vec(x), rtol, maxit,
+                            self._vec(x0) if x0 is not None else None, infos)
         if st not in (0, 6):
             self._check(st, "solve")
-        return x, info
+        return x, (infos[0] if self.R == 1 else list(infos))
 
     def colour_step(self, level, colour, x, b):
         x = x.clone()
-        self._check(_lib.bmg_colour_step(self.h, level, colour, _ptr(x), _ptr(b)), "colour_step")
+        self._check(_lib.bmg_colour_step(self.h, level, colour, self._vec(x, level), self._vec(b, level)),
+                    "colour_step")
         return x
 
     def smooth(self, level, steps, x, b):
         x = x.clone()
-        self._check(_lib.bmg_smooth(self.h, level, steps, _ptr(x), _ptr(b)), "smooth")
+        self._check(_lib.bmg_smooth(self.h, level, steps, self._vec(x, level), self._vec(b, level)), "smooth")
         return x
 
     def restrict(self, level, rf):
         bc = self.zeros(level - 1)
-        self._check(_lib.bmg_restrict(self.h, level, _ptr(rf), _ptr(bc)), "restrict")
+        self._check(_lib.bmg_restrict(self.h, level, self._vec(rf, level), _ptr(bc)), "restrict")
         return bc
 
     def prolong_add(self, level, xc, xf):
         xf = xf.clone()
-        self._check(_lib.bmg_prolong_add(self.h, level, _ptr(xc), _ptr(xf)), "prolong_add")
+        self._check(_lib.bmg_prolong_add(self.h, level, self._vec(xc, level - 1), self._vec(xf, level)),
+                    "prolong_add")
         return xf
 
     def kernel_timing(self, level, max_launches=4096):
@@ -214,7 +234,7 @@ class Solver:
 
     def coarse_solve(self, b):
         x = self.zeros(0)
-        self._check(_lib.bmg_coarse_solve(self.h, _ptr(b), _ptr(x)), "coarse_solve")
+        self._check(_lib.bmg_coarse_solve(self.h, self._vec(b, 0), _ptr(x)), "coarse_solve")
         return x
 
 def quad_points(params: Params):
@@ -279,6 +299,8 @@ def export_level_matrix(params: Params, kappa, level):
     return out.reshape(n, n)
 
 
-def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=DENSE_COARSE_DEFAULT, **kw):
-    p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart, dense_coarse_max)
+def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=DENSE_COARSE_DEFAULT, n_rhs=1,
+                  **kw):
+    p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart, dense_coarse_max,
+                    n_rhs)
     return Solver(p, w.kappa, device=device, **kw)

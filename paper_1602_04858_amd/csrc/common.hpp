@@ -90,17 +90,21 @@ void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const vo
 void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s);
 void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s);
 void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipStream_t s);
-// y = B x for a dense symmetric n x n matrix
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, hipStream_t s);
+// Y = B X for a dense symmetric n x n matrix and nrhs columns of n entries
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s);
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s);
-void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s);
+// dst = src on the essential (constrained) rows, nrhs columns ld apart
+void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, int nrhs, int64_t ld,
+                             hipStream_t s);
 
-// FP64 Krylov helpers
+// FP64 Krylov helpers for nrhs right-hand sides: column r of Krylov vector k at
+// V + k ldv + r n; per-right-hand-side results ostride / cstride / dstride apart
 void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_t n, double* partial,
-                 double* out, hipStream_t s);
-void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, double sign,
-                  int64_t n, hipStream_t s);
-void launch_scale(double* dst, const double* src, const double* denom, bool take_sqrt, int64_t n, hipStream_t s);
+                 double* out, int nrhs, int64_t ostride, hipStream_t s);
+void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, int64_t cstride,
+                  double sign, int64_t n, int nrhs, hipStream_t s);
+void launch_scale(double* dst, const double* src, const double* denom, int64_t dstride, const int32_t* live,
+                  bool take_sqrt, int64_t n, int nrhs, hipStream_t s);
 void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s);
 int dots_partial_count();
 

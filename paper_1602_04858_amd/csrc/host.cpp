@@ -42,6 +42,7 @@ struct LevelInfo {
 struct bmg_ctx {
   bmg_params p{};
   int K = 1, prec = 0, sprec = 0, bcm = 0;
+  int R = 1;  // right-hand sides (columns of every vector)
   size_t tsize = 8, ssize = 8;
   hipStream_t stream = nullptr;
   bool own_ws = false;
@@ -62,6 +63,7 @@ struct bmg_ctx {
   // FP64 Krylov storage
   double *V = nullptr, *Z = nullptr, *w = nullptr, *rr = nullptr, *ax = nullptr, *t0 = nullptr, *t1 = nullptr;
   double *hdev = nullptr, *partial = nullptr;
+  int32_t* live = nullptr;  // per right-hand side: 1 while its Arnoldi process runs
   // V-cycle captured as a graph (captured on a private stream, launched on `stream`)
   hipStream_t cap_stream = nullptr;
   hipGraph_t vgraph = nullptr;
@@ -93,6 +95,8 @@ bmg_status fail(bmg_ctx* c, bmg_status s, const std::string& msg) {
 int64_t n_u_of(int N, int k) { return 2LL * N * (N + 1) * (k + 1) + 2LL * k * (k + 1) * N * N; }
 int64_t n_p_of(int N, int k) { return (int64_t)(k + 1) * (k + 1) * N * N; }
 
+constexpr int kMaxRhs = 16;
+
 int npatch_colour(int N, int colour) {
   const int c3x = colour % 3, c3y = colour / 3;
   if (c3x > N || c3y > N) return 0;
@@ -113,6 +117,7 @@ bmg_status check_params(const bmg_params* p) {
     return BMG_E_ARG;
   if (p->restart < 1 || p->restart > 512) return BMG_E_ARG;
   if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
+  if (p->n_rhs < 0 || p->n_rhs > kMaxRhs) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -463,6 +468,10 @@ int choose_jc(const bmg_ctx* c) {
   return jc;
 }
 
+// per right-hand side in hdev: [0, m+2) first Gram-Schmidt pass, [m+2, 2m+4) second,
+// 2m+4: squared norm, then spare entries
+int64_t hd_stride(const bmg_ctx* c) { return 2 * (c->p.restart + 2) + 8; }
+
 // assigns every device pointer of the context; with a null base only sizes
 size_t layout(bmg_ctx* c, char* base) {
   Bump B(base);
@@ -474,9 +483,9 @@ size_t layout(bmg_ctx* c, char* base) {
     const int64_t nc = (int64_t)L.N * L.N;
     L.kap = B.take(nc * ts);
     L.kap64 = (double*)B.take(nc * sizeof(double));
-    L.x = B.take(L.ndof * ts);
-    L.b = B.take(L.ndof * ts);
-    L.r = B.take(L.ndof * ts);
+    L.x = B.take(L.ndof * c->R * ts);
+    L.b = B.take(L.ndof * c->R * ts);
+    L.r = B.take(L.ndof * c->R * ts);
     if (j > 0)
       for (int col = 0; col < 9; ++col) {
         const bool pk = packed_level(K, L.N);
@@ -495,7 +504,7 @@ size_t layout(bmg_ctx* c, char* base) {
   c->elemT = B.take(c->prec == 0 ? elem_bytes<double>(K) : elem_bytes<float>(K));
   c->elem64 = B.take(elem_bytes<double>(K));
   c->xferT = B.take(c->prec == 0 ? xfer_bytes<double>(K) : xfer_bytes<float>(K));
-  const int64_t n = c->lev.back().ndof;
+  const int64_t n = c->lev.back().ndof * c->R;  // all columns of one Krylov vector
   const int m = c->p.restart;
   // one region shared by the Krylov vectors (solve) and the setup batch
   const size_t kry = ((size_t)(2 * m + 4) * n + 64) * sizeof(double);
@@ -519,8 +528,9 @@ size_t layout(bmg_ctx* c, char* base) {
     c->ax = (double*)R.take(n * sizeof(double));
     c->t0 = c->t1 = nullptr;
   }
-  c->hdev = (double*)B.take((size_t)(2 * (m + 2) + 8) * sizeof(double));
-  c->partial = (double*)B.take((size_t)dots_partial_count() * (m + 2) * sizeof(double));
+  c->hdev = (double*)B.take((size_t)hd_stride(c) * c->R * sizeof(double));
+  c->partial = (double*)B.take((size_t)dots_partial_count() * (m + 2) * c->R * sizeof(double));
+  c->live = (int32_t*)B.take((size_t)c->R * sizeof(int32_t));
   return B.off + kAlign;
 }
 
@@ -569,6 +579,7 @@ void setup_types(bmg_ctx* c) {
   c->tsize = c->prec == 0 ? 8 : 4;
   c->ssize = c->sprec == 0 ? 8 : c->sprec == 1 ? 4 : 2;
   c->bcm = bc_mask(c->p);
+  c->R = std::max(1, c->p.n_rhs);
 }
 
 template <typename T, int K>
@@ -863,6 +874,7 @@ struct Vecs {
 
 Vecs level_vecs(bmg_ctx* c) {
   Vecs v;
+  v.nrhs = c->R;
   for (auto& L : c->lev) {
     v.x.push_back(L.x);
     v.b.push_back(L.b);
@@ -876,8 +888,8 @@ Vecs level_vecs(bmg_ctx* c) {
 void vcycle_level(bmg_ctx* c, int j, const Vecs& v, bool use_dense) {
   LevelInfo& L = c->lev[j];
   const int nr = v.nrhs;
-  if (use_dense && c->jc > 0 && j == c->jc && nr == 1) {
-    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], v.x[j], c->stream);
+  if (use_dense && c->jc > 0 && j == c->jc) {
+    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], v.x[j], nr, c->stream);
     return;
   }
   if (j == 0) {
@@ -949,17 +961,19 @@ bool capture_vcycle(bmg_ctx* c) {
 }
 
 // z = B_J r with FP64 r, z (device); the essential rows are inverted exactly.
+// z = B_J r for all R columns (FP64 r, z on the device); the essential rows are
+// inverted exactly.
 void apply_precond(bmg_ctx* c, const double* r, double* z) {
   LevelInfo& L = c->lev.back();
-  launch_cast(c->prec, 0, r, L.b, L.ndof, c->stream);
+  launch_cast(c->prec, 0, r, L.b, L.ndof * c->R, c->stream);
   if (c->timing_level < 0 && capture_vcycle(c)) hipGraphLaunch(c->vexec, c->stream);
   else vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
-  launch_cast(0, c->prec, L.x, z, L.ndof, c->stream);
-  launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->stream);
+  launch_cast(0, c->prec, L.x, z, L.ndof * c->R, c->stream);
+  launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->R, L.ndof, c->stream);
 }
 
 void apply_op64(bmg_ctx* c, int j, const double* x, double* y) {
-  launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, 1, c->lev[j].ndof, c->stream);
+  launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, c->R, c->lev[j].ndof, c->stream);
 }
 
 // kappa of level j from the finest field: arithmetic mean of the 4 children per level (Section 4.1)
@@ -1159,12 +1173,13 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) {
 bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x, const double* b) {
   if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || colour < 0 || colour > 8) return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
-  launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
-  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
+  const int64_t nt = L.ndof * h->R;
+  launch_cast(h->prec, 0, x, L.x, nt, h->stream);
+  launch_cast(h->prec, 0, b, L.b, nt, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
                 L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1,
-                packed_level(h->K, L.N), 1, L.ndof, h->stream);
-  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+                packed_level(h->K, L.N), h->R, L.ndof, h->stream);
+  launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 }
@@ -1172,10 +1187,11 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
 bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, const double* b) {
   if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || steps < 0) return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
-  launch_cast(h->prec, 0, x, L.x, L.ndof, h->stream);
-  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
-  smooth_level(h, level, steps, L.x, L.b, 1);
-  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+  const int64_t nt = L.ndof * h->R;
+  launch_cast(h->prec, 0, x, L.x, nt, h->stream);
+  launch_cast(h->prec, 0, b, L.b, nt, h->stream);
+  smooth_level(h, level, steps, L.x, L.b, h->R);
+  launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 }
@@ -1184,9 +1200,9 @@ bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* b
   if (!h || !rf || !bc || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
-  launch_cast(h->prec, 0, rf, F.r, F.ndof, h->stream);
-  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, 1, F.ndof, C.ndof, h->stream);
-  launch_cast(0, h->prec, C.b, bc, C.ndof, h->stream);
+  launch_cast(h->prec, 0, rf, F.r, F.ndof * h->R, h->stream);
+  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, h->R, F.ndof, C.ndof, h->stream);
+  launch_cast(0, h->prec, C.b, bc, C.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 }
@@ -1195,10 +1211,10 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
   if (!h || !xc || !xf || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
-  launch_cast(h->prec, 0, xc, C.x, C.ndof, h->stream);
-  launch_cast(h->prec, 0, xf, F.x, F.ndof, h->stream);
-  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, 1, C.ndof, F.ndof, h->stream);
-  launch_cast(0, h->prec, F.x, xf, F.ndof, h->stream);
+  launch_cast(h->prec, 0, xc, C.x, C.ndof * h->R, h->stream);
+  launch_cast(h->prec, 0, xf, F.x, F.ndof * h->R, h->stream);
+  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, h->R, C.ndof, F.ndof, h->stream);
+  launch_cast(0, h->prec, F.x, xf, F.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 }
@@ -1206,9 +1222,9 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
 bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) {
   if (!h || !b || !x) return BMG_E_ARG;
   LevelInfo& L = h->lev[0];
-  launch_cast(h->prec, 0, b, L.b, L.ndof, h->stream);
-  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, 1, h->stream);
-  launch_cast(0, h->prec, L.x, x, L.ndof, h->stream);
+  launch_cast(h->prec, 0, b, L.b, L.ndof * h->R, h->stream);
+  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, h->R, h->stream);
+  launch_cast(0, h->prec, L.x, x, L.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 }
@@ -1217,125 +1233,194 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
                      bmg_solve_info* info) {
   if (!h || !b || !x || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
   const int J = (int)h->lev.size() - 1;
-  const int64_t n = h->lev[J].ndof;
+  const int R = h->R;
+  const int64_t n = h->lev[J].ndof;  // entries of one column
+  const int64_t ldv = n * R;         // distance between Krylov vectors
   const int m = h->p.restart;
+  const int64_t HS = hd_stride(h), NS = 2 * (m + 2);
   hipStream_t s = h->stream;
-  double* hd = h->hdev;  // [0..m+1]: first Gram-Schmidt pass, [m+2..]: second, [2m+4]: norms
-  std::vector<double> hh(2 * (m + 2) + 8);
-  auto readback = [&](int cnt) -> bmg_status {
-    HIPCHK(h, hipMemcpyAsync(hh.data(), hd, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  double* hd = h->hdev;  // per column (HS apart): [0, m+2) first Gram-Schmidt pass, [m+2, NS) second, NS: norm^2
+  std::vector<double> hh((size_t)HS * R), up((size_t)HS * R, 0.0);
+  auto readback = [&]() -> bmg_status {
+    HIPCHK(h, hipMemcpyAsync(hh.data(), hd, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     return BMG_OK;
   };
-  // ||b||
-  launch_dots(b, 1, n, b, n, h->partial, hd, s);
-  bmg_status st = readback(1);
-  if (st) return st;
-  const double bnorm = std::sqrt(hh[0]);
-  if (!std::isfinite(bnorm)) return fail(h, BMG_E_NONFINITE, "right-hand side is not finite");
-  if (x0) HIPCHK(h, hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  else HIPCHK(h, hipMemsetAsync(x, 0, n * sizeof(double), s));
-  if (bnorm == 0.0) {
-    HIPCHK(h, hipMemsetAsync(x, 0, n * sizeof(double), s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    if (info) *info = {0, 1, 0.0, 0.0};
+  auto upload = [&]() -> bmg_status {
+    HIPCHK(h, hipMemcpyAsync(hd, up.data(), up.size() * sizeof(double), hipMemcpyHostToDevice, s));
     return BMG_OK;
+  };
+  // which columns the scaling kernels keep (device copy changed only when it changes)
+  std::vector<int32_t> live_dev(R, -1);
+  auto set_live = [&](const std::vector<int32_t>& l) -> bmg_status {
+    if (l == live_dev) return BMG_OK;
+    live_dev = l;
+    HIPCHK(h, hipMemcpyAsync(h->live, live_dev.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));  // live_dev may change before the next synchronisation
+    return BMG_OK;
+  };
+  bmg_status st;
+  // ||b_r||
+  launch_dots(b, 1, ldv, b, n, h->partial, hd + NS, R, HS, s);
+  if ((st = readback())) return st;
+  struct Col {
+    double bnorm = 0.0, est = 1.0, prev_beta = -1.0;
+    int its = 0;
+    bool open = true, conv = false, stalled = false;
+  };
+  std::vector<Col> col(R);
+  for (int r = 0; r < R; ++r) {
+    col[r].bnorm = std::sqrt(hh[(size_t)r * HS + NS]);
+    if (!std::isfinite(col[r].bnorm)) return fail(h, BMG_E_NONFINITE, "right-hand side is not finite");
   }
-  int its = 0;
-  bool conv = false;
-  double est = 1.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  if (x0) HIPCHK(h, hipMemcpyAsync(x, x0, ldv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else HIPCHK(h, hipMemsetAsync(x, 0, ldv * sizeof(double), s));
+  for (int r = 0; r < R; ++r)
+    if (col[r].bnorm == 0.0) {  // b_r = 0: x_r = 0
+      HIPCHK(h, hipMemsetAsync(x + (size_t)r * n, 0, n * sizeof(double), s));
+      col[r].open = false;
+      col[r].conv = true;
+      col[r].est = 0.0;
+    }
+  // per column: Hessenberg matrix (Givens-reduced), rotations, rhs of the LSQ problem
+  std::vector<double> H((size_t)(m + 1) * m * R), cs((size_t)m * R), sn((size_t)m * R), g((size_t)(m + 1) * R),
+      y(m);
   // Each restart cycle starts from the true residual, so convergence is confirmed on
   // ||b - A x|| itself (iterative refinement when the Arnoldi estimate has drifted
-  // from it); a cycle that reduces the true residual by less than 10% ends the solve.
-  double prev_beta = -1.0;
-  bool stalled = false;
-  while (!conv && its < maxit) {
-    // r = b - A x
+  // from it); a cycle that reduces the true residual by less than 10% ends the
+  // column's solve.
+  for (;;) {
+    bool any_open = false;
+    for (auto& c : col) any_open |= c.open;
+    if (!any_open) break;
+    // r = b - A x, ||r||
     apply_op64(h, J, x, h->ax);
-    launch_sub(h->rr, b, h->ax, n, s);
-    launch_dots(h->rr, 1, n, h->rr, n, h->partial, hd, s);
-    if ((st = readback(1))) return st;
-    const double beta = std::sqrt(hh[0]);
-    if (!std::isfinite(beta)) return fail(h, BMG_E_NONFINITE, "residual is not finite");
-    est = beta / bnorm;
-    if (beta <= rtol * bnorm) {
-      conv = true;
-      break;
+    launch_sub(h->rr, b, h->ax, ldv, s);
+    launch_dots(h->rr, 1, ldv, h->rr, n, h->partial, hd + NS, R, HS, s);
+    if ((st = readback())) return st;
+    std::vector<int32_t> act(R, 0);
+    bool any = false;
+    for (int r = 0; r < R; ++r) {
+      Col& c = col[r];
+      if (!c.open) continue;
+      const double beta = std::sqrt(hh[(size_t)r * HS + NS]);
+      if (!std::isfinite(beta)) return fail(h, BMG_E_NONFINITE, "residual is not finite");
+      c.est = beta / c.bnorm;
+      if (beta <= rtol * c.bnorm) {
+        c.conv = true;
+        c.open = false;
+      } else if (c.prev_beta >= 0.0 && beta > 0.9 * c.prev_beta) {
+        c.stalled = true;
+        c.open = false;
+      } else if (c.its >= maxit) {
+        c.open = false;
+      } else {
+        c.prev_beta = beta;
+        act[r] = 1;
+        any = true;
+        up[(size_t)r * HS + NS] = beta;
+        double* Hr = &H[(size_t)r * (m + 1) * m];
+        std::fill(Hr, Hr + (size_t)(m + 1) * m, 0.0);
+        std::fill(&g[(size_t)r * (m + 1)], &g[(size_t)r * (m + 1)] + (m + 1), 0.0);
+        g[(size_t)r * (m + 1)] = beta;
+      }
     }
-    if (prev_beta >= 0.0 && beta > 0.9 * prev_beta) {
-      stalled = true;
-      break;
-    }
-    prev_beta = beta;
-    hh[0] = beta;
-    HIPCHK(h, hipMemcpyAsync(hd + 2 * (m + 2), hh.data(), sizeof(double), hipMemcpyHostToDevice, s));
-    launch_scale(h->V, h->rr, hd + 2 * (m + 2), false, n, s);
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int i = 0;
-    for (; i < m && its < maxit; ++i) {
-      double* vi = h->V + (size_t)i * n;
-      double* zi = h->Z + (size_t)i * n;
+    if (!any) break;
+    // V_0 = r / beta on the running columns, 0 on the others
+    if ((st = upload())) return st;
+    if ((st = set_live(act))) return st;
+    launch_scale(h->V, h->rr, hd + NS, HS, h->live, false, n, R, s);
+    std::vector<int32_t> run = act;
+    std::vector<int> icount(R, 0);
+    for (int i = 0; i < m; ++i) {
+      double* vi = h->V + (size_t)i * ldv;
+      double* zi = h->Z + (size_t)i * ldv;
       apply_precond(h, vi, zi);
       apply_op64(h, J, zi, h->w);
       // classical Gram-Schmidt, two passes
-      launch_dots(h->V, i + 1, n, h->w, n, h->partial, hd, s);
-      launch_axpys(h->w, h->V, i + 1, n, hd, -1.0, n, s);
-      launch_dots(h->V, i + 1, n, h->w, n, h->partial, hd + (m + 2), s);
-      launch_axpys(h->w, h->V, i + 1, n, hd + (m + 2), -1.0, n, s);
-      launch_dots(h->w, 1, n, h->w, n, h->partial, hd + 2 * (m + 2), s);
-      if ((st = readback(2 * (m + 2) + 1))) return st;
-      const double hn = std::sqrt(hh[2 * (m + 2)]);
-      for (int k2 = 0; k2 <= i; ++k2) H[(size_t)k2 * m + i] = hh[k2] + hh[(m + 2) + k2];
-      H[(size_t)(i + 1) * m + i] = hn;
-      for (int k2 = 0; k2 < i; ++k2) {
-        const double a = H[(size_t)k2 * m + i], cc = H[(size_t)(k2 + 1) * m + i];
-        H[(size_t)k2 * m + i] = cs[k2] * a + sn[k2] * cc;
-        H[(size_t)(k2 + 1) * m + i] = -sn[k2] * a + cs[k2] * cc;
+      launch_dots(h->V, i + 1, ldv, h->w, n, h->partial, hd, R, HS, s);
+      launch_axpys(h->w, h->V, i + 1, ldv, hd, HS, -1.0, n, R, s);
+      launch_dots(h->V, i + 1, ldv, h->w, n, h->partial, hd + (m + 2), R, HS, s);
+      launch_axpys(h->w, h->V, i + 1, ldv, hd + (m + 2), HS, -1.0, n, R, s);
+      launch_dots(h->w, 1, ldv, h->w, n, h->partial, hd + NS, R, HS, s);
+      if ((st = readback())) return st;
+      bool still = false;
+      for (int r = 0; r < R; ++r) {
+        if (!run[r]) continue;
+        Col& c = col[r];
+        const double* hr = &hh[(size_t)r * HS];
+        double* Hr = &H[(size_t)r * (m + 1) * m];
+        double* csr = &cs[(size_t)r * m];
+        double* snr = &sn[(size_t)r * m];
+        double* gr = &g[(size_t)r * (m + 1)];
+        const double hn = std::sqrt(hr[NS]);
+        for (int k2 = 0; k2 <= i; ++k2) Hr[(size_t)k2 * m + i] = hr[k2] + hr[(m + 2) + k2];
+        Hr[(size_t)(i + 1) * m + i] = hn;
+        for (int k2 = 0; k2 < i; ++k2) {
+          const double a = Hr[(size_t)k2 * m + i], cc = Hr[(size_t)(k2 + 1) * m + i];
+          Hr[(size_t)k2 * m + i] = csr[k2] * a + snr[k2] * cc;
+          Hr[(size_t)(k2 + 1) * m + i] = -snr[k2] * a + csr[k2] * cc;
+        }
+        const double a = Hr[(size_t)i * m + i], cc = Hr[(size_t)(i + 1) * m + i];
+        const double den = std::hypot(a, cc);
+        if (!std::isfinite(den) || den == 0.0) return fail(h, BMG_E_NONFINITE, "Arnoldi breakdown");
+        csr[i] = a / den;
+        snr[i] = cc / den;
+        Hr[(size_t)i * m + i] = den;
+        Hr[(size_t)(i + 1) * m + i] = 0.0;
+        gr[i + 1] = -snr[i] * gr[i];
+        gr[i] = csr[i] * gr[i];
+        ++c.its;
+        icount[r] = i + 1;
+        c.est = std::fabs(gr[i + 1]) / c.bnorm;
+        // a column that reaches rtol is confirmed on the true residual by the next cycle
+        if (std::fabs(gr[i + 1]) <= rtol * c.bnorm || hn == 0.0 || c.its >= maxit) run[r] = 0;
+        else still = true;
       }
-      const double a = H[(size_t)i * m + i], cc = H[(size_t)(i + 1) * m + i];
-      const double den = std::hypot(a, cc);
-      if (!std::isfinite(den) || den == 0.0) return fail(h, BMG_E_NONFINITE, "Arnoldi breakdown");
-      cs[i] = a / den;
-      sn[i] = cc / den;
-      H[(size_t)i * m + i] = den;
-      H[(size_t)(i + 1) * m + i] = 0.0;
-      g[i + 1] = -sn[i] * g[i];
-      g[i] = cs[i] * g[i];
-      ++its;
-      est = std::fabs(g[i + 1]) / bnorm;
-      if (std::fabs(g[i + 1]) <= rtol * bnorm || hn == 0.0) {
-        ++i;  // confirmed on the true residual by the next cycle
-        break;
+      if (!still || i + 1 == m) break;
+      if ((st = set_live(run))) return st;
+      launch_scale(h->V + (size_t)(i + 1) * ldv, h->w, hd + NS, HS, h->live, true, n, R, s);
+    }
+    // x_r += Z_r y_r with y_r from the triangular system of column r
+    int imax = 0;
+    std::fill(up.begin(), up.end(), 0.0);
+    for (int r = 0; r < R; ++r) {
+      const int ic = icount[r];
+      imax = std::max(imax, ic);
+      const double* Hr = &H[(size_t)r * (m + 1) * m];
+      const double* gr = &g[(size_t)r * (m + 1)];
+      for (int q = ic - 1; q >= 0; --q) {
+        double sum = gr[q];
+        for (int cc = q + 1; cc < ic; ++cc) sum -= Hr[(size_t)q * m + cc] * y[cc];
+        y[q] = sum / Hr[(size_t)q * m + q];
       }
-      if (i + 1 < m) launch_scale(h->V + (size_t)(i + 1) * n, h->w, hd + 2 * (m + 2), true, n, s);
+      for (int q = 0; q < ic; ++q) up[(size_t)r * HS + q] = y[q];
     }
-    for (int r = i - 1; r >= 0; --r) {
-      double sum = g[r];
-      for (int cc = r + 1; cc < i; ++cc) sum -= H[(size_t)r * m + cc] * y[cc];
-      y[r] = sum / H[(size_t)r * m + r];
-    }
-    HIPCHK(h, hipMemcpyAsync(hd, y.data(), i * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_axpys(x, h->Z, i, n, hd, 1.0, n, s);
-    HIPCHK(h, hipStreamSynchronize(s));  // hd is reused by the next restart
+    if ((st = upload())) return st;
+    launch_axpys(x, h->Z, imax, ldv, hd, HS, 1.0, n, R, s);
+    HIPCHK(h, hipStreamSynchronize(s));  // hd and up are reused by the next cycle
   }
-  // true residual
+  // true residuals
   apply_op64(h, J, x, h->ax);
-  launch_sub(h->rr, b, h->ax, n, s);
-  launch_dots(h->rr, 1, n, h->rr, n, h->partial, hd, s);
-  if ((st = readback(1))) return st;
+  launch_sub(h->rr, b, h->ax, ldv, s);
+  launch_dots(h->rr, 1, ldv, h->rr, n, h->partial, hd + NS, R, HS, s);
+  if ((st = readback())) return st;
   HIPCHK(h, hipGetLastError());
-  if (info) {
-    info->iterations = its;
-    info->converged = conv;
-    info->rel_residual_estimate = est;
-    info->rel_residual_true = std::sqrt(hh[0]) / bnorm;
+  bool all = true, stalled = false;
+  for (int r = 0; r < R; ++r) {
+    const Col& c = col[r];
+    all &= c.conv;
+    stalled |= c.stalled;
+    if (info) {
+      info[r].iterations = c.its;
+      info[r].converged = c.conv;
+      info[r].rel_residual_estimate = c.est;
+      info[r].rel_residual_true = c.bnorm > 0.0 ? std::sqrt(hh[(size_t)r * HS + NS]) / c.bnorm : 0.0;
+    }
   }
-  return conv ? BMG_OK
-              : fail(h, BMG_E_NOT_CONVERGED,
-                     stalled ? "true residual stagnates above rtol (attainable accuracy reached)" : "maxit reached");
+  return all ? BMG_OK
+             : fail(h, BMG_E_NOT_CONVERGED,
+                    stalled ? "true residual stagnates above rtol (attainable accuracy reached)" : "maxit reached");
 }
 
 bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy) {

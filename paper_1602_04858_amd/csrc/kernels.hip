@@ -849,27 +849,44 @@ __global__ __launch_bounds__(256) void k_identity(T* __restrict__ x, int64_t n, 
   }
 }
 
-// y = B x for a symmetric n x n matrix stored densely: one wavefront per row,
-// four independent partial sums per lane, streamed (non-temporal) matrix loads.
-template <typename T>
+// Y = B X for a symmetric n x n matrix stored densely and NR right-hand sides
+// (columns of n entries): one wavefront per row, the row streamed once
+// (non-temporal loads) for all columns, four independent partial sums per lane and
+// column (the summation order of a column does not depend on NR).
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_dense_rows(const T* __restrict__ B, int64_t n, const T* __restrict__ x,
                                                     T* __restrict__ y) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const T* r = B + row * n;
-  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+  T a0[NR], a1[NR], a2[NR], a3[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) a0[c] = a1[c] = a2[c] = a3[c] = T(0);
   int64_t j = lane;
   for (; j + 192 < n; j += 256) {
-    a0 += __builtin_nontemporal_load(r + j) * x[j];
-    a1 += __builtin_nontemporal_load(r + j + 64) * x[j + 64];
-    a2 += __builtin_nontemporal_load(r + j + 128) * x[j + 128];
-    a3 += __builtin_nontemporal_load(r + j + 192) * x[j + 192];
+    const T b0 = __builtin_nontemporal_load(r + j), b1 = __builtin_nontemporal_load(r + j + 64);
+    const T b2 = __builtin_nontemporal_load(r + j + 128), b3 = __builtin_nontemporal_load(r + j + 192);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T* xc = x + c * n;
+      a0[c] += b0 * xc[j];
+      a1[c] += b1 * xc[j + 64];
+      a2[c] += b2 * xc[j + 128];
+      a3[c] += b3 * xc[j + 192];
+    }
   }
-  for (; j < n; j += 64) a0 += __builtin_nontemporal_load(r + j) * x[j];
-  T s = (a0 + a1) + (a2 + a3);
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) y[row] = s;
+  for (; j < n; j += 64) {
+    const T b0 = __builtin_nontemporal_load(r + j);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) a0[c] += b0 * x[c * n + j];
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    T s = (a0[c] + a1[c]) + (a2[c] + a3[c]);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) y[c * n + row] = s;
+  }
 }
 
 template <typename TO, typename TI>
@@ -879,8 +896,11 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
 }
 
 template <typename TO, int K>
-__global__ __launch_bounds__(256) void k_copy_cons(int N, int bcm, const double* __restrict__ src, TO* __restrict__ dst) {
+__global__ __launch_bounds__(256) void k_copy_cons(int N, int bcm, const double* __restrict__ src, TO* __restrict__ dst,
+                                                   int64_t ld) {
   using D = Dims<K>;
+  src += blockIdx.y * ld;
+  dst += blockIdx.y * ld;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 4 * N * D::NB) return;
   const int side = t / (N * D::NB), r = t % (N * D::NB), f = r / D::NB, bb = r % D::NB;
@@ -909,9 +929,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// Krylov vectors of several right-hand sides: column r of vector k at V + k ldv + r n
+// (blockIdx.y = r); every right-hand side keeps its own results.
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int nvec, int64_t ldv,
                                               const double* __restrict__ w, int64_t n, double* __restrict__ partial) {
   __shared__ double sh[8];
+  V += blockIdx.y * n;
+  w += blockIdx.y * n;
+  partial += (int64_t)blockIdx.y * nvec * gridDim.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int c0 = 0; c0 < nvec; c0 += kDotChunk) {
     double acc[kDotChunk];
@@ -933,8 +958,10 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int 
 }
 
 __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int64_t ostride) {
   __shared__ double sh[8];
+  partial += (int64_t)blockIdx.y * gridDim.x * nblk;
+  out += blockIdx.y * ostride;
   double s = 0.0;
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(int64_t)blockIdx.x * nblk + i];
   s = block_sum(s, sh);
@@ -942,7 +969,11 @@ __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ p
 }
 
 __global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const double* __restrict__ V, int nvec,
-                                               int64_t ldv, const double* __restrict__ coef, double sign, int64_t n) {
+                                               int64_t ldv, const double* __restrict__ coef, int64_t cstride,
+                                               double sign, int64_t n) {
+  w += blockIdx.y * n;
+  V += blockIdx.y * n;
+  coef += blockIdx.y * cstride;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int v = 0; v < nvec; ++v) s += coef[v] * V[(int64_t)v * ldv + i];
@@ -950,9 +981,15 @@ __global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const dou
   }
 }
 
+// dst = src / denom (or / sqrt(denom)) per right-hand side; 0 where live[r] == 0
 __global__ __launch_bounds__(256) void k_scale(double* __restrict__ dst, const double* __restrict__ src,
-                                               const double* __restrict__ denom, int take_sqrt, int64_t n) {
-  const double f = 1.0 / (take_sqrt ? sqrt(denom[0]) : denom[0]);
+                                               const double* __restrict__ denom, int64_t dstride,
+                                               const int32_t* __restrict__ live, int take_sqrt, int64_t n) {
+  const int r = blockIdx.y;
+  dst += r * n;
+  src += r * n;
+  const double d = denom[r * dstride];
+  const double f = live[r] ? 1.0 / (take_sqrt ? sqrt(d) : d) : 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i] * f;
 }
@@ -1093,14 +1130,33 @@ void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipSt
   else hipLaunchKernelGGL((k_identity<float>), dim3(g), dim3(256), 0, s, (float*)x, n, col0, nrhs);
 }
 
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, hipStream_t s) {
+template <typename T, int NR>
+static void dense_t(const void* B, int64_t n, const void* x, void* y, hipStream_t s) {
   const unsigned g = (unsigned)((n + 3) / 4);
-  if (prec == 0)
-    hipLaunchKernelGGL((k_dense_rows<double>), dim3(g), dim3(256), 0, s, (const double*)B, n, (const double*)x,
-                       (double*)y);
-  else
-    hipLaunchKernelGGL((k_dense_rows<float>), dim3(g), dim3(256), 0, s, (const float*)B, n, (const float*)x,
-                       (float*)y);
+  hipLaunchKernelGGL((k_dense_rows<T, NR>), dim3(g), dim3(256), 0, s, (const T*)B, n, (const T*)x, (T*)y);
+}
+template <typename T>
+static void dense_nr(const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s) {
+  // columns in groups of at most 8 (registers of the partial sums)
+  const size_t ts = sizeof(T);
+  for (int c0 = 0; c0 < nrhs; c0 += 8) {
+    const void* xc = (const char*)x + (size_t)c0 * n * ts;
+    void* yc = (char*)y + (size_t)c0 * n * ts;
+    switch (std::min(8, nrhs - c0)) {
+      case 1: dense_t<T, 1>(B, n, xc, yc, s); break;
+      case 2: dense_t<T, 2>(B, n, xc, yc, s); break;
+      case 3: dense_t<T, 3>(B, n, xc, yc, s); break;
+      case 4: dense_t<T, 4>(B, n, xc, yc, s); break;
+      case 5: dense_t<T, 5>(B, n, xc, yc, s); break;
+      case 6: dense_t<T, 6>(B, n, xc, yc, s); break;
+      case 7: dense_t<T, 7>(B, n, xc, yc, s); break;
+      default: dense_t<T, 8>(B, n, xc, yc, s); break;
+    }
+  }
+}
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s) {
+  if (prec == 0) dense_nr<double>(B, n, x, y, nrhs, s);
+  else dense_nr<float>(B, n, x, y, nrhs, s);
 }
 
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s) {
@@ -1115,33 +1171,36 @@ void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t
     hipLaunchKernelGGL((k_cast<float, float>), dim3(g), dim3(256), 0, s, (const float*)src, (float*)dst, n);
 }
 
-void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, hipStream_t s) {
+void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, int nrhs, int64_t ld,
+                             hipStream_t s) {
   const int n = 4 * N * (K + 1);
-  dim3 g((n + 255) / 256), bl(256);
+  dim3 g((n + 255) / 256, nrhs), bl(256);
   if (K == 1) {
-    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 1>), g, bl, 0, s, N, bcm, src, (double*)dst);
-    else hipLaunchKernelGGL((k_copy_cons<float, 1>), g, bl, 0, s, N, bcm, src, (float*)dst);
+    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 1>), g, bl, 0, s, N, bcm, src, (double*)dst, ld);
+    else hipLaunchKernelGGL((k_copy_cons<float, 1>), g, bl, 0, s, N, bcm, src, (float*)dst, ld);
   } else {
-    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 2>), g, bl, 0, s, N, bcm, src, (double*)dst);
-    else hipLaunchKernelGGL((k_copy_cons<float, 2>), g, bl, 0, s, N, bcm, src, (float*)dst);
+    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 2>), g, bl, 0, s, N, bcm, src, (double*)dst, ld);
+    else hipLaunchKernelGGL((k_copy_cons<float, 2>), g, bl, 0, s, N, bcm, src, (float*)dst, ld);
   }
 }
 
 int dots_partial_count() { return kDotBlocks; }
 
 void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_t n, double* partial, double* out,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, s, V, nvec, ldv, w, n, partial);
-  hipLaunchKernelGGL(k_dots_final, dim3(nvec), dim3(256), 0, s, partial, kDotBlocks, out);
+                 int nrhs, int64_t ostride, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(kDotBlocks, nrhs), dim3(256), 0, s, V, nvec, ldv, w, n, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3(nvec, nrhs), dim3(256), 0, s, partial, kDotBlocks, out, ostride);
 }
 
-void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, double sign, int64_t n,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_axpys, dim3(grid_for(n)), dim3(256), 0, s, w, V, nvec, ldv, coef, sign, n);
+void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, int64_t cstride, double sign,
+                  int64_t n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpys, dim3(grid_for(n), nrhs), dim3(256), 0, s, w, V, nvec, ldv, coef, cstride, sign, n);
 }
 
-void launch_scale(double* dst, const double* src, const double* denom, bool take_sqrt, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, dst, src, denom, (int)take_sqrt, n);
+void launch_scale(double* dst, const double* src, const double* denom, int64_t dstride, const int32_t* live,
+                  bool take_sqrt, int64_t n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n), nrhs), dim3(256), 0, s, dst, src, denom, dstride, live,
+                     (int)take_sqrt, n);
 }
 
 void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s) {

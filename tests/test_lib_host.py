@@ -40,13 +40,15 @@ def test_status_strings():
 @pytest.mark.parametrize("change,expect", [
     (dict(k=3), 2), (dict(k=0), 2), (dict(n0=1), 1), (dict(levels=-1), 1), (dict(mu=-1.0), 1),
     (dict(sigma=0.0), 1), (dict(m_fine=0), 1), (dict(restart=0), 1), (dict(cycle=5), 1),
-    (dict(n0=2, levels=12), 1), (dict(prec=7), 1), (dict(dense=-1), 1), (dict(dense=70000), 1)])
+    (dict(n0=2, levels=12), 1), (dict(prec=7), 1), (dict(dense=-1), 1), (dict(dense=70000), 1),
+    (dict(n_rhs=-1), 1), (dict(n_rhs=17), 1)])
 def test_parameter_validation(change, expect):
     args = dict(n0=2, levels=2, k=1, mu=1.0, sigma=6.0, bc=[D, D, O, O], prec=0)
     args.update(change)
     p = bmg.make_params(args["n0"], args["levels"], args["k"], args["mu"], args["sigma"], args["bc"],
                         prec=args["prec"], m_fine=args.get("m_fine", 2), restart=args.get("restart", 10),
-                        cycle=args.get("cycle", 1), dense_coarse_max=args.get("dense", 0))
+                        cycle=args.get("cycle", 1), dense_coarse_max=args.get("dense", 0),
+                        n_rhs=args.get("n_rhs", 1))
     with pytest.raises(bmg.BmgError) as e:
         bmg.plan(p)
     assert e.value.status == expect
@@ -67,6 +69,19 @@ def test_smoother_layout_rule_matches_patch_construction(n0):
 def test_plan_grows_with_levels():
     sizes = [bmg.plan(bmg.make_params(2, J, 1, 1e-2, 6.0, [D, D, O, O], restart=20)) for J in (2, 3, 4)]
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_plan_counts_every_right_hand_side():
+    """n_rhs columns: Krylov and level vectors grow by n_rhs, the setup products do not;
+    n_rhs = 0 is read as 1."""
+    def plan(r):
+        return bmg.plan(bmg.make_params(2, 4, 1, 1e-2, 6.0, [D, D, O, O], restart=20, n_rhs=r))
+    one, zero, four, sixteen = plan(1), plan(0), plan(4), plan(16)
+    assert zero == one
+    per_rhs = (four - one) / 3
+    assert per_rhs > 0 and abs((sixteen - one) - 15 * per_rhs) <= 15 * 4096
+    n = 2 * 32 * 33 * 2 + 2 * 2 * 32 * 32 + 4 * 32 * 32  # finest ndof, N = 32, k = 1
+    assert per_rhs >= (2 * 20 + 4) * n * 8  # FP64 Krylov vectors of one column
 
 
 def test_nonfinite_and_negative_kappa_rejected():
