@@ -66,6 +66,48 @@ def cpu_baseline(w, iterations_full, sample_its):
             "seconds_per_iteration": per_it}
 
 
+def bench_c4(args, torch, bmg, inputs):
+    """C4: a batch of independent problems (N in {128, 256, 384, 512}, mu log-uniform
+    in [1e-4, 1], per-problem kappa contrast), FP32 V-cycle inside FP64 FGMRES, solved
+    together over several worker streams.  One step = one solve of every problem."""
+    ws = [inputs.workload("C4", i) for i in range(args.problems)]
+    dense = 4000
+    params = [bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 40, dense)
+              for w in ws]
+    t0 = time.perf_counter()
+    batch = bmg.Batch(params, [w.kappa for w in ws], nstreams=args.streams)
+    setup = time.perf_counter() - t0
+    bs = [torch.as_tensor(bmg.assemble_rhs(p, w.source), dtype=torch.float64, device="cuda")
+          for p, w in zip(params, ws)]
+    ndofs = [batch.ndof(i) for i in range(len(ws))]
+    log(f"bench: C4 {len(ws)} problems, {sum(ndofs)} dofs, setup {setup:.1f} s, {args.streams} streams")
+    xs = None
+    for _ in range(args.warmup):
+        xs, infos, st = batch.solve(bs, rtol=args.rtol, maxit=1000, xs=xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xs, infos, st = batch.solve(bs, rtol=args.rtol, maxit=1000, xs=xs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = [i.iterations for i in infos]
+    worst = max(i.rel_residual_true for i in infos)
+    value = args.steps * len(ws) / dt
+    log(f"bench: C4 {value:.2f} problems/s, iterations {min(its)}..{max(its)}, worst true residual {worst:.2e}")
+    out = {"metric": "C4 batch: problems solved/s to 1e-10 rel resid (FP32 V-cycle in FP64 FGMRES)",
+           "value": value, "unit": "problems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
+           "config": {"workload": f"C4: {len(ws)} problems, N in {{128,256,384,512}}, RT_1, mu log-uniform "
+                                  "[1e-4,1], seeded kappa contrast 1e4-1e6 + channels, smooth random f; "
+                                  f"batch over {args.streams} streams, dense coarse <= {dense} dofs",
+                      "problems": len(ws), "streams": args.streams, "rtol": args.rtol},
+           "total_dofs": sum(ndofs), "iterations_min": min(its), "iterations_max": max(its),
+           "dof_iters_per_s": sum(n * i for n, i in zip(ndofs, its)) * args.steps / dt,
+           "worst_true_rel_residual": worst, "setup_s": setup, "status": st}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,8 +117,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy"],
-                    help="C2 (default, the benchmark configuration) or the 1024^2 precision study")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4"],
+                    help="C2 (default, the benchmark configuration), the 1024^2 precision study, or the "
+                         "48-problem batch")
+    ap.add_argument("--streams", type=int, default=4, help="C4: worker streams of the batch")
+    ap.add_argument("--problems", type=int, default=48, help="C4: problems in the batch")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -101,6 +146,9 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: copy calibration, 3 copies of {args.copy_calibration} MiB")
         del src, dst
+
+    if args.workload == "C4":
+        return bench_c4(args, torch, bmg, inputs)
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")

@@ -46,6 +46,7 @@ extern "C" {
 #endif
 
 typedef struct bmg_ctx* bmg_handle;
+typedef struct bmg_batch* bmg_batch_handle;
 
 typedef enum {
   BMG_OK = 0,
@@ -137,6 +138,32 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
  *          iterations; info: NULL or an array of n_rhs records, one per column. */
 bmg_status bmg_solve(bmg_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
                      const double* x0_dev, bmg_solve_info* info);
+
+/* ----- batches of independent problems ----- */
+/* Set up nprob independent problems (their own mesh, degree, mu, kappa, boundary
+ * conditions and precision; params[i] and kappa_host[i] as for bmg_setup) that
+ * are solved together.  The library allocates every problem's workspace and
+ * nstreams worker streams (0 = 4, at most 16, default priority); the solves of a
+ * batch call are spread over the worker streams, one host thread per stream, so
+ * the V-cycles of different problems run concurrently on the GPU.  hip_stream is
+ * the caller's stream that a batch call is ordered with (NULL = default stream).
+ * Setup runs problem after problem (each uses every host thread). */
+bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double* const* kappa_host,
+                           int32_t nstreams, void* hip_stream, bmg_batch_handle* out);
+/* Solve every problem of the batch: b_dev[i] / x_dev[i] are device pointers (host
+ * arrays of nprob pointers) laid out as for bmg_solve of problem i; info is NULL or
+ * an array with one record per right-hand side of every problem, in problem order.
+ * Work queued on the caller's stream before the call is waited for, and the
+ * caller's stream waits for the batch.  Returns the first hard failure in problem
+ * order, else BMG_E_NOT_CONVERGED if some problem did not converge, else BMG_OK;
+ * bmg_batch_last_error names the problem. */
+bmg_status bmg_batch_solve(bmg_batch_handle b, const double* const* b_dev, double* const* x_dev, double rtol,
+                           int32_t maxit, bmg_solve_info* info);
+/* The handle of problem i (sizes, single V-cycles, step entry points).  Owned by
+ * the batch: do not destroy it, and do not use it while a batch call runs. */
+bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out);
+const char* bmg_batch_last_error(bmg_batch_handle b);
+bmg_status bmg_batch_destroy(bmg_batch_handle b);
 
 /* ----- setup-side host calls (no handle, no device) ----- */
 /* Quadrature points of bmg_assemble_rhs on the finest mesh of p (host arrays).

@@ -63,8 +63,12 @@ _sig = {
     "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
     "bmg_kernel_timing": [_VP, _I32, _I32],
     "bmg_kernel_timing_read": [_VP, _P(_I32), _P(_D), _P(_D)],
+    "bmg_batch_setup": [_I32, _P(Params), _P(_P(_D)), _I32, _VP, _P(_VP)],
+    "bmg_batch_solve": [_VP, _P(_VP), _P(_VP), _D, _I32, _P(SolveInfo)],
+    "bmg_batch_handle_of": [_VP, _I32, _P(_VP)],
+    "bmg_batch_destroy": [_VP],
 }
-EXPORTS = list(_sig) + ["bmg_status_string", "bmg_last_error"]
+EXPORTS = list(_sig) + ["bmg_status_string", "bmg_last_error", "bmg_batch_last_error"]
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -73,6 +77,8 @@ _lib.bmg_status_string.argtypes = [C.c_int]
 _lib.bmg_status_string.restype = C.c_char_p
 _lib.bmg_last_error.argtypes = [_VP]
 _lib.bmg_last_error.restype = C.c_char_p
+_lib.bmg_batch_last_error.argtypes = [_VP]
+_lib.bmg_batch_last_error.restype = C.c_char_p
 
 
 class BmgError(RuntimeError):
@@ -236,6 +242,77 @@ class Solver:
         x = self.zeros(0)
         self._check(_lib.bmg_coarse_solve(self.h, self._vec(b, 0), _ptr(x)), "coarse_solve")
         return x
+
+class Batch:
+    """Independent problems solved together (bmg_batch_*): one handle per problem,
+    the solves spread over `nstreams` worker streams."""
+
+    def __init__(self, params_list, kappas, nstreams=4, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        n = len(params_list)
+        self.params = list(params_list)
+        self._kap = [np.ascontiguousarray(kp, dtype=np.float64) for kp in kappas]
+        if len(self._kap) != n:
+            raise ValueError("one kappa field per problem")
+        arr = (Params * n)(*self.params)
+        kptr = (_P(_D) * n)(*[kp.ctypes.data_as(_P(_D)) for kp in self._kap])
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = _lib.bmg_batch_setup(n, arr, kptr, nstreams, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st:
+            raise BmgError(st, "batch_setup")
+        self.h = h
+        self.n = n
+        self._del = False
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.bmg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ndof(self, i):
+        hi = C.c_void_p()
+        st = _lib.bmg_batch_handle_of(self.h, i, C.byref(hi))
+        if st:
+            raise BmgError(st, "batch_handle_of")
+        N, nu, npr = C.c_int32(), C.c_int64(), C.c_int64()
+        _lib.bmg_sizes(hi, self.params[i].levels, C.byref(N), C.byref(nu), C.byref(npr))
+        return nu.value + npr.value
+
+    def solve(self, bs, rtol=1e-10, maxit=500, xs=None):
+        """bs: one device tensor per problem (n_rhs columns as for Solver.solve).
+        Returns (xs, infos, status) with one SolveInfo per right-hand side."""
+        t = self.torch
+        if len(bs) != self.n:
+            raise ValueError("one right-hand side per problem")
+        if xs is None:
+            xs = [t.zeros_like(b) for b in bs]
+        nrec = 0
+        for i, (b, x) in enumerate(zip(bs, xs)):
+            R = max(1, self.params[i].n_rhs)
+            n = self.ndof(i) * R
+            for v in (b, x):
+                if v.dtype != t.float64 or v.device != self.device or not v.is_contiguous() or v.numel() != n:
+                    raise ValueError(f"problem {i}: expected a contiguous float64 tensor of {n} entries")
+            nrec += R
+        bp = (_VP * self.n)(*[b.data_ptr() for b in bs])
+        xp = (_VP * self.n)(*[x.data_ptr() for x in xs])
+        infos = (SolveInfo * nrec)()
+        st = _lib.bmg_batch_solve(self.h, bp, xp, rtol, maxit, infos)
+        if st not in (0, 6):
+            raise BmgError(st, f"batch_solve: {_lib.bmg_batch_last_error(self.h).decode()}")
+        return xs, list(infos), st
+
 
 def quad_points(params: Params):
     N = params.n0 << params.levels

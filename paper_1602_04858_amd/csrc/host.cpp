@@ -79,6 +79,17 @@ struct bmg_ctx {
   std::string err;
 };
 
+// Independent problems solved together: one handle per problem, worker streams
+// that the solves are spread over (one host thread per stream).
+struct bmg_batch {
+  std::vector<bmg_handle> h;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t start = nullptr;
+  hipStream_t user = nullptr;
+  std::string err;
+};
+
 namespace {
 
 bmg_status fail(bmg_ctx* c, bmg_status s, const std::string& msg) {
@@ -1586,6 +1597,111 @@ bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int
   const RefData R = make_refdata(p->k, p->mu, p->sigma);
   std::vector<double> A = dense_level(R, p->k, bc_mask(*p), N, kappa_level(kappa, p->n0, p->levels, level));
   std::copy(A.begin(), A.end(), out);
+  return BMG_OK;
+}
+
+
+// ----- batches of independent problems -----
+static void batch_free(bmg_batch* b) {
+  for (auto h : b->h)
+    if (h) bmg_destroy(h);
+  for (auto e : b->done)
+    if (e) hipEventDestroy(e);
+  if (b->start) hipEventDestroy(b->start);
+  for (auto s : b->streams)
+    if (s) hipStreamDestroy(s);
+  delete b;
+}
+
+bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double* const* kappa_host,
+                           int32_t nstreams, void* hip_stream, bmg_batch_handle* out) {
+  if (!out || !params || !kappa_host || nprob < 1 || nprob > 4096 || nstreams < 0 || nstreams > 16)
+    return BMG_E_ARG;
+  for (int i = 0; i < nprob; ++i) {
+    bmg_status s = check_params(&params[i]);
+    if (s) return s;
+    if (!kappa_host[i]) return BMG_E_ARG;
+  }
+  bmg_batch* b = new bmg_batch();
+  b->user = (hipStream_t)hip_stream;
+  const int S = std::min(nstreams == 0 ? 4 : nstreams, nprob);
+  b->streams.assign(S, nullptr);
+  b->done.assign(S, nullptr);
+  for (int w = 0; w < S; ++w)
+    if (hipStreamCreateWithFlags(&b->streams[w], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done[w], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return BMG_E_HIP;
+    }
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+    batch_free(b);
+    return BMG_E_HIP;
+  }
+  b->h.assign(nprob, nullptr);
+  for (int i = 0; i < nprob; ++i) {
+    bmg_status s = bmg_setup(&params[i], kappa_host[i], nullptr, 0, b->streams[i % S], &b->h[i]);
+    if (s) {
+      batch_free(b);
+      return s;
+    }
+  }
+  *out = b;
+  return BMG_OK;
+}
+
+bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out) {
+  if (!b || !out || i < 0 || i >= (int)b->h.size()) return BMG_E_ARG;
+  *out = b->h[i];
+  return BMG_OK;
+}
+
+bmg_status bmg_batch_solve(bmg_batch_handle b, const double* const* b_dev, double* const* x_dev, double rtol,
+                           int32_t maxit, bmg_solve_info* info) {
+  if (!b || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
+  const int n = (int)b->h.size(), S = (int)b->streams.size();
+  std::vector<int64_t> info_off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (!b_dev[i] || !x_dev[i]) return BMG_E_ARG;
+    info_off[i + 1] = info_off[i] + b->h[i]->R;
+  }
+  // the worker streams start after the work already queued on the caller's stream
+  if (hipEventRecord(b->start, b->user) != hipSuccess) return BMG_E_HIP;
+  for (int w = 0; w < S; ++w)
+    if (hipStreamWaitEvent(b->streams[w], b->start, 0) != hipSuccess) return BMG_E_HIP;
+  std::vector<bmg_status> st(n, BMG_OK);
+  std::atomic<int> next{0};
+  auto worker = [&](int w) {
+    for (int i = next++; i < n; i = next++) {
+      bmg_handle h = b->h[i];
+      h->stream = b->streams[w];  // a handle is driven by one worker at a time
+      st[i] = bmg_solve(h, b_dev[i], x_dev[i], rtol, maxit, nullptr, info ? info + info_off[i] : nullptr);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < S; ++w) th.emplace_back(worker, w);
+  worker(0);
+  for (auto& t : th) t.join();
+  for (int w = 0; w < S; ++w) {
+    if (hipEventRecord(b->done[w], b->streams[w]) != hipSuccess) return BMG_E_HIP;
+    if (hipStreamWaitEvent(b->user, b->done[w], 0) != hipSuccess) return BMG_E_HIP;
+  }
+  // the first hard failure in problem order, else the first NOT_CONVERGED
+  int pick = -1;
+  for (int i = 0; i < n && pick < 0; ++i)
+    if (st[i] != BMG_OK && st[i] != BMG_E_NOT_CONVERGED) pick = i;
+  for (int i = 0; i < n && pick < 0; ++i)
+    if (st[i] != BMG_OK) pick = i;
+  if (pick < 0) return BMG_OK;
+  b->err = "problem " + std::to_string(pick) + ": " + b->h[pick]->err;
+  return st[pick];
+}
+
+const char* bmg_batch_last_error(bmg_batch_handle b) { return b ? b->err.c_str() : "null batch"; }
+
+bmg_status bmg_batch_destroy(bmg_batch_handle b) {
+  if (!b) return BMG_E_ARG;
+  for (auto s : b->streams) hipStreamSynchronize(s);
+  batch_free(b);
   return BMG_OK;
 }
 

@@ -188,3 +188,23 @@ def test_quadrature_points_match_oracle():
     c1, f1 = quad_points(8, 2)
     c2, f2 = bmg.quad_points(p)
     assert np.abs(c1 - c2).max() < 1e-15 and np.abs(f1 - f2).max() < 1e-15
+
+
+def test_batch_setup_rejects_bad_arguments():
+    """Validated before any device work (runs without a GPU)."""
+    import ctypes as C
+    lib = bmg.lib()
+    p = bmg.make_params(2, 1, 1, 1.0, 6.0, [D, D, O, O])
+    arr = (bmg.Params * 1)(p)
+    kap = np.ones(16)
+    kptr = (C.POINTER(C.c_double) * 1)(kap.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    assert lib.bmg_batch_setup(0, arr, kptr, 4, None, C.byref(h)) == 1
+    assert lib.bmg_batch_setup(1, arr, kptr, 17, None, C.byref(h)) == 1
+    assert lib.bmg_batch_setup(1, arr, kptr, -1, None, C.byref(h)) == 1
+    bad = (bmg.Params * 1)(bmg.make_params(2, 1, 3, 1.0, 6.0, [D, D, O, O]))
+    assert lib.bmg_batch_setup(1, bad, kptr, 4, None, C.byref(h)) == 2
+    nullk = (C.POINTER(C.c_double) * 1)()
+    assert lib.bmg_batch_setup(1, arr, nullk, 4, None, C.byref(h)) == 1
+    assert lib.bmg_batch_solve(None, None, None, 1e-10, 10, None) == 1
+    assert lib.bmg_batch_destroy(None) == 1
