@@ -463,14 +463,16 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
   }
-  // PF: this lane's column of the full inverse; PK: rotated entry i in lane i mod 64
-  S areg[PF ? NSR : 1];
-  const bool pre = PF && active && !ext_guess && lane < NSR;
+  // PF: column `lane` of the full inverse of this patch (n = NSR, or NSE for an
+  // extended patch; column-major), every entry prefetched into registers so that no
+  // patch streams its inverse in the product; PK: rotated entry i in lane i mod 64
+  S areg[PF ? NSE : 1];
   if (PF) {
-    const S* A = inv + (size_t)pc * NSR * NSR;
-    const int lc = lane < NSR ? lane : NSR - 1;
+    const int n0 = ext_guess ? NSE : NSR;
+    const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NSE * NSE : inv + (size_t)pc * NSR * NSR;
+    const int lc = lane < n0 ? lane : n0 - 1;
 #pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * NSR + lc];
+    for (int u = 0; u < (PF ? NSE : 1); ++u) areg[u] = A[min(u, n0 - 1) * n0 + lc];
   }
   S apk[NQ];
   if (PK) {
@@ -611,11 +613,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     }
     return;
   }
-  if (PF && !is_ext && pre) {
-    T acc = T(0);
+  if (PF) {
+    // one product length for both layouts: r is zero beyond the patch size
+    if (lane < ns) {
+      T acc = T(0);
 #pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
-    if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
+      for (int u = 0; u < (PF ? NSE : 1); ++u) acc += T(areg[u]) * rs[w][u];
+      if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
+    }
     return;
   }
   const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
