@@ -223,6 +223,8 @@ bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches);
 bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes);
 
 const char* bmg_status_string(bmg_status s);
+/* Message of the last failure on h; with h == NULL, of the last bmg_setup or
+ * bmg_batch_setup of the calling thread that failed after argument validation. */
 const char* bmg_last_error(bmg_handle h);
 
 #ifdef __cplusplus

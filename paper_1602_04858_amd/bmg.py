@@ -18,6 +18,11 @@ LIBPATH = os.path.join(HERE, "libbmg.so")
 if not os.path.exists(LIBPATH):
     raise ImportError(f"{LIBPATH} is not built; run paper_1602_04858_amd/build.py (hipcc, gfx950)")
 
+# torch first: its HIP runtime (soname libamdhip64.so.7) is then the one libbmg.so
+# binds to.  Loading libbmg.so first would bring in a second HIP/HSA runtime from
+# the system ROCm, and whichever initialises second finds no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIBPATH)
 
 BC_DIRICHLET, BC_OPEN = 0, 1
@@ -140,7 +145,7 @@ class Solver:
         h = C.c_void_p()
         st = _lib.bmg_setup(C.byref(params), kap, ws_ptr, ws_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st:
-            raise BmgError(st, "setup")
+            raise BmgError(st, f"setup: {_lib.bmg_last_error(None).decode()}")
         self.h = h
         self.J = params.levels
         self.k = params.k
@@ -264,7 +269,7 @@ class Batch:
         h = C.c_void_p()
         st = _lib.bmg_batch_setup(n, arr, kptr, nstreams, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st:
-            raise BmgError(st, "batch_setup")
+            raise BmgError(st, f"batch_setup: {_lib.bmg_last_error(None).decode()}")
         self.h = h
         self.n = n
         self._del = False

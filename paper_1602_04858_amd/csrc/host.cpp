@@ -92,6 +92,9 @@ struct bmg_batch {
 
 namespace {
 
+// message of the last bmg_setup of this thread that failed after validation
+thread_local std::string g_setup_err = "null handle";
+
 bmg_status fail(bmg_ctx* c, bmg_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
@@ -1043,7 +1046,7 @@ const char* bmg_status_string(bmg_status s) {
   return "unknown";
 }
 
-const char* bmg_last_error(bmg_handle h) { return h ? h->err.c_str() : "null handle"; }
+const char* bmg_last_error(bmg_handle h) { return h ? h->err.c_str() : g_setup_err.c_str(); }
 
 bmg_status bmg_plan(const bmg_params* p, size_t* bytes) {
   bmg_status s = check_params(p);
@@ -1104,7 +1107,8 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   if (!st) st = build_dense(c);
   if (!st && hipDeviceSynchronize() != hipSuccess) st = fail(c, BMG_E_HIP, "setup synchronisation failed");
   if (st) {
-    if (c->own_ws) hipFree(c->ws);
+    g_setup_err = c->err;
+    if (c->own_ws) (void)hipFree(c->ws);
     delete c;
     return st;
   }
@@ -1627,13 +1631,17 @@ bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double
   const int S = std::min(nstreams == 0 ? 4 : nstreams, nprob);
   b->streams.assign(S, nullptr);
   b->done.assign(S, nullptr);
-  for (int w = 0; w < S; ++w)
-    if (hipStreamCreateWithFlags(&b->streams[w], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->done[w], hipEventDisableTiming) != hipSuccess) {
+  for (int w = 0; w < S; ++w) {
+    hipError_t e = hipStreamCreateWithFlags(&b->streams[w], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[w], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      g_setup_err = std::string("worker stream: ") + hipGetErrorString(e);
       batch_free(b);
       return BMG_E_HIP;
     }
+  }
   if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+    g_setup_err = "batch event";
     batch_free(b);
     return BMG_E_HIP;
   }
@@ -1641,6 +1649,7 @@ bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double
   for (int i = 0; i < nprob; ++i) {
     bmg_status s = bmg_setup(&params[i], kappa_host[i], nullptr, 0, b->streams[i % S], &b->h[i]);
     if (s) {
+      g_setup_err = "problem " + std::to_string(i) + ": " + g_setup_err;
       batch_free(b);
       return s;
     }

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 int colour, int npatch, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
-  constexpr int NL = D::NL, NV = D::NV, NSR = D::NSR, NSE = D::NSE;
+  constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
   // Storage of the pseudo-inverses (chosen per level by the host):
   //   PK (RT_1, bandwidth-bound levels): symmetric "rotated diagonal" blocks,
   //       R[d n + t] = A+[t][(t + d) mod n] for d = 0 .. n/2 (n (n/2 + 1) entries,
@@ -394,6 +394,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
                                  //               1: u_y of the cell across the outer vertical face]
   __shared__ T zs[4][4 * NL];
+  __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
   __shared__ S aps[4][((K == 1) && PKD) ? NPR : 1];
   x += blockIdx.y * ld;
@@ -502,45 +503,64 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
 #pragma unroll
     for (int q = 0; q < NEQ; ++q)
       if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
+    if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
   }
   lds_barrier();
 
-  // 2. row contributions of every patch cell (cell blocks + its four faces)
+  // 2. row contributions of every patch cell (cell blocks + its four faces), one
+  // branch-free path for all rows.  A velocity row (component c, local index dd)
+  // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
+  // - h Dm[:, dd] . p, where the faces across which component c is tangential give
+  // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
+  // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
+  // coefficient rows and vectors by LDS address; absent terms read the zero block.
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int e = lane + 64 * q;
     if (e >= 4 * NL) break;
     const int s = e / NL, d = e % NL;
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    T z = T(0);
-    if (active && in_dom(cx, cy)) {
-      const T* xl = xs[w][s];
-      if (d < 2 * NV) {
-        const T khh = kv[q] * hh;
-        if (d < NV) {
-          int tl = F_INT, tu = F_INT;
-          const T* nl = nullptr;
-          const T* nu = nullptr;
-          if (cy == 0) tl = boundary_type(bcm, 2);
-          else nl = (s >= 2) ? xs[w][s - 2] : nb[w][s][0];
-          if (cy == N - 1) tu = boundary_type(bcm, 3);
-          else nu = (s < 2) ? xs[w][s + 2] : nb[w][s][0];
-          z = comp_row<T, K>(Es, d, xl, xl + 2 * NV, Es.Dx, khh, mh, tl, nl, tu, nu);
-        } else {
-          int tl = F_INT, tu = F_INT;
-          const T* nl = nullptr;
-          const T* nu = nullptr;
-          if (cx == 0) tl = boundary_type(bcm, 0);
-          else nl = (s & 1) ? xs[w][s - 1] + NV : nb[w][s][1];
-          if (cx == N - 1) tu = boundary_type(bcm, 1);
-          else nu = (s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV;
-          z = comp_row<T, K>(Es, d - NV, xl + NV, xl + 2 * NV, Es.Dy, khh, mh, tl, nl, tu, nu);
-        }
-      } else {
-        z = pres_row<T, K>(Es, d - 2 * NV, xl, xl + NV, mh);
-      }
+    const T* xl = xs[w][s];
+    const bool vel = d < 2 * NV;
+    const int comp = d >= NV ? 1 : 0;
+    const int dd = vel ? d - comp * NV : d - 2 * NV;
+    // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
+    const bool lo_bnd = comp ? cx == 0 : cy == 0;
+    const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
+    const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
+    const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
+    const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
+    const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
+    const int ro = dd * NV;
+    const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
+    const T* c_mass = vel ? Es.M + ro : zblk;
+    const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
+    const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
+    const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
+    const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
+    const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
+    const T* v_self = vel ? xl + comp * NV : xl;
+    const T* v_nlo = vel ? nl : xl + NV;
+    const T* pv = xl + 2 * NV;
+    const T khh = vel ? kv[q] * hh : T(0);
+    T a = T(0), g = T(0);
+    auto term = [&](int i) {
+      a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
+      a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
+    };
+    if (PK) {
+      // bandwidth-bound levels: partial unrolling keeps the registers (and so the
+      // blocks per CU) of the rest of the kernel
+#pragma unroll 2
+      for (int i = 0; i < NV; ++i) term(i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) term(i);
     }
-    zs[w][e] = z;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
+    const T z = (vel ? a : mh * a) + mh * g;
+    zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
   }
   lds_barrier();
 
