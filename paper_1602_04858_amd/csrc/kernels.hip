@@ -17,6 +17,8 @@
 //              one thread per coarse cell, tensor-product 1-D re-expansion.
 //   k_coarse   x_0 = A_0^{-1} b_0 with the precomputed FP64 inverse.
 //   Krylov     FP64 multi-dot (deterministic two-stage reduction), multi-axpy.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace bmg {
@@ -367,12 +369,12 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
 // prefetched into registers (RT_1, regular layout), the patch layout is decoded
 // arithmetically and b on the patch is loaded -- so the dependent chain is one
 // gather of x, the local residual in LDS, an FMA chain on registers and the store.
-template <typename T, typename S, int K, int TAG, bool PKD>
+template <typename T, typename S, int K, int TAG, bool PKD, bool MC>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
-                                                int colour, int npatch, int64_t ld) {
+                                                int colour, int npatch, int64_t ld, int nrhs, int ncol) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
@@ -397,8 +399,6 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
   __shared__ S aps[4][((K == 1) && PKD) ? NPR : 1];
-  x += blockIdx.y * ld;
-  b += blockIdx.y * ld;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + w;
   const bool active = p < npatch;
@@ -409,15 +409,18 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
   const int ext = active ? extidx[pc] : -1;
+  // right-hand-side columns of this block: c0 .. c1-1 (ld apart); MC = several
+  const int c0 = MC ? blockIdx.y * ncol : blockIdx.y, c1 = MC ? min(c0 + ncol, nrhs) : c0 + 1;
 
   // 0. issue every load that does not depend on the correction: the gather of x
   // (first: it is needed first), the element matrices, b on the patch, then the
   // patch-inverse column of this lane (needed last).  The loads are unconditional
   // (clamped in-bounds indices, masked where the value is used) so that no branch
   // separates them from their uses; they complete in order and the later ones stay
-  // in flight through the LDS-only barriers below.
+  // in flight through the LDS-only barriers below.  Indices are kept for the later
+  // columns of the block.
   constexpr int NG = (4 * NL + 63) / 64, NN = (8 * NV + 63) / 64;
-  T gx[NG], gn[NN];
+  int gxi[NG], gni[NN];
   bool okx[NG], okn[NN];
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int s = (e / NL) & 3, d = e % NL;
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     okx[q] = e < 4 * NL && in_dom(cx, cy) && !I::cons(N, bcm, cx, cy, d);
-    gx[q] = x[okx[q] ? I::g(N, cx, cy, d) : 0];
+    gxi[q] = okx[q] ? I::g(N, cx, cy, d) : 0;
   }
 #pragma unroll
   for (int q = 0; q < NN; ++q) {
@@ -437,7 +440,15 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     else ncx = (s & 1) ? cx + 1 : cx - 1;
     const int dd = which * NV + d;
     okn[q] = e < 8 * NV && in_dom(cx, cy) && in_dom(ncx, ncy) && !I::cons(N, bcm, ncx, ncy, dd);
-    gn[q] = x[okn[q] ? I::g(N, ncx, ncy, dd) : 0];
+    gni[q] = okn[q] ? I::g(N, ncx, ncy, dd) : 0;
+  }
+  T gx[NG], gn[NN];
+  {
+    const T* xc = x + (int64_t)c0 * ld;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gx[q] = xc[gxi[q]];
+#pragma unroll
+    for (int q = 0; q < NN; ++q) gn[q] = xc[gni[q]];
   }
   constexpr int NE = (int)(sizeof(Elem<T, K>) / sizeof(T)), NEQ = (NE + 255) / 256;
   T ev[NEQ];
@@ -455,7 +466,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int t = lane + 64 * q;
     decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
     if (!active || t >= (ext_guess ? NSE : NSR)) gi[q] = -1;
-    bv[q] = b[gi[q] >= 0 ? gi[q] : 0];
+    bv[q] = b[(int64_t)c0 * ld + (gi[q] >= 0 ? gi[q] : 0)];
   }
   T kv[NG];
 #pragma unroll
@@ -482,177 +493,199 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const S* A = inv + (size_t)pc * NPR;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) apk[q] = A[min(lane + 64 * q, NPR - 1)];
-  }
-
-  // 1. gathered values and element matrices to LDS
+    if (MC && !ext_guess) {
+      // several columns: stage the inverse now (read only in the products)
 #pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    const int e = lane + 64 * q;
-    if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < NN; ++q) {
-    const int e = lane + 64 * q;
-    if (e < 8 * NV) {
-      const int s = e / (2 * NV), r = e % (2 * NV);
-      nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+      for (int q = 0; q < NQ; ++q)
+        if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
     }
   }
-  {
-    T* dst = reinterpret_cast<T*>(&Es);
-#pragma unroll
-    for (int q = 0; q < NEQ; ++q)
-      if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
-    if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
-  }
-  lds_barrier();
-
-  // 2. row contributions of every patch cell (cell blocks + its four faces), one
-  // branch-free path for all rows.  A velocity row (component c, local index dd)
-  // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
-  // - h Dm[:, dd] . p, where the faces across which component c is tangential give
-  // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
-  // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
-  // coefficient rows and vectors by LDS address; absent terms read the zero block.
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    const int e = lane + 64 * q;
-    if (e >= 4 * NL) break;
-    const int s = e / NL, d = e % NL;
-    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    const T* xl = xs[w][s];
-    const bool vel = d < 2 * NV;
-    const int comp = d >= NV ? 1 : 0;
-    const int dd = vel ? d - comp * NV : d - 2 * NV;
-    // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
-    const bool lo_bnd = comp ? cx == 0 : cy == 0;
-    const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
-    const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
-    const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
-    const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
-    const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
-    const int ro = dd * NV;
-    const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
-    const T* c_mass = vel ? Es.M + ro : zblk;
-    const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
-    const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
-    const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
-    const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
-    const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
-    const T* v_self = vel ? xl + comp * NV : xl;
-    const T* v_nlo = vel ? nl : xl + NV;
-    const T* pv = xl + 2 * NV;
-    const T khh = vel ? kv[q] * hh : T(0);
-    T a = T(0), g = T(0);
-    auto term = [&](int i) {
-      a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
-      a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
-    };
-    if (PK) {
-      // bandwidth-bound levels: partial unrolling keeps the registers (and so the
-      // blocks per CU) of the rest of the kernel
-#pragma unroll 2
-      for (int i = 0; i < NV; ++i) term(i);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) term(i);
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
-    const T z = (vel ? a : mh * a) + mh * g;
-    zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
-  }
-  lds_barrier();
-
-  // 3. local residual (b - A x) on the patch entries.  The layout follows from the
-  // vertex position (extended iff an outer face of the patch lies on an open
-  // side); setup checks this rule against the patch construction.
   const bool is_ext = ext_guess;
   const int ns = is_ext ? NSE : NSR;
-  T xold[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int t = lane + 64 * q;
-    xold[q] = T(0);
-    if (t < NSE) {
-      T r = T(0);
-      if (gi[q] >= 0) {
-        r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
-        xold[q] = (&xs[w][0][0])[zA[q]];
-      }
-      rs[w][t] = r;
-    }
-  }
-  // regular rotated inverse to LDS (the extended ones are read from HBM below)
-  if (PK && !ext_guess) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
-  }
-  lds_barrier();
 
-  // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
-  if (!active) return;
-  if (PK) {
-    // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
-    //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
-    // consecutive lanes read consecutive entries, so the LDS reads are conflict-free
-    const int t = lane;
-    if (t < ns) {
-      T acc = T(0);
-      if (!is_ext) {
-        const S* Rp = aps[w];
+  for (int c = c0;;) {
+    T* xc = x + (int64_t)c * ld;
+    // 1. gathered values (and, once, the element matrices and the zero block) to LDS
 #pragma unroll
-        for (int d = 0; d <= NSR / 2; ++d) {
-          int u = t + d;
-          u -= u >= NSR ? NSR : 0;
-          acc += T(Rp[d * NSR + t]) * rs[w][u];
+    for (int q = 0; q < NG; ++q) {
+      const int e = lane + 64 * q;
+      if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NN; ++q) {
+      const int e = lane + 64 * q;
+      if (e < 8 * NV) {
+        const int s = e / (2 * NV), r = e % (2 * NV);
+        nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+      }
+    }
+    if (c == c0) {
+      T* dst = reinterpret_cast<T*>(&Es);
+#pragma unroll
+      for (int q = 0; q < NEQ; ++q)
+        if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
+      if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
+    }
+    lds_barrier();
+
+    // 2. row contributions of every patch cell (cell blocks + its four faces), one
+    // branch-free path for all rows.  A velocity row (component c, local index dd)
+    // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
+    // - h Dm[:, dd] . p, where the faces across which component c is tangential give
+    // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
+    // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
+    // coefficient rows and vectors by LDS address; absent terms read the zero block.
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int e = lane + 64 * q;
+      if (e >= 4 * NL) break;
+      const int s = e / NL, d = e % NL;
+      const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+      const T* xl = xs[w][s];
+      const bool vel = d < 2 * NV;
+      const int comp = d >= NV ? 1 : 0;
+      const int dd = vel ? d - comp * NV : d - 2 * NV;
+      // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
+      const bool lo_bnd = comp ? cx == 0 : cy == 0;
+      const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
+      const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
+      const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
+      const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
+      const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
+      const int ro = dd * NV;
+      const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
+      const T* c_mass = vel ? Es.M + ro : zblk;
+      const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
+      const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
+      const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
+      const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
+      const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
+      const T* v_self = vel ? xl + comp * NV : xl;
+      const T* v_nlo = vel ? nl : xl + NV;
+      const T* pv = xl + 2 * NV;
+      const T khh = vel ? kv[q] * hh : T(0);
+      T a = T(0), g = T(0);
+      auto term = [&](int i) {
+        a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
+        a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
+      };
+      if (PK) {
+        // bandwidth-bound levels: partial unrolling keeps the registers (and so the
+        // blocks per CU) of the rest of the kernel
+#pragma unroll 2
+        for (int i = 0; i < NV; ++i) term(i);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) term(i);
+      }
+#pragma unroll
+      for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
+      const T z = (vel ? a : mh * a) + mh * g;
+      zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
+    }
+    lds_barrier();
+
+    // 3. local residual (b - A x) on the patch entries.  The layout follows from the
+    // vertex position (extended iff an outer face of the patch lies on an open
+    // side); setup checks this rule against the patch construction.
+    T xold[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int t = lane + 64 * q;
+      xold[q] = T(0);
+      if (t < NSE) {
+        T r = T(0);
+        if (gi[q] >= 0) {
+          r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
+          xold[q] = (&xs[w][0][0])[zA[q]];
         }
+        rs[w][t] = r;
+      }
+    }
+    // regular rotated inverse to LDS, once (the extended ones are read from HBM below)
+    if (PK && !MC && !ext_guess) {
 #pragma unroll
-        for (int d = 1; d < NSR / 2; ++d) {
-          int u = t - d;
-          u += u < 0 ? NSR : 0;
-          acc += T(Rp[d * NSR + u]) * rs[w][u];
+      for (int q = 0; q < NQ; ++q)
+        if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+    }
+    lds_barrier();
+
+    // the next column's gather and b are issued before the product of this one
+    const bool more = MC && c + 1 < c1;
+    if (more) {
+      const T* xn = x + (int64_t)(c + 1) * ld;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) gx[q] = xn[gxi[q]];
+#pragma unroll
+      for (int q = 0; q < NN; ++q) gn[q] = xn[gni[q]];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) bv[q] = b[(int64_t)(c + 1) * ld + (gi[q] >= 0 ? gi[q] : 0)];
+    }
+
+    // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
+    if (active) {
+      if (PK) {
+        // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
+        //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
+        // consecutive lanes read consecutive entries, so the LDS reads are conflict-free
+        const int t = lane;
+        if (t < ns) {
+          T acc = T(0);
+          if (!is_ext) {
+            const S* Rp = aps[w];
+#pragma unroll
+            for (int d = 0; d <= NSR / 2; ++d) {
+              int u = t + d;
+              u -= u >= NSR ? NSR : 0;
+              acc += T(Rp[d * NSR + t]) * rs[w][u];
+            }
+#pragma unroll
+            for (int d = 1; d < NSR / 2; ++d) {
+              int u = t - d;
+              u += u < 0 ? NSR : 0;
+              acc += T(Rp[d * NSR + u]) * rs[w][u];
+            }
+          } else {
+            const S* Rp = invx + (size_t)ext * NPE;
+#pragma unroll 4
+            for (int d = 0; d <= NSE / 2; ++d) {
+              int u = t + d;
+              u -= u >= NSE ? NSE : 0;
+              acc += T(Rp[d * NSE + t]) * rs[w][u];
+            }
+#pragma unroll 4
+            for (int d = 1; d < NSE / 2; ++d) {
+              int u = t - d;
+              u += u < 0 ? NSE : 0;
+              acc += T(Rp[d * NSE + u]) * rs[w][u];
+            }
+          }
+          if (gi[0] >= 0) xc[gi[0]] = xold[0] + acc;
+        }
+      } else if (PF) {
+        // one product length for both layouts: r is zero beyond the patch size
+        if (lane < ns) {
+          T acc = T(0);
+#pragma unroll
+          for (int u = 0; u < (PF ? NSE : 1); ++u) acc += T(areg[u]) * rs[w][u];
+          if (gi[0] >= 0) xc[gi[0]] = xold[0] + acc;
         }
       } else {
-        const S* Rp = invx + (size_t)ext * NPE;
-#pragma unroll 4
-        for (int d = 0; d <= NSE / 2; ++d) {
-          int u = t + d;
-          u -= u >= NSE ? NSE : 0;
-          acc += T(Rp[d * NSE + t]) * rs[w][u];
-        }
-#pragma unroll 4
-        for (int d = 1; d < NSE / 2; ++d) {
-          int u = t - d;
-          u += u < 0 ? NSE : 0;
-          acc += T(Rp[d * NSE + u]) * rs[w][u];
+        const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const int t = lane + 64 * q;
+          if (t < ns) {
+            T acc = T(0);
+#pragma unroll 8
+            for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
+            if (gi[q] >= 0) xc[gi[q]] = xold[q] + acc;
+          }
         }
       }
-      if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
     }
-    return;
-  }
-  if (PF) {
-    // one product length for both layouts: r is zero beyond the patch size
-    if (lane < ns) {
-      T acc = T(0);
-#pragma unroll
-      for (int u = 0; u < (PF ? NSE : 1); ++u) acc += T(areg[u]) * rs[w][u];
-      if (gi[0] >= 0) x[gi[0]] = xold[0] + acc;
-    }
-    return;
-  }
-  const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int t = lane + 64 * q;
-    if (t < ns) {
-      T acc = T(0);
-#pragma unroll 8
-      for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
-      if (gi[q] >= 0) x[gi[q]] = xold[q] + acc;
-    }
+    if (!more) break;
+    ++c;
   }
 }
 
@@ -1066,16 +1099,28 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
                      const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs,
                      int64_t ld, hipStream_t s) {
   if (npatch <= 0) return;
-  dim3 g((npatch + 3) / 4, nrhs), bl(256);
-#define BMG_KC(TAG, PKD)                                                                                        \
-  hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h, \
-                     (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour, npatch, ld)
-  if (finest) {
-    if (packed) BMG_KC(1, true);
-    else BMG_KC(1, false);
+  // columns per block: all of them on the bandwidth-bound levels (the inverse is read
+  // once per patch); elsewhere enough blocks to fill the device come first
+  const int nblk = (npatch + 3) / 4;
+  int ncol = 1;
+  if (nrhs > 1) {
+    if (packed) ncol = nrhs;
+    else ncol = std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
+  }
+  dim3 g(nblk, (nrhs + ncol - 1) / ncol), bl(256);
+#define BMG_KC(TAG, PKD, MC)                                                                                    \
+  hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,     \
+                     (T)L.h, (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour,  \
+                     npatch, ld, nrhs, ncol)
+  if (ncol > 1) {
+    if (packed) BMG_KC(0, true, true);
+    else BMG_KC(0, false, true);
+  } else if (finest) {
+    if (packed) BMG_KC(1, true, false);
+    else BMG_KC(1, false, false);
   } else {
-    if (packed) BMG_KC(0, true);
-    else BMG_KC(0, false);
+    if (packed) BMG_KC(0, true, false);
+    else BMG_KC(0, false, false);
   }
 #undef BMG_KC
 }

@@ -164,3 +164,26 @@ def test_wrong_column_count_rejected(torch, bmg):
     sm = _solver(bmg, case, _kappa(case), 3)
     with pytest.raises(ValueError):
         sm.vcycle(torch.zeros(sm.ndof(), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_bandwidth_bound_levels_columns(torch, bmg, prec):
+    """C2 size (256^2, rotated inverses on the two finest levels): the columns of a
+    3-column V-cycle and colour step are those of one-column calls; on these levels
+    one block applies a patch inverse to all columns."""
+    w = inputs.workload("C2")
+    R = 3
+    sm = bmg.from_workload(w, prec=prec, restart=10, n_rhs=R)
+    s1 = bmg.from_workload(w, prec=prec, restart=10)
+    n = s1.ndof()
+    r = torch.stack([torch.as_tensor(inputs.random_vector(n, 80 + c), device="cuda") for c in range(R)]).contiguous()
+    z = sm.vcycle(r)
+    tol = 1e-14 if prec == 0 else 1e-6
+    for c in range(R):
+        z1 = s1.vcycle(r[c].contiguous())
+        assert _rel(z[c].cpu().numpy(), z1.cpu().numpy()) <= tol, c
+    J = w.levels
+    xm = sm.colour_step(J, 4, torch.zeros_like(r), r)
+    for c in range(R):
+        x1 = s1.colour_step(J, 4, torch.zeros_like(r[c]), r[c].contiguous())
+        assert _rel(xm[c].cpu().numpy(), x1.cpu().numpy()) <= tol, c
