@@ -108,6 +108,59 @@ def bench_c4(args, torch, bmg, inputs):
     print(json.dumps(out), flush=True)
 
 
+def bench_c5(args, torch, bmg, inputs):
+    import numpy as np
+    """C5 generator (RT_2, layered kappa, 16 smooth right-hand sides) at --n cells per
+    side: the n_rhs columns solved together (FP64 FGMRES(8) per column, lockstep), with
+    the FP32 and BF16-inverse V-cycles, and the FP64 V-cycle beside them."""
+    w = inputs.scaled_workload("C5", args.n)
+    R = args.rhs
+    srcs = [inputs.smooth_source(5100 + c) for c in range(R)]
+    res = {}
+    B = None
+    for key, prec in (("fp32", bmg.P_FP32), ("bf16", bmg.P_BF16), ("fp64", bmg.P_FP64)):
+        p = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 8,
+                            args.dense_coarse_max, R)
+        t0 = time.perf_counter()
+        s = bmg.Solver(p, w.kappa)
+        setup = time.perf_counter() - t0
+        if B is None:
+            B = torch.as_tensor(np.stack([bmg.assemble_rhs(p, f) for f in srcs]), dtype=torch.float64, device="cuda")
+            ndof = s.ndof()
+            log(f"bench: C5@{w.n} k=2, {R} right-hand sides x {ndof} dofs")
+        x = s.zeros()
+        for _ in range(args.warmup):
+            x, infos = s.solve(B, rtol=args.rtol, maxit=1000, x=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, infos = s.solve(B, rtol=args.rtol, maxit=1000, x=x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = [i.iterations for i in infos]
+        res[key] = {"solves_per_s": args.steps * R / dt, "iterations_min": min(its), "iterations_max": max(its),
+                    "worst_true_rel_residual": max(i.rel_residual_true for i in infos), "setup_s": setup,
+                    "dof_iters_per_s": ndof * sum(its) * args.steps / dt, "x": x}
+        log(f"bench: C5 {key} {res[key]['solves_per_s']:.2f} solves/s, iterations {min(its)}..{max(its)}, "
+            f"setup {setup:.1f} s")
+        s.close()
+        del s
+    ref = res["fp64"]["x"]
+    for key in res:
+        res[key]["rel_diff_vs_fp64"] = (torch.linalg.norm(res[key].pop("x") - ref) / torch.linalg.norm(ref)).item()
+    out = {"metric": f"C5 multi-RHS: right-hand sides solved/s to {args.rtol:g} rel resid",
+           "value": res["fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
+           "config": {"workload": f"C5 generator at {w.n}x{w.n}: RT_2 x dQ_2, mu=1e-2, 85 log-normal layers + "
+                                  f"channels, {R} smooth random right-hand sides solved together, FGMRES(8)",
+                      "N": w.n, "levels": w.levels + 1, "k": w.k, "n_rhs": R, "rtol": args.rtol},
+           "ndof_per_rhs": ndof, "paths": res,
+           "speedup_fp32_vs_fp64": res["fp32"]["solves_per_s"] / res["fp64"]["solves_per_s"],
+           "speedup_bf16_vs_fp64": res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,11 +170,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4"],
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4", "C5"],
                     help="C2 (default, the benchmark configuration), the 1024^2 precision study, or the "
                          "48-problem batch")
     ap.add_argument("--streams", type=int, default=4, help="C4: worker streams of the batch")
     ap.add_argument("--problems", type=int, default=48, help="C4: problems in the batch")
+    ap.add_argument("--n", type=int, default=512, help="C5: cells per side (the 2048^2 generator at this size)")
+    ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -149,6 +204,8 @@ def main():
 
     if args.workload == "C4":
         return bench_c4(args, torch, bmg, inputs)
+    if args.workload == "C5":
+        return bench_c5(args, torch, bmg, inputs)
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
