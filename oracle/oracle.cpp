@@ -28,7 +28,10 @@
 //               restriction is its transpose (eq. 3 acting on residuals).
 //   * smoother: vertex-patch Ritz projections (Section 3.3), symmetric
 //               multiplicative (eq. smoother-Multiplicative), patches visited colour
-//               by colour (9 colours by vertex index mod 3), forward then backward.
+//               by colour, forward then backward.  Two colourings of the vertices:
+//               S9, 9 colours (vx mod 3) + 3 (vy mod 3); L8, the 8 cosets of the
+//               lattice spanned by (2, 2) and (2, -2).  Same-colour patches never
+//               touch each other's dofs, so the order inside a colour is immaterial.
 //   * cycle:    standard or variable V-cycle with coarse direct solve (Section 3.2).
 //   * Krylov:   right-preconditioned flexible GMRES with modified Gram-Schmidt.
 #include <algorithm>
@@ -252,6 +255,7 @@ struct Patch {
 
 struct Level {
   int N, k;
+  int colouring = 0, ncolours = 9;
   double h, mu, sigma;
   int bc[4];
   int nb, nv, np, nloc;  // k+1, (k+2)(k+1), (k+1)^2, 2nv+np
@@ -520,12 +524,21 @@ void assemble(Level& L) {
   L.A = from_triplets(L.ndof, L.ndof, te);
 }
 
+// Colour of vertex (vx, vy): S9 (scheme 0) or L8 (scheme 1).  L8 is the coset of the
+// lattice {(x, y): x, y even, x - y = 0 mod 4} = span{(2, 2), (2, -2)} containing the
+// vertex: parity of vx, parity of vy, and whether (vx - vy) mod 4 is 0/1 or 2/3.
+int vertex_colour(int scheme, int vx, int vy) {
+  if (scheme == 0) return (vx % 3) + 3 * (vy % 3);
+  const int d = ((vx - vy) % 4 + 4) % 4;
+  return (vx & 1) + 2 * (vy & 1) + 4 * (d >= 2 ? 1 : 0);
+}
+
 // The support of velocity dof g (1 or 2 cells) lies inside the patch cell set?
 void build_patches(Level& L) {
   const int N = L.N;
   std::vector<std::pair<int, int>> order;  // (colour, vertex)
   for (int vy = 0; vy <= N; ++vy)
-    for (int vx = 0; vx <= N; ++vx) order.push_back({(vx % 3) + 3 * (vy % 3), vy * (N + 1) + vx});
+    for (int vx = 0; vx <= N; ++vx) order.push_back({vertex_colour(L.colouring, vx, vy), vy * (N + 1) + vx});
   std::sort(order.begin(), order.end());
   L.patches.assign(order.size(), Patch());
   for (int c = 0; c <= 9; ++c) L.colour_start[c] = 0;
@@ -693,10 +706,11 @@ void colour_step(const Level& L, int colour, double* x, const double* b) {
   }
 }
 
-// One application of the symmetric multiplicative smoother: colours 0..8 then 7..0.
+// One application of the symmetric multiplicative smoother: colours 0..C-1, then
+// C-2..0 (the last colour once: its local projections are idempotent).
 void smooth_once(const Level& L, double* x, const double* b) {
-  for (int c = 0; c < 9; ++c) colour_step(L, c, x, b);
-  for (int c = 7; c >= 0; --c) colour_step(L, c, x, b);
+  for (int c = 0; c < L.ncolours; ++c) colour_step(L, c, x, b);
+  for (int c = L.ncolours - 2; c >= 0; --c) colour_step(L, c, x, b);
 }
 
 void restrict_(const Level& F, const double* rf, double* bc, int nc) {
@@ -740,14 +754,18 @@ void vcycle_level(const Ctx& X, int j, const double* b, double* x) {
 }
 
 Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const double* kappa,
-            int cycle, int m_fine) {
+            int cycle, int m_fine, int colouring) {
   auto X = std::make_unique<Ctx>();
   X->J = J;
   X->k = k;
   X->cycle = cycle;
   X->m_fine = m_fine;
   X->lev.resize(J + 1);
-  for (int j = 0; j <= J; ++j) init_level(X->lev[j], n0 << j, k, mu, sigma, bc);
+  for (int j = 0; j <= J; ++j) {
+    init_level(X->lev[j], n0 << j, k, mu, sigma, bc);
+    X->lev[j].colouring = colouring;
+    X->lev[j].ncolours = colouring ? 8 : 9;
+  }
   // kappa: finest given, coarser levels by arithmetic averaging of the 4 children
   X->lev[J].kappa.assign(kappa, kappa + (size_t)(n0 << J) * (n0 << J));
   for (int j = J; j >= 1; --j) {
@@ -791,8 +809,8 @@ Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const 
 extern "C" {
 
 void* orc_create(int n0, int J, int k, double mu, double sigma, const int* bc,
-                 const double* kappa, int cycle, int m_fine) {
-  return create(n0, J, k, mu, sigma, bc, kappa, cycle, m_fine);
+                 const double* kappa, int cycle, int m_fine, int colouring) {
+  return create(n0, J, k, mu, sigma, bc, kappa, cycle, m_fine, colouring);
 }
 void orc_destroy(void* p) { delete static_cast<Ctx*>(p); }
 

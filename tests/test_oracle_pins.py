@@ -346,22 +346,75 @@ def test_prolongation_is_embedding(k, bc):
 # --------------------------------------------------------------------------
 # P8: colouring -- brute-force independence of same-colour patches
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("n0,J,k", [(2, 2, 1), (3, 1, 1), (2, 1, 2)])
-def test_same_colour_patches_do_not_interact(n0, J, k):
+def _l8_colour(vx, vy):
+    """Coset of span{(2,2),(2,-2)} = {(x, y): x, y even, x = y mod 4}: written here
+    from the lattice itself (the representative reached by subtracting lattice
+    vectors), not from the oracle's formula."""
+    # reduce modulo the lattice: (4, 0) and (0, 4) are in it, then (2, 2) takes x to {0, 1}
+    x, y = vx % 4, vy % 4
+    if x >= 2:
+        x, y = x - 2, (y - 2) % 4
+    return (x, y)
+
+
+@pytest.mark.parametrize("colouring", [0, 1])
+@pytest.mark.parametrize("n0,J,k", [(2, 2, 1), (3, 1, 1), (2, 1, 2), (3, 2, 1)])
+def test_same_colour_patches_do_not_interact(n0, J, k, colouring):
     n = n0 << J
-    o = Oracle(n0, J, k, 1.0, 6.0, [D, O, D, O], np.ones(n * n), 1, 1)
+    o = Oracle(n0, J, k, 1.0, 6.0, [D, O, D, O], np.ones(n * n), 1, 1, colouring)
     A = o.csr()
     patches = [o.patch(p) for p in range(o.npatch())]
     assert len(patches) == (n + 1) ** 2
-    for c in range(9):
+    ncol = 9 if colouring == 0 else 8
+    assert max(p[2] for p in patches) == ncol - 1
+    reps = {}
+    for c in range(ncol):
         same = [p for p in patches if p[2] == c]
+        assert same
         for a in same:
-            assert a[2] == (a[0] % 3) + 3 * (a[1] % 3)
+            if colouring == 0:
+                assert a[2] == (a[0] % 3) + 3 * (a[1] % 3)
+            else:
+                # one colour per coset of the lattice, one coset per colour
+                rep = _l8_colour(a[0], a[1])
+                assert reps.setdefault(rep, c) == c
             reads = set(A[a[3]].indices)
             for bb in same:
                 if bb is a:
                     continue
                 assert not (set(bb[3]) & reads)
+    if colouring == 1:
+        assert len(reps) == 8 and len(set(reps.values())) == 8
+
+
+def test_l8_smoother_is_a_symmetric_preconditioner_that_converges():
+    """With the L8 colouring (sweep 0..7, 6..0) the V-cycle is still symmetric and
+    FGMRES converges like with S9 (same method, other patch order)."""
+    n0, J, k = 2, 3, 1
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 8, 1e-3, 1.0)
+    o9 = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2, 0)
+    o8 = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2, 1)
+    nd = o8.ndof()
+    free = np.flatnonzero(~o8.constrained())
+    rng = np.random.default_rng(3)
+    idx = rng.choice(free, 40, replace=False)
+    B = np.zeros((len(idx), nd))
+    for r, i in enumerate(idx):
+        e = np.zeros(nd)
+        e[i] = 1.0
+        B[r] = o8.vcycle(e)
+    Bs = B[:, idx]
+    assert np.abs(Bs - Bs.T).max() < 1e-10 * np.abs(Bs).max()
+    b = o8.rhs(inputs.smooth_source(3))
+    x8, its8, _, tr8 = o8.fgmres(b, rtol=1e-10, maxit=200, restart=60)
+    x9, its9, _, tr9 = o9.fgmres(b, rtol=1e-10, maxit=200, restart=60)
+    assert its8 > 0 and its9 > 0 and abs(its8 - its9) <= 3
+    assert np.linalg.norm(x8 - x9) <= 1e-8 * np.linalg.norm(x9)
+    # the two smoothers differ (another order of the patch projections)
+    e = np.zeros(nd)
+    e[free[nd // 3]] = 1.0
+    assert np.abs(o8.smooth(1, np.zeros(nd), e) - o9.smooth(1, np.zeros(nd), e)).max() > 1e-8
 
 
 def test_patch_sizes():
