@@ -179,6 +179,9 @@ def main():
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
+    ap.add_argument("--colouring", default="S9", choices=["S9", "L8"],
+                    help="vertex colouring of the smoother (S9: 9 colours, 17 colour steps per smoothing "
+                         "step; L8: 8 colours, 15)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -209,8 +212,9 @@ def main():
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
+    colouring = bmg.COLOURING_L8 if args.colouring == "L8" else bmg.COLOURING_S9
     p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
-                          args.dense_coarse_max)
+                          args.dense_coarse_max, 1, colouring)
     t0 = time.perf_counter()
     s64 = bmg.Solver(p64, w.kappa)
     setup64 = time.perf_counter() - t0
@@ -224,7 +228,7 @@ def main():
 
     # roofline of the finest-level smoother kernel: events around its launches
     J = w.levels
-    s64.kernel_timing(J, 34 * (max(its64) + 4))  # launches of the finest smoother in one solve
+    s64.kernel_timing(J, 34 * (max(its64) + 4))  # at least the launches of the finest smoother in one solve
     s64.solve(b, rtol=args.rtol, maxit=1000)
     nl, ms, by = s64.kernel_timing_read()
     s64.kernel_timing(-1, 0)
@@ -243,15 +247,16 @@ def main():
                                   f"H(div)-DG {'Darcy' if w.mu == 0 else 'Brinkman'} mu={w.mu:g}, seeded log-normal "
                                   "kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, f=(1,0), no-slip left/right, "
                                   "open top/bottom; variable V-cycle m=2, FP64 V-cycle inside FP64 FGMRES(100), "
-                                  "rtol 1e-10",
-                      "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol},
+                                  f"rtol 1e-10, {args.colouring} colouring",
+                      "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol,
+                      "colouring": args.colouring},
            "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
     if not args.no_mixed:
         for key, prec in (("mixed", bmg.P_FP32), ("mixed_bf16", bmg.P_BF16)):
             p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
-                                  args.dense_coarse_max)
+                                  args.dense_coarse_max, 1, colouring)
             s32 = bmg.Solver(p32, w.kappa)
             x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
             s32.kernel_timing(J, 34 * (max(its32) + 4))

@@ -64,6 +64,10 @@ enum { BMG_BC_DIRICHLET = 0, BMG_BC_OPEN = 1 };                 /* sides: 0 x=0,
 enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1, BMG_P_BF16 = 2 };        /* preconditioner arithmetic: FP64; FP32;
                                                                    FP32 with bfloat16-stored patch inverses */
 enum { BMG_CYCLE_STANDARD = 0, BMG_CYCLE_VARIABLE = 1 };        /* m(j) = m_fine or m_fine 2^(J-j), Section 3.2 */
+enum { BMG_COLOURING_S9 = 0,  /* 9 colours, (vx mod 3) + 3 (vy mod 3); a smoothing step is colours 0..8, 7..0 */
+       BMG_COLOURING_L8 = 1   /* 8 colours, the cosets of the lattice spanned by (2, 2) and (2, -2):
+                                 (vx mod 2) + 2 (vy mod 2) + 4 [(vx - vy) mod 4 >= 2]; colours 0..7, 6..0 */
+};
 
 typedef struct {
   int32_t n0;            /* cells per side of the coarsest mesh T_0, 2 <= n0 <= 64 */
@@ -82,6 +86,9 @@ typedef struct {
   int32_t n_rhs;         /* right-hand sides solved together, 1..16 (0 is read as 1).  Every vector
                             argument of a handle call then holds n_rhs columns of the level's ndof
                             entries, column r at offset r * ndof (column-major, contiguous) */
+  int32_t colouring;     /* BMG_COLOURING_*: vertex colouring of the multiplicative smoother (the
+                            order of the patch projections of Section 3.3; same-colour patches never
+                            touch each other's dofs, so a colour is one parallel step) */
 } bmg_params;
 
 typedef struct {
@@ -184,13 +191,19 @@ bmg_status bmg_assemble_rhs(const bmg_params* p, const double* f_qp, const doubl
 
 /* Vertex patch (vx, vy) of level 1 <= j <= levels (Section 3.3, the cells sharing
  * the vertex; dofs whose support lies in them, essential dofs excluded): writes n,
- * the dofs in ascending global order, the colour (vx mod 3) + 3 (vy mod 3) and, if
+ * the dofs in ascending global order, its colour under p->colouring and, if
  * inv_host is not NULL, the FP64 pseudo-inverse of the patch matrix (row-major
  * n x n) exactly as setup computes it.  dofs_host must hold 12(k+1) + 8k(k+1) +
  * 4(k+1)^2 ints (an upper bound on n), inv_host the square of that many doubles.
  * kappa_host is the finest-level field as for bmg_setup. */
 bmg_status bmg_export_patch(const bmg_params* p, const double* kappa_host, int32_t level, int32_t vx, int32_t vy,
                             int32_t* n, int32_t* dofs_host, double* inv_host, int32_t* colour);
+
+/* Colour of every vertex (vx, vy) of level 1 <= j <= levels under p->colouring,
+ * at vy * (N_j + 1) + vx of colour_host ((N_j + 1)^2 ints, may be NULL), and the
+ * number of colours.  Patch p of a colour is the p-th vertex of that colour in
+ * row-major order. */
+bmg_status bmg_export_colouring(const bmg_params* p, int32_t level, int32_t* ncolours, int32_t* colour_host);
 
 /* Dense A_j (row-major, FP64) of a level with at most 32 cells per side, from the
  * reference-element blocks the kernels use; essential rows/cols are the identity. */
@@ -199,9 +212,9 @@ bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa_host
 /* ----- single steps of the cycle, for step-by-step checks (FP64 in/out, n_rhs
  * columns of the level's ndof entries) ----- */
 /* One colour step of the smoother on level j >= 1: for every vertex patch of the
- * colour (colour = (vx mod 3) + 3 (vy mod 3)), x[S] += A_S^+ (b - A_j x)[S]. */
+ * colour (under p->colouring), x[S] += A_S^+ (b - A_j x)[S]. */
 bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x_dev, const double* b_dev);
-/* `steps` applications of the symmetric smoother R_j (colours 0..8 then 7..0). */
+/* `steps` applications of the symmetric smoother R_j (colours 0..C-1 then C-2..0). */
 bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x_dev, const double* b_dev);
 /* b_{j-1} = P_j^T r_j (restriction; eq. 3 applied to residuals). */
 bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf_dev, double* bc_dev);
@@ -213,8 +226,8 @@ bmg_status bmg_coarse_solve(bmg_handle h, const double* b_dev, double* x_dev);
 /* ----- measurement ----- */
 /* Record HIP events around the colour launches of the smoother on `level` (>= 1),
  * for at most max_launches launches from now on (-1 switches timing off).  One
- * event pair brackets the 17 back-to-back launches of each smoothing step (so the
- * timed span holds the 16 short gaps between them); the events are recorded on
+ * event pair brackets the 2C - 1 back-to-back launches of each smoothing step (so
+ * the timed span holds the short gaps between them); the events are recorded on
  * the handle's stream, and V-cycles run without the graph while timing is on. */
 bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches);
 /* Launches timed so far, the summed duration of the bracketed spans and the bytes

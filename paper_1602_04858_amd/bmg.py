@@ -28,6 +28,7 @@ _lib = C.CDLL(LIBPATH)
 BC_DIRICHLET, BC_OPEN = 0, 1
 P_FP64, P_FP32, P_BF16 = 0, 1, 2
 CYCLE_STANDARD, CYCLE_VARIABLE = 0, 1
+COLOURING_S9, COLOURING_L8 = 0, 1
 
 STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM", 4: "BMG_E_HIP",
           5: "BMG_E_SINGULAR", 6: "BMG_E_NOT_CONVERGED", 7: "BMG_E_NONFINITE", 8: "BMG_E_STATE"}
@@ -37,7 +38,7 @@ class Params(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
                 ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32),
-                ("n_rhs", C.c_int32)]
+                ("n_rhs", C.c_int32), ("colouring", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -66,6 +67,7 @@ _sig = {
     "bmg_coarse_solve": [_VP, _VP, _VP],
     "bmg_export_patch": [_P(Params), _dp, _I32, _I32, _I32, _P(_I32), _ip, _VP, _P(_I32)],
     "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
+    "bmg_export_colouring": [_P(Params), _I32, _P(_I32), _VP],
     "bmg_kernel_timing": [_VP, _I32, _I32],
     "bmg_kernel_timing_read": [_VP, _P(_I32), _P(_D), _P(_D)],
     "bmg_batch_setup": [_I32, _P(Params), _P(_P(_D)), _I32, _VP, _P(_VP)],
@@ -100,7 +102,7 @@ DENSE_COARSE_DEFAULT = 16384
 
 
 def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
-                dense_coarse_max=0, n_rhs=1):
+                dense_coarse_max=0, n_rhs=1, colouring=COLOURING_S9):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
@@ -108,6 +110,7 @@ def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, pr
     p.cycle, p.m_fine, p.precond_prec, p.restart = cycle, m_fine, prec, restart
     p.dense_coarse_max = dense_coarse_max
     p.n_rhs = n_rhs
+    p.colouring = colouring
     return p
 
 
@@ -354,6 +357,17 @@ def assemble_rhs(params: Params, f, s=None, g=None):
     return b
 
 
+def export_colouring(params: Params, level):
+    """(number of colours, colour of every vertex as an (N+1, N+1) array indexed [vy, vx])."""
+    N = params.n0 << level
+    out = np.zeros((N + 1) * (N + 1), np.int32)
+    nc = C.c_int32()
+    st = _lib.bmg_export_colouring(C.byref(params), level, C.byref(nc), out.ctypes.data_as(C.c_void_p))
+    if st:
+        raise BmgError(st, "export_colouring")
+    return nc.value, out.reshape(N + 1, N + 1)
+
+
 def export_patch(params: Params, kappa, level, vx, vy, with_inverse=True):
     """(dofs ascending, pseudo-inverse or None, colour) of vertex patch (vx, vy)."""
     k = params.k
@@ -382,7 +396,7 @@ def export_level_matrix(params: Params, kappa, level):
 
 
 def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=DENSE_COARSE_DEFAULT, n_rhs=1,
-                  **kw):
+                  colouring=COLOURING_S9, **kw):
     p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart, dense_coarse_max,
-                    n_rhs)
+                    n_rhs, colouring)
     return Solver(p, w.kappa, device=device, **kw)

@@ -75,7 +75,50 @@ struct LevelArgs {
   int bcm;
   double h;
   const void* kap;  // kappa of the level, arithmetic `prec`
+  int colouring;    // COLOURING_S9 or COLOURING_L8
 };
+
+// Vertex colourings of the smoother: S9, colour (vx mod 3) + 3 (vy mod 3); L8, the
+// 8 cosets of the lattice spanned by (2, 2) and (2, -2) (x, y even, x = y mod 4),
+// colour (vx mod 2) + 2 (vy mod 2) + 4 [(vx - vy) mod 4 >= 2].  Patch p of a colour
+// is the p-th vertex of its class in row-major order.
+enum { COLOURING_S9 = 0, COLOURING_L8 = 1 };
+__host__ __device__ inline int colour_count(int scheme) { return scheme == COLOURING_L8 ? 8 : 9; }
+__host__ __device__ inline int colour_of(int scheme, int vx, int vy) {
+  if (scheme != COLOURING_L8) return (vx % 3) + 3 * (vy % 3);
+  return (vx & 1) + 2 * (vy & 1) + 4 * ((((vx - vy) % 4 + 4) % 4) >= 2 ? 1 : 0);
+}
+// L8, colour c: rows vy = py, py + 2, ...; in row vy the vertices vx = ((vy + m) mod 4) + 4 i
+// with m = (vx - vy) mod 4 = 2 (c >> 2) + (px - py mod 2)
+__host__ __device__ inline int l8_row_count(int N, int vy, int m) {
+  const int v0 = (vy + m) & 3;
+  return v0 <= N ? (N - v0) / 4 + 1 : 0;
+}
+__host__ __device__ inline int npatch_of(int scheme, int N, int colour) {
+  if (scheme != COLOURING_L8) {
+    const int c3x = colour % 3, c3y = colour / 3;
+    if (c3x > N || c3y > N) return 0;
+    return ((N - c3x) / 3 + 1) * ((N - c3y) / 3 + 1);
+  }
+  const int px = colour & 1, py = (colour >> 1) & 1, m = 2 * (colour >> 2) + ((px - py) & 1);
+  int n = 0;
+  for (int vy = py; vy <= N; vy += 2) n += l8_row_count(N, vy, m);
+  return n;
+}
+__host__ __device__ inline void patch_vertex(int scheme, int N, int colour, int p, int& vx, int& vy) {
+  if (scheme != COLOURING_L8) {
+    const int c3x = colour % 3, c3y = colour / 3;
+    const int nvx = (N - c3x) / 3 + 1;
+    vx = c3x + 3 * (p % nvx);
+    vy = c3y + 3 * (p / nvx);
+    return;
+  }
+  const int px = colour & 1, py = (colour >> 1) & 1, m = 2 * (colour >> 2) + ((px - py) & 1);
+  const int nA = l8_row_count(N, py, m), nB = py + 2 <= N ? l8_row_count(N, py + 2, m) : 0;
+  const int pair = p / (nA + nB), rem = p - pair * (nA + nB);
+  vy = py + 4 * pair + (rem < nA ? 0 : 2);
+  vx = ((vy + m) & 3) + 4 * (rem < nA ? rem : rem - nA);
+}
 
 // Level kernels work on nrhs vectors stored ld elements apart (grid.y = vector).
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,

@@ -111,11 +111,7 @@ int64_t n_p_of(int N, int k) { return (int64_t)(k + 1) * (k + 1) * N * N; }
 
 constexpr int kMaxRhs = 16;
 
-int npatch_colour(int N, int colour) {
-  const int c3x = colour % 3, c3y = colour / 3;
-  if (c3x > N || c3y > N) return 0;
-  return ((N - c3x) / 3 + 1) * ((N - c3y) / 3 + 1);
-}
+
 
 bmg_status check_params(const bmg_params* p) {
   if (!p) return BMG_E_ARG;
@@ -132,6 +128,7 @@ bmg_status check_params(const bmg_params* p) {
   if (p->restart < 1 || p->restart > 512) return BMG_E_ARG;
   if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
   if (p->n_rhs < 0 || p->n_rhs > kMaxRhs) return BMG_E_ARG;
+  if (p->colouring != COLOURING_S9 && p->colouring != COLOURING_L8) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -561,19 +558,23 @@ void init_levels(bmg_ctx* c) {
     if (j > 0) {
       HostIdx I(L.N, p.k, c->bcm);
       for (int col = 0; col < 9; ++col) {
-        L.npatch[col] = npatch_colour(L.N, col);
+        L.npatch[col] = col < colour_count(p.colouring) ? npatch_of(p.colouring, L.N, col) : 0;
         int ne = 0;
-        const int c3x = col % 3, c3y = col / 3;
-        // only vertices next to an open side can need the extended layout
-        for (int vy = c3y; vy <= L.N; vy += 3)
-          for (int vx = c3x; vx <= L.N; vx += 3) {
-            const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
-            const bool e = near && needs_ext(I, vx, vy);
-            if (e != ext_rule(I, vx, vy)) c->layout_mismatch = true;
-            if (e) ++ne;
-          }
+        for (int q = 0; q < L.npatch[col]; ++q) {
+          int vx, vy;
+          patch_vertex(p.colouring, L.N, col, q, vx, vy);
+          // only vertices next to an open side can need the extended layout
+          const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
+          const bool e = near && needs_ext(I, vx, vy);
+          if (e != ext_rule(I, vx, vy) || colour_of(p.colouring, vx, vy) != col) c->layout_mismatch = true;
+          if (e) ++ne;
+        }
         L.next[col] = ne;
       }
+      // the colour classes enumerate every vertex exactly once
+      int total = 0;
+      for (int col = 0; col < 9; ++col) total += L.npatch[col];
+      if (total != (L.N + 1) * (L.N + 1)) c->layout_mismatch = true;
     }
   }
 }
@@ -776,12 +777,12 @@ bmg_status build_patches(bmg_ctx* c, int j) {
   for (int col = 0; col < 9; ++col) {
     const int np = L.npatch[col];
     if (np == 0) continue;
-    const int c3x = col % 3, c3y = col / 3;
-    const int nvx = (L.N - c3x) / 3 + 1;
+    const int scheme = c->p.colouring;
     std::vector<int32_t> ext(np, -1);
     int ne = 0;
     for (int p = 0; p < np; ++p) {
-      const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+      int vx, vy;
+      patch_vertex(scheme, L.N, col, p, vx, vy);
       const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
       if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
     }
@@ -790,7 +791,8 @@ bmg_status build_patches(bmg_ctx* c, int j) {
     std::vector<double> reg((size_t)np * er, 0.0), exd((size_t)std::max(ne, 1) * ee, 0.0);
     std::atomic<int> bad{0};
     parallel_for(np, [&](int p) {
-      const int vx = c3x + 3 * (p % nvx), vy = c3y + 3 * (p / nvx);
+      int vx, vy;
+      patch_vertex(scheme, L.N, col, p, vx, vy);
       const bool isx = ext[p] >= 0;
       PatchLayout P = build_layout(I, vx, vy, isx);
       std::vector<double> A, pinv;
@@ -834,6 +836,7 @@ LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
   a.bcm = c->bcm;
   a.h = c->lev[j].h;
   a.kap = fp64 ? (const void*)c->lev[j].kap64 : c->lev[j].kap;
+  a.colouring = c->p.colouring;
   return a;
 }
 
@@ -857,12 +860,14 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs
   LevelArgs a = largs(c, j, c->prec == 0);
   const bool timed = (c->timing_level == j);
   for (int st = 0; st < steps; ++st) {
-    // one event pair around the 17 back-to-back launches of a smoothing step, so
+    // one event pair around the 2C - 1 back-to-back launches of a smoothing step, so
     // that no marker sits between two colour kernels
     const bool rec = timed && c->ev_used + 2 <= c->ev.size();
     if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
-    for (int i = 0; i < 17; ++i) {
-      const int col = i < 9 ? i : 16 - i;
+    // colours 0..C-1 then C-2..0
+    const int C = colour_count(c->p.colouring);
+    for (int i = 0; i < 2 * C - 1; ++i) {
+      const int col = i < C ? i : 2 * C - 2 - i;
       launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
                     L.npatch[col], j == (int)c->lev.size() - 1, packed_level(c->K, L.N), nrhs, L.ndof, c->stream);
       if (rec) c->timed_bytes += colour_bytes(c, j, col) * nrhs;
@@ -870,7 +875,7 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs
     if (rec) {
       hipEventRecord(c->ev[c->ev_used + 1], c->stream);
       c->ev_used += 2;
-      c->timed_launches += 17;
+      c->timed_launches += 2 * colour_count(c->p.colouring) - 1;
     }
   }
 }
@@ -1127,7 +1132,7 @@ bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) 
   h->timed_bytes = 0.0;
   h->timing_level = level;
   if (level < 0) return BMG_OK;
-  h->ev.resize((size_t)2 * ((max_launches + 16) / 17));
+  h->ev.resize((size_t)2 * ((max_launches + 14) / 15));
   for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   return BMG_OK;
 }
@@ -1186,7 +1191,9 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) {
 
 // Step entry points: FP64 vectors in/out, run in the handle's arithmetic.
 bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x, const double* b) {
-  if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || colour < 0 || colour > 8) return BMG_E_ARG;
+  if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || colour < 0 ||
+      colour >= colour_count(h->p.colouring))
+    return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
   const int64_t nt = L.ndof * h->R;
   launch_cast(h->prec, 0, x, L.x, nt, h->stream);
@@ -1574,7 +1581,7 @@ bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t le
     if (P.g[t] >= 0) idx.push_back(t);
   *n = (int32_t)idx.size();
   for (size_t i = 0; i < idx.size(); ++i) dofs[i] = (int32_t)P.g[idx[i]];
-  if (colour) *colour = (vx % 3) + 3 * (vy % 3);
+  if (colour) *colour = colour_of(p->colouring, vx, vy);
   if (inv) {
     LevelInfo L;
     L.N = N;
@@ -1588,6 +1595,18 @@ bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t le
     for (size_t i = 0; i < m; ++i)
       for (size_t j = 0; j < m; ++j) inv[i * m + j] = pinv[(size_t)idx[i] * P.ns + idx[j]];
   }
+  return BMG_OK;
+}
+
+bmg_status bmg_export_colouring(const bmg_params* p, int32_t level, int32_t* ncolours, int32_t* colour_host) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if (level < 1 || level > p->levels) return BMG_E_ARG;
+  const int N = p->n0 << level;
+  if (ncolours) *ncolours = colour_count(p->colouring);
+  if (colour_host)
+    for (int vy = 0; vy <= N; ++vy)
+      for (int vx = 0; vx <= N; ++vx) colour_host[vy * (N + 1) + vx] = colour_of(p->colouring, vx, vy);
   return BMG_OK;
 }
 

@@ -374,7 +374,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
-                                                int colour, int npatch, int64_t ld, int nrhs, int ncol) {
+                                                int colour, int scheme, int npatch, int64_t ld, int nrhs,
+                                                int ncol) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
@@ -403,9 +404,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   const int p = blockIdx.x * 4 + w;
   const bool active = p < npatch;
   const int pc = active ? p : npatch - 1;  // in-bounds stand-in for idle waves
-  const int c3x = colour % 3, c3y = colour / 3;
-  const int nvx = (N - c3x) / 3 + 1;
-  const int vx = c3x + 3 * (pc % nvx), vy = c3y + 3 * (pc / nvx);
+  int vx, vy;
+  patch_vertex(scheme, N, colour, pc, vx, vy);
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
   const int ext = active ? extidx[pc] : -1;
@@ -1111,7 +1111,7 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
 #define BMG_KC(TAG, PKD, MC)                                                                                    \
   hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,     \
                      (T)L.h, (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour,  \
-                     npatch, ld, nrhs, ncol)
+                     L.colouring, npatch, ld, nrhs, ncol)
   if (ncol > 1) {
     if (packed) BMG_KC(0, true, true);
     else BMG_KC(0, false, true);

@@ -208,3 +208,35 @@ def test_batch_setup_rejects_bad_arguments():
     assert lib.bmg_batch_setup(1, arr, nullk, 4, None, C.byref(h)) == 1
     assert lib.bmg_batch_solve(None, None, None, 1e-10, 10, None) == 1
     assert lib.bmg_batch_destroy(None) == 1
+
+
+@pytest.mark.parametrize("colouring", [0, 1])
+def test_colouring_export_matches_oracle(colouring):
+    """bmg_export_colouring and the colour of bmg_export_patch equal the oracle's
+    patch colours, vertex by vertex (S9 and L8)."""
+    for n0, J, k in ((2, 2, 1), (3, 2, 1), (2, 2, 2)):
+        n = n0 << J
+        kap = np.ones(n * n)
+        p = bmg.make_params(n0, J, k, 1.0, 6.0, [D, D, O, O], colouring=colouring)
+        o = Oracle(n0, J, k, 1.0, 6.0, [D, D, O, O], kap, 1, 2, colouring)
+        ncol, col = bmg.export_colouring(p, J)
+        assert ncol == (9 if colouring == 0 else 8)
+        for pi in range(o.npatch()):
+            vx, vy, c, _, _, _ = o.patch(pi)
+            assert col[vy, vx] == c
+        assert bmg.export_patch(p, kap, J, 1, 2, with_inverse=False)[2] == col[2, 1]
+
+
+@pytest.mark.parametrize("colouring", [0, 1])
+def test_colour_classes_cover_every_vertex(colouring):
+    """The kernels enumerate patch p of a colour arithmetically; setup (and plan)
+    refuse with BMG_E_STATE unless that enumeration visits every vertex once with its
+    own colour.  Many mesh sizes and all boundary combinations."""
+    for n0 in (2, 3, 5):
+        for J in (1, 2, 3, 4):
+            for code in (0, 5, 10, 15):
+                bc = [(code >> s) & 1 for s in range(4)]
+                bmg.plan(bmg.make_params(n0, J, 1, 1e-2, 6.0, bc, restart=4, colouring=colouring))
+    with pytest.raises(bmg.BmgError) as e:
+        bmg.plan(bmg.make_params(2, 2, 1, 1e-2, 6.0, [D, D, O, O], colouring=2))
+    assert e.value.status == 1
