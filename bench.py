@@ -46,13 +46,14 @@ def timed_solves(torch, s, b, steps, warmup, rtol):
     return x, info, dt, its
 
 
-def cpu_baseline(w, iterations_full, sample_its):
-    """The oracle (plain FP64 CPU) on the same workload: setup untimed, then the
-    first `sample_its` FGMRES iterations timed and scaled to a full solve."""
+def cpu_baseline(w, iterations_full, sample_its, colouring=0):
+    """The oracle (plain FP64 CPU) on the same workload and smoother colouring: setup
+    untimed, then the first `sample_its` FGMRES iterations timed and scaled to a full
+    solve."""
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    o = Oracle.from_workload(w)
+    o = Oracle(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.kappa, w.cycle, w.m_fine, colouring)
     b = o.rhs(w.source)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -179,9 +180,10 @@ def main():
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
-    ap.add_argument("--colouring", default="S9", choices=["S9", "L8"],
+    ap.add_argument("--colouring", default="auto", choices=["S9", "L8", "auto"],
                     help="vertex colouring of the smoother (S9: 9 colours, 17 colour steps per smoothing "
-                         "step; L8: 8 colours, 15)")
+                         "step; L8: 8 colours, 15; auto: the faster one per precision, timed by bmg_autotune "
+                         "before the timed region)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -213,8 +215,19 @@ def main():
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")
     colouring = bmg.COLOURING_L8 if args.colouring == "L8" else bmg.COLOURING_S9
-    p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
-                          args.dense_coarse_max, 1, colouring)
+    tuned = {}
+
+    def choose(p, key):
+        if args.colouring != "auto":
+            return p
+        best, ms = bmg.autotune(p, w.kappa)
+        tuned[key] = {"chosen": "L8" if best.colouring == bmg.COLOURING_L8 else "S9", "ms_per_vcycle": ms}
+        log(f"bench: autotune {key}: S9 {ms['S9']:.3f} ms, L8 {ms['L8']:.3f} ms per V-cycle -> "
+            f"{tuned[key]['chosen']}")
+        return best
+
+    p64 = choose(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
+                                 args.dense_coarse_max, 1, colouring), "fp64")
     t0 = time.perf_counter()
     s64 = bmg.Solver(p64, w.kappa)
     setup64 = time.perf_counter() - t0
@@ -240,6 +253,7 @@ def main():
             "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
     log(f"bench: finest smoother {achieved:.0f} GB/s over {nl} launches, avg {avg_s * 1e6:.1f} us")
 
+    col64 = "L8" if p64.colouring == bmg.COLOURING_L8 else "S9"
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -247,16 +261,16 @@ def main():
                                   f"H(div)-DG {'Darcy' if w.mu == 0 else 'Brinkman'} mu={w.mu:g}, seeded log-normal "
                                   "kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, f=(1,0), no-slip left/right, "
                                   "open top/bottom; variable V-cycle m=2, FP64 V-cycle inside FP64 FGMRES(100), "
-                                  f"rtol 1e-10, {args.colouring} colouring",
+                                  f"rtol 1e-10, {col64} colouring",
                       "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol,
-                      "colouring": args.colouring},
+                      "colouring": col64},
            "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
     if not args.no_mixed:
         for key, prec in (("mixed", bmg.P_FP32), ("mixed_bf16", bmg.P_BF16)):
-            p32 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
-                                  args.dense_coarse_max, 1, colouring)
+            p32 = choose(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
+                                         args.dense_coarse_max, 1, colouring), key)
             s32 = bmg.Solver(p32, w.kappa)
             x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
             s32.kernel_timing(J, 34 * (max(its32) + 4))
@@ -275,10 +289,12 @@ def main():
             s32.close()
             del s32
 
+    if tuned:
+        out["autotune"] = tuned
     out["roofline"] = roof
     if not args.no_cpu_baseline and args.workload == "C2":
         log("bench: CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(w, its64[-1], args.cpu_sample_its)
+        out["cpu_baseline"] = cpu_baseline(w, its64[-1], args.cpu_sample_its, p64.colouring)
     print(json.dumps(out), flush=True)
 
 

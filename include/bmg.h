@@ -172,6 +172,17 @@ bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out);
 const char* bmg_batch_last_error(bmg_batch_handle b);
 bmg_status bmg_batch_destroy(bmg_batch_handle b);
 
+/* ----- autotuning ----- */
+/* Pick the smoother schedule for p: set up a handle for every candidate colouring
+ * (S9, L8), time `trials` preconditioner applications (V-cycles, graph replay) on
+ * hip_stream with HIP events, and write the parameters of the fastest into *best
+ * (p with its colouring replaced).  ms_per_vcycle: NULL or 2 doubles, the measured
+ * time per V-cycle of S9 and L8.  The candidates give the same method with another
+ * order of the patch projections (Section 3.3); iteration counts are not measured.
+ * Allocates and frees its own device memory; costs two setups. */
+bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
+                        bmg_params* best, double* ms_per_vcycle);
+
 /* ----- setup-side host calls (no handle, no device) ----- */
 /* Quadrature points of bmg_assemble_rhs on the finest mesh of p (host arrays).
  * cell_xy: N*N cells x q*q points (point iy*q + ix) x 2, q = k+2 Gauss points per

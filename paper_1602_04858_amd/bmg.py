@@ -68,6 +68,7 @@ _sig = {
     "bmg_export_patch": [_P(Params), _dp, _I32, _I32, _I32, _P(_I32), _ip, _VP, _P(_I32)],
     "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
     "bmg_export_colouring": [_P(Params), _I32, _P(_I32), _VP],
+    "bmg_autotune": [_P(Params), _dp, _VP, _I32, _P(Params), _VP],
     "bmg_kernel_timing": [_VP, _I32, _I32],
     "bmg_kernel_timing_read": [_VP, _P(_I32), _P(_D), _P(_D)],
     "bmg_batch_setup": [_I32, _P(Params), _P(_P(_D)), _I32, _VP, _P(_VP)],
@@ -355,6 +356,20 @@ def assemble_rhs(params: Params, f, s=None, g=None):
     if st:
         raise BmgError(st, "assemble_rhs")
     return b
+
+
+def autotune(params: Params, kappa, trials=5, device="cuda"):
+    """(parameters with the faster colouring, {"S9": ms, "L8": ms} per V-cycle), by bmg_autotune."""
+    import torch
+    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    stream = torch.cuda.current_stream(torch.device(device))
+    best = Params()
+    ms = np.zeros(2)
+    st = _lib.bmg_autotune(C.byref(params), kap, C.c_void_p(stream.cuda_stream), trials, C.byref(best),
+                           ms.ctypes.data_as(C.c_void_p))
+    if st:
+        raise BmgError(st, f"autotune: {_lib.bmg_last_error(None).decode()}")
+    return best, {"S9": float(ms[0]), "L8": float(ms[1])}
 
 
 def export_colouring(params: Params, level):

@@ -1733,4 +1733,54 @@ bmg_status bmg_batch_destroy(bmg_batch_handle b) {
   return BMG_OK;
 }
 
+
+// ----- autotuning of the smoother schedule -----
+bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
+                        bmg_params* best, double* ms_per_vcycle) {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if (!best || trials < 1 || trials > 1000) return BMG_E_ARG;
+  if ((st = check_kappa(p, kappa_host))) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double best_ms = -1.0;
+  for (int cand = 0; cand < 2; ++cand) {
+    bmg_params q = *p;
+    q.colouring = cand == 0 ? BMG_COLOURING_S9 : BMG_COLOURING_L8;
+    bmg_handle h = nullptr;
+    if ((st = bmg_setup(&q, kappa_host, nullptr, 0, hip_stream, &h))) return st;
+    LevelInfo& L = h->lev.back();
+    const int64_t n = L.ndof * h->R;
+    double* r = nullptr;
+    double* z = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.0f;
+    bool ok = hipMalloc((void**)&r, n * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&z, n * sizeof(double)) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess;
+    if (ok) {
+      // a smooth-free input: constant 1 on the free rows (the timing does not depend on the values)
+      std::vector<double> one(n, 1.0);
+      ok = hipMemcpyAsync(r, one.data(), n * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess;
+      apply_precond(h, r, z);  // captures the graph
+      ok = ok && hipEventRecord(e0, s) == hipSuccess;
+      for (int t = 0; ok && t < trials; ++t) apply_precond(h, r, z);
+      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (r) (void)hipFree(r);
+    if (z) (void)hipFree(z);
+    bmg_destroy(h);
+    if (!ok) return BMG_E_HIP;
+    const double per = ms / trials;
+    if (ms_per_vcycle) ms_per_vcycle[cand] = per;
+    if (best_ms < 0.0 || per < best_ms) {
+      best_ms = per;
+      *best = q;
+    }
+  }
+  return BMG_OK;
+}
+
 }  // extern "C"

@@ -118,3 +118,15 @@ def test_l8_c2_full_size(torch, bmg):
     assert i8.converged == 1 and i8.rel_residual_true < 2e-10
     assert abs(i8.iterations - i9.iterations) <= 3
     assert _rel(x8.cpu().numpy(), x9.cpu().numpy()) < 1e-8
+
+
+def test_autotune_returns_a_measured_candidate(torch, bmg):
+    case = CASES[0]
+    n0, J, k, mu, sigma, bc = case
+    n = n0 << J
+    kap = inputs.kappa_lognormal_channels(n, 5, channels=3, width=2)
+    p = bmg.make_params(n0, J, k, mu, sigma, bc, prec=1, restart=20, dense_coarse_max=16384)
+    best, ms = bmg.autotune(p, kap, trials=3)
+    assert ms["S9"] > 0 and ms["L8"] > 0
+    assert best.colouring == (1 if ms["L8"] < ms["S9"] else 0)
+    assert (best.n0, best.levels, best.k, best.precond_prec) == (n0, J, k, 1)
