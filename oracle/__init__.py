@@ -73,6 +73,7 @@ def lib():
             "orc_level_destroy": (V, [P]),
             "orc_level_ndof": (I, [P]),
             "orc_level_rows": (V, [P, I, _ip, _dp, _dp]),
+            "orc_set_smoother": (V, [P, I, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -103,8 +104,10 @@ def gauss(q: int):
 class Oracle:
     """One problem: mesh hierarchy, level operators, patches, transfers, coarse solve."""
 
-    def __init__(self, n0, levels, k, mu, sigma, bc, kappa, cycle=1, m_fine=2, colouring=0):
-        """colouring: 0 = S9 ((vx mod 3) + 3 (vy mod 3)), 1 = L8 (cosets of span{(2,2),(2,-2)})."""
+    def __init__(self, n0, levels, k, mu, sigma, bc, kappa, cycle=1, m_fine=2, colouring=0, smoother=0,
+                 omega=0.25):
+        """colouring: 0 = S9 ((vx mod 3) + 3 (vy mod 3)), 1 = L8 (cosets of span{(2,2),(2,-2)}).
+        smoother: 0 = symmetric multiplicative (Section 3.3), 1 = additive with damping omega."""
         self.n0, self.J, self.k, self.mu, self.sigma = n0, levels, k, mu, sigma
         self.colouring = colouring
         self.bc = np.ascontiguousarray(bc, dtype=np.int32)
@@ -114,6 +117,8 @@ class Oracle:
         self.h = lib().orc_create(n0, levels, k, mu, sigma, self.bc, kap, cycle, m_fine, colouring)
         if not self.h:
             raise RuntimeError("oracle setup failed (singular coarse matrix)")
+        if smoother:
+            lib().orc_set_smoother(self.h, smoother, float(omega))
 
     @classmethod
     def from_workload(cls, w):

@@ -256,6 +256,8 @@ struct Patch {
 struct Level {
   int N, k;
   int colouring = 0, ncolours = 9;
+  int smoother = 0;     // 0: symmetric multiplicative, 1: additive
+  double omega = 0.25;  // damping of the additive smoother
   double h, mu, sigma;
   int bc[4];
   int nb, nv, np, nloc;  // k+1, (k+2)(k+1), (k+1)^2, 2nv+np
@@ -706,9 +708,32 @@ void colour_step(const Level& L, int colour, double* x, const double* b) {
   }
 }
 
+// One application of the additive Schwarz smoother over the same patch spaces:
+// x += omega sum_v R_v^T A_v^+ R_v (b - A x), every local problem solved with the
+// residual of the input x (the paper's multiplicative smoother applies the same
+// projections one after the other; the damping omega is a parameter of this variant).
+void additive_once(const Level& L, double* x, const double* b) {
+  std::vector<double> r(L.ndof), y(L.ndof, 0.0);
+  for (int i = 0; i < L.ndof; ++i) r[i] = b[i] - L.A.row_dot(i, x);
+  for (const Patch& P : L.patches) {
+    const int n = (int)P.dofs.size();
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += P.inv[(size_t)i * n + j] * r[P.dofs[j]];
+      y[P.dofs[i]] += s;
+    }
+  }
+  for (int i = 0; i < L.ndof; ++i) x[i] += L.omega * y[i];
+}
+
 // One application of the symmetric multiplicative smoother: colours 0..C-1, then
-// C-2..0 (the last colour once: its local projections are idempotent).
+// C-2..0 (the last colour once: its local projections are idempotent); or of the
+// additive one.
 void smooth_once(const Level& L, double* x, const double* b) {
+  if (L.smoother == 1) {
+    additive_once(L, x, b);
+    return;
+  }
   for (int c = 0; c < L.ncolours; ++c) colour_step(L, c, x, b);
   for (int c = L.ncolours - 2; c >= 0; --c) colour_step(L, c, x, b);
 }
@@ -861,6 +886,13 @@ void orc_colour_step(void* p, int j, int colour, double* x, const double* b) {
 }
 void orc_smooth(void* p, int j, int steps, double* x, const double* b) {
   for (int s = 0; s < steps; ++s) smooth_once(LV(p, j), x, b);
+}
+// smoother 0: multiplicative (default), 1: additive with damping omega; all levels
+void orc_set_smoother(void* p, int smoother, double omega) {
+  for (Level& L : static_cast<Ctx*>(p)->lev) {
+    L.smoother = smoother;
+    L.omega = omega;
+  }
 }
 int orc_p_nnz(void* p, int j) { return (int)LV(p, j).P.v.size(); }
 void orc_p_csr(void* p, int j, int* rp, int* ci, double* v) {

@@ -521,3 +521,60 @@ def test_sampled_rows_equal_assembled_operator(k, bc):
     y = o.apply(x)
     rows = np.arange(o.ndof())
     assert np.abs(lv.rows(rows, x) - y).max() <= 1e-14 * np.abs(y).max()
+
+
+# --------------------------------------------------------------------------
+# Additive vertex-patch Schwarz variant (same patch spaces, one residual)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k,bc", [(1, [D, D, O, O]), (2, [D, O, D, O])])
+def test_additive_step_is_the_damped_sum_of_patch_corrections(k, bc):
+    """x + omega sum_v R_v^T A_v^+ R_v (b - A x), written here from the exported
+    operator and patch inverses, equals the oracle's additive smoothing step."""
+    n0, J = 2, 2
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 9, 1e-3, 1.0)
+    omega = 0.3
+    o = Oracle(n0, J, k, 1e-2, 6.0 if k == 1 else 12.0, bc, kap, 1, 2, 0, 1, omega)
+    A = o.csr()
+    nd = o.ndof()
+    cons = o.constrained()
+    x = inputs.random_vector(nd, 1)
+    b = inputs.random_vector(nd, 2)
+    x[cons] = 0.0
+    b[cons] = 0.0
+    r = b - A @ x
+    y = np.zeros(nd)
+    for p in range(o.npatch()):
+        _, _, _, dofs, _, inv = o.patch(p)
+        y[dofs] += inv @ r[dofs]
+    expect = x + omega * y
+    got = o.smooth(1, x, b)
+    assert np.abs(got - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_additive_vcycle_is_symmetric_and_converges():
+    n0, J, k = 2, 3, 1
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 10, 1e-3, 1.0)
+    oa = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2, 0, 1, 0.25)
+    nd = oa.ndof()
+    free = np.flatnonzero(~oa.constrained())
+    rng = np.random.default_rng(5)
+    idx = rng.choice(free, 40, replace=False)
+    B = np.zeros((len(idx), nd))
+    for r_, i in enumerate(idx):
+        e = np.zeros(nd)
+        e[i] = 1.0
+        B[r_] = oa.vcycle(e)
+    Bs = B[:, idx]
+    assert np.abs(Bs - Bs.T).max() < 1e-10 * np.abs(Bs).max()
+    b = oa.rhs(inputs.smooth_source(3))
+    xa, itsa, _, tra = oa.fgmres(b, rtol=1e-10, maxit=300, restart=100)
+    om = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2)
+    xm, itsm, _, _ = om.fgmres(b, rtol=1e-10, maxit=300, restart=100)
+    assert itsa > 0 and tra < 2e-10
+    assert np.linalg.norm(xa - xm) <= 1e-8 * np.linalg.norm(xm)
+    # zero damping: the smoother does nothing
+    o0 = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2, 0, 1, 0.0)
+    x0 = inputs.random_vector(nd, 7)
+    assert np.array_equal(o0.smooth(1, x0, b), x0)
