@@ -184,6 +184,10 @@ def main():
                     help="vertex colouring of the smoother (S9: 9 colours, 17 colour steps per smoothing "
                          "step; L8: 8 colours, 15; auto: the faster one per precision, timed by bmg_autotune "
                          "before the timed region)")
+    ap.add_argument("--smoother", default="multiplicative", choices=["multiplicative", "additive"],
+                    help="the paper's symmetric multiplicative smoother, or the additive variant over the same "
+                         "patches (damping --omega)")
+    ap.add_argument("--omega", type=float, default=0.25)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer three times (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -226,8 +230,9 @@ def main():
             f"{tuned[key]['chosen']}")
         return best
 
+    smoother = bmg.SMOOTHER_ADDITIVE if args.smoother == "additive" else bmg.SMOOTHER_MULTIPLICATIVE
     p64 = choose(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
-                                 args.dense_coarse_max, 1, colouring), "fp64")
+                                 args.dense_coarse_max, 1, colouring, smoother, args.omega), "fp64")
     t0 = time.perf_counter()
     s64 = bmg.Solver(p64, w.kappa)
     setup64 = time.perf_counter() - t0
@@ -261,16 +266,16 @@ def main():
                                   f"H(div)-DG {'Darcy' if w.mu == 0 else 'Brinkman'} mu={w.mu:g}, seeded log-normal "
                                   "kappa (log10 ~ N(-3,1.5) in [-6,0]) + 20 channels, f=(1,0), no-slip left/right, "
                                   "open top/bottom; variable V-cycle m=2, FP64 V-cycle inside FP64 FGMRES(100), "
-                                  f"rtol 1e-10, {col64} colouring",
+                                  f"rtol 1e-10, {col64} colouring, {args.smoother} smoother",
                       "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "rtol": args.rtol,
-                      "colouring": col64},
+                      "colouring": col64, "smoother": args.smoother},
            "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
     if not args.no_mixed:
         for key, prec in (("mixed", bmg.P_FP32), ("mixed_bf16", bmg.P_BF16)):
             p32 = choose(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
-                                         args.dense_coarse_max, 1, colouring), key)
+                                         args.dense_coarse_max, 1, colouring, smoother, args.omega), key)
             s32 = bmg.Solver(p32, w.kappa)
             x32, info32, dt32, its32 = timed_solves(torch, s32, b, args.steps, args.warmup, args.rtol)
             s32.kernel_timing(J, 34 * (max(its32) + 4))

@@ -64,6 +64,7 @@ enum { BMG_BC_DIRICHLET = 0, BMG_BC_OPEN = 1 };                 /* sides: 0 x=0,
 enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1, BMG_P_BF16 = 2 };        /* preconditioner arithmetic: FP64; FP32;
                                                                    FP32 with bfloat16-stored patch inverses */
 enum { BMG_CYCLE_STANDARD = 0, BMG_CYCLE_VARIABLE = 1 };        /* m(j) = m_fine or m_fine 2^(J-j), Section 3.2 */
+enum { BMG_SMOOTHER_MULTIPLICATIVE = 0, BMG_SMOOTHER_ADDITIVE = 1 };
 enum { BMG_COLOURING_S9 = 0,  /* 9 colours, (vx mod 3) + 3 (vy mod 3); a smoothing step is colours 0..8, 7..0 */
        BMG_COLOURING_L8 = 1   /* 8 colours, the cosets of the lattice spanned by (2, 2) and (2, -2):
                                  (vx mod 2) + 2 (vy mod 2) + 4 [(vx - vy) mod 4 >= 2]; colours 0..7, 6..0 */
@@ -89,6 +90,12 @@ typedef struct {
   int32_t colouring;     /* BMG_COLOURING_*: vertex colouring of the multiplicative smoother (the
                             order of the patch projections of Section 3.3; same-colour patches never
                             touch each other's dofs, so a colour is one parallel step) */
+  int32_t smoother;      /* BMG_SMOOTHER_*: 0 (default) the symmetric multiplicative smoother of
+                            eq. (smoother-Multiplicative); 1 the additive Schwarz smoother over the same
+                            patch spaces, x += omega sum_v R_v^T A_v^+ R_v (b - A x) */
+  double omega;          /* damping of the additive smoother, 0 < omega <= 1 (each cell lies in at
+                            most four patches, so omega <= 1/4 keeps a step a contraction; 0.25 is
+                            used in the tests); ignored by the multiplicative one */
 } bmg_params;
 
 typedef struct {
@@ -222,10 +229,12 @@ bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa_host
 
 /* ----- single steps of the cycle, for step-by-step checks (FP64 in/out, n_rhs
  * columns of the level's ndof entries) ----- */
-/* One colour step of the smoother on level j >= 1: for every vertex patch of the
- * colour (under p->colouring), x[S] += A_S^+ (b - A_j x)[S]. */
+/* One colour step of the multiplicative smoother on level j >= 1: for every vertex
+ * patch of the colour (under p->colouring), x[S] += A_S^+ (b - A_j x)[S] (the same
+ * step whatever p->smoother says). */
 bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x_dev, const double* b_dev);
-/* `steps` applications of the symmetric smoother R_j (colours 0..C-1 then C-2..0). */
+/* `steps` applications of the smoother R_j of p->smoother (multiplicative: colours
+ * 0..C-1 then C-2..0; additive: the damped sum of all patch corrections). */
 bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x_dev, const double* b_dev);
 /* b_{j-1} = P_j^T r_j (restriction; eq. 3 applied to residuals). */
 bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf_dev, double* bc_dev);

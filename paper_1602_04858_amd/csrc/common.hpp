@@ -123,9 +123,11 @@ __host__ __device__ inline void patch_vertex(int scheme, int N, int colour, int 
 // Level kernels work on nrhs vectors stored ld elements apart (grid.y = vector).
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
                bool residual, int nrhs, int64_t ld, hipStream_t s);
+// omega == 0: one colour step of the multiplicative smoother (b = right-hand side);
+// omega > 0: the colour's share of an additive step, x[S] += omega A_S^+ b[S] (b = residual)
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
-                   bool finest, bool packed, int nrhs, int64_t ld, hipStream_t s);
+                   bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s);
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
                      int64_t ldf, int64_t ldc, hipStream_t s);
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,

@@ -129,6 +129,8 @@ bmg_status check_params(const bmg_params* p) {
   if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
   if (p->n_rhs < 0 || p->n_rhs > kMaxRhs) return BMG_E_ARG;
   if (p->colouring != COLOURING_S9 && p->colouring != COLOURING_L8) return BMG_E_ARG;
+  if (p->smoother != BMG_SMOOTHER_MULTIPLICATIVE && p->smoother != BMG_SMOOTHER_ADDITIVE) return BMG_E_ARG;
+  if (p->smoother == BMG_SMOOTHER_ADDITIVE && !(p->omega > 0.0 && p->omega <= 1.0)) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -855,27 +857,38 @@ double colour_bytes(const bmg_ctx* c, int j, int col) {
          ext * ((double)inv_entries(pk, nse) * c->ssize + (gather + 2.0 * nse) * c->tsize);
 }
 
-void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, int nrhs) {
+// `steps` smoothing steps on level j (nrhs columns; r: scratch of the same shape).
+// Multiplicative: colours 0..C-1 then C-2..0, each one launch.  Additive: the
+// residual of x once, then every colour adds its damped patch corrections computed
+// from that residual (colour by colour, so that the updates of a launch are disjoint).
+void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r, int nrhs) {
   LevelInfo& L = c->lev[j];
   LevelArgs a = largs(c, j, c->prec == 0);
   const bool timed = (c->timing_level == j);
+  const bool additive = c->p.smoother == BMG_SMOOTHER_ADDITIVE;
+  const int C = colour_count(c->p.colouring);
+  const int nl = additive ? C : 2 * C - 1;
+  const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c->K, L.N);
   for (int st = 0; st < steps; ++st) {
-    // one event pair around the 2C - 1 back-to-back launches of a smoothing step, so
+    if (additive) launch_op(c->K, c->prec, c->elemT, a, x, b, r, true, nrhs, L.ndof, c->stream);
+    // one event pair around the back-to-back colour launches of a smoothing step, so
     // that no marker sits between two colour kernels
     const bool rec = timed && c->ev_used + 2 <= c->ev.size();
     if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
-    // colours 0..C-1 then C-2..0
-    const int C = colour_count(c->p.colouring);
-    for (int i = 0; i < 2 * C - 1; ++i) {
+    for (int i = 0; i < nl; ++i) {
       const int col = i < C ? i : 2 * C - 2 - i;
-      launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
-                    L.npatch[col], j == (int)c->lev.size() - 1, packed_level(c->K, L.N), nrhs, L.ndof, c->stream);
+      if (additive)
+        launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, r, L.inv[col], L.invx[col], L.extidx[col], col,
+                      L.npatch[col], finest, pk, nrhs, L.ndof, c->p.omega, c->stream);
+      else
+        launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
+                      L.npatch[col], finest, pk, nrhs, L.ndof, 0.0, c->stream);
       if (rec) c->timed_bytes += colour_bytes(c, j, col) * nrhs;
     }
     if (rec) {
       hipEventRecord(c->ev[c->ev_used + 1], c->stream);
       c->ev_used += 2;
-      c->timed_launches += 2 * colour_count(c->p.colouring) - 1;
+      c->timed_launches += nl;
     }
   }
 }
@@ -917,14 +930,14 @@ void vcycle_level(bmg_ctx* c, int j, const Vecs& v, bool use_dense) {
   }
   const int m = smoothing_steps(c, j);
   launch_fill_zero(c->prec, v.x[j], L.ndof * nr, c->stream);
-  smooth_level(c, j, m, v.x[j], v.b[j], nr);
+  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr);
   LevelArgs a = largs(c, j, c->prec == 0);
   launch_op(c->K, c->prec, c->elemT, a, v.x[j], v.b[j], v.r[j], true, nr, L.ndof, c->stream);
   LevelInfo& C = c->lev[j - 1];
   launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, v.r[j], v.b[j - 1], nr, L.ndof, C.ndof, c->stream);
   vcycle_level(c, j - 1, v, use_dense);
   launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, v.x[j - 1], v.x[j], nr, C.ndof, L.ndof, c->stream);
-  smooth_level(c, j, m, v.x[j], v.b[j], nr);
+  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr);
 }
 
 // Dense B_jc: the V-cycle of level jc applied to the unit vectors, a chunk of
@@ -1200,7 +1213,7 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(h->prec, 0, b, L.b, nt, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
                 L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1,
-                packed_level(h->K, L.N), h->R, L.ndof, h->stream);
+                packed_level(h->K, L.N), h->R, L.ndof, 0.0, h->stream);
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -1212,7 +1225,7 @@ bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, con
   const int64_t nt = L.ndof * h->R;
   launch_cast(h->prec, 0, x, L.x, nt, h->stream);
   launch_cast(h->prec, 0, b, L.b, nt, h->stream);
-  smooth_level(h, level, steps, L.x, L.b, h->R);
+  smooth_level(h, level, steps, L.x, L.b, L.r, h->R);
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

@@ -369,13 +369,13 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
 // prefetched into registers (RT_1, regular layout), the patch layout is decoded
 // arithmetically and b on the patch is loaded -- so the dependent chain is one
 // gather of x, the local residual in LDS, an FMA chain on registers and the store.
-template <typename T, typename S, int K, int TAG, bool PKD, bool MC>
+template <typename T, typename S, int K, int TAG, bool PKD, bool MC, bool ADD>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
                                                 int colour, int scheme, int npatch, int64_t ld, int nrhs,
-                                                int ncol) {
+                                                int ncol, T omega) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     gni[q] = okn[q] ? I::g(N, ncx, ncy, dd) : 0;
   }
   T gx[NG], gn[NN];
-  {
+  if (!ADD) {
     const T* xc = x + (int64_t)c0 * ld;
 #pragma unroll
     for (int q = 0; q < NG; ++q) gx[q] = xc[gxi[q]];
@@ -459,14 +459,17 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   }
   const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
                          (vy == N - 1 && !(bcm & 8));
+  // bv: b on the patch entries (multiplicative) or the residual there (additive:
+  // b is then the residual of the input x, and xv holds x on the patch entries)
   int gi[NT], zA[NT], zB[NT];
-  T bv[NT];
+  T bv[NT], xv[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const int t = lane + 64 * q;
     decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
     if (!active || t >= (ext_guess ? NSE : NSR)) gi[q] = -1;
     bv[q] = b[(int64_t)c0 * ld + (gi[q] >= 0 ? gi[q] : 0)];
+    if (ADD) xv[q] = x[(int64_t)c0 * ld + (gi[q] >= 0 ? gi[q] : 0)];
   }
   T kv[NG];
 #pragma unroll
@@ -505,85 +508,87 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
 
   for (int c = c0;;) {
     T* xc = x + (int64_t)c * ld;
-    // 1. gathered values (and, once, the element matrices and the zero block) to LDS
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const int e = lane + 64 * q;
-      if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < NN; ++q) {
-      const int e = lane + 64 * q;
-      if (e < 8 * NV) {
-        const int s = e / (2 * NV), r = e % (2 * NV);
-        nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+    if (!ADD) {
+      // 1. gathered values (and, once, the element matrices and the zero block) to LDS
+  #pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const int e = lane + 64 * q;
+        if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
       }
-    }
-    if (c == c0) {
-      T* dst = reinterpret_cast<T*>(&Es);
-#pragma unroll
-      for (int q = 0; q < NEQ; ++q)
-        if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
-      if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
-    }
-    lds_barrier();
+  #pragma unroll
+      for (int q = 0; q < NN; ++q) {
+        const int e = lane + 64 * q;
+        if (e < 8 * NV) {
+          const int s = e / (2 * NV), r = e % (2 * NV);
+          nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+        }
+      }
+      if (c == c0) {
+        T* dst = reinterpret_cast<T*>(&Es);
+  #pragma unroll
+        for (int q = 0; q < NEQ; ++q)
+          if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
+        if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
+      }
+      lds_barrier();
 
-    // 2. row contributions of every patch cell (cell blocks + its four faces), one
-    // branch-free path for all rows.  A velocity row (component c, local index dd)
-    // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
-    // - h Dm[:, dd] . p, where the faces across which component c is tangential give
-    // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
-    // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
-    // coefficient rows and vectors by LDS address; absent terms read the zero block.
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const int e = lane + 64 * q;
-      if (e >= 4 * NL) break;
-      const int s = e / NL, d = e % NL;
-      const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-      const T* xl = xs[w][s];
-      const bool vel = d < 2 * NV;
-      const int comp = d >= NV ? 1 : 0;
-      const int dd = vel ? d - comp * NV : d - 2 * NV;
-      // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
-      const bool lo_bnd = comp ? cx == 0 : cy == 0;
-      const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
-      const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
-      const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
-      const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
-      const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
-      const int ro = dd * NV;
-      const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
-      const T* c_mass = vel ? Es.M + ro : zblk;
-      const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
-      const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
-      const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
-      const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
-      const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
-      const T* v_self = vel ? xl + comp * NV : xl;
-      const T* v_nlo = vel ? nl : xl + NV;
-      const T* pv = xl + 2 * NV;
-      const T khh = vel ? kv[q] * hh : T(0);
-      T a = T(0), g = T(0);
-      auto term = [&](int i) {
-        a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
-        a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
-      };
-      if (PK) {
-        // bandwidth-bound levels: partial unrolling keeps the registers (and so the
-        // blocks per CU) of the rest of the kernel
-#pragma unroll 2
-        for (int i = 0; i < NV; ++i) term(i);
-      } else {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) term(i);
+      // 2. row contributions of every patch cell (cell blocks + its four faces), one
+      // branch-free path for all rows.  A velocity row (component c, local index dd)
+      // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
+      // - h Dm[:, dd] . p, where the faces across which component c is tangential give
+      // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
+      // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
+      // coefficient rows and vectors by LDS address; absent terms read the zero block.
+  #pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const int e = lane + 64 * q;
+        if (e >= 4 * NL) break;
+        const int s = e / NL, d = e % NL;
+        const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+        const T* xl = xs[w][s];
+        const bool vel = d < 2 * NV;
+        const int comp = d >= NV ? 1 : 0;
+        const int dd = vel ? d - comp * NV : d - 2 * NV;
+        // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
+        const bool lo_bnd = comp ? cx == 0 : cy == 0;
+        const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
+        const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
+        const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
+        const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
+        const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
+        const int ro = dd * NV;
+        const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
+        const T* c_mass = vel ? Es.M + ro : zblk;
+        const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
+        const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
+        const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
+        const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
+        const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
+        const T* v_self = vel ? xl + comp * NV : xl;
+        const T* v_nlo = vel ? nl : xl + NV;
+        const T* pv = xl + 2 * NV;
+        const T khh = vel ? kv[q] * hh : T(0);
+        T a = T(0), g = T(0);
+        auto term = [&](int i) {
+          a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
+          a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
+        };
+        if (PK) {
+          // bandwidth-bound levels: partial unrolling keeps the registers (and so the
+          // blocks per CU) of the rest of the kernel
+  #pragma unroll 2
+          for (int i = 0; i < NV; ++i) term(i);
+        } else {
+  #pragma unroll
+          for (int i = 0; i < NV; ++i) term(i);
+        }
+  #pragma unroll
+        for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
+        const T z = (vel ? a : mh * a) + mh * g;
+        zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
       }
-#pragma unroll
-      for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
-      const T z = (vel ? a : mh * a) + mh * g;
-      zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
+      lds_barrier();
     }
-    lds_barrier();
 
     // 3. local residual (b - A x) on the patch entries.  The layout follows from the
     // vertex position (extended iff an outer face of the patch lies on an open
@@ -596,8 +601,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       if (t < NSE) {
         T r = T(0);
         if (gi[q] >= 0) {
-          r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
-          xold[q] = (&xs[w][0][0])[zA[q]];
+          if (ADD) {
+            r = bv[q];
+            xold[q] = xv[q];
+          } else {
+            r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
+            xold[q] = (&xs[w][0][0])[zA[q]];
+          }
         }
         rs[w][t] = r;
       }
@@ -614,12 +624,17 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const bool more = MC && c + 1 < c1;
     if (more) {
       const T* xn = x + (int64_t)(c + 1) * ld;
+      if (!ADD) {
 #pragma unroll
-      for (int q = 0; q < NG; ++q) gx[q] = xn[gxi[q]];
+        for (int q = 0; q < NG; ++q) gx[q] = xn[gxi[q]];
 #pragma unroll
-      for (int q = 0; q < NN; ++q) gn[q] = xn[gni[q]];
+        for (int q = 0; q < NN; ++q) gn[q] = xn[gni[q]];
+      }
 #pragma unroll
-      for (int q = 0; q < NT; ++q) bv[q] = b[(int64_t)(c + 1) * ld + (gi[q] >= 0 ? gi[q] : 0)];
+      for (int q = 0; q < NT; ++q) {
+        bv[q] = b[(int64_t)(c + 1) * ld + (gi[q] >= 0 ? gi[q] : 0)];
+        if (ADD) xv[q] = xn[gi[q] >= 0 ? gi[q] : 0];
+      }
     }
 
     // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
@@ -660,7 +675,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
               acc += T(Rp[d * NSE + u]) * rs[w][u];
             }
           }
-          if (gi[0] >= 0) xc[gi[0]] = xold[0] + acc;
+          if (gi[0] >= 0) xc[gi[0]] = xold[0] + (ADD ? omega * acc : acc);
         }
       } else if (PF) {
         // one product length for both layouts: r is zero beyond the patch size
@@ -668,7 +683,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           T acc = T(0);
 #pragma unroll
           for (int u = 0; u < (PF ? NSE : 1); ++u) acc += T(areg[u]) * rs[w][u];
-          if (gi[0] >= 0) xc[gi[0]] = xold[0] + acc;
+          if (gi[0] >= 0) xc[gi[0]] = xold[0] + (ADD ? omega * acc : acc);
         }
       } else {
         const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
@@ -679,7 +694,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
             T acc = T(0);
 #pragma unroll 8
             for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
-            if (gi[q] >= 0) xc[gi[q]] = xold[q] + acc;
+            if (gi[q] >= 0) xc[gi[q]] = xold[q] + (ADD ? omega * acc : acc);
           }
         }
       }
@@ -1097,7 +1112,7 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
                      const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs,
-                     int64_t ld, hipStream_t s) {
+                     int64_t ld, double omega, hipStream_t s) {
   if (npatch <= 0) return;
   // columns per block: all of them on the bandwidth-bound levels (the inverse is read
   // once per patch); elsewhere enough blocks to fill the device come first
@@ -1108,28 +1123,37 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
     else ncol = std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
   }
   dim3 g(nblk, (nrhs + ncol - 1) / ncol), bl(256);
-#define BMG_KC(TAG, PKD, MC)                                                                                    \
-  hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,     \
+#define BMG_KC(TAG, PKD, MC, ADD)                                                                               \
+  hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC, ADD>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,  \
                      (T)L.h, (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour,  \
-                     L.colouring, npatch, ld, nrhs, ncol)
-  if (ncol > 1) {
-    if (packed) BMG_KC(0, true, true);
-    else BMG_KC(0, false, true);
+                     L.colouring, npatch, ld, nrhs, ncol, (T)omega)
+  if (omega > 0.0) {
+    // additive step: b is the residual of x
+    if (packed) {
+      if (ncol > 1) BMG_KC(0, true, true, true);
+      else BMG_KC(0, true, false, true);
+    } else {
+      if (ncol > 1) BMG_KC(0, false, true, true);
+      else BMG_KC(0, false, false, true);
+    }
+  } else if (ncol > 1) {
+    if (packed) BMG_KC(0, true, true, false);
+    else BMG_KC(0, false, true, false);
   } else if (finest) {
-    if (packed) BMG_KC(1, true, false);
-    else BMG_KC(1, false, false);
+    if (packed) BMG_KC(1, true, false, false);
+    else BMG_KC(1, false, false, false);
   } else {
-    if (packed) BMG_KC(0, true, false);
-    else BMG_KC(0, false, false);
+    if (packed) BMG_KC(0, true, false, false);
+    else BMG_KC(0, false, false, false);
   }
 #undef BMG_KC
 }
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
-                   bool packed, int nrhs, int64_t ld, hipStream_t s) {
+                   bool packed, int nrhs, int64_t ld, double omega, hipStream_t s) {
 #define BMG_COL(T, S, KK) \
-  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, s)
+  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, s)
   if (K == 1) {
     if (prec == 0) BMG_COL(double, double, 1);
     else if (sprec == 0) BMG_COL(float, double, 1);

@@ -41,14 +41,16 @@ def test_status_strings():
     (dict(k=3), 2), (dict(k=0), 2), (dict(n0=1), 1), (dict(levels=-1), 1), (dict(mu=-1.0), 1),
     (dict(sigma=0.0), 1), (dict(m_fine=0), 1), (dict(restart=0), 1), (dict(cycle=5), 1),
     (dict(n0=2, levels=12), 1), (dict(prec=7), 1), (dict(dense=-1), 1), (dict(dense=70000), 1),
-    (dict(n_rhs=-1), 1), (dict(n_rhs=17), 1)])
+    (dict(n_rhs=-1), 1), (dict(n_rhs=17), 1), (dict(smoother=2), 1), (dict(smoother=1, omega=0.0), 1),
+    (dict(smoother=1, omega=1.5), 1), (dict(colouring=3), 1)])
 def test_parameter_validation(change, expect):
     args = dict(n0=2, levels=2, k=1, mu=1.0, sigma=6.0, bc=[D, D, O, O], prec=0)
     args.update(change)
     p = bmg.make_params(args["n0"], args["levels"], args["k"], args["mu"], args["sigma"], args["bc"],
                         prec=args["prec"], m_fine=args.get("m_fine", 2), restart=args.get("restart", 10),
                         cycle=args.get("cycle", 1), dense_coarse_max=args.get("dense", 0),
-                        n_rhs=args.get("n_rhs", 1))
+                        n_rhs=args.get("n_rhs", 1), colouring=args.get("colouring", 0),
+                        smoother=args.get("smoother", 0), omega=args.get("omega", 0.25))
     with pytest.raises(bmg.BmgError) as e:
         bmg.plan(p)
     assert e.value.status == expect
