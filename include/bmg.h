@@ -65,6 +65,7 @@ enum { BMG_P_FP64 = 0, BMG_P_FP32 = 1, BMG_P_BF16 = 2 };        /* preconditione
                                                                    FP32 with bfloat16-stored patch inverses */
 enum { BMG_CYCLE_STANDARD = 0, BMG_CYCLE_VARIABLE = 1 };        /* m(j) = m_fine or m_fine 2^(J-j), Section 3.2 */
 enum { BMG_SMOOTHER_MULTIPLICATIVE = 0, BMG_SMOOTHER_ADDITIVE = 1 };
+enum { BMG_KAPPA_ARITHMETIC = 0, BMG_KAPPA_HARMONIC = 1 /* 0 if a child is 0 */, BMG_KAPPA_GEOMETRIC = 2 };
 enum { BMG_COLOURING_S9 = 0,  /* 9 colours, (vx mod 3) + 3 (vy mod 3); a smoothing step is colours 0..8, 7..0 */
        BMG_COLOURING_L8 = 1   /* 8 colours, the cosets of the lattice spanned by (2, 2) and (2, -2):
                                  (vx mod 2) + 2 (vy mod 2) + 4 [(vx - vy) mod 4 >= 2]; colours 0..7, 6..0 */
@@ -96,6 +97,8 @@ typedef struct {
   double omega;          /* damping of the additive smoother, 0 < omega <= 1 (each cell lies in at
                             most four patches, so omega <= 1/4 keeps a step a contraction; 0.25 is
                             used in the tests); ignored by the multiplicative one */
+  int32_t coarse_kappa;  /* BMG_KAPPA_*: kappa of a coarse cell from its four children; Section 4.1
+                            uses the arithmetic mean (default) and notes that other choices are possible */
 } bmg_params;
 
 typedef struct {
@@ -108,7 +111,7 @@ typedef struct {
 /* Device memory the library needs for these parameters (bmg_setup workspace). */
 bmg_status bmg_plan(const bmg_params* p, size_t* workspace_bytes);
 
-/* Build the hierarchy and every setup product: coarse kappa by arithmetic averaging
+/* Build the hierarchy and every setup product: coarse kappa by averaging (p->coarse_kappa)
  * of the four children (Section 4.1), level operators, patch pseudo-inverses
  * (Section 3.3: the local Ritz projection on the vertex patch, pseudo-inverse with
  * zero patch-mean pressure when the patch problem has the constant-pressure null

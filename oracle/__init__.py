@@ -41,7 +41,7 @@ def lib():
         L = C.CDLL(LIB)
         V, I, D, P = None, C.c_int, C.c_double, C.c_void_p
         sig = {
-            "orc_create": (P, [I, I, I, D, D, _ip, _dp, I, I, I]),
+            "orc_create": (P, [I, I, I, D, D, _ip, _dp, I, I, I, I]),
             "orc_destroy": (V, [P]),
             "orc_ndof": (I, [P, I]), "orc_n_u": (I, [P, I]), "orc_N": (I, [P, I]),
             "orc_singular": (I, [P, I]),
@@ -105,16 +105,18 @@ class Oracle:
     """One problem: mesh hierarchy, level operators, patches, transfers, coarse solve."""
 
     def __init__(self, n0, levels, k, mu, sigma, bc, kappa, cycle=1, m_fine=2, colouring=0, smoother=0,
-                 omega=0.25):
+                 omega=0.25, kappa_avg=0):
         """colouring: 0 = S9 ((vx mod 3) + 3 (vy mod 3)), 1 = L8 (cosets of span{(2,2),(2,-2)}).
-        smoother: 0 = symmetric multiplicative (Section 3.3), 1 = additive with damping omega."""
+        smoother: 0 = symmetric multiplicative (Section 3.3), 1 = additive with damping omega.
+        kappa_avg: coarse kappa from the four children, 0 arithmetic (Section 4.1), 1 harmonic,
+        2 geometric."""
         self.n0, self.J, self.k, self.mu, self.sigma = n0, levels, k, mu, sigma
         self.colouring = colouring
         self.bc = np.ascontiguousarray(bc, dtype=np.int32)
         kap = _f64(kappa)
         n = n0 << levels
         assert kap.size == n * n
-        self.h = lib().orc_create(n0, levels, k, mu, sigma, self.bc, kap, cycle, m_fine, colouring)
+        self.h = lib().orc_create(n0, levels, k, mu, sigma, self.bc, kap, cycle, m_fine, colouring, kappa_avg)
         if not self.h:
             raise RuntimeError("oracle setup failed (singular coarse matrix)")
         if smoother:

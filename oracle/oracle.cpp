@@ -22,7 +22,9 @@
 //               tangential part by the Nitsche terms of eq. (BCh); an open side
 //               carries no boundary term.
 //   * hierarchy: uniform refinement, re-discretisation per level, cell kappa
-//               averaged arithmetically (Section 3 and Section 4.1).
+//               averaged over the four children: arithmetically (Section 4.1, the
+//               default), or harmonically / geometrically (the other choices the
+//               paper allows).
 //   * transfer: the natural injection (Section 3.1) computed by applying the fine
 //               degree-of-freedom functionals to coarse basis functions;
 //               restriction is its transpose (eq. 3 acting on residuals).
@@ -778,8 +780,19 @@ void vcycle_level(const Ctx& X, int j, const double* b, double* x) {
     if (L.cons[i]) x[i] = b[i];
 }
 
+// Coarse kappa of one cell from its four children: 0 arithmetic mean, 1 harmonic
+// mean (0 if a child is 0), 2 geometric mean.
+double average4(int mode, double a, double b, double c, double d) {
+  if (mode == 1) {
+    if (a == 0.0 || b == 0.0 || c == 0.0 || d == 0.0) return 0.0;
+    return 4.0 / (1.0 / a + 1.0 / b + 1.0 / c + 1.0 / d);
+  }
+  if (mode == 2) return std::sqrt(std::sqrt(a * b) * std::sqrt(c * d));
+  return 0.25 * (a + b + c + d);
+}
+
 Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const double* kappa,
-            int cycle, int m_fine, int colouring) {
+            int cycle, int m_fine, int colouring, int kappa_avg) {
   auto X = std::make_unique<Ctx>();
   X->J = J;
   X->k = k;
@@ -791,7 +804,7 @@ Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const 
     X->lev[j].colouring = colouring;
     X->lev[j].ncolours = colouring ? 8 : 9;
   }
-  // kappa: finest given, coarser levels by arithmetic averaging of the 4 children
+  // kappa: finest given, coarser levels by averaging the 4 children
   X->lev[J].kappa.assign(kappa, kappa + (size_t)(n0 << J) * (n0 << J));
   for (int j = J; j >= 1; --j) {
     const Level& F = X->lev[j];
@@ -799,10 +812,9 @@ Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const 
     C.kappa.assign((size_t)C.N * C.N, 0.0);
     for (int cy = 0; cy < C.N; ++cy)
       for (int cx = 0; cx < C.N; ++cx)
-        C.kappa[cy * C.N + cx] = 0.25 * (F.kappa[(2 * cy) * F.N + 2 * cx] +
-                                         F.kappa[(2 * cy) * F.N + 2 * cx + 1] +
-                                         F.kappa[(2 * cy + 1) * F.N + 2 * cx] +
-                                         F.kappa[(2 * cy + 1) * F.N + 2 * cx + 1]);
+        C.kappa[cy * C.N + cx] = average4(kappa_avg, F.kappa[(2 * cy) * F.N + 2 * cx],
+                                          F.kappa[(2 * cy) * F.N + 2 * cx + 1], F.kappa[(2 * cy + 1) * F.N + 2 * cx],
+                                          F.kappa[(2 * cy + 1) * F.N + 2 * cx + 1]);
   }
   for (int j = 0; j <= J; ++j) {
     assemble(X->lev[j]);
@@ -834,8 +846,8 @@ Ctx* create(int n0, int J, int k, double mu, double sigma, const int* bc, const 
 extern "C" {
 
 void* orc_create(int n0, int J, int k, double mu, double sigma, const int* bc,
-                 const double* kappa, int cycle, int m_fine, int colouring) {
-  return create(n0, J, k, mu, sigma, bc, kappa, cycle, m_fine, colouring);
+                 const double* kappa, int cycle, int m_fine, int colouring, int kappa_avg) {
+  return create(n0, J, k, mu, sigma, bc, kappa, cycle, m_fine, colouring, kappa_avg);
 }
 void orc_destroy(void* p) { delete static_cast<Ctx*>(p); }
 

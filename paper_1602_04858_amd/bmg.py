@@ -30,6 +30,7 @@ P_FP64, P_FP32, P_BF16 = 0, 1, 2
 CYCLE_STANDARD, CYCLE_VARIABLE = 0, 1
 COLOURING_S9, COLOURING_L8 = 0, 1
 SMOOTHER_MULTIPLICATIVE, SMOOTHER_ADDITIVE = 0, 1
+KAPPA_ARITHMETIC, KAPPA_HARMONIC, KAPPA_GEOMETRIC = 0, 1, 2
 
 STATUS = {0: "BMG_OK", 1: "BMG_E_ARG", 2: "BMG_E_UNSUPPORTED", 3: "BMG_E_NOMEM", 4: "BMG_E_HIP",
           5: "BMG_E_SINGULAR", 6: "BMG_E_NOT_CONVERGED", 7: "BMG_E_NONFINITE", 8: "BMG_E_STATE"}
@@ -39,7 +40,8 @@ class Params(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
                 ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32),
-                ("n_rhs", C.c_int32), ("colouring", C.c_int32), ("smoother", C.c_int32), ("omega", C.c_double)]
+                ("n_rhs", C.c_int32), ("colouring", C.c_int32), ("smoother", C.c_int32), ("omega", C.c_double),
+                ("coarse_kappa", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -104,7 +106,8 @@ DENSE_COARSE_DEFAULT = 16384
 
 
 def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
-                dense_coarse_max=0, n_rhs=1, colouring=COLOURING_S9, smoother=SMOOTHER_MULTIPLICATIVE, omega=0.25):
+                dense_coarse_max=0, n_rhs=1, colouring=COLOURING_S9, smoother=SMOOTHER_MULTIPLICATIVE, omega=0.25,
+                coarse_kappa=KAPPA_ARITHMETIC):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
@@ -115,6 +118,7 @@ def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, pr
     p.colouring = colouring
     p.smoother = smoother
     p.omega = float(omega)
+    p.coarse_kappa = coarse_kappa
     return p
 
 

@@ -129,6 +129,7 @@ bmg_status check_params(const bmg_params* p) {
   if (p->dense_coarse_max < 0 || p->dense_coarse_max > 65535) return BMG_E_ARG;
   if (p->n_rhs < 0 || p->n_rhs > kMaxRhs) return BMG_E_ARG;
   if (p->colouring != COLOURING_S9 && p->colouring != COLOURING_L8) return BMG_E_ARG;
+  if (p->coarse_kappa < BMG_KAPPA_ARITHMETIC || p->coarse_kappa > BMG_KAPPA_GEOMETRIC) return BMG_E_ARG;
   if (p->smoother != BMG_SMOOTHER_MULTIPLICATIVE && p->smoother != BMG_SMOOTHER_ADDITIVE) return BMG_E_ARG;
   if (p->smoother == BMG_SMOOTHER_ADDITIVE && !(p->omega > 0.0 && p->omega <= 1.0)) return BMG_E_ARG;
   return BMG_OK;
@@ -1008,8 +1009,18 @@ void apply_op64(bmg_ctx* c, int j, const double* x, double* y) {
   launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, c->R, c->lev[j].ndof, c->stream);
 }
 
-// kappa of level j from the finest field: arithmetic mean of the 4 children per level (Section 4.1)
-std::vector<double> kappa_level(const double* fine, int n0, int J, int j) {
+// kappa of level j from the finest field, each coarse cell from its 4 children:
+// arithmetic mean (Section 4.1), harmonic mean (0 if a child is 0) or geometric mean
+double mean4(int mode, double a, double b, double c, double d) {
+  if (mode == BMG_KAPPA_HARMONIC) {
+    if (a == 0.0 || b == 0.0 || c == 0.0 || d == 0.0) return 0.0;
+    return 4.0 / (1.0 / a + 1.0 / b + 1.0 / c + 1.0 / d);
+  }
+  if (mode == BMG_KAPPA_GEOMETRIC) return std::sqrt(std::sqrt(a * b) * std::sqrt(c * d));
+  return 0.25 * (a + b + c + d);
+}
+
+std::vector<double> kappa_level(const double* fine, int n0, int J, int j, int mode) {
   int N = n0 << J;
   std::vector<double> cur(fine, fine + (size_t)N * N);
   for (int l = J; l > j; --l) {
@@ -1018,7 +1029,7 @@ std::vector<double> kappa_level(const double* fine, int n0, int J, int j) {
     for (int cy = 0; cy < Nc; ++cy)
       for (int cx = 0; cx < Nc; ++cx) {
         const size_t f = (size_t)(2 * cy) * N + 2 * cx;
-        nx[(size_t)cy * Nc + cx] = 0.25 * (cur[f] + cur[f + 1] + cur[f + N] + cur[f + N + 1]);
+        nx[(size_t)cy * Nc + cx] = mean4(mode, cur[f], cur[f + 1], cur[f + N], cur[f + N + 1]);
       }
     cur.swap(nx);
     N = Nc;
@@ -1113,7 +1124,7 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   layout(c, c->ws);
   c->ref = make_refdata(p->k, p->mu, p->sigma);
   // kappa hierarchy: arithmetic mean of the four children (Section 4.1)
-  for (int j = 0; j <= p->levels; ++j) c->lev[j].kappa = kappa_level(kappa, p->n0, p->levels, j);
+  for (int j = 0; j <= p->levels; ++j) c->lev[j].kappa = kappa_level(kappa, p->n0, p->levels, j, p->coarse_kappa);
   bmg_status st = upload_all_consts(c);
   for (size_t j = 0; !st && j < c->lev.size(); ++j) {
     LevelInfo& L = c->lev[j];
@@ -1599,7 +1610,7 @@ bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t le
     LevelInfo L;
     L.N = N;
     L.h = 1.0 / N;
-    L.kappa = kappa_level(kappa, p->n0, p->levels, level);
+    L.kappa = kappa_level(kappa, p->n0, p->levels, level, p->coarse_kappa);
     const RefData R = make_refdata(p->k, p->mu, p->sigma);
     std::vector<double> A, pinv;
     patch_matrix(I, R, L, vx, vy, P, A);
@@ -1631,7 +1642,7 @@ bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int
   const int N = p->n0 << level;
   if (N > 32) return BMG_E_ARG;
   const RefData R = make_refdata(p->k, p->mu, p->sigma);
-  std::vector<double> A = dense_level(R, p->k, bc_mask(*p), N, kappa_level(kappa, p->n0, p->levels, level));
+  std::vector<double> A = dense_level(R, p->k, bc_mask(*p), N, kappa_level(kappa, p->n0, p->levels, level, p->coarse_kappa));
   std::copy(A.begin(), A.end(), out);
   return BMG_OK;
 }

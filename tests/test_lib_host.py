@@ -42,7 +42,7 @@ def test_status_strings():
     (dict(sigma=0.0), 1), (dict(m_fine=0), 1), (dict(restart=0), 1), (dict(cycle=5), 1),
     (dict(n0=2, levels=12), 1), (dict(prec=7), 1), (dict(dense=-1), 1), (dict(dense=70000), 1),
     (dict(n_rhs=-1), 1), (dict(n_rhs=17), 1), (dict(smoother=2), 1), (dict(smoother=1, omega=0.0), 1),
-    (dict(smoother=1, omega=1.5), 1), (dict(colouring=3), 1)])
+    (dict(smoother=1, omega=1.5), 1), (dict(colouring=3), 1), (dict(coarse_kappa=3), 1)])
 def test_parameter_validation(change, expect):
     args = dict(n0=2, levels=2, k=1, mu=1.0, sigma=6.0, bc=[D, D, O, O], prec=0)
     args.update(change)
@@ -50,7 +50,8 @@ def test_parameter_validation(change, expect):
                         prec=args["prec"], m_fine=args.get("m_fine", 2), restart=args.get("restart", 10),
                         cycle=args.get("cycle", 1), dense_coarse_max=args.get("dense", 0),
                         n_rhs=args.get("n_rhs", 1), colouring=args.get("colouring", 0),
-                        smoother=args.get("smoother", 0), omega=args.get("omega", 0.25))
+                        smoother=args.get("smoother", 0), omega=args.get("omega", 0.25),
+                        coarse_kappa=args.get("coarse_kappa", 0))
     with pytest.raises(bmg.BmgError) as e:
         bmg.plan(p)
     assert e.value.status == expect
@@ -144,11 +145,13 @@ def test_patch_pseudo_inverses_match_oracle(case):
     assert worst < 1e-11, worst
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("case", CASES)
-def test_level_matrix_matches_oracle(case):
+def test_level_matrix_matches_oracle(case, mode):
+    """Every level's operator (so the coarse kappa of each averaging) against the oracle."""
     n0, J, k, mu, sigma, bc, kap = _case(case, seed=5)
-    o = Oracle(n0, J, k, mu, sigma, list(bc), kap, 1, 2)
-    p = bmg.make_params(n0, J, k, mu, sigma, bc)
+    o = Oracle(n0, J, k, mu, sigma, list(bc), kap, 1, 2, kappa_avg=mode)
+    p = bmg.make_params(n0, J, k, mu, sigma, bc, coarse_kappa=mode)
     for j in range(J + 1):
         A = o.csr(j).toarray()
         B = bmg.export_level_matrix(p, kap, j)

@@ -488,15 +488,45 @@ def test_iterations_do_not_grow_under_refinement(mu):
     assert max(counts) - counts[0] <= 2, counts
 
 
-def test_kappa_arithmetic_averaging():
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_kappa_averaging(mode):
+    """Coarse kappa from the four children: arithmetic (Section 4.1), harmonic,
+    geometric -- against numpy means, two levels down (so the averaging composes)."""
     n0, J = 2, 2
     n = n0 << J
     kap = inputs.kappa_random_cells(n, 21, 1e-6, 1.0)
-    o = Oracle(n0, J, 1, 1.0, 6.0, [D, D, O, O], kap, 1, 2)
-    k1 = o.kappa(1).reshape(4, 4)
-    kf = kap.reshape(8, 8)
-    ref = 0.25 * (kf[0::2, 0::2] + kf[0::2, 1::2] + kf[1::2, 0::2] + kf[1::2, 1::2])
-    assert np.allclose(k1, ref, rtol=1e-15)
+    o = Oracle(n0, J, 1, 1.0, 6.0, [D, D, O, O], kap, 1, 2, kappa_avg=mode)
+
+    def down(kf):
+        q = np.stack([kf[0::2, 0::2], kf[0::2, 1::2], kf[1::2, 0::2], kf[1::2, 1::2]])
+        if mode == 0:
+            return q.mean(axis=0)
+        if mode == 1:
+            return 4.0 / (1.0 / q).sum(axis=0)
+        return np.exp(np.log(q).mean(axis=0))
+
+    k1 = down(kap.reshape(8, 8))
+    k0 = down(k1)
+    assert np.allclose(o.kappa(1).reshape(4, 4), k1, rtol=1e-13)
+    assert np.allclose(o.kappa(0).reshape(2, 2), k0, rtol=1e-13)
+    # ordering of the means (AM >= GM >= HM) on the same children
+    if mode == 1:
+        am = Oracle(n0, J, 1, 1.0, 6.0, [D, D, O, O], kap, 1, 2).kappa(1)
+        assert np.all(o.kappa(1) <= am * (1 + 1e-14))
+
+
+def test_coarse_kappa_variants_all_precondition():
+    """Every averaging gives a convergent preconditioner; harmonic averaging keeps
+    low-permeability barriers on coarse levels (the robustness study of the paper's
+    remark on other choices)."""
+    w = inputs.scaled_workload("C2", 16)
+    its = {}
+    for mode in (0, 1, 2):
+        o = Oracle(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.kappa, 1, 2, kappa_avg=mode)
+        x, it, _, tr = o.fgmres(o.rhs(w.source), rtol=1e-10, maxit=300)
+        assert it > 0 and tr < 1e-9
+        its[mode] = it
+    assert max(its.values()) < 100
 
 
 def test_standard_vs_variable_cycle_both_converge():
