@@ -51,7 +51,7 @@ typedef struct bmg_batch* bmg_batch_handle;
 typedef enum {
   BMG_OK = 0,
   BMG_E_ARG = 1,           /* invalid argument (null pointer, out-of-range parameter) */
-  BMG_E_UNSUPPORTED = 2,   /* valid but not implemented (e.g. k outside {1,2}) */
+  BMG_E_UNSUPPORTED = 2,   /* valid but not implemented (e.g. k outside {0,1,2}) */
   BMG_E_NOMEM = 3,         /* workspace too small or device allocation failed */
   BMG_E_HIP = 4,           /* a HIP runtime call failed */
   BMG_E_SINGULAR = 5,      /* a local or coarse matrix could not be inverted */
@@ -74,7 +74,7 @@ enum { BMG_COLOURING_S9 = 0,  /* 9 colours, (vx mod 3) + 3 (vy mod 3); a smoothi
 typedef struct {
   int32_t n0;            /* cells per side of the coarsest mesh T_0, 2 <= n0 <= 64 */
   int32_t levels;        /* J >= 0 refinements; finest N = n0 << levels <= 4096 */
-  int32_t k;             /* Raviart-Thomas degree, 1 or 2 */
+  int32_t k;             /* Raviart-Thomas degree, 0, 1 or 2 (RT_k x dQ_k; Section 2) */
   double mu;             /* viscosity, >= 0 (0 = Darcy) */
   double sigma;          /* penalty constant; Section 4.1 uses (k+1)(k+2); face penalty 2 mu sigma / h_j */
   int32_t bc[4];         /* BMG_BC_* per side */

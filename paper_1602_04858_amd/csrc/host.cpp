@@ -115,7 +115,7 @@ constexpr int kMaxRhs = 16;
 
 bmg_status check_params(const bmg_params* p) {
   if (!p) return BMG_E_ARG;
-  if (p->k != 1 && p->k != 2) return BMG_E_UNSUPPORTED;
+  if (p->k < 0 || p->k > 2) return BMG_E_UNSUPPORTED;
   if (p->n0 < 2 || p->n0 > 64 || p->levels < 0 || p->levels > 12) return BMG_E_ARG;
   if ((int64_t)p->n0 << p->levels > 4096) return BMG_E_ARG;
   if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
@@ -458,11 +458,11 @@ struct Bump {
 
 template <typename T>
 size_t elem_bytes(int K) {
-  return K == 1 ? sizeof(Elem<T, 1>) : sizeof(Elem<T, 2>);
+  return K == 0 ? sizeof(Elem<T, 0>) : K == 1 ? sizeof(Elem<T, 1>) : sizeof(Elem<T, 2>);
 }
 template <typename T>
 size_t xfer_bytes(int K) {
-  return K == 1 ? sizeof(Xfer<T, 1>) : sizeof(Xfer<T, 2>);
+  return K == 0 ? sizeof(Xfer<T, 0>) : K == 1 ? sizeof(Xfer<T, 1>) : sizeof(Xfer<T, 2>);
 }
 
 int nsr_of(int k) { return 4 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1); }
@@ -470,7 +470,7 @@ int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1
 // Stored entries of one patch pseudo-inverse: rotated symmetric block (RT_1 on levels
 // with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
 // mod n] for d = 0 .. n/2, n even) or full column-major block.
-bool packed_level(int k, int N) { return k == 1 && N >= 192; }
+bool packed_level(int k, int N) { return k <= 1 && N >= 192; }
 int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
@@ -641,7 +641,13 @@ bmg_status upload_consts(bmg_ctx* c, void* dst, bool elem, bool as_double) {
 
 bmg_status upload_all_consts(bmg_ctx* c) {
   bmg_status s;
-  if (c->K == 1) {
+  if (c->K == 0) {
+    s = c->prec == 0 ? upload_consts<double, 0>(c, c->elemT, true, false) : upload_consts<float, 0>(c, c->elemT, true, false);
+    if (s) return s;
+    s = upload_consts<double, 0>(c, c->elem64, true, true);
+    if (s) return s;
+    s = c->prec == 0 ? upload_consts<double, 0>(c, c->xferT, false, false) : upload_consts<float, 0>(c, c->xferT, false, false);
+  } else if (c->K == 1) {
     s = c->prec == 0 ? upload_consts<double, 1>(c, c->elemT, true, false) : upload_consts<float, 1>(c, c->elemT, true, false);
     if (s) return s;
     s = upload_consts<double, 1>(c, c->elem64, true, true);

@@ -386,8 +386,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   //   PF (RT_1, latency-bound levels): full column-major blocks, the column of this
   //       lane prefetched into registers;
   //   otherwise (RT_2): full blocks streamed from HBM in the product.
-  constexpr bool PK = (K == 1) && PKD;
-  constexpr bool PF = (K == 1) && !PKD;
+  constexpr bool PK = (K <= 1) && PKD;
+  constexpr bool PF = (K <= 1) && !PKD;
   constexpr int NPR = NSR * (NSR / 2 + 1), NPE = NSE * (NSE / 2 + 1);  // rotated entries
   static_assert(NSR % 2 == 0 && NSE % 2 == 0, "rotated storage needs an even patch size");
   constexpr int NQ = PK ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T zs[4][4 * NL];
   __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
-  __shared__ S aps[4][((K == 1) && PKD) ? NPR : 1];
+  __shared__ S aps[4][((K <= 1) && PKD) ? NPR : 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + w;
   const bool active = p < npatch;
@@ -1100,7 +1100,10 @@ static void op_t(const void* elem, const LevelArgs& L, const void* x, const void
 
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
                bool residual, int nrhs, int64_t ld, hipStream_t s) {
-  if (K == 1) {
+  if (K == 0) {
+    if (prec == 0) op_t<double, 0>(elem, L, x, b, y, residual, nrhs, ld, s);
+    else op_t<float, 0>(elem, L, x, b, y, residual, nrhs, ld, s);
+  } else if (K == 1) {
     if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
     else op_t<float, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
   } else {
@@ -1154,7 +1157,12 @@ void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs
                    bool packed, int nrhs, int64_t ld, double omega, hipStream_t s) {
 #define BMG_COL(T, S, KK) \
   colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, s)
-  if (K == 1) {
+  if (K == 0) {
+    if (prec == 0) BMG_COL(double, double, 0);
+    else if (sprec == 0) BMG_COL(float, double, 0);
+    else if (sprec == 1) BMG_COL(float, float, 0);
+    else BMG_COL(float, bf16, 0);
+  } else if (K == 1) {
     if (prec == 0) BMG_COL(double, double, 1);
     else if (sprec == 0) BMG_COL(float, double, 1);
     else if (sprec == 1) BMG_COL(float, float, 1);
@@ -1177,7 +1185,10 @@ static void restrict_t(const void* xfer, int Nc, int bcm, const void* rf, void* 
 }
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
                      int64_t ldf, int64_t ldc, hipStream_t s) {
-  if (K == 1) {
+  if (K == 0) {
+    if (prec == 0) restrict_t<double, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    else restrict_t<float, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+  } else if (K == 1) {
     if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
     else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
   } else {
@@ -1195,7 +1206,10 @@ static void prolong_t(const void* xfer, int Nc, int bcm, const void* xc, void* x
 }
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
                     int64_t ldc, int64_t ldf, hipStream_t s) {
-  if (K == 1) {
+  if (K == 0) {
+    if (prec == 0) prolong_t<double, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    else prolong_t<float, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+  } else if (K == 1) {
     if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
     else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
   } else {
@@ -1269,7 +1283,10 @@ void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst
                              hipStream_t s) {
   const int n = 4 * N * (K + 1);
   dim3 g((n + 255) / 256, nrhs), bl(256);
-  if (K == 1) {
+  if (K == 0) {
+    if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 0>), g, bl, 0, s, N, bcm, src, (double*)dst, ld);
+    else hipLaunchKernelGGL((k_copy_cons<float, 0>), g, bl, 0, s, N, bcm, src, (float*)dst, ld);
+  } else if (K == 1) {
     if (dst_prec == 0) hipLaunchKernelGGL((k_copy_cons<double, 1>), g, bl, 0, s, N, bcm, src, (double*)dst, ld);
     else hipLaunchKernelGGL((k_copy_cons<float, 1>), g, bl, 0, s, N, bcm, src, (float*)dst, ld);
   } else {

@@ -200,7 +200,11 @@ RefData make_refdata(int k, double mu, double sigma) {
 
 void gauss_points(int q, double* x, double* w) {
   double s[4], ws[4];
-  if (q == 3) {
+  if (q == 2) {
+    const double r = 1.0 / std::sqrt(3.0);
+    s[0] = -r; s[1] = r;
+    ws[0] = 1.0; ws[1] = 1.0;
+  } else if (q == 3) {
     double r = std::sqrt(3.0 / 5.0);
     s[0] = -r; s[1] = 0.0; s[2] = r;
     ws[0] = 5.0 / 9.0; ws[1] = 8.0 / 9.0; ws[2] = 5.0 / 9.0;
@@ -211,7 +215,7 @@ void gauss_points(int q, double* x, double* w) {
     s[0] = -b; s[1] = -a; s[2] = a; s[3] = b;
     ws[0] = wb; ws[1] = wa; ws[2] = wa; ws[3] = wb;
   } else {
-    throw std::runtime_error("gauss_points: q must be 3 or 4");
+    throw std::runtime_error("gauss_points: q must be 2, 3 or 4");
   }
   for (int i = 0; i < q; ++i) {
     x[i] = 0.5 * (1.0 + s[i]);

@@ -54,6 +54,8 @@ CASES = [
     (2, 3, 1, 1e-1, 6.0, (O, D, O, D)),
     (3, 2, 2, 1e-2, 12.0, (D, D, O, O)),
     (2, 2, 2, 0.0, 12.0, (D, O, D, O)),
+    (2, 4, 0, 1e-2, 2.0, (D, D, O, O)),
+    (3, 3, 0, 0.0, 2.0, (D, D, D, D)),
 ]
 IDS = [f"n0{c[0]}J{c[1]}k{c[2]}mu{c[3]}bc{''.join(map(str, c[5]))}" for c in CASES]
 
@@ -331,3 +333,32 @@ def test_c3_full_size(torch, bmg, name, rtol):
             (prec, info.iterations, i64.iterations)
         assert _rel(_np(x), ref) < 100 * rtol, prec
         del s
+
+
+
+def test_rt0_at_256(torch, bmg):
+    """RT_0 x dQ_0 at 256^2 (the C2 generator): rotated inverses on the two finest
+    levels (k <= 1), whole colour steps and a V-cycle against the oracle, and a solve."""
+    w = inputs.scaled_workload("C2", 256)
+    o = Oracle(w.n0, w.levels, 0, w.mu, 2.0, list(w.bc), w.kappa, 1, 2)
+    p = bmg.make_params(w.n0, w.levels, 0, w.mu, 2.0, w.bc, w.cycle, w.m_fine, 0, 60, 16384)
+    s = bmg.Solver(p, w.kappa)
+    J = w.levels
+    n = o.ndof()
+    cons = o.constrained()
+    x = inputs.random_vector(n, 61)
+    b = inputs.random_vector(n, 62)
+    x[cons] = 0.0
+    b[cons] = 0.0
+    xg = torch.as_tensor(x, device="cuda")
+    bg = torch.as_tensor(b, device="cuda")
+    for colour in (0, 5):
+        xg = s.colour_step(J, colour, xg, bg)
+        x = o.colour_step(colour, x, b)
+        assert _rel(_np(xg), x) < 1e-12, colour
+    assert _rel(_np(s.vcycle(bg)), o.vcycle(b)) < 1e-10
+    src = inputs.constant_source(1.0, 0.0)
+    xs, info = s.solve(_dev(torch, bmg.assemble_rhs(p, src)), rtol=1e-10, maxit=300)
+    b_o = o.rhs(src)
+    _, its, _, _ = o.fgmres(b_o, rtol=1e-10, maxit=300, restart=60)
+    assert info.converged == 1 and abs(info.iterations - abs(its)) <= 1, (info.iterations, its)

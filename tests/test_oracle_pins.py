@@ -205,15 +205,17 @@ def test_brinkman_convergence_rates(k):
     assert rg[-1] > k - 0.15, rg
 
 
-def test_darcy_convergence_rates():
-    k = 1
+@pytest.mark.parametrize("k", [0, 1])
+def test_darcy_convergence_rates(k):
+    """Darcy (mu = 0): velocity and pressure in L^2 at order k + 1 (RT_0 x dQ_0: first
+    order, RT_1 x dQ_1: second order)."""
     u, _ = inputs.manufactured_c1()
     pi = math.pi
     p = lambda x, y: np.cos(pi * x) * np.cos(pi * y)
     gp = lambda x, y: np.stack([-pi * np.sin(pi * x) * np.cos(pi * y), -pi * np.cos(pi * x) * np.sin(pi * y)], -1)
     eus, eps = [], []
     for n in [4, 8, 16, 32]:
-        o = Oracle(2, int(math.log2(n // 2)), k, 0.0, 6.0, [D, D, D, D], np.ones(n * n), 1, 2)
+        o = Oracle(2, int(math.log2(n // 2)), k, 0.0, (k + 1) * (k + 2.0), [D, D, D, D], np.ones(n * n), 1, 2)
         b = o.rhs(lambda x, y: u(x, y) + gp(x, y))
         x, its, _, tr = o.fgmres(b, rtol=1e-12, maxit=200)
         eu, ep, _ = _l2_errors(Space(n, k), x, u, p)
@@ -358,7 +360,7 @@ def _l8_colour(vx, vy):
 
 
 @pytest.mark.parametrize("colouring", [0, 1])
-@pytest.mark.parametrize("n0,J,k", [(2, 2, 1), (3, 1, 1), (2, 1, 2), (3, 2, 1)])
+@pytest.mark.parametrize("n0,J,k", [(2, 2, 1), (3, 1, 1), (2, 1, 2), (3, 2, 1), (2, 2, 0)])
 def test_same_colour_patches_do_not_interact(n0, J, k, colouring):
     n = n0 << J
     o = Oracle(n0, J, k, 1.0, 6.0, [D, O, D, O], np.ones(n * n), 1, 1, colouring)
@@ -608,3 +610,52 @@ def test_additive_vcycle_is_symmetric_and_converges():
     o0 = Oracle(n0, J, k, 1e-2, 6.0, [D, D, O, O], kap, 1, 2, 0, 1, 0.0)
     x0 = inputs.random_vector(nd, 7)
     assert np.array_equal(o0.smooth(1, x0, b), x0)
+
+
+# --------------------------------------------------------------------------
+# RT_0 x dQ_0 (k = 0)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mu", [1.0, 1e-2, 0.0])
+def test_rt0_constant_solution_is_reproduced(mu):
+    """RT_0 x dQ_0 contains constant velocities and pressures: u = (0.7, -0.4), p = 0
+    with f = kappa u is reproduced exactly (Nitsche terms consistent, essential
+    normal data), and the multigrid-preconditioned solve finds it."""
+    n0, J = 2, 2
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 31, 0.1, 10.0)
+    o = Oracle(n0, J, 0, mu, 2.0, [D, D, D, D], kap, 1, 2)
+    uc = np.array([0.7, -0.4])
+    u = lambda x, y: np.broadcast_to(uc, np.shape(x) + (2,)).copy()
+    f = lambda x, y: _cell_kappa(kap, n, x, y)[..., None] * u(x, y)
+    b = o.rhs(f, g=u)
+    x = o.direct_solve(b)
+    sp = Space(n, 0)
+    rng = np.random.default_rng(4)
+    X, Y = rng.random(100), rng.random(100)
+    uh, _, divh, ph = sp.evaluate(x, X, Y)
+    assert np.abs(uh - u(X, Y)).max() < 1e-11
+    assert np.abs(divh).max() < 1e-11
+    assert np.abs(ph - sp.pressure_mean(x)).max() < 1e-10
+    xm, its, _, tr = o.fgmres(b, rtol=1e-12, maxit=100)
+    assert its > 0 and tr < 1e-11
+
+
+def test_rt0_patch_sizes_and_level_independent_iterations():
+    """Interior RT_0 patches hold the 4 interior faces and 4 pressures (8 dofs); for
+    Darcy the V-cycle's FGMRES iteration count does not grow when the same
+    coefficient field is resolved on finer meshes (it falls, as in the paper's RT_0
+    columns)."""
+    o = Oracle(2, 2, 0, 1.0, 2.0, [O, O, O, O], np.ones(64), 1, 1)
+    sizes = [len(o.patch(p)[3]) for p in range(o.npatch())]
+    assert max(sizes) == 12 and 8 in sizes  # 8 inside, up to 12 with open-side outer faces
+    its = []
+    base = inputs.kappa_lognormal_channels(16, 7, channels=2, width=1).reshape(16, 16)
+    for J in (3, 4, 5):
+        n = 2 << J
+        r = n // 16  # the same coefficient field, resolved on finer meshes
+        kap = np.repeat(np.repeat(base, r, axis=0), r, axis=1).reshape(-1)
+        o = Oracle(2, J, 0, 0.0, 2.0, [D, D, O, O], kap, 1, 2)
+        _, it, _, tr = o.fgmres(o.rhs(inputs.smooth_source(5)), rtol=1e-10, maxit=200)
+        assert tr < 1e-9
+        its.append(it)
+    assert its[-1] <= its[0] and its[1] <= its[0] + 1, its
