@@ -401,7 +401,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T rs[4][NSE];
   __shared__ S aps[4][((K <= 1) && PKD) ? NPR : 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int p = blockIdx.x * 4 + w;
+  // XCD-aware order: the hardware hands consecutive blocks to the 8 XCDs in turn, so
+  // block b works on the (b mod 8)-th contiguous range of patches (a horizontal strip
+  // of the mesh, the same in every colour launch); values a neighbouring patch of the
+  // strip wrote in the previous colour step are then likely in this XCD's L2
+  // (only on grids the host padded to a multiple of 8; small grids keep the plain order)
+  const int gdim = gridDim.x;
+  const int lb = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
+  const int p = lb * 4 + w;
   const bool active = p < npatch;
   const int pc = active ? p : npatch - 1;  // in-bounds stand-in for idle waves
   int vx, vy;
@@ -1125,7 +1132,11 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
     if (packed) ncol = nrhs;
     else ncol = std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
   }
-  dim3 g(nblk, (nrhs + ncol - 1) / ncol), bl(256);
+  // large grids: a multiple of the 8 XCDs (the kernel then maps blocks to strips);
+  // small ones (coarse levels, setup batches): one block per 4 patches, plain order
+  // (a count that happens to be a multiple of 8 gets one idle block more)
+  const int gxb = nblk >= 64 ? (nblk + 7) / 8 * 8 : (nblk % 8 == 0 ? nblk + 1 : nblk);
+  dim3 g(gxb, (nrhs + ncol - 1) / ncol), bl(256);
 #define BMG_KC(TAG, PKD, MC, ADD)                                                                               \
   hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC, ADD>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,  \
                      (T)L.h, (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour,  \
