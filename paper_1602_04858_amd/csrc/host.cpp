@@ -881,7 +881,7 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
     // one event pair around the back-to-back colour launches of a smoothing step, so
     // that no marker sits between two colour kernels
     const bool rec = timed && c->ev_used + 2 <= c->ev.size();
-    if (rec) hipEventRecord(c->ev[c->ev_used], c->stream);
+    if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
     for (int i = 0; i < nl; ++i) {
       const int col = i < C ? i : 2 * C - 2 - i;
       if (additive)
@@ -893,7 +893,7 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
       if (rec) c->timed_bytes += colour_bytes(c, j, col) * nrhs;
     }
     if (rec) {
-      hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+      (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
       c->ev_used += 2;
       c->timed_launches += nl;
     }
@@ -991,7 +991,7 @@ bool capture_vcycle(bmg_ctx* c) {
   if (ok) ok = hipGraphInstantiate(&c->vexec, c->vgraph, nullptr, nullptr, 0) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
-    if (c->vgraph) hipGraphDestroy(c->vgraph);
+    if (c->vgraph) (void)hipGraphDestroy(c->vgraph);
     c->vgraph = nullptr;
     c->vexec = nullptr;
     c->graph_failed = true;
@@ -1005,8 +1005,13 @@ bool capture_vcycle(bmg_ctx* c) {
 void apply_precond(bmg_ctx* c, const double* r, double* z) {
   LevelInfo& L = c->lev.back();
   launch_cast(c->prec, 0, r, L.b, L.ndof * c->R, c->stream);
-  if (c->timing_level < 0 && capture_vcycle(c)) hipGraphLaunch(c->vexec, c->stream);
-  else vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
+  // the captured graph (eager launches while kernel timing is on, or if the graph
+  // cannot be built or launched)
+  const bool graphed = c->timing_level < 0 && capture_vcycle(c) && hipGraphLaunch(c->vexec, c->stream) == hipSuccess;
+  if (!graphed) {
+    if (c->timing_level < 0) (void)hipGetLastError();  // a failed graph launch is replaced, not reported
+    vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
+  }
   launch_cast(0, c->prec, L.x, z, L.ndof * c->R, c->stream);
   launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->R, L.ndof, c->stream);
 }
@@ -1123,7 +1128,7 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   }
   c->ws_bytes = need;
   if (c->layout_mismatch) {
-    if (c->own_ws) hipFree(c->ws);
+    if (c->own_ws) (void)hipFree(c->ws);
     delete c;
     return BMG_E_STATE;
   }
@@ -1155,7 +1160,7 @@ bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) 
   if (!h || level < -1 || level >= (int)h->lev.size() || level == 0 || max_launches < 0 || max_launches > 1 << 20)
     return BMG_E_ARG;
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  for (auto e : h->ev) hipEventDestroy(e);
+  for (auto e : h->ev) (void)hipEventDestroy(e);
   h->ev.clear();
   h->ev_used = 0;
   h->timed_launches = 0;
@@ -1184,14 +1189,14 @@ bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total
 
 bmg_status bmg_destroy(bmg_handle h) {
   if (!h) return BMG_E_ARG;
-  hipStreamSynchronize(h->stream);
-  for (auto e : h->ev) hipEventDestroy(e);
-  if (h->vexec) hipGraphExecDestroy(h->vexec);
-  if (h->vgraph) hipGraphDestroy(h->vgraph);
-  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  (void)hipStreamSynchronize(h->stream);
+  for (auto e : h->ev) (void)hipEventDestroy(e);
+  if (h->vexec) (void)hipGraphExecDestroy(h->vexec);
+  if (h->vgraph) (void)hipGraphDestroy(h->vgraph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_ws) {
-    hipStreamSynchronize(h->stream);
-    hipFree(h->ws);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->ws);
   }
   delete h;
   return BMG_OK;
@@ -1659,10 +1664,10 @@ static void batch_free(bmg_batch* b) {
   for (auto h : b->h)
     if (h) bmg_destroy(h);
   for (auto e : b->done)
-    if (e) hipEventDestroy(e);
-  if (b->start) hipEventDestroy(b->start);
+    if (e) (void)hipEventDestroy(e);
+  if (b->start) (void)hipEventDestroy(b->start);
   for (auto s : b->streams)
-    if (s) hipStreamDestroy(s);
+    if (s) (void)hipStreamDestroy(s);
   delete b;
 }
 
@@ -1758,7 +1763,7 @@ const char* bmg_batch_last_error(bmg_batch_handle b) { return b ? b->err.c_str()
 
 bmg_status bmg_batch_destroy(bmg_batch_handle b) {
   if (!b) return BMG_E_ARG;
-  for (auto s : b->streams) hipStreamSynchronize(s);
+  for (auto s : b->streams) (void)hipStreamSynchronize(s);
   batch_free(b);
   return BMG_OK;
 }
