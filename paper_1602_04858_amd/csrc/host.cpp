@@ -470,7 +470,15 @@ int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1
 // Stored entries of one patch pseudo-inverse: rotated symmetric block (RT_1 on levels
 // with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
 // mod n] for d = 0 .. n/2, n even) or full column-major block.
-bool packed_level(int k, int N) { return k <= 1 && N >= 192; }
+bool packed_level(const bmg_ctx* c, int N) {
+  if (N < 192) return false;
+  if (c->K <= 1) return true;
+  // RT_2: only for several columns (the block stages a patch's inverse in LDS once for
+  // all of them) and bfloat16 entries (four rotated blocks in 38 KB of LDS; with FP32
+  // entries a block needs 89 KB, one block per CU, slower than streaming: C5 at 512^2
+  // 3.2 vs 5.1 solves/s)
+  return c->R > 1 && c->sprec == 2;
+}
 int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
@@ -502,7 +510,7 @@ size_t layout(bmg_ctx* c, char* base) {
     L.r = B.take(L.ndof * c->R * ts);
     if (j > 0)
       for (int col = 0; col < 9; ++col) {
-        const bool pk = packed_level(K, L.N);
+        const bool pk = packed_level(c, L.N);
         L.inv[col] = B.take((size_t)L.npatch[col] * inv_entries(pk, nsr) * ss);
         L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * inv_entries(pk, nse) * ss);
         L.extidx[col] = (int32_t*)B.take((size_t)std::max(L.npatch[col], 1) * sizeof(int32_t));
@@ -795,7 +803,7 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       const bool near = vx == 1 || vx == L.N - 1 || vy == 1 || vy == L.N - 1;
       if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
     }
-    const bool pk = packed_level(c->K, L.N);
+    const bool pk = packed_level(c, L.N);
     const int64_t er = inv_entries(pk, nsr), ee = inv_entries(pk, nse);
     std::vector<double> reg((size_t)np * er, 0.0), exd((size_t)std::max(ne, 1) * ee, 0.0);
     std::atomic<int> bad{0};
@@ -859,7 +867,7 @@ double colour_bytes(const bmg_ctx* c, int j, int col) {
   const double gather = 12.0 * NB + 4.0 * NI + 4.0 * NP + 8.0 * NV + 4.0;
   const double reg = L.npatch[col] - L.next[col], ext = L.next[col];
   // x on the patch is written once (its old values come with the gather)
-  const bool pk = packed_level(K, L.N);
+  const bool pk = packed_level(c, L.N);
   return reg * ((double)inv_entries(pk, nsr) * c->ssize + (gather + 2.0 * nsr) * c->tsize) +
          ext * ((double)inv_entries(pk, nse) * c->ssize + (gather + 2.0 * nse) * c->tsize);
 }
@@ -875,7 +883,7 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
   const bool additive = c->p.smoother == BMG_SMOOTHER_ADDITIVE;
   const int C = colour_count(c->p.colouring);
   const int nl = additive ? C : 2 * C - 1;
-  const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c->K, L.N);
+  const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c, L.N);
   for (int st = 0; st < steps; ++st) {
     if (additive) launch_op(c->K, c->prec, c->elemT, a, x, b, r, true, nrhs, L.ndof, c->stream);
     // one event pair around the back-to-back colour launches of a smoothing step, so
@@ -1235,7 +1243,7 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(h->prec, 0, b, L.b, nt, h->stream);
   launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
                 L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1,
-                packed_level(h->K, L.N), h->R, L.ndof, 0.0, h->stream);
+                packed_level(h, L.N), h->R, L.ndof, 0.0, h->stream);
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

@@ -386,11 +386,12 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   //   PF (RT_1, latency-bound levels): full column-major blocks, the column of this
   //       lane prefetched into registers;
   //   otherwise (RT_2): full blocks streamed from HBM in the product.
-  constexpr bool PK = (K <= 1) && PKD;
+  // (RT_2 rotated blocks only with 4- or 2-byte entries: four of them fit in LDS)
+  constexpr bool PK = PKD && (K <= 1 || sizeof(S) <= 4);
   constexpr bool PF = (K <= 1) && !PKD;
   constexpr int NPR = NSR * (NSR / 2 + 1), NPE = NSE * (NSE / 2 + 1);  // rotated entries
   static_assert(NSR % 2 == 0 && NSE % 2 == 0, "rotated storage needs an even patch size");
-  constexpr int NQ = PK ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
+  constexpr int NQ = (PK && K <= 1) ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
   constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
   __shared__ Elem<T, K> Es;
   __shared__ T xs[4][4][NL];
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T zs[4][4 * NL];
   __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
-  __shared__ S aps[4][((K <= 1) && PKD) ? NPR : 1];
+  __shared__ S aps[4][(PKD && (K <= 1 || sizeof(S) <= 4)) ? NPR : 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // XCD-aware order: the hardware hands consecutive blocks to the 8 XCDs in turn, so
   // block b works on the (b mod 8)-th contiguous range of patches (a horizontal strip
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     for (int u = 0; u < (PF ? NSE : 1); ++u) areg[u] = A[min(u, n0 - 1) * n0 + lc];
   }
   S apk[NQ];
-  if (PK) {
+  if (PK && K <= 1) {
     // the regular slot exists for every patch; extended patches read their own
     // inverse from HBM in the product
     const S* A = inv + (size_t)pc * NPR;
@@ -509,6 +510,11 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       for (int q = 0; q < NQ; ++q)
         if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
     }
+  } else if (PK && MC && !ext_guess) {
+    // RT_2 (4704 rotated entries, too many for registers): copied to LDS once for
+    // all columns of the block
+    const S* A = inv + (size_t)pc * NPR;
+    for (int i = lane; i < NPR; i += 64) aps[w][i] = A[i];
   }
   const bool is_ext = ext_guess;
   const int ns = is_ext ? NSE : NSR;
@@ -621,9 +627,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     }
     // regular rotated inverse to LDS, once (the extended ones are read from HBM below)
     if (PK && !MC && !ext_guess) {
+      if (K <= 1) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+        for (int q = 0; q < NQ; ++q)
+          if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+      } else {
+        const S* A = inv + (size_t)pc * NPR;
+        for (int i = lane; i < NPR; i += 64) aps[w][i] = A[i];
+      }
     }
     lds_barrier();
 
@@ -649,12 +660,11 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       if (PK) {
         // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
         //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
-        // consecutive lanes read consecutive entries, so the LDS reads are conflict-free
-        const int t = lane;
-        if (t < ns) {
+        // consecutive lanes read consecutive entries, so the LDS reads are conflict-free.
+        // Rows t = lane + 64 q (RT_2 patches have more than 64 entries).
+        auto rot = [&](const S* Rp, int n, int t) {
           T acc = T(0);
-          if (!is_ext) {
-            const S* Rp = aps[w];
+          if (K <= 1) {  // n == NSR: fully unrolled
 #pragma unroll
             for (int d = 0; d <= NSR / 2; ++d) {
               int u = t + d;
@@ -668,21 +678,47 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
               acc += T(Rp[d * NSR + u]) * rs[w][u];
             }
           } else {
-            const S* Rp = invx + (size_t)ext * NPE;
-#pragma unroll 4
-            for (int d = 0; d <= NSE / 2; ++d) {
+#pragma unroll 8
+            for (int d = 0; d <= n / 2; ++d) {
               int u = t + d;
-              u -= u >= NSE ? NSE : 0;
-              acc += T(Rp[d * NSE + t]) * rs[w][u];
+              u -= u >= n ? n : 0;
+              acc += T(Rp[d * n + t]) * rs[w][u];
             }
-#pragma unroll 4
-            for (int d = 1; d < NSE / 2; ++d) {
+#pragma unroll 8
+            for (int d = 1; d < n / 2; ++d) {
               int u = t - d;
-              u += u < 0 ? NSE : 0;
-              acc += T(Rp[d * NSE + u]) * rs[w][u];
+              u += u < 0 ? n : 0;
+              acc += T(Rp[d * n + u]) * rs[w][u];
             }
           }
-          if (gi[0] >= 0) xc[gi[0]] = xold[0] + (ADD ? omega * acc : acc);
+          return acc;
+        };
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const int t = lane + 64 * q;
+          if (t < ns) {
+            T acc;
+            if (!is_ext) {
+              acc = rot(aps[w], NSR, t);
+            } else {
+              // extended (boundary) patches: their own rotated block, read from HBM
+              const S* Rp = invx + (size_t)ext * NPE;
+              acc = T(0);
+#pragma unroll 4
+              for (int d = 0; d <= NSE / 2; ++d) {
+                int u = t + d;
+                u -= u >= NSE ? NSE : 0;
+                acc += T(Rp[d * NSE + t]) * rs[w][u];
+              }
+#pragma unroll 4
+              for (int d = 1; d < NSE / 2; ++d) {
+                int u = t - d;
+                u += u < 0 ? NSE : 0;
+                acc += T(Rp[d * NSE + u]) * rs[w][u];
+              }
+            }
+            if (gi[q] >= 0) xc[gi[q]] = xold[q] + (ADD ? omega * acc : acc);
+          }
         }
       } else if (PF) {
         // one product length for both layouts: r is zero beyond the patch size

@@ -187,3 +187,40 @@ def test_bandwidth_bound_levels_columns(torch, bmg, prec):
     for c in range(R):
         x1 = s1.colour_step(J, 4, torch.zeros_like(r[c]), r[c].contiguous())
         assert _rel(xm[c].cpu().numpy(), x1.cpu().numpy()) <= tol, c
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-5), (2, 1e-2)])
+def test_rt2_rotated_columns(torch, bmg, prec, tol):
+    """RT_2 with several columns on a 256^2 level: with bfloat16 storage the patch
+    inverses are stored as rotated blocks and staged in LDS once per block for all
+    columns (FP32 storage streams full blocks).  One colour step
+    per column against the oracle (FP32 / bfloat16-storage tolerances), and a 2-column
+    solve that reaches the true residual and matches the FP64 one-column solves."""
+    w = inputs.scaled_workload("C5", 256)
+    R = 2
+    pm = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 30, 16384, R)
+    sm = bmg.Solver(pm, w.kappa)
+    o = Oracle(w.n0, w.levels, w.k, w.mu, w.sigma, list(w.bc), w.kappa, 1, 2)
+    J = w.levels
+    n = o.ndof(J)
+    cons = o.constrained(J)
+    xs, bs = [], []
+    for c in range(R):
+        x = inputs.random_vector(n, 300 + c)
+        b = inputs.random_vector(n, 310 + c)
+        x[cons] = 0.0
+        b[cons] = 0.0
+        xs.append(x)
+        bs.append(b)
+    xg = sm.colour_step(J, 4, torch.as_tensor(np.stack(xs), device="cuda"), torch.as_tensor(np.stack(bs), device="cuda"))
+    X = xg.cpu().numpy()
+    for c in range(R):
+        assert _rel(X[c], o.colour_step(4, xs[c], bs[c])) < tol, c
+    B = np.stack([bmg.assemble_rhs(pm, inputs.smooth_source(5100 + c)) for c in range(R)])
+    x, infos = sm.solve(torch.as_tensor(B, device="cuda"), rtol=1e-10, maxit=300)
+    s64 = bmg.Solver(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, 0, 30, 16384),
+                     w.kappa)
+    for c in range(R):
+        assert infos[c].converged == 1 and infos[c].rel_residual_true < 2e-10, c
+        x64, _ = s64.solve(torch.as_tensor(B[c], device="cuda"), rtol=1e-10, maxit=300)
+        assert _rel(x[c].cpu().numpy(), x64.cpu().numpy()) < 1e-8, c
