@@ -117,7 +117,8 @@ bmg_status bmg_plan(const bmg_params* p, size_t* workspace_bytes);
  * zero patch-mean pressure when the patch problem has the constant-pressure null
  * mode), transfers and the coarse inverse (Section 3.2, B_0 = A_0^{-1}).
  *   kappa_host: N*N doubles, cell (cx, cy) at cy*N + cx, N = n0 << levels; finite,
- *               > 0 (BMG_E_NONFINITE / BMG_E_ARG otherwise); copied, not retained.
+ *               >= 0 if mu > 0 (0: Stokes), > 0 if mu = 0 (BMG_E_NONFINITE /
+ *               BMG_E_ARG otherwise); copied, not retained.
  *   workspace_dev / bytes: caller-owned device memory of at least bmg_plan bytes
  *               (256-byte aligned), or NULL / 0 to let the library allocate it.
  *   hip_stream: hipStream_t for all work (NULL = default stream).

@@ -471,13 +471,11 @@ int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1
 // with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
 // mod n] for d = 0 .. n/2, n even) or full column-major block.
 bool packed_level(const bmg_ctx* c, int N) {
-  if (N < 192) return false;
-  if (c->K <= 1) return true;
-  // RT_2: only for several columns (the block stages a patch's inverse in LDS once for
-  // all of them) and bfloat16 entries (four rotated blocks in 38 KB of LDS; with FP32
-  // entries a block needs 89 KB, one block per CU, slower than streaming: C5 at 512^2
-  // 3.2 vs 5.1 solves/s)
-  return c->R > 1 && c->sprec == 2;
+  // RT_2 keeps full blocks: with several columns in FP32 arithmetic the colour kernel
+  // multiplies them by all columns at once on the matrix cores (each entry read once);
+  // the RT_2 rotated path (LDS-staged) is kept in the kernel but not chosen (FP32
+  // entries need 89 KB of LDS per block)
+  return c->K <= 1 && N >= 192;
 }
 int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }
 
@@ -1059,9 +1057,12 @@ std::vector<double> kappa_level(const double* fine, int n0, int J, int j, int mo
 bmg_status check_kappa(const bmg_params* p, const double* kappa) {
   if (!kappa) return BMG_E_ARG;
   const int N = p->n0 << p->levels;
+  // kappa >= 0 with viscosity (kappa = 0: the Stokes end of the Brinkman family),
+  // kappa > 0 for Darcy
+  const bool stokes_ok = p->mu > 0.0;
   for (int64_t i = 0; i < (int64_t)N * N; ++i) {
     if (!std::isfinite(kappa[i])) return BMG_E_NONFINITE;
-    if (!(kappa[i] > 0.0)) return BMG_E_ARG;
+    if (stokes_ok ? !(kappa[i] >= 0.0) : !(kappa[i] > 0.0)) return BMG_E_ARG;
   }
   return BMG_OK;
 }

@@ -388,7 +388,11 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   //   otherwise (RT_2): full blocks streamed from HBM in the product.
   // (RT_2 rotated blocks only with 4- or 2-byte entries: four of them fit in LDS)
   constexpr bool PK = PKD && (K <= 1 || sizeof(S) <= 4);
-  constexpr bool PF = (K <= 1) && !PKD;
+  // MF: several columns in FP32 arithmetic with full-storage inverses -- the residuals
+  // of all columns are formed first, then one MFMA product Y = A+ [r_1 .. r_C] reads
+  // every inverse entry once for all columns
+  constexpr bool MF = MC && !PK && sizeof(T) == 4;
+  constexpr bool PF = (K <= 1) && !PKD && !MF;
   constexpr int NPR = NSR * (NSR / 2 + 1), NPE = NSE * (NSE / 2 + 1);  // rotated entries
   static_assert(NSR % 2 == 0 && NSE % 2 == 0, "rotated storage needs an even patch size");
   constexpr int NQ = (PK && K <= 1) ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
@@ -400,6 +404,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   __shared__ T zs[4][4 * NL];
   __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
+  __shared__ T rsa[MF ? 4 : 1][MF ? 16 : 1][MF ? NSE : 1];  // MF: residuals of every column
+  __shared__ int gis[MF ? 4 : 1][MF ? NSE : 1];              // MF: global index of every slot
   __shared__ S aps[4][(PKD && (K <= 1 || sizeof(S) <= 4)) ? NPR : 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   // XCD-aware order: the hardware hands consecutive blocks to the 8 XCDs in turn, so
@@ -622,7 +628,12 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
             xold[q] = (&xs[w][0][0])[zA[q]];
           }
         }
-        rs[w][t] = r;
+        if (MF) {
+          rsa[w][c - c0][t] = r;
+          if (c == c0) gis[w][t] = gi[q];
+        } else {
+          rs[w][t] = r;
+        }
       }
     }
     // regular rotated inverse to LDS, once (the extended ones are read from HBM below)
@@ -656,7 +667,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     }
 
     // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
-    if (active) {
+    if (active && !MF) {
       if (PK) {
         // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
         //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
@@ -744,6 +755,49 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     }
     if (!more) break;
     ++c;
+  }
+
+  if (MF) {
+    // Y (n x C) = A+ (n x n) R (n x C) by v_mfma_f32_16x16x4f32 tiles: A operand lane l
+    // holds A[16 rt + l % 16][4 ks + l / 16] (column-major storage: entry (row, col) at
+    // col n + row), B operand R[4 ks + l / 16][l % 16] from LDS, result lane l register
+    // v: Y[16 rt + 4 (l / 16) + v][l % 16].  n is a multiple of 4; rows past n are 0.
+    typedef float mf4 __attribute__((ext_vector_type(4)));
+    constexpr int NRT = (NSE + 15) / 16;
+    lds_barrier();
+    if (active) {
+      const int n = is_ext ? NSE : NSR;
+      const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
+      const int ncols = c1 - c0;
+      const int j = lane & 15, kq = lane >> 4;
+      mf4 acc[NRT];
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mf4{0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < n / 4; ++ks) {
+        const int kk = 4 * ks + kq;
+        const float bval = j < ncols ? (float)rsa[w][j][kk] : 0.f;
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+          const int row = 16 * rt + j;
+          const float aval = row < n ? (float)A[(size_t)kk * n + row] : 0.f;
+          acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[rt], 0, 0, 0);
+        }
+      }
+      if (j < ncols) {
+        T* xc = x + (int64_t)(c0 + j) * ld;
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rt + 4 * kq + v;
+            if (row < n) {
+              const int g = gis[w][row];
+              // same-colour patches write disjoint entries: the read-modify-write is safe
+              if (g >= 0) xc[g] += ADD ? omega * (T)acc[rt][v] : (T)acc[rt][v];
+            }
+          }
+      }
+    }
   }
 }
 

@@ -224,3 +224,29 @@ def test_rt2_rotated_columns(torch, bmg, prec, tol):
         assert infos[c].converged == 1 and infos[c].rel_residual_true < 2e-10, c
         x64, _ = s64.solve(torch.as_tensor(B[c], device="cuda"), rtol=1e-10, maxit=300)
         assert _rel(x[c].cpu().numpy(), x64.cpu().numpy()) < 1e-8, c
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 1e-5)])
+def test_mfma_multi_column_product(torch, bmg, prec, tol):
+    """16 columns of RT_2 at 256^2: the fine levels run blocks of several columns whose
+    patch products are MFMA tiles (inverse read once for all columns); every column of
+    the V-cycle equals the one-column V-cycle (vector product) to FP32 rounding, and a
+    16-column solve converges like the one-column one."""
+    w = inputs.scaled_workload("C5", 256)
+    R = 16
+    sm = bmg.Solver(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 8, 16384, R),
+                    w.kappa)
+    s1 = bmg.Solver(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 8, 16384),
+                    w.kappa)
+    n = s1.ndof()
+    r = torch.stack([torch.as_tensor(inputs.random_vector(n, 400 + c), device="cuda") for c in range(R)]).contiguous()
+    z = sm.vcycle(r)
+    for c in (0, 5, 15):
+        z1 = s1.vcycle(r[c].contiguous())
+        assert _rel(z[c].cpu().numpy(), z1.cpu().numpy()) <= tol, c
+    B = np.stack([bmg.assemble_rhs(sm.params, inputs.smooth_source(5100 + c)) for c in range(R)])
+    x, infos = sm.solve(torch.as_tensor(B, device="cuda"), rtol=1e-10, maxit=300)
+    x1, i1 = s1.solve(torch.as_tensor(B[3], device="cuda"), rtol=1e-10, maxit=300)
+    assert all(i.converged == 1 and i.rel_residual_true < 2e-10 for i in infos)
+    assert abs(infos[3].iterations - i1.iterations) <= 1
+    assert _rel(x[3].cpu().numpy(), x1.cpu().numpy()) < 1e-8

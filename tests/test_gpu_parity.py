@@ -362,3 +362,46 @@ def test_rt0_at_256(torch, bmg):
     b_o = o.rhs(src)
     _, its, _, _ = o.fgmres(b_o, rtol=1e-10, maxit=300, restart=60)
     assert info.converged == 1 and abs(info.iterations - abs(its)) <= 1, (info.iterations, its)
+
+
+@pytest.mark.parametrize("bc", [(D, D, O, O), (D, D, D, D)], ids=["open", "closed"])
+def test_stokes_limit_kappa_zero(torch, bmg, bc):
+    """kappa = 0 everywhere (Stokes, mu > 0): the degenerate end of the Brinkman
+    family; and kappa with zero cells mixed in."""
+    for kind in ("zero", "mixed"):
+        n0, J, k = 2, 4, 1
+        n = n0 << J
+        if kind == "zero":
+            kap = np.zeros(n * n)
+        else:
+            kap = inputs.kappa_lognormal_channels(n, 8, channels=2, width=1)
+            kap[::3] = 0.0
+        o = Oracle(n0, J, k, 1.0, 6.0, list(bc), kap, 1, 2)
+        s = bmg.Solver(bmg.make_params(n0, J, k, 1.0, 6.0, bc, restart=60), kap)
+        src = inputs.smooth_source(71)
+        b_o = o.rhs(src)
+        b_g = bmg.assemble_rhs(s.params, src)
+        if o.singular():
+            pidx = o.n_u() + np.arange(n * n) * (k + 1) ** 2
+            b_o[pidx] -= b_o[pidx].mean()
+            b_g = b_o.copy()
+        x, info = s.solve(_dev(torch, b_g), rtol=1e-10, maxit=300)
+        x_tight, its, _, _ = o.fgmres(b_o, rtol=1e-13, maxit=400, restart=60)
+        x = _np(x)
+        if o.singular():
+            from fe import Space
+            sp = Space(n, k)
+            x = sp.remove_pressure_mean(x)
+            x_tight = sp.remove_pressure_mean(x_tight)
+        assert info.converged == 1 and info.rel_residual_true < 2e-10, kind
+        assert _rel(x, x_tight) < 1e-8, kind
+
+
+def test_zero_right_hand_side(torch, bmg):
+    """b = 0: x = 0 after no iteration, whatever x0 holds."""
+    o, s, _ = _setup(bmg, CASES[0])
+    n = s.ndof()
+    x0 = _dev(torch, inputs.random_vector(n, 5))
+    x, info = s.solve(torch.zeros(n, dtype=torch.float64, device="cuda"), rtol=1e-10, maxit=10, x0=x0)
+    assert info.converged == 1 and info.iterations == 0
+    assert not _np(x).any()

@@ -98,6 +98,12 @@ def test_nonfinite_and_negative_kappa_rejected():
     with pytest.raises(bmg.BmgError) as e:
         bmg.export_patch(p, kap, 1, 1, 1)
     assert e.value.status == 1
+    # zero is the Stokes limit with viscosity, invalid for Darcy
+    kap[3] = 0.0
+    bmg.export_patch(p, kap, 1, 1, 1)
+    with pytest.raises(bmg.BmgError) as e:
+        bmg.export_patch(bmg.make_params(2, 1, 1, 0.0, 6.0, [D, D, O, O]), kap, 1, 1, 1)
+    assert e.value.status == 1
 
 
 CASES = [
