@@ -471,10 +471,12 @@ int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1
 // with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
 // mod n] for d = 0 .. n/2, n even) or full column-major block.
 bool packed_level(const bmg_ctx* c, int N) {
-  // RT_2 keeps full blocks: with several columns in FP32 arithmetic the colour kernel
-  // multiplies them by all columns at once on the matrix cores (each entry read once);
-  // the RT_2 rotated path (LDS-staged) is kept in the kernel but not chosen (FP32
-  // entries need 89 KB of LDS per block)
+  // Several columns in FP32 arithmetic keep full blocks: the colour kernel multiplies
+  // a block by all columns at once on the matrix cores (each entry read once), which
+  // beats the rotated per-column products.  RT_2 keeps full blocks always (its rotated
+  // LDS-staged path stays in the kernel but is not chosen: FP32 entries need 89 KB of
+  // LDS per block).
+  if (c->R > 1 && c->prec != 0) return false;
   return c->K <= 1 && N >= 192;
 }
 int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }

@@ -1214,12 +1214,13 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
                      const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs,
                      int64_t ld, double omega, hipStream_t s) {
   if (npatch <= 0) return;
-  // columns per block: all of them on the bandwidth-bound levels (the inverse is read
-  // once per patch); elsewhere enough blocks to fill the device come first
+  // columns per block: all of them on the bandwidth-bound levels (N >= 192: the inverse
+  // is read once per patch for all columns); elsewhere enough blocks to fill the
+  // device come first
   const int nblk = (npatch + 3) / 4;
   int ncol = 1;
   if (nrhs > 1) {
-    if (packed) ncol = nrhs;
+    if (packed || L.N >= 192) ncol = std::min(nrhs, 16);
     else ncol = std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
   }
   // large grids: a multiple of the 8 XCDs (the kernel then maps blocks to strips);

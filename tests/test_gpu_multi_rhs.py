@@ -168,9 +168,11 @@ def test_wrong_column_count_rejected(torch, bmg):
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_bandwidth_bound_levels_columns(torch, bmg, prec):
-    """C2 size (256^2, rotated inverses on the two finest levels): the columns of a
-    3-column V-cycle and colour step are those of one-column calls; on these levels
-    one block applies a patch inverse to all columns."""
+    """C2 size (256^2): the columns of a 3-column V-cycle and colour step are those of
+    one-column calls; on the two finest levels one block applies a patch inverse to
+    all columns (FP64: rotated blocks in LDS; FP32 arithmetic: full blocks on the
+    matrix cores, while the one-column handle stores rotated symmetrised blocks -- the
+    same inverse, so the columns agree to FP32 rounding, 1e-5)."""
     w = inputs.workload("C2")
     R = 3
     sm = bmg.from_workload(w, prec=prec, restart=10, n_rhs=R)
@@ -178,7 +180,7 @@ def test_bandwidth_bound_levels_columns(torch, bmg, prec):
     n = s1.ndof()
     r = torch.stack([torch.as_tensor(inputs.random_vector(n, 80 + c), device="cuda") for c in range(R)]).contiguous()
     z = sm.vcycle(r)
-    tol = 1e-14 if prec == 0 else 1e-6
+    tol = 1e-14 if prec == 0 else 1e-5
     for c in range(R):
         z1 = s1.vcycle(r[c].contiguous())
         assert _rel(z[c].cpu().numpy(), z1.cpu().numpy()) <= tol, c
