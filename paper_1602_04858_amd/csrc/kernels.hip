@@ -75,6 +75,16 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders this wave's own LDS accesses (values one lane wrote, another lane of the same
+// wave reads): a wave's LDS instructions execute in program order, so this only keeps
+// the compiler from moving accesses across it.  Waves of a block do not wait for each
+// other here.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // one velocity component (NV values, comp 0 = u_x, 1 = u_y) of a cell; essential dofs read as 0
 template <int K, typename T>
 __device__ __forceinline__ void load_comp(const T* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
@@ -398,22 +408,40 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   constexpr int NQ = (PK && K <= 1) ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
   constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
   __shared__ Elem<T, K> Es;
-  __shared__ T xs[4][4][NL];
-  __shared__ T nb[4][4][2][NV];  // [wave][slot][0: u_x of the cell across the outer horizontal face,
-                                 //               1: u_y of the cell across the outer vertical face]
-  __shared__ T zs[4][4 * NL];
   __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
   __shared__ T rs[4][NSE];
   __shared__ T rsa[MF ? 4 : 1][MF ? 16 : 1][MF ? NSE : 1];  // MF: residuals of every column
   __shared__ int gis[MF ? 4 : 1][MF ? NSE : 1];              // MF: global index of every slot
-  __shared__ S aps[4][(PKD && (K <= 1 || sizeof(S) <= 4)) ? NPR : 1];
+  // Per-wave region: the gathered cell values xs[slot][NL], the neighbour values
+  // nb[slot][0: u_x of the cell across the outer horizontal face, 1: u_y of the cell
+  // across the outer vertical face][NV], the row contributions zs[4 NL], and the staged
+  // rotated inverse aps[NPR].  With one column the wave stages its inverse only after
+  // its last read of xs / nb / zs, so the inverse overlays them (OVL): that keeps an
+  // FP64 RT_1 block under 32 KB of LDS, five blocks per CU instead of four.
+  constexpr bool OVL = PK && !MC;
+  constexpr int WSB = (int)sizeof(T) * (4 * NL + 8 * NV + 4 * NL);
+  constexpr int APB = (int)sizeof(S) * (PK ? NPR : 1);
+  constexpr int RB = ((OVL ? (WSB > APB ? WSB : APB) : WSB + APB) + 15) / 16 * 16;
+  __shared__ __attribute__((aligned(16))) unsigned char wpool[4 * RB];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  unsigned char* const wreg = wpool + w * RB;
+  T(*const xw)[NL] = reinterpret_cast<T(*)[NL]>(wreg);
+  T(*const nbw)[2][NV] = reinterpret_cast<T(*)[2][NV]>(wreg + sizeof(T) * 4 * NL);
+  T* const zw = reinterpret_cast<T*>(wreg + sizeof(T) * (4 * NL + 8 * NV));
+  S* const apw = reinterpret_cast<S*>(wreg + (OVL ? 0 : WSB));
   // XCD-aware order: the hardware hands consecutive blocks to the 8 XCDs in turn, so
   // block b works on the (b mod 8)-th contiguous range of patches (a horizontal strip
   // of the mesh, the same in every colour launch); values a neighbouring patch of the
   // strip wrote in the previous colour step are then likely in this XCD's L2
   // (only on grids the host padded to a multiple of 8; small grids keep the plain order)
-  const int gdim = gridDim.x;
+  // every kernel argument is wanted in the first microseconds: take them in one batch
+  // of scalar loads (one memory round trip for the first wave on a CU) rather than
+  // the several dependent batches the scheduler would otherwise place near each use.
+  // (A pass-through of the grid size, without side effects, so that the scalar load
+  // of `ext` below is still seen as reading unmodified memory.)
+  int gdim;
+  asm("" : "=s"(gdim) : "0"((int)gridDim.x), "s"(N), "s"(bcm), "s"(colour), "s"(scheme), "s"(npatch), "s"(ld),
+      "s"(Ep), "s"(kap), "s"(x), "s"(b), "s"(inv), "s"(invx), "s"(extidx), "s"(h));
   const int lb = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
   const int p = lb * 4 + w;
   const bool active = p < npatch;
@@ -422,7 +450,9 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   patch_vertex(scheme, N, colour, pc, vx, vy);
   const T mh = -h, hh = h * h;
   auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
-  const int ext = active ? extidx[pc] : -1;
+  // index of the extended inverse (pc is in bounds for every wave).  Unconditional, so
+  // that the wave does not wait for it before the gathers
+  const int ext = extidx[pc];
   // right-hand-side columns of this block: c0 .. c1-1 (ld apart); MC = several
   const int c0 = MC ? blockIdx.y * ncol : blockIdx.y, c1 = MC ? min(c0 + ncol, nrhs) : c0 + 1;
 
@@ -514,13 +544,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
       // several columns: stage the inverse now (read only in the products)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+        if (lane + 64 * q < NPR) apw[lane + 64 * q] = apk[q];
     }
   } else if (PK && MC && !ext_guess) {
     // RT_2 (4704 rotated entries, too many for registers): copied to LDS once for
     // all columns of the block
     const S* A = inv + (size_t)pc * NPR;
-    for (int i = lane; i < NPR; i += 64) aps[w][i] = A[i];
+    for (int i = lane; i < NPR; i += 64) apw[i] = A[i];
   }
   const bool is_ext = ext_guess;
   const int ns = is_ext ? NSE : NSR;
@@ -532,14 +562,14 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   #pragma unroll
       for (int q = 0; q < NG; ++q) {
         const int e = lane + 64 * q;
-        if (e < 4 * NL) xs[w][e / NL][e % NL] = okx[q] ? gx[q] : T(0);
+        if (e < 4 * NL) xw[e / NL][e % NL] = okx[q] ? gx[q] : T(0);
       }
   #pragma unroll
       for (int q = 0; q < NN; ++q) {
         const int e = lane + 64 * q;
         if (e < 8 * NV) {
           const int s = e / (2 * NV), r = e % (2 * NV);
-          nb[w][s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
+          nbw[s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
         }
       }
       if (c == c0) {
@@ -549,7 +579,11 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
         if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
       }
-      lds_barrier();
+      // the element matrices are shared by the block; the rest is the wave's own
+      if (c == c0)
+        lds_barrier();
+      else
+        wave_lds_sync();
 
       // 2. row contributions of every patch cell (cell blocks + its four faces), one
       // branch-free path for all rows.  A velocity row (component c, local index dd)
@@ -564,7 +598,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
         if (e >= 4 * NL) break;
         const int s = e / NL, d = e % NL;
         const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-        const T* xl = xs[w][s];
+        const T* xl = xw[s];
         const bool vel = d < 2 * NV;
         const int comp = d >= NV ? 1 : 0;
         const int dd = vel ? d - comp * NV : d - 2 * NV;
@@ -573,8 +607,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
         const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
         const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
         const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
-        const T* nl = comp ? ((s & 1) ? xs[w][s - 1] + NV : nb[w][s][1]) : ((s >= 2) ? xs[w][s - 2] : nb[w][s][0]);
-        const T* nu = comp ? ((s & 1) ? nb[w][s][1] : xs[w][s + 1] + NV) : ((s < 2) ? xs[w][s + 2] : nb[w][s][0]);
+        const T* nl = comp ? ((s & 1) ? xw[s - 1] + NV : nbw[s][1]) : ((s >= 2) ? xw[s - 2] : nbw[s][0]);
+        const T* nu = comp ? ((s & 1) ? nbw[s][1] : xw[s + 1] + NV) : ((s < 2) ? xw[s + 2] : nbw[s][0]);
         const int ro = dd * NV;
         const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
         const T* c_mass = vel ? Es.M + ro : zblk;
@@ -604,9 +638,9 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   #pragma unroll
         for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
         const T z = (vel ? a : mh * a) + mh * g;
-        zs[w][e] = (active && in_dom(cx, cy)) ? z : T(0);
+        zw[e] = (active && in_dom(cx, cy)) ? z : T(0);
       }
-      lds_barrier();
+      wave_lds_sync();  // this wave's own LDS region only
     }
 
     // 3. local residual (b - A x) on the patch entries.  The layout follows from the
@@ -624,8 +658,8 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
             r = bv[q];
             xold[q] = xv[q];
           } else {
-            r = bv[q] - zs[w][zA[q]] - (zB[q] >= 0 ? zs[w][zB[q]] : T(0));
-            xold[q] = (&xs[w][0][0])[zA[q]];
+            r = bv[q] - zw[zA[q]] - (zB[q] >= 0 ? zw[zB[q]] : T(0));
+            xold[q] = (&xw[0][0])[zA[q]];
           }
         }
         if (MF) {
@@ -636,18 +670,20 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
         }
       }
     }
-    // regular rotated inverse to LDS, once (the extended ones are read from HBM below)
+    // regular rotated inverse to LDS, once (the extended ones are read from HBM below);
+    // with OVL it overwrites this wave's xs / nb / zs, whose reads are all above
+    if (OVL) __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (PK && !MC && !ext_guess) {
       if (K <= 1) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          if (lane + 64 * q < NPR) aps[w][lane + 64 * q] = apk[q];
+          if (lane + 64 * q < NPR) apw[lane + 64 * q] = apk[q];
       } else {
         const S* A = inv + (size_t)pc * NPR;
-        for (int i = lane; i < NPR; i += 64) aps[w][i] = A[i];
+        for (int i = lane; i < NPR; i += 64) apw[i] = A[i];
       }
     }
-    lds_barrier();
+    wave_lds_sync();  // this wave's own LDS region only
 
     // the next column's gather and b are issued before the product of this one
     const bool more = MC && c + 1 < c1;
@@ -710,7 +746,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           if (t < ns) {
             T acc;
             if (!is_ext) {
-              acc = rot(aps[w], NSR, t);
+              acc = rot(apw, NSR, t);
             } else {
               // extended (boundary) patches: their own rotated block, read from HBM
               const S* Rp = invx + (size_t)ext * NPE;
@@ -764,7 +800,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     // v: Y[16 rt + 4 (l / 16) + v][l % 16].  n is a multiple of 4; rows past n are 0.
     typedef float mf4 __attribute__((ext_vector_type(4)));
     constexpr int NRT = (NSE + 15) / 16;
-    lds_barrier();
+    wave_lds_sync();  // this wave's own LDS region only
     if (active) {
       const int n = is_ext ? NSE : NSR;
       const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
