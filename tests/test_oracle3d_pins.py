@@ -1,0 +1,181 @@
+"""Pins of the 3-D oracle against what the mathematics fixes (CPU only).
+
+Each test is chosen so that a plausible slip in the 3-D assembly, transfers or smoother
+(a dropped face term, a wrong sign of the pressure coupling, a transposed block, a
+wrong child offset, a missing Nitsche term) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import oracle3d as o3
+
+
+def _kappa(n, seed, lo=-2.0, hi=0.0):
+    return 10.0 ** np.random.default_rng(seed).uniform(lo, hi, n ** 3)
+
+
+def _cell_kappa(kap, n, x, y, z):
+    c = lambda t: np.minimum((np.asarray(t) * n).astype(int), n - 1)
+    return kap[(c(z) * n + c(y)) * n + c(x)]
+
+
+# P1: u = (y, z, x) (divergence free, in RT_1), p = xyz - 1/8 (in dQ_1, mean 0):
+# f = -mu lap u + kappa u + grad p; g = u on all sides.  The discrete solution is exact.
+@pytest.mark.parametrize("mu", [1.0, 1e-2])
+def test_polynomial_solution_is_reproduced_3d(mu):
+    n0, levels = 1, 2
+    n = n0 << (levels - 1)
+    kap = _kappa(n, 5)
+    o = o3.Oracle3D(n0, levels, 1, mu, 6.0, kap)
+    lev = o.lev[-1]
+    k_at = lambda x, y, z: _cell_kappa(kap, n, x, y, z)
+    f = lambda x, y, z: np.array([k_at(x, y, z) * y + y * z, k_at(x, y, z) * z + x * z, k_at(x, y, z) * x + x * y])
+    g = lambda x, y, z: np.array([y, z, x])
+    b = lev.rhs(f, g)
+    rng = np.random.default_rng(7)
+    P = rng.random((40, 3))
+    ue = np.stack([P[:, 1], P[:, 2], P[:, 0]], 1)
+    pe = P[:, 0] * P[:, 1] * P[:, 2] - 0.125
+    for x in (o.direct_solve(b), o.fgmres(b, rtol=1e-13, maxit=50)[0]):
+        U, Pv = o3.evaluate(lev, x, P)
+        assert np.abs(U - ue).max() < 1e-11
+        assert np.abs(Pv - o.pressure_mean(x) - pe).max() < 1e-10
+
+
+# P2: f = grad(phi), phi the continuous trilinear hat at an interior vertex, g = 0:
+# u_h = 0 and p_h = phi (up to the mean) exactly -- pins the sign and the scaling of
+# the pressure coupling against the body force.
+def test_hat_gradient_pressure_robustness_3d():
+    n0, levels = 2, 2
+    n = n0 << (levels - 1)
+    h = 1.0 / n
+    o = o3.Oracle3D(n0, levels, 1, 1e-2, 6.0, _kappa(n, 9, -6.0, 0.0))
+    lev = o.lev[-1]
+    v = np.array([2, 1, 3]) * h
+    hat1 = lambda t, c: np.maximum(0.0, 1.0 - np.abs(t - c) / h)
+    dhat1 = lambda t, c: np.where(np.abs(t - c) < h, -np.sign(t - c) / h, 0.0)
+    phi = lambda x, y, z: hat1(x, v[0]) * hat1(y, v[1]) * hat1(z, v[2])
+    f = lambda x, y, z: np.array([dhat1(x, v[0]) * hat1(y, v[1]) * hat1(z, v[2]),
+                                  hat1(x, v[0]) * dhat1(y, v[1]) * hat1(z, v[2]),
+                                  hat1(x, v[0]) * hat1(y, v[1]) * dhat1(z, v[2])])
+    zero = lambda x, y, z: np.zeros((3,) + np.shape(x))
+    x = o.direct_solve(lev.rhs(f, zero))
+    P = np.random.default_rng(3).random((60, 3))
+    U, Pv = o3.evaluate(lev, x, P)
+    assert np.abs(U).max() < 1e-11
+    # the hat integrates to h^3 over the unit cube
+    assert np.abs((Pv - o.pressure_mean(x)) - (phi(P[:, 0], P[:, 1], P[:, 2]) - h ** 3)).max() < 1e-10
+
+
+def test_operator_symmetry_and_essential_rows_3d():
+    lev = o3.Level(4, 1, 0.3, 6.0, _kappa(4, 1))
+    for A in (lev.A, lev.A_full):
+        assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    cons = np.flatnonzero(lev.sp.cons)
+    assert len(cons) == 6 * 16 * 4  # six sides, 16 faces each, (k+1)^2 dofs per face
+    Ac = lev.A[cons]
+    assert np.array_equal(Ac.indices, cons) and np.all(Ac.data == 1.0)
+    # the constant pressure is in the kernel of the operator with essential normals
+    assert np.abs(lev.A @ lev.cvec).max() < 1e-13
+
+
+def test_divergence_free_solution_3d():
+    o = o3.Oracle3D(2, 2, 1, 1e-2, 6.0, _kappa(4, 4, -6.0, 0.0))
+    lev = o.lev[-1]
+    zero = lambda x, y, z: np.zeros((3,) + np.shape(x))
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    x = o.direct_solve(lev.rhs(zero, g))
+    nu = lev.sp.n_u
+    div = lev.A_full[nu:, :nu] @ x[:nu]
+    assert np.abs(div).max() < 1e-12
+    # the essential normal values are those of g: 1 on x-faces at x = 0 and x = 1
+    assert np.abs(x[lev.sp.cons] - lev.essential_values(g)[lev.sp.cons]).max() == 0.0
+
+
+def test_patch_pseudo_inverse_invariants_3d():
+    lev = o3.Level(4, 1, 0.5, 6.0, _kappa(4, 2))
+    sm = o3.Smoother(lev)
+    rng = np.random.default_rng(0)
+    sizes = set()
+    for pi in rng.choice(len(sm.patches), 12, replace=False).tolist() + [0, len(sm.patches) // 2]:
+        (vx, vy, vz), dofs, rows, pinv, singular = sm.patches[pi]
+        sizes.add(len(dofs))
+        A_S = rows[:, dofs].toarray()
+        assert singular
+        c = lev.cvec[dofs] / np.linalg.norm(lev.cvec[dofs])
+        assert np.abs(A_S @ pinv @ A_S - A_S).max() < 1e-10 * np.abs(A_S).max()
+        assert np.abs(pinv @ c).max() < 1e-10 * np.abs(pinv).max()
+        assert np.abs(pinv - pinv.T).max() < 1e-10 * np.abs(pinv).max()
+        # after one patch correction the local residual lies in the kernel direction
+        x = rng.standard_normal(lev.sp.ndof)
+        x[lev.sp.cons] = 0.0
+        b = rng.standard_normal(lev.sp.ndof)
+        r = b[dofs] - rows @ x
+        x[dofs] += pinv @ r
+        r2 = b[dofs] - rows @ x
+        assert np.abs(r2 - c * (c @ r2)).max() < 1e-9 * np.abs(r).max()
+    # interior patch: 12 inner faces x 4 + 8 cells x (12 interior + 8 pressure) = 208
+    assert 208 in sizes
+
+
+def test_colour_classes_do_not_interact_3d():
+    lev = o3.Level(4, 1, 1.0, 6.0, _kappa(4, 3))
+    sm = o3.Smoother(lev)
+    A = lev.A.tocsr()
+    for col in range(27):
+        ps = sm.colours[col]
+        for i in range(len(ps)):
+            for j in range(i + 1, len(ps)):
+                d1, d2 = sm.patches[ps[i]][1], sm.patches[ps[j]][1]
+                assert not set(d1.tolist()) & set(d2.tolist())
+                assert A[d1][:, d2].nnz == 0
+
+
+def test_prolongation_is_the_embedding_3d():
+    Sc, Sf = o3.Space(2, 1), o3.Space(4, 1)
+    P = o3.prolongation(Sc, Sf)
+    kap = np.ones(8)
+    lc, lf = o3.Level(2, 1, 1.0, 6.0, kap), o3.Level(4, 1, 1.0, 6.0, np.ones(64))
+    rng = np.random.default_rng(11)
+    xc = rng.standard_normal(Sc.ndof)
+    xc[Sc.cons] = 0.0
+    xf = P @ xc
+    pts = rng.random((50, 3))
+    Uc, Pc = o3.evaluate(lc, xc, pts)
+    Uf, Pf = o3.evaluate(lf, xf, pts)
+    assert np.abs(Uc - Uf).max() < 1e-12
+    assert np.abs(Pc - Pf).max() < 1e-12
+    assert np.all(np.abs(P[np.flatnonzero(Sf.cons)]).sum(axis=1) == 0)
+
+
+def test_vcycle_is_symmetric_3d():
+    o = o3.Oracle3D(1, 3, 1, 1e-2, 6.0, _kappa(4, 6, -4.0, 0.0))
+    n = o.lev[-1].sp.ndof
+    free = ~o.lev[-1].sp.cons
+    rng = np.random.default_rng(2)
+    u, v = rng.standard_normal(n) * free, rng.standard_normal(n) * free
+    a, b = u @ o.vcycle(v), v @ o.vcycle(u)
+    assert abs(a - b) < 1e-10 * abs(a)
+
+
+def test_coarse_only_is_exact_3d():
+    o = o3.Oracle3D(2, 1, 1, 0.1, 6.0, _kappa(2, 8))
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    b = lev.rhs(lambda x, y, z: np.zeros((3,) + np.shape(x)), g)
+    _, its, tr = o.fgmres(b, rtol=1e-10, maxit=10)
+    assert its == 1 and tr < 1e-12
+
+
+def test_multigrid_matches_direct_solve_3d():
+    o = o3.Oracle3D(2, 3, 1, 1e-2, 6.0, 10.0 ** np.clip(np.random.default_rng(12).normal(-3, 1.5, 512), -6, 0))
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    b = lev.rhs(lambda x, y, z: np.zeros((3,) + np.shape(x)), g)
+    xm, its, tr = o.fgmres(b, rtol=1e-12, maxit=60)
+    xd = o.direct_solve(b)
+    d = xm - xd
+    d[lev.sp.n_u:] -= o.pressure_mean(xm) - o.pressure_mean(xd)
+    assert tr < 1e-11 and its <= 15
+    assert np.abs(d).max() < 1e-8 * np.abs(xd).max()
