@@ -162,6 +162,54 @@ def bench_c5(args, torch, bmg, inputs):
     print(json.dumps(out), flush=True)
 
 
+def bench_d3(args, torch, bmg, inputs):
+    """3-D Brinkman (Section 4, SPE10-like layered kappa stand-in): RT_1 x dQ_1 on an
+    n^3 hexahedral mesh, mu = 1e-2, g = (1, 0, 0) on all sides, f = 0, FP64 V-cycle in
+    FP64 FGMRES to --rtol."""
+    import numpy as np
+    n = args.n3
+    levels = int(round(math.log2(n))) + 1
+    kap = inputs.kappa_layered3(n, 6000)
+    p = bmg.make_params3(1, levels, 1e-2, restart=50)
+    t0 = time.perf_counter()
+    s = bmg.Solver3(p, kap)
+    setup = time.perf_counter() - t0
+    b = torch.as_tensor(bmg.assemble_rhs3(p, kap, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0)), device="cuda")
+    ndof = s.ndof()
+    log(f"bench: 3-D N={n} levels={levels} ndof {ndof}, setup {setup:.1f} s")
+    for _ in range(args.warmup):
+        x, info = s.solve(b, rtol=args.rtol, maxit=500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        x, info = s.solve(b, rtol=args.rtol, maxit=500)
+        its.append(info.iterations)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = torch.empty_like(b)
+    # one V-cycle timed alone (HIP events on the solver's stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    for _ in range(3):
+        r = s.vcycle(b)
+    ev1.record(s.stream)
+    ev1.synchronize()
+    vc_ms = ev0.elapsed_time(ev1) / 3
+    log(f"bench: 3-D {args.steps / dt:.3f} solves/s, iterations {its}, true residual "
+        f"{info.rel_residual_true:.2e}, V-cycle {vc_ms:.2f} ms")
+    out = {"metric": f"3-D Brinkman solves/s to {args.rtol:g} rel resid", "value": args.steps / dt,
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"3-D Brinkman {n}^3 hexahedra, RT_1 x dQ_1, mu=1e-2, g=(1,0,0) on all sides, "
+                                  "f=0, 85-layer log-normal kappa (SPE10 stand-in), variable V-cycle m=2, "
+                                  "FP64 FGMRES(50)", "N": n, "levels": levels, "k": 1, "rtol": args.rtol},
+           "ndof": ndof, "iterations": its[-1], "dof_iters_per_s": ndof * sum(its) / dt,
+           "true_rel_residual": info.rel_residual_true, "setup_s": setup, "vcycle_ms": vc_ms}
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,13 +219,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4", "C5"],
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3"],
                     help="C2 (default, the benchmark configuration), the 1024^2 precision study, or the "
                          "48-problem batch")
     ap.add_argument("--streams", type=int, default=4, help="C4: worker streams of the batch")
     ap.add_argument("--problems", type=int, default=48, help="C4: problems in the batch")
     ap.add_argument("--n", type=int, default=512, help="C5: cells per side (the 2048^2 generator at this size)")
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
+    ap.add_argument("--n3", type=int, default=32, help="D3: cells per side of the 3-D mesh (a power of two)")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     ap.add_argument("--colouring", default="auto", choices=["S9", "L8", "auto"],
@@ -215,6 +264,8 @@ def main():
         return bench_c4(args, torch, bmg, inputs)
     if args.workload == "C5":
         return bench_c5(args, torch, bmg, inputs)
+    if args.workload == "D3":
+        return bench_d3(args, torch, bmg, inputs)
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")

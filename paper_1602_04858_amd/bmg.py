@@ -422,3 +422,169 @@ def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=D
     p = make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, restart, dense_coarse_max,
                     n_rhs, colouring)
     return Solver(p, w.kappa, device=device, **kw)
+
+
+# ---------------------------------------------------------------------------------
+# 3-D (hexahedral) path: include/bmg3.h
+# ---------------------------------------------------------------------------------
+class Params3(C.Structure):
+    _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
+                ("sigma", C.c_double), ("cycle", C.c_int32), ("m_fine", C.c_int32), ("restart", C.c_int32)]
+
+
+_sig3 = {
+    "bmg3_setup": [_P(Params3), _dp, _VP, _P(_VP)],
+    "bmg3_destroy": [_VP],
+    "bmg3_sizes": [_VP, _I32, _P(_I32), _P(_I64), _P(_I64), _P(_I64)],
+    "bmg3_assemble_rhs": [_P(Params3), _dp, _dp, _dp, _dp],
+    "bmg3_apply": [_VP, _I32, _VP, _VP],
+    "bmg3_smooth": [_VP, _I32, _I32, _VP, _VP],
+    "bmg3_vcycle": [_VP, _VP, _VP],
+    "bmg3_solve": [_VP, _VP, _VP, _D, _I32, _P(SolveInfo)],
+    "bmg3_export_patch": [_VP, _I32, _I32, _I32, _I32, _P(_I32), _ip, _VP],
+    "bmg3_export_level_csr": [_P(Params3), _dp, _I32, _P(_I64), _VP, _VP, _VP],
+    "bmg3_export_patch_host": [_P(Params3), _dp, _I32, _I32, _I32, _I32, _P(_I32), _ip, _VP],
+}
+EXPORTS += list(_sig3) + ["bmg3_last_error"]
+for _name, _args in _sig3.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.bmg3_last_error.argtypes = [_VP]
+_lib.bmg3_last_error.restype = C.c_char_p
+
+
+def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, restart=50, k=1):
+    p = Params3()
+    p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
+    p.cycle, p.m_fine, p.restart = cycle, m_fine, restart
+    return p
+
+
+def assemble_rhs3(params: Params3, kappa, f=(0.0, 0.0, 0.0), g=(1.0, 0.0, 0.0)):
+    """Right-hand side for constant body force f and constant boundary data g (host)."""
+    N = params.n0 << (params.levels - 1)
+    nb = 2
+    NF = (N + 1) * N * N * nb * nb
+    n = 3 * NF + 3 * nb * nb * N ** 3 + nb ** 3 * N ** 3
+    out = np.zeros(n)
+    st = _lib.bmg3_assemble_rhs(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64),
+                                np.ascontiguousarray(f, dtype=np.float64), np.ascontiguousarray(g, dtype=np.float64),
+                                out)
+    if st:
+        raise BmgError(st, f"assemble_rhs3: {_lib.bmg3_last_error(None).decode()}")
+    return out
+
+
+class Solver3:
+    """One 3-D problem on the GPU (handle of the C library; it owns its device memory)."""
+
+    def __init__(self, params: Params3, kappa, device="cuda"):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = _lib.bmg3_setup(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st:
+            raise BmgError(st, f"setup3: {_lib.bmg3_last_error(None).decode()}")
+        self.h = h
+        self.levels = params.levels
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.bmg3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st:
+            raise BmgError(st, f"{what}: {_lib.bmg3_last_error(self.h).decode()}")
+
+    def sizes(self, level=None):
+        level = self.levels - 1 if level is None else level
+        N, nu, npr, npa = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(_lib.bmg3_sizes(self.h, level, C.byref(N), C.byref(nu), C.byref(npr), C.byref(npa)), "sizes")
+        return N.value, nu.value, npr.value, npa.value
+
+    def ndof(self, level=None):
+        _, a, b, _ = self.sizes(level)
+        return a + b
+
+    def _vec(self, t, level=None):
+        n = self.ndof(level)
+        if t.dtype != self.torch.float64 or t.device != self.device or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"expected a contiguous float64 tensor of {n} entries on {self.device}")
+        return _ptr(t)
+
+    def apply(self, x, level=None):
+        level = self.levels - 1 if level is None else level
+        y = self.torch.empty_like(x)
+        self._check(_lib.bmg3_apply(self.h, level, self._vec(x, level), self._vec(y, level)), "apply")
+        return y
+
+    def smooth(self, level, steps, x, b):
+        self._check(_lib.bmg3_smooth(self.h, level, steps, self._vec(x, level), self._vec(b, level)), "smooth")
+
+    def vcycle(self, r):
+        z = self.torch.empty_like(r)
+        self._check(_lib.bmg3_vcycle(self.h, self._vec(r), self._vec(z)), "vcycle")
+        return z
+
+    def solve(self, b, rtol=1e-10, maxit=200):
+        x = self.torch.empty_like(b)
+        info = SolveInfo()
+        st = _lib.bmg3_solve(self.h, self._vec(b), self._vec(x), float(rtol), int(maxit), C.byref(info))
+        if st and st != 6:
+            self._check(st, "solve")
+        return x, info
+
+    def export_patch(self, level, vx, vy, vz):
+        n = C.c_int32()
+        dofs = np.zeros(208, dtype=np.int32)
+        pinv = np.zeros(208 * 208)
+        self._check(_lib.bmg3_export_patch(self.h, level, vx, vy, vz, C.byref(n), dofs,
+                                           pinv.ctypes.data_as(C.c_void_p)), "export_patch")
+        m = n.value
+        return dofs[:m].copy(), pinv[:m * m].reshape(m, m).T.copy()
+
+
+def export_level_csr3(params: Params3, kappa, level):
+    """(rowptr, colidx, values) of the library's level operator (host assembly)."""
+    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    nnz = C.c_int64()
+    st = _lib.bmg3_export_level_csr(C.byref(params), kap, level, C.byref(nnz), None, None, None)
+    if st:
+        raise BmgError(st, f"export_level_csr3: {_lib.bmg3_last_error(None).decode()}")
+    N = params.n0 << level
+    n = 3 * (N + 1) * N * N * 4 + 12 * N ** 3 + 8 * N ** 3
+    rp = np.zeros(n + 1, dtype=np.int32)
+    ci = np.zeros(nnz.value, dtype=np.int32)
+    v = np.zeros(nnz.value)
+    st = _lib.bmg3_export_level_csr(C.byref(params), kap, level, C.byref(nnz), rp.ctypes.data_as(C.c_void_p),
+                                    ci.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p))
+    if st:
+        raise BmgError(st, "export_level_csr3")
+    return rp, ci, v
+
+
+def export_patch_host3(params: Params3, kappa, level, vx, vy, vz):
+    """(dofs, pseudo-inverse) of one vertex patch, assembled on the host by the library."""
+    n = C.c_int32()
+    dofs = np.zeros(208, dtype=np.int32)
+    pinv = np.zeros(208 * 208)
+    st = _lib.bmg3_export_patch_host(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64), level, vx, vy,
+                                     vz, C.byref(n), dofs, pinv.ctypes.data_as(C.c_void_p))
+    if st:
+        raise BmgError(st, f"export_patch_host3: {_lib.bmg3_last_error(None).decode()}")
+    m = n.value
+    return dofs[:m].copy(), pinv[:m * m].reshape(m, m).T.copy()

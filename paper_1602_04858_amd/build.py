@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbmg.so")
-SOURCES = ["kernels.hip", "host.cpp", "refelem.cpp"]
+SOURCES = ["kernels.hip", "host.cpp", "refelem.cpp", "kernels3d.hip", "host3d.cpp"]
 ARCH = os.environ.get("BMG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

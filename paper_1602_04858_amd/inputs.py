@@ -126,6 +126,21 @@ def kappa_layered(n: int, seed: int, layers: int = 85, channels: int = 20,
     return np.power(10.0, g).reshape(-1)
 
 
+def kappa_layered3(n: int, seed: int, layers: int = 85) -> np.ndarray:
+    """3-D stand-in for the layered SPE10 field (Section 4, 3-D Brinkman test): horizontal
+    layers along z, layer l covering z-rows floor(l*n/layers) .. floor((l+1)*n/layers)-1,
+    with log10 kappa of the layer ~ U[-5, 0] and cells N(mean, 1), clipped to [-6, 1].
+    Cells are ordered c = (cz*N + cy)*N + cx."""
+    st = _Stream(seed)
+    means = -5.0 + 5.0 * st.uniform(layers)
+    g = np.empty((n, n, n))
+    for l in range(layers):
+        z0, z1 = (l * n) // layers, ((l + 1) * n) // layers
+        if z1 > z0:
+            g[z0:z1] = means[l] + st.normal((z1 - z0) * n * n).reshape(z1 - z0, n, n)
+    return np.power(10.0, np.clip(g, -6.0, 1.0)).reshape(-1)
+
+
 def kappa_constant(n: int, value: float = 1.0) -> np.ndarray:
     return np.full(n * n, float(value))
 

@@ -1,0 +1,77 @@
+"""Host side of the library's 3-D path against the 3-D oracle (CPU only).
+
+The library assembles its level operators, right-hand sides and patch pseudo-inverses
+on the host (code of its own, by reference integrals scaled per level); these tests
+compare those host products with the oracle's quadrature of the definitions.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import oracle3d as o3
+
+bmg = pytest.importorskip("paper_1602_04858_amd.bmg")
+
+
+def _kappa(n, seed):
+    return 10.0 ** np.clip(np.random.default_rng(seed).normal(-3, 1.5, n ** 3), -6, 0)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_level_operator_matches_oracle(level):
+    p = bmg.make_params3(1, 3, 1e-2)
+    kap = _kappa(4, 1)
+    o = o3.Oracle3D(1, 3, 1, 1e-2, 6.0, kap)
+    rp, ci, v = bmg.export_level_csr3(p, kap, level)
+    n = len(rp) - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    Ao = o.lev[level].A
+    assert A.shape == Ao.shape
+    assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
+
+
+def test_rhs_matches_oracle():
+    p = bmg.make_params3(2, 2, 0.3)
+    kap = _kappa(4, 2)
+    f, g = (0.5, -1.0, 0.25), (1.0, 0.3, -0.2)
+    b = bmg.assemble_rhs3(p, kap, f, g)
+    lev = o3.Level(4, 1, 0.3, 6.0, kap)
+    bo = lev.rhs(lambda x, y, z: np.array([c + 0 * x for c in f]), lambda x, y, z: np.array([c + 0 * x for c in g]))
+    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+
+
+@pytest.mark.parametrize("vertex", [(2, 2, 2), (0, 0, 0), (4, 1, 2), (1, 4, 4), (3, 0, 1)])
+def test_patch_pseudo_inverse_matches_oracle(vertex):
+    p = bmg.make_params3(1, 3, 1e-2)
+    kap = _kappa(4, 3)
+    dofs, pinv = bmg.export_patch_host3(p, kap, 2, *vertex)
+    lev = o3.Level(4, 1, 1e-2, 6.0, kap)
+    d_o, cells = o3.patch_dofs(lev.sp, *vertex)
+    A_S = lev.A[d_o][:, d_o].toarray()
+    po = o3.patch_pinv(A_S, lev.sp, d_o, cells, True)
+    assert np.array_equal(dofs, d_o)
+    assert np.abs(pinv - po).max() <= 1e-9 * np.abs(po).max()
+
+
+@pytest.mark.parametrize("change,expect", [(dict(k=2), 2), (dict(k=0), 2), (dict(n0=0), 1), (dict(levels=0), 1),
+                                           (dict(mu=0.0), 1), (dict(sigma=-1.0), 1), (dict(m_fine=0), 1),
+                                           (dict(restart=0), 1), (dict(cycle=3), 1), (dict(n0=8, levels=5), 1)])
+def test_setup3_rejects_bad_parameters(change, expect):
+    import ctypes as C
+    kw = dict(n0=1, levels=2, mu=1e-2)
+    p = bmg.make_params3(kw["n0"], kw["levels"], kw["mu"])
+    for key, val in change.items():
+        setattr(p, key, val)
+    N = max(p.n0, 1) << max(p.levels - 1, 0)
+    h = C.c_void_p()
+    st = bmg.lib().bmg3_setup(C.byref(p), np.ones(min(N, 64) ** 3), None, C.byref(h))
+    assert st == expect and not h.value
+
+
+def test_setup3_rejects_negative_kappa():
+    import ctypes as C
+    p = bmg.make_params3(1, 2, 1e-2)
+    kap = np.ones(8)
+    kap[3] = -1.0
+    h = C.c_void_p()
+    assert bmg.lib().bmg3_setup(C.byref(p), kap, None, C.byref(h)) == 1
