@@ -235,15 +235,18 @@ bool gj_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
       a[(size_t)c * n + j] *= d;
       inv[(size_t)c * n + j] *= d;
     }
-    for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
+    auto eliminate = [&](int64_t r) {
+      if (r == c) return;
       const double f = a[(size_t)r * n + c];
-      if (f == 0.0) continue;
+      if (f == 0.0) return;
       for (int j = 0; j < n; ++j) {
         a[(size_t)r * n + j] -= f * a[(size_t)c * n + j];
         inv[(size_t)r * n + j] -= f * inv[(size_t)c * n + j];
       }
-    }
+    };
+    if (n > 1024) par_for(n, eliminate);  // the coarsest-level matrix
+    else
+      for (int r = 0; r < n; ++r) eliminate(r);
   }
   return true;
 }
@@ -790,7 +793,7 @@ int msteps(const bmg3_ctx* c, int j) {
 void vcycle3(bmg3_ctx* c, int j, const double* b, double* x) {
   Level3& L = c->lev[j];
   if (j == 0) {
-    launch_coarse(0, (int)c->n0dof, c->coarse_inv, b, x, 1, c->s);
+    launch_dense_gemv(0, c->coarse_inv, c->n0dof, b, x, 1, c->s);
     return;
   }
   Level3& Lc = c->lev[j - 1];
@@ -858,9 +861,9 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
         a[(size_t)n * m + L.S.n_u + cl * NP3] = cv;
       }
       if (!gj_inverse((int)m, a, inv)) return bail(BMG_E_SINGULAR, "coarse matrix is singular");
-      std::vector<double> ci((size_t)n * n);
+      std::vector<double> ci((size_t)n * n);  // row-major (applied row by row)
       for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = 0; k < n; ++k) ci[(size_t)k * n + i] = inv[(size_t)i * m + k];
+        for (int64_t k = 0; k < n; ++k) ci[(size_t)i * n + k] = inv[(size_t)i * m + k];
       c->n0dof = n;
       if (upload(c, &c->coarse_inv, ci.data(), ci.size())) return bail(BMG_E_NOMEM, "device allocation failed");
     } else {

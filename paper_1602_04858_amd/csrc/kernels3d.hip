@@ -48,39 +48,79 @@ __global__ __launch_bounds__(256) void k3_csr(int64_t nrows, const int32_t* __re
 // Patches of one colour are the contiguous range [p0, p0 + gridDim.x) of the level's
 // patch list; patch p has the dofs pdofs[poff[p] .. poff[p+1]) (ascending) and its
 // pseudo-inverse at pinv + ioff[p], column-major (entry (t, u) at u n + t).
-__global__ __launch_bounds__(256) void k3_colour(int p0, const int64_t* __restrict__ poff,
+//
+// A patch's work is two dependent streams (the CSR rows of its dofs, then its n x n
+// pseudo-inverse, 346 KB for n = 208), so the kernel is built for loads in flight:
+// the residual rows take eight lanes each with the row loop unrolled, and in the
+// product each of the BS/64 waves takes its share of the columns for all rows, issuing
+// 4 rows x 8 columns of loads before their FMAs; the partial sums meet in LDS.  BS =
+// 1024 serves levels with fewer patches in a colour than CUs (the chains get 4x
+// shorter; the CUs would idle anyway), BS = 256 the fine levels.
+template <int BS>
+__global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restrict__ poff,
                                                  const int32_t* __restrict__ pdofs, const int64_t* __restrict__ ioff,
                                                  const double* __restrict__ pinv, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
                                                  double* __restrict__ x, const double* __restrict__ b) {
   __shared__ double rs[kMaxPatch3];
+  constexpr int NW = BS / 64;
+  __shared__ double part[NW][kMaxPatch3];
   __shared__ int32_t gs[kMaxPatch3];
   const int p = p0 + (int)blockIdx.x;
   const int64_t o = poff[p];
   const int n = (int)(poff[p + 1] - o);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) gs[t] = pdofs[o + t];
+  for (int t = threadIdx.x; t < n; t += BS) gs[t] = pdofs[o + t];
   __syncthreads();
-  // local residual: 32 rows at a time, eight lanes per row
+  // local residual: BS/8 rows at a time, eight lanes per row
   const int sub = threadIdx.x % kRowLanes, rl = threadIdx.x / kRowLanes;
-  for (int t0 = 0; t0 < n; t0 += 256 / kRowLanes) {
+  for (int t0 = 0; t0 < n; t0 += BS / kRowLanes) {
     const int t = t0 + rl;
     double s = 0.0;
     int gi = 0;
     if (t < n) {
       gi = gs[t];
-      for (int e = rp[gi] + sub; e < rp[gi + 1]; e += kRowLanes) s += v[e] * x[ci[e]];
+      const int e1 = rp[gi + 1];
+#pragma unroll 4
+      for (int e = rp[gi] + sub; e < e1; e += kRowLanes) s += v[e] * x[ci[e]];
     }
     s = lane_group_sum(s);
     if (t < n && sub == 0) rs[t] = b[gi] - s;
   }
   __syncthreads();
-  // correction y = A+ r; every x read of this block is done, and same-colour patches
-  // neither share dofs nor couple through A, so the writes race with nothing
+  // correction y = A+ r: wave w sums the columns u in [u0, u1) for rows lane + 64 i
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = (n + NW - 1) / NW, u0 = w * q, u1 = min(n, u0 + q);
   const double* A = pinv + ioff[p];
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double acc = 0.0;
-    for (int u = 0; u < n; ++u) acc += A[(int64_t)u * n + t] * rs[u];
-    x[gs[t]] += acc;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ub = u0; ub < u1; ub += 8) {
+    double a[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int t = lane + 64 * i;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int u = ub + k;
+        a[i][k] = (t < n && u < u1) ? A[(int64_t)u * n + t] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double r = ub + k < u1 ? rs[ub + k] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] += a[i][k] * r;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (lane + 64 * i < n) part[w][lane + 64 * i] = acc[i];
+  __syncthreads();
+  // every x read of this block is done, and same-colour patches neither share dofs nor
+  // couple through A, so the writes race with nothing
+  for (int t = threadIdx.x; t < n; t += BS) {
+    double y = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) y += part[k][t];
+    x[gs[t]] += y;
   }
 }
 
@@ -107,7 +147,10 @@ void launch3_colour(int p0, int npatch, const int64_t* poff, const int32_t* pdof
                     const double* pinv, const int32_t* rp, const int32_t* ci, const double* v, double* x,
                     const double* b, hipStream_t s) {
   if (npatch <= 0) return;
-  hipLaunchKernelGGL(k3_colour, dim3(npatch), dim3(256), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x, b);
+  if (npatch < 256)
+    hipLaunchKernelGGL(k3_colour<1024>, dim3(npatch), dim3(1024), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x, b);
+  else
+    hipLaunchKernelGGL(k3_colour<256>, dim3(npatch), dim3(256), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x, b);
 }
 
 void launch3_copy_idx(const int32_t* idx, int64_t n, const double* src, double* dst, hipStream_t s) {

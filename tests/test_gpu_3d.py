@@ -60,7 +60,7 @@ def test_smoothing_step_3d(level):
     assert np.abs(xg.cpu().numpy() - xo).max() <= 1e-11 * np.abs(xo).max()
 
 
-@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4)])
+@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4), (2, 2), (4, 2)])
 def test_vcycle_3d(n0, levels):
     s, o, _ = _pair(n0, levels)
     n = o.lev[-1].sp.ndof
@@ -70,7 +70,7 @@ def test_vcycle_3d(n0, levels):
     assert np.abs(z - zo).max() <= 1e-10 * np.abs(zo).max()
 
 
-@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4)])
+@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4), (2, 2), (4, 2)])
 def test_solve_3d_matches_oracle(n0, levels):
     s, o, kap = _pair(n0, levels)
     lev = o.lev[-1]
