@@ -345,9 +345,10 @@ def main():
             s32.close()
             del s32
 
-    if not args.no_mixed:
+    if not args.no_mixed and args.workload == "C2":
         # batched: 16 right-hand sides of the same problem solved together with the FP32
-        # V-cycle (each column its own FGMRES; one V-cycle launch serves all columns)
+        # V-cycle (each column its own FGMRES; one V-cycle launch serves all columns).
+        # C2 only: at 1024^2 sixteen FGMRES(100) bases would not fit in HBM
         R = 16
         pb = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP32, 100,
                              args.dense_coarse_max, R, p64.colouring, smoother, args.omega)

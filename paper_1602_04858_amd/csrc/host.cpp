@@ -1127,12 +1127,14 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   if (workspace) {
     if (bytes < need || ((uintptr_t)workspace % kAlign) != 0) {
       delete c;
+      g_setup_err = "workspace smaller than bmg_plan's size or not 256-byte aligned";
       return BMG_E_NOMEM;
     }
     c->ws = (char*)workspace;
   } else {
     if (hipMalloc((void**)&c->ws, need) != hipSuccess) {
       delete c;
+      g_setup_err = "hipMalloc of the " + std::to_string(need >> 20) + " MiB workspace failed";
       return BMG_E_NOMEM;
     }
     c->own_ws = true;
