@@ -56,6 +56,9 @@ typedef struct {
   int32_t cycle;   /* 0: m_fine smoothing steps on every level; 1: variable, m_fine 2^(J-j) */
   int32_t m_fine;  /* >= 1 */
   int32_t restart; /* FGMRES restart length, 1 .. 200 */
+  int32_t precond_prec; /* storage of the patch pseudo-inverses: 0 FP64, 1 FP32 (rounded to nearest;
+                           vectors, residuals and arithmetic stay FP64; FGMRES absorbs the
+                           perturbed V-cycle, as with the reduced-precision V-cycles of bmg.h) */
 } bmg3_params;
 
 /* Assemble levels, transfers and patch pseudo-inverses for the fine-level kappa

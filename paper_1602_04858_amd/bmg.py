@@ -429,7 +429,8 @@ def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=D
 # ---------------------------------------------------------------------------------
 class Params3(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
-                ("sigma", C.c_double), ("cycle", C.c_int32), ("m_fine", C.c_int32), ("restart", C.c_int32)]
+                ("sigma", C.c_double), ("cycle", C.c_int32), ("m_fine", C.c_int32), ("restart", C.c_int32),
+                ("precond_prec", C.c_int32)]
 
 
 _sig3 = {
@@ -454,10 +455,11 @@ _lib.bmg3_last_error.argtypes = [_VP]
 _lib.bmg3_last_error.restype = C.c_char_p
 
 
-def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, restart=50, k=1):
+def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, restart=50, k=1, prec=P_FP64):
+    """prec: P_FP64, or P_FP32 for FP32-stored patch pseudo-inverses (FP64 arithmetic)."""
     p = Params3()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
-    p.cycle, p.m_fine, p.restart = cycle, m_fine, restart
+    p.cycle, p.m_fine, p.restart, p.precond_prec = cycle, m_fine, restart, prec
     return p
 
 

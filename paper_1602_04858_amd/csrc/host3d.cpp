@@ -582,7 +582,7 @@ struct Level3 {
   int64_t npatch = 0;
   int64_t *poff = nullptr, *ioff = nullptr;
   int32_t* pdofs = nullptr;
-  double* pinv = nullptr;
+  void* pinv = nullptr;  // doubles or floats (bmg3_params.precond_prec)
   int cstart[28] = {0};
   std::vector<int64_t> patch_of_vertex;  // vertex -> patch index
   std::vector<int64_t> hpoff, hioff;
@@ -644,6 +644,7 @@ bmg_status check3(const bmg3_params* p) {
   if ((int64_t)p->n0 << (p->levels - 1) > 64) return BMG_E_ARG;
   if (!(p->mu > 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
   if ((p->cycle != 0 && p->cycle != 1) || p->m_fine < 1 || p->restart < 1 || p->restart > 200) return BMG_E_ARG;
+  if (p->precond_prec != 0 && p->precond_prec != 1) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -759,7 +760,16 @@ bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
   if ((s = upload(c, &L.poff, L.hpoff.data(), L.hpoff.size()))) return fail3(c, s, "device allocation failed");
   if ((s = upload(c, &L.ioff, L.hioff.data(), L.hioff.size()))) return fail3(c, s, "device allocation failed");
   if ((s = upload(c, &L.pdofs, L.hpdofs.data(), L.hpdofs.size()))) return fail3(c, s, "device allocation failed");
-  if ((s = upload(c, &L.pinv, pinv.data(), pinv.size()))) return fail3(c, s, "device allocation failed");
+  if (c->p.precond_prec == 1) {
+    std::vector<float> pf(pinv.begin(), pinv.end());
+    float* d = nullptr;
+    if ((s = upload(c, &d, pf.data(), pf.size()))) return fail3(c, s, "device allocation failed");
+    L.pinv = d;
+  } else {
+    double* d = nullptr;
+    if ((s = upload(c, &d, pinv.data(), pinv.size()))) return fail3(c, s, "device allocation failed");
+    L.pinv = d;
+  }
   return BMG_OK;
 }
 
@@ -780,8 +790,8 @@ std::vector<double> coarsen(const std::vector<double>& kf, int Nc) {
 void smooth_step3(bmg3_ctx* c, Level3& L, double* x, const double* b) {
   for (int k = 0; k < 53; ++k) {
     const int col = k < 27 ? k : 52 - k;
-    launch3_colour(L.cstart[col], L.cstart[col + 1] - L.cstart[col], L.poff, L.pdofs, L.ioff, L.pinv, L.A.rp,
-                   L.A.ci, L.A.v, x, b, c->s);
+    launch3_colour(L.cstart[col], L.cstart[col + 1] - L.cstart[col], L.poff, L.pdofs, L.ioff, L.pinv,
+                   c->p.precond_prec, L.A.rp, L.A.ci, L.A.v, x, b, c->s);
   }
 }
 
@@ -1038,9 +1048,17 @@ bmg_status bmg3_export_patch(bmg3_handle h, int32_t level, int32_t vx, int32_t v
   const int64_t o = L.hpoff[p], cnt = L.hpoff[p + 1] - o;
   *n = (int32_t)cnt;
   std::memcpy(dofs_host, L.hpdofs.data() + o, cnt * sizeof(int32_t));
-  if (pinv_host && hipMemcpy(pinv_host, L.pinv + L.hioff[p], cnt * cnt * sizeof(double), hipMemcpyDeviceToHost) !=
-                       hipSuccess)
+  if (!pinv_host) return BMG_OK;
+  if (h->p.precond_prec == 1) {
+    std::vector<float> tmp(cnt * cnt);
+    if (hipMemcpy(tmp.data(), (const float*)L.pinv + L.hioff[p], tmp.size() * sizeof(float), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return fail3(h, BMG_E_HIP, "hipMemcpy failed");
+    for (size_t i = 0; i < tmp.size(); ++i) pinv_host[i] = tmp[i];
+  } else if (hipMemcpy(pinv_host, (const double*)L.pinv + L.hioff[p], cnt * cnt * sizeof(double),
+                       hipMemcpyDeviceToHost) != hipSuccess) {
     return fail3(h, BMG_E_HIP, "hipMemcpy failed");
+  }
   return BMG_OK;
 }
 

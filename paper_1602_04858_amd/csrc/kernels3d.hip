@@ -6,7 +6,8 @@
 //   k3_colour  one colour step of the symmetric multiplicative vertex-patch smoother
 //              (Section 3, eq. smoother-Multiplicative): a block per patch forms the
 //              local residual (b - A x) on the patch rows, applies the patch
-//              pseudo-inverse (dense, column-major) and adds the correction into x
+//              pseudo-inverse (dense, column-major, FP64 or FP32 storage, FP64
+//              arithmetic) and adds the correction into x
 //   k3_copy_idx  x[i] = b[i] on the essential rows (identity rows of the operator)
 #include <hip/hip_runtime.h>
 
@@ -56,10 +57,10 @@ __global__ __launch_bounds__(256) void k3_csr(int64_t nrows, const int32_t* __re
 // 4 rows x 8 columns of loads before their FMAs; the partial sums meet in LDS.  BS =
 // 1024 serves levels with fewer patches in a colour than CUs (the chains get 4x
 // shorter; the CUs would idle anyway), BS = 256 the fine levels.
-template <int BS>
+template <int BS, typename S>
 __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restrict__ poff,
                                                  const int32_t* __restrict__ pdofs, const int64_t* __restrict__ ioff,
-                                                 const double* __restrict__ pinv, const int32_t* __restrict__ rp,
+                                                 const S* __restrict__ pinv, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
                                                  double* __restrict__ x, const double* __restrict__ b) {
   __shared__ double rs[kMaxPatch3];
@@ -90,24 +91,30 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
   // correction y = A+ r: wave w sums the columns u in [u0, u1) for rows lane + 64 i
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = (n + NW - 1) / NW, u0 = w * q, u1 = min(n, u0 + q);
-  const double* A = pinv + ioff[p];
+  const S* A = pinv + ioff[p];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int ub = u0; ub < u1; ub += 8) {
-    double a[4][8];
+    // all 32 loads are issued before the first wait.  FP64: masked loads.  FP32:
+    // unconditional loads at clamped (in-bounds) indices, widened only in the FMAs
+    // (masked FP32 loads were each compiled into a branch with its own wait and
+    // conversion); rows t >= n are never stored and columns u >= u1 meet r = 0 below.
+    S a[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int t = lane + 64 * i;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int u = ub + k;
-        a[i][k] = (t < n && u < u1) ? A[(int64_t)u * n + t] : 0.0;
+        if constexpr (sizeof(S) == 8)
+          a[i][k] = (t < n && ub + k < u1) ? A[(int64_t)(ub + k) * n + t] : S(0);
+        else
+          a[i][k] = A[(int64_t)min(ub + k, u1 - 1) * n + min(t, n - 1)];
       }
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const double r = ub + k < u1 ? rs[ub + k] : 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] += a[i][k] * r;
+      for (int i = 0; i < 4; ++i) acc[i] += (double)a[i][k] * r;
     }
   }
 #pragma unroll
@@ -143,14 +150,24 @@ void launch3_csr(int mode, int64_t nrows, const int32_t* rp, const int32_t* ci, 
   else hipLaunchKernelGGL(k3_csr<2>, g, bl, 0, s, nrows, rp, ci, v, x, b, y);
 }
 
+template <typename S>
+static void colour_t(int p0, int npatch, const int64_t* poff, const int32_t* pdofs, const int64_t* ioff,
+                     const S* pinv, const int32_t* rp, const int32_t* ci, const double* v, double* x,
+                     const double* b, hipStream_t s) {
+  if (npatch < 256)
+    hipLaunchKernelGGL((k3_colour<1024, S>), dim3(npatch), dim3(1024), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v,
+                       x, b);
+  else
+    hipLaunchKernelGGL((k3_colour<256, S>), dim3(npatch), dim3(256), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x,
+                       b);
+}
+
 void launch3_colour(int p0, int npatch, const int64_t* poff, const int32_t* pdofs, const int64_t* ioff,
-                    const double* pinv, const int32_t* rp, const int32_t* ci, const double* v, double* x,
+                    const void* pinv, int sprec, const int32_t* rp, const int32_t* ci, const double* v, double* x,
                     const double* b, hipStream_t s) {
   if (npatch <= 0) return;
-  if (npatch < 256)
-    hipLaunchKernelGGL(k3_colour<1024>, dim3(npatch), dim3(1024), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x, b);
-  else
-    hipLaunchKernelGGL(k3_colour<256>, dim3(npatch), dim3(256), 0, s, p0, poff, pdofs, ioff, pinv, rp, ci, v, x, b);
+  if (sprec == 1) colour_t(p0, npatch, poff, pdofs, ioff, (const float*)pinv, rp, ci, v, x, b, s);
+  else colour_t(p0, npatch, poff, pdofs, ioff, (const double*)pinv, rp, ci, v, x, b, s);
 }
 
 void launch3_copy_idx(const int32_t* idx, int64_t n, const double* src, double* dst, hipStream_t s) {

@@ -130,3 +130,29 @@ def test_solve_3d_at_n16_sampled():
     y = s.apply(_dev(xr)).cpu().numpy()
     assert np.abs(y - lev.A @ xr).max() <= 1e-13 * np.abs(y).max()
     s.close()
+
+
+def test_fp32_stored_inverses_3d():
+    """FP32 storage of the patch pseudo-inverses (FP64 arithmetic and vectors): the
+    stored entries are the FP64 host ones rounded to nearest, the V-cycle moves by about
+    the FP32 rounding of the inverses (each entry relative 2^-24; tolerance 2e-5 allows
+    for the sums over the smoothing steps of all levels), and FGMRES still reaches 1e-10
+    with at most one more iteration."""
+    s, o, kap = _pair(1, 4)
+    s32 = bmg.Solver3(bmg.make_params3(1, 4, MU, prec=bmg.P_FP32), kap)
+    for v in [(3, 3, 3), (0, 8, 2)]:
+        _, p32 = s32.export_patch(3, *v)
+        _, p64 = bmg.export_patch_host3(s.params, kap, 3, *v)
+        assert np.array_equal(p32, p64.astype(np.float32).astype(np.float64))
+    n = o.lev[-1].sp.ndof
+    r = np.random.default_rng(21).standard_normal(n)
+    z32 = s32.vcycle(_dev(r)).cpu().numpy()
+    zo = o.vcycle(r)
+    assert np.abs(z32 - zo).max() <= 2e-5 * np.abs(zo).max()
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    b = _dev(lev.rhs(lambda x, y, z: np.zeros((3,) + np.shape(x)), g))
+    _, i64 = s.solve(b, rtol=1e-10)
+    _, i32 = s32.solve(b, rtol=1e-10)
+    assert i32.converged and i32.rel_residual_true <= 1e-10 and i32.iterations <= i64.iterations + 1
+    s32.close()

@@ -55,7 +55,8 @@ def test_patch_pseudo_inverse_matches_oracle(vertex):
 
 @pytest.mark.parametrize("change,expect", [(dict(k=2), 2), (dict(k=0), 2), (dict(n0=0), 1), (dict(levels=0), 1),
                                            (dict(mu=0.0), 1), (dict(sigma=-1.0), 1), (dict(m_fine=0), 1),
-                                           (dict(restart=0), 1), (dict(cycle=3), 1), (dict(n0=8, levels=5), 1)])
+                                           (dict(restart=0), 1), (dict(cycle=3), 1), (dict(n0=8, levels=5), 1),
+                                           (dict(precond_prec=2), 1), (dict(precond_prec=-1), 1)])
 def test_setup3_rejects_bad_parameters(change, expect):
     import ctypes as C
     kw = dict(n0=1, levels=2, mu=1e-2)
