@@ -337,6 +337,21 @@ def main():
             "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
     log(f"bench: finest smoother {achieved:.0f} GB/s over {nl} launches, avg {avg_s * 1e6:.1f} us")
 
+    std_cycle = None
+    if args.workload == "C2" and not args.no_mixed:
+        # the standard V-cycle (m_J = 2 smoothing steps on every level) beside the paper's
+        # variable one (m_j = m_J 2^(J-j)): far fewer coarse-level launches, more iterations
+        ps = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, bmg.CYCLE_STANDARD, w.m_fine, bmg.P_FP64, 100,
+                             args.dense_coarse_max, 1, p64.colouring, smoother, args.omega)
+        ss = bmg.Solver(ps, w.kappa)
+        xs, infs, dts, itss = timed_solves(torch, ss, b, args.steps, args.warmup, args.rtol)
+        std_cycle = {"value": args.steps / dts, "unit": "solves/s", "precond": "fp64, standard V-cycle m=2",
+                     "iterations": itss[-1], "true_rel_residual": infs.rel_residual_true,
+                     "rel_diff_vs_variable": (torch.linalg.norm(xs - x64) / torch.linalg.norm(x64)).item()}
+        log(f"bench: FP64 standard V-cycle {args.steps / dts:.3f} solves/s, iterations {itss}")
+        ss.close()
+        del ss
+
     col64 = "L8" if p64.colouring == bmg.COLOURING_L8 else "S9"
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt64 / args.steps * 1e3, "higher_is_better": True,
@@ -394,6 +409,8 @@ def main():
             f"{min(itsb)}..{max(itsb)}")
         sb.close()
         del sb
+    if std_cycle:
+        out["standard_vcycle"] = std_cycle
     if tuned:
         out["autotune"] = tuned
     out["roofline"] = roof
