@@ -7,6 +7,7 @@ wrong child offset, a missing Nitsche term) fails at least one of them.
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from oracle import oracle3d as o3
 
@@ -179,3 +180,48 @@ def test_multigrid_matches_direct_solve_3d():
     d[lev.sp.n_u:] -= o.pressure_mean(xm) - o.pressure_mean(xd)
     assert tr < 1e-11 and its <= 15
     assert np.abs(d).max() < 1e-8 * np.abs(xd).max()
+
+
+# P3 (3-D): smooth solution u = (sin pi y, sin pi z, sin pi x) (divergence free), p =
+# cos pi x cos pi y cos pi z (mean 0), kappa = 1: the L2 velocity error falls as h^2
+# and the pressure error at least as h (RT_1 x dQ_1 theory), measured by Gauss
+# quadrature over every cell.
+def _l2_errors(lev, x, u, p):
+    S, rb, N, h = lev.sp, lev.rb, lev.N, lev.h
+    X, W = o3.cube_rule(4)
+    v, _ = rb.vel(X)
+    pv = rb.pres(X)
+    nu = len(rb.lu)
+    eu = ep = 0.0
+    pm = x[S.n_u::S.NB ** 3].mean()
+    for t, cc in enumerate(lev.cells):
+        d = lev.cell_dof_table[t]
+        P = (np.array(cc)[None, :] + X) * h
+        uh = np.einsum("i,iqa->qa", x[d[:nu]], v)
+        ph = x[d[nu:]] @ pv - pm
+        ue = np.stack(u(P[:, 0], P[:, 1], P[:, 2]), -1)
+        eu += h ** 3 * np.sum(W[:, None] * (uh - ue) ** 2)
+        ep += h ** 3 * np.sum(W * (ph - p(P[:, 0], P[:, 1], P[:, 2])) ** 2)
+    return np.sqrt(eu), np.sqrt(ep)
+
+
+def test_brinkman_convergence_rates_3d():
+    mu, pi = 1.0, np.pi
+    u = lambda x, y, z: (np.sin(pi * y), np.sin(pi * z), np.sin(pi * x))
+    p = lambda x, y, z: np.cos(pi * x) * np.cos(pi * y) * np.cos(pi * z)
+    f = lambda x, y, z: np.array([(mu * pi ** 2 + 1.0) * np.sin(pi * y) - pi * np.sin(pi * x) * np.cos(pi * y) * np.cos(pi * z),
+                                  (mu * pi ** 2 + 1.0) * np.sin(pi * z) - pi * np.cos(pi * x) * np.sin(pi * y) * np.cos(pi * z),
+                                  (mu * pi ** 2 + 1.0) * np.sin(pi * x) - pi * np.cos(pi * x) * np.cos(pi * y) * np.sin(pi * z)])
+    g = lambda x, y, z: np.array(u(x, y, z))
+    errs = []
+    for n in (2, 4, 8):
+        lev = o3.Level(n, 1, mu, 6.0, np.ones(n ** 3))
+        # sparse direct solve, bordered with the constant pressure (mean zero)
+        c = lev.cvec / np.linalg.norm(lev.cvec)
+        Bd = sp.bmat([[lev.A, sp.csr_matrix(c[:, None])], [sp.csr_matrix(c[None, :]), None]]).tocsc()
+        x = spla.spsolve(Bd, np.concatenate([lev.rhs(f, g), [0.0]]))[:-1]
+        errs.append(_l2_errors(lev, x, u, p))
+    ru = np.log2(errs[1][0] / errs[2][0])
+    rp = np.log2(errs[1][1] / errs[2][1])
+    assert ru > 1.8, errs
+    assert rp > 0.9, errs
