@@ -522,16 +522,19 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
     kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
   }
-  // PF: column `lane` of the full inverse of this patch (n = NSR, or NSE for an
-  // extended patch; column-major), every entry prefetched into registers so that no
-  // patch streams its inverse in the product; PK: rotated entry i in lane i mod 64
-  S areg[PF ? NSE : 1];
+  // PF: the first NSR entries of column `lane` of the full inverse of this patch (n =
+  // NSR, or NSE for an extended patch; column-major) prefetched into registers, so that
+  // a regular patch streams nothing in the product; an extended (boundary) patch reads
+  // its remaining NSE - NSR entries there.  (Prefetching all NSE entries cost 32 more
+  // VGPRs in FP64: two waves per SIMD instead of three, and grids of more than 512
+  // blocks ran in two rounds.)  PK: rotated entry i in lane i mod 64
+  S areg[PF ? NSR : 1];
   if (PF) {
     const int n0 = ext_guess ? NSE : NSR;
     const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NSE * NSE : inv + (size_t)pc * NSR * NSR;
     const int lc = lane < n0 ? lane : n0 - 1;
 #pragma unroll
-    for (int u = 0; u < (PF ? NSE : 1); ++u) areg[u] = A[min(u, n0 - 1) * n0 + lc];
+    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * n0 + lc];
   }
   S apk[NQ];
   if (PK && K <= 1) {
@@ -768,11 +771,16 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
           }
         }
       } else if (PF) {
-        // one product length for both layouts: r is zero beyond the patch size
+        // the first NSR terms from registers, the rest (extended patches) from memory
         if (lane < ns) {
           T acc = T(0);
 #pragma unroll
-          for (int u = 0; u < (PF ? NSE : 1); ++u) acc += T(areg[u]) * rs[w][u];
+          for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
+          if (is_ext) {
+            const S* Ax = invx + (size_t)ext * NSE * NSE;
+#pragma unroll
+            for (int u = NSR; u < (PF ? NSE : NSR); ++u) acc += T(Ax[u * NSE + lane]) * rs[w][u];
+          }
           if (gi[0] >= 0) xc[gi[0]] = xold[0] + (ADD ? omega * acc : acc);
         }
       } else {
