@@ -336,6 +336,22 @@ def main():
             "kernel": "k_colour<double,double,1,1> (finest-level colour step)",
             "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
     log(f"bench: finest smoother {achieved:.0f} GB/s over {nl} launches, avg {avg_s * 1e6:.1f} us")
+    # a STREAM-style copy on this GPU (2 GiB read + 2 GiB written per copy, HIP events)
+    # as the attainable HBM rate beside the published peak
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roof["measured_copy_gbs"] = copy_gbs
+    roof["frac_of_measured_copy"] = achieved / copy_gbs
+    log(f"bench: device copy {copy_gbs:.0f} GB/s; finest smoother at {achieved / copy_gbs:.2f} of it")
 
     std_cycle = None
     if args.workload == "C2" and not args.no_mixed:
