@@ -156,3 +156,24 @@ def test_fp32_stored_inverses_3d():
     _, i32 = s32.solve(b, rtol=1e-10)
     assert i32.converged and i32.rel_residual_true <= 1e-10 and i32.iterations <= i64.iterations + 1
     s32.close()
+
+
+def test_not_converged_and_argument_errors_3d():
+    import ctypes as C
+    s, o, _ = _pair(1, 3)
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    b = _dev(lev.rhs(lambda x, y, z: np.zeros((3,) + np.shape(x)), g))
+    x, info = s.solve(b, rtol=1e-14, maxit=2)
+    assert info.converged == 0 and info.iterations == 2 and info.rel_residual_true > 1e-14
+    lib = bmg.lib()
+    y = torch.empty_like(b)
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    assert lib.bmg3_apply(s.h, 7, ptr(b), ptr(y)) == 1
+    assert lib.bmg3_smooth(s.h, 0, 1, ptr(y), ptr(b)) == 1
+    assert lib.bmg3_solve(s.h, ptr(b), ptr(y), 0.0, 10, None) == 1
+    assert lib.bmg3_solve(s.h, ptr(b), ptr(y), 1e-10, 0, None) == 1
+    n = C.c_int32()
+    dofs = np.zeros(208, dtype=np.int32)
+    assert lib.bmg3_export_patch(s.h, 2, 5, 0, 0, C.byref(n), dofs, None) == 1
+    assert lib.bmg3_sizes(s.h, 3, None, None, None, None) == 1

@@ -76,3 +76,17 @@ def test_setup3_rejects_negative_kappa():
     kap[3] = -1.0
     h = C.c_void_p()
     assert bmg.lib().bmg3_setup(C.byref(p), kap, None, C.byref(h)) == 1
+
+
+def test_host_exports_reject_bad_arguments():
+    import ctypes as C
+    p = bmg.make_params3(1, 3, 1e-2)
+    kap = _kappa(4, 1)
+    n = C.c_int32()
+    dofs = np.zeros(208, dtype=np.int32)
+    lib = bmg.lib()
+    assert lib.bmg3_export_patch_host(C.byref(p), kap, 2, 5, 0, 0, C.byref(n), dofs, None) == 1
+    assert lib.bmg3_export_patch_host(C.byref(p), kap, 0, 0, 0, 0, C.byref(n), dofs, None) == 1
+    nnz = C.c_int64()
+    assert lib.bmg3_export_level_csr(C.byref(p), kap, 3, C.byref(nnz), None, None, None) == 1
+    assert lib.bmg3_export_level_csr(C.byref(p), kap, 1, C.byref(nnz), None, None, None) == 0 and nnz.value > 0
