@@ -66,7 +66,7 @@ typedef struct {
  * and upload them.  hip_stream: the hipStream_t every later call uses (NULL = default).
  * Cost at N = 32: ~17 s of host time and ~14 GB of device memory (12 GB of FP64 patch
  * pseudo-inverses, half with FP32 storage); both grow 8x per refinement, so N = 64
- * needs ~100 GB of device and host memory. */
+ * needs ~100 GB of device and host memory.
  * BMG_E_ARG on invalid parameters or kappa, BMG_E_NOMEM / BMG_E_HIP on device errors,
  * BMG_E_SINGULAR if a patch or the coarse matrix cannot be inverted. */
 bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_stream, bmg3_handle* out);

@@ -257,3 +257,18 @@ def test_colour_classes_cover_every_vertex(colouring):
     with pytest.raises(bmg.BmgError) as e:
         bmg.plan(bmg.make_params(2, 2, 1, 1e-2, 6.0, [D, D, O, O], colouring=2))
     assert e.value.status == 1
+
+
+def test_public_headers_compile_as_c_and_cxx():
+    import shutil
+    import subprocess
+    inc = os.path.join(ROOT, "include")
+    for name in sorted(os.listdir(inc)):
+        if not name.endswith(".h"):
+            continue
+        for cc, lang in (("gcc", "c"), ("g++", "c++")):
+            if shutil.which(cc) is None:
+                continue
+            r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-x", lang, "-I", inc, os.path.join(inc, name)],
+                               capture_output=True, text=True)
+            assert r.returncode == 0, (name, lang, r.stderr)
