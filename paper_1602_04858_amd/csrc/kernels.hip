@@ -300,13 +300,15 @@ __device__ __forceinline__ int kind_to_local(int kind, int b) {
 // Entry t of the patch layout: global index gi (-1 if not part of the patch
 // space) and the positions zA / zB of the row contributions of the patch cells
 // (slot * NL + local dof) that sum to row gi (zB >= 0 only for faces inside the patch).
-template <int K>
+// INT: the vertex is at least two cells from the boundary (every cell and neighbour
+// in the domain, nothing essential, regular layout).
+template <int K, bool INT = false>
 __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int N, int bcm, int& gi, int& zA,
                                             int& zB) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NB = D::NB, NI = D::NI, NP = D::NP, NV = D::NV, NL = D::NL;
-  auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
+  auto in_dom = [&](int cx, int cy) { return INT || (cx >= 0 && cx < N && cy >= 0 && cy < N); };
   gi = -1;
   zA = -1;
   zB = -1;
@@ -344,7 +346,7 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
       cyu = ayA;
       du = kind_to_local<K>(kA, bb);
     }
-    if (ok && !I::cons(N, bcm, cxu, cyu, du)) {
+    if (ok && (INT || !I::cons(N, bcm, cxu, cyu, du))) {
       gi = I::g(N, cxu, cyu, du);
       // zA is always the first existing contribution, zB the second (if any)
       const int za = vA ? sA * NL + kind_to_local<K>(kA, bb) : -1;
@@ -449,399 +451,29 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   int vx, vy;
   patch_vertex(scheme, N, colour, pc, vx, vy);
   const T mh = -h, hh = h * h;
-  auto in_dom = [&](int cx, int cy) { return cx >= 0 && cx < N && cy >= 0 && cy < N; };
   // index of the extended inverse (pc is in bounds for every wave).  Unconditional, so
   // that the wave does not wait for it before the gathers
   const int ext = extidx[pc];
   // right-hand-side columns of this block: c0 .. c1-1 (ld apart); MC = several
   const int c0 = MC ? blockIdx.y * ncol : blockIdx.y, c1 = MC ? min(c0 + ncol, nrhs) : c0 + 1;
 
-  // 0. issue every load that does not depend on the correction: the gather of x
-  // (first: it is needed first), the element matrices, b on the patch, then the
-  // patch-inverse column of this lane (needed last).  The loads are unconditional
-  // (clamped in-bounds indices, masked where the value is used) so that no branch
-  // separates them from their uses; they complete in order and the later ones stay
-  // in flight through the LDS-only barriers below.  Indices are kept for the later
-  // columns of the block.
-  constexpr int NG = (4 * NL + 63) / 64, NN = (8 * NV + 63) / 64;
-  int gxi[NG], gni[NN];
-  bool okx[NG], okn[NN];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    const int e = lane + 64 * q;
-    const int s = (e / NL) & 3, d = e % NL;
-    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    okx[q] = e < 4 * NL && in_dom(cx, cy) && !I::cons(N, bcm, cx, cy, d);
-    gxi[q] = okx[q] ? I::g(N, cx, cy, d) : 0;
-  }
-#pragma unroll
-  for (int q = 0; q < NN; ++q) {
-    const int e = lane + 64 * q;
-    const int s = (e / (2 * NV)) & 3, r = e % (2 * NV), which = r / NV, d = r % NV;
-    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    int ncx = cx, ncy = cy;
-    if (which == 0) ncy = (s < 2) ? cy - 1 : cy + 1;
-    else ncx = (s & 1) ? cx + 1 : cx - 1;
-    const int dd = which * NV + d;
-    okn[q] = e < 8 * NV && in_dom(cx, cy) && in_dom(ncx, ncy) && !I::cons(N, bcm, ncx, ncy, dd);
-    gni[q] = okn[q] ? I::g(N, ncx, ncy, dd) : 0;
-  }
-  T gx[NG], gn[NN];
-  if (!ADD) {
-    const T* xc = x + (int64_t)c0 * ld;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) gx[q] = xc[gxi[q]];
-#pragma unroll
-    for (int q = 0; q < NN; ++q) gn[q] = xc[gni[q]];
-  }
-  constexpr int NE = (int)(sizeof(Elem<T, K>) / sizeof(T)), NEQ = (NE + 255) / 256;
-  T ev[NEQ];
-  {
-    const T* src = reinterpret_cast<const T*>(Ep);
-#pragma unroll
-    for (int q = 0; q < NEQ; ++q) ev[q] = src[min((int)threadIdx.x + 256 * q, NE - 1)];
-  }
-  const bool ext_guess = (vx == 1 && !(bcm & 1)) || (vx == N - 1 && !(bcm & 2)) || (vy == 1 && !(bcm & 4)) ||
-                         (vy == N - 1 && !(bcm & 8));
-  // bv: b on the patch entries (multiplicative) or the residual there (additive:
-  // b is then the residual of the input x, and xv holds x on the patch entries)
-  int gi[NT], zA[NT], zB[NT];
-  T bv[NT], xv[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int t = lane + 64 * q;
-    decode_slot<K>(t, ext_guess, vx, vy, N, bcm, gi[q], zA[q], zB[q]);
-    if (!active || t >= (ext_guess ? NSE : NSR)) gi[q] = -1;
-    bv[q] = b[(int64_t)c0 * ld + (gi[q] >= 0 ? gi[q] : 0)];
-    if (ADD) xv[q] = x[(int64_t)c0 * ld + (gi[q] >= 0 ? gi[q] : 0)];
-  }
-  T kv[NG];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    const int s = ((lane + 64 * q) / NL) & 3;
-    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    kv[q] = kap[in_dom(cx, cy) ? cy * N + cx : 0];
-  }
-  // PF: the first NSR entries of column `lane` of the full inverse of this patch (n =
-  // NSR, or NSE for an extended patch; column-major) prefetched into registers, so that
-  // a regular patch streams nothing in the product; an extended (boundary) patch reads
-  // its remaining NSE - NSR entries there.  (Prefetching all NSE entries cost 32 more
-  // VGPRs in FP64: two waves per SIMD instead of three, and grids of more than 512
-  // blocks ran in two rounds.)  PK: rotated entry i in lane i mod 64
-  S areg[PF ? NSR : 1];
-  if (PF) {
-    const int n0 = ext_guess ? NSE : NSR;
-    const S* A = ext_guess ? invx + (size_t)(ext >= 0 ? ext : 0) * NSE * NSE : inv + (size_t)pc * NSR * NSR;
-    const int lc = lane < n0 ? lane : n0 - 1;
-#pragma unroll
-    for (int u = 0; u < (PF ? NSR : 1); ++u) areg[u] = A[u * n0 + lc];
-  }
-  S apk[NQ];
-  if (PK && K <= 1) {
-    // the regular slot exists for every patch; extended patches read their own
-    // inverse from HBM in the product
-    const S* A = inv + (size_t)pc * NPR;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) apk[q] = A[min(lane + 64 * q, NPR - 1)];
-    if (MC && !ext_guess) {
-      // several columns: stage the inverse now (read only in the products)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (lane + 64 * q < NPR) apw[lane + 64 * q] = apk[q];
+  // FP64 single-column RT_1 launches (the bandwidth-bound finest levels and the
+  // latency-bound full-storage ones of the FP64 V-cycle) carry a second copy of the
+  // body for vertices at least two cells from the boundary, with the boundary logic
+  // compiled out (a wave-uniform branch; both copies execute the same barriers).
+  // Other instantiations compile the general body alone.
+  constexpr bool FAST = K == 1 && !MC && !ADD && sizeof(T) == 8;
+  if constexpr (FAST) {
+    if (vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2) {
+      constexpr bool INT = true;
+#include "colour_body.inc"
+    } else {
+      constexpr bool INT = false;
+#include "colour_body.inc"
     }
-  } else if (PK && MC && !ext_guess) {
-    // RT_2 (4704 rotated entries, too many for registers): copied to LDS once for
-    // all columns of the block
-    const S* A = inv + (size_t)pc * NPR;
-    for (int i = lane; i < NPR; i += 64) apw[i] = A[i];
-  }
-  const bool is_ext = ext_guess;
-  const int ns = is_ext ? NSE : NSR;
-
-  for (int c = c0;;) {
-    T* xc = x + (int64_t)c * ld;
-    if (!ADD) {
-      // 1. gathered values (and, once, the element matrices and the zero block) to LDS
-  #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const int e = lane + 64 * q;
-        if (e < 4 * NL) xw[e / NL][e % NL] = okx[q] ? gx[q] : T(0);
-      }
-  #pragma unroll
-      for (int q = 0; q < NN; ++q) {
-        const int e = lane + 64 * q;
-        if (e < 8 * NV) {
-          const int s = e / (2 * NV), r = e % (2 * NV);
-          nbw[s][r / NV][r % NV] = okn[q] ? gn[q] : T(0);
-        }
-      }
-      if (c == c0) {
-        T* dst = reinterpret_cast<T*>(&Es);
-  #pragma unroll
-        for (int q = 0; q < NEQ; ++q)
-          if ((int)threadIdx.x + 256 * q < NE) dst[threadIdx.x + 256 * q] = ev[q];
-        if ((int)threadIdx.x < NP * NV) zblk[threadIdx.x] = T(0);
-      }
-      // the element matrices are shared by the block; the rest is the wave's own
-      if (c == c0)
-        lds_barrier();
-      else
-        wave_lds_sync();
-
-      // 2. row contributions of every patch cell (cell blocks + its four faces), one
-      // branch-free path for all rows.  A velocity row (component c, local index dd)
-      // is (Kmu + kappa h^2 M + S_lo + S_hi)[dd] . u_c + N_lo[dd] . u_lo + N_hi[dd] . u_hi
-      // - h Dm[:, dd] . p, where the faces across which component c is tangential give
-      // the self/neighbour blocks F (interior), Nb (Dirichlet) or nothing (open); a
-      // pressure row q is -h (Dx[q] . u_x + Dy[q] . u_y).  Every lane picks its
-      // coefficient rows and vectors by LDS address; absent terms read the zero block.
-  #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const int e = lane + 64 * q;
-        if (e >= 4 * NL) break;
-        const int s = e / NL, d = e % NL;
-        const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-        const T* xl = xw[s];
-        const bool vel = d < 2 * NV;
-        const int comp = d >= NV ? 1 : 0;
-        const int dd = vel ? d - comp * NV : d - 2 * NV;
-        // component 0 is tangential on the horizontal faces (cy), component 1 on the vertical ones (cx)
-        const bool lo_bnd = comp ? cx == 0 : cy == 0;
-        const bool hi_bnd = comp ? cx == N - 1 : cy == N - 1;
-        const int tl = lo_bnd ? boundary_type(bcm, comp ? 0 : 2) : F_INT;
-        const int tu = hi_bnd ? boundary_type(bcm, comp ? 1 : 3) : F_INT;
-        const T* nl = comp ? ((s & 1) ? xw[s - 1] + NV : nbw[s][1]) : ((s >= 2) ? xw[s - 2] : nbw[s][0]);
-        const T* nu = comp ? ((s & 1) ? nbw[s][1] : xw[s + 1] + NV) : ((s < 2) ? xw[s + 2] : nbw[s][0]);
-        const int ro = dd * NV;
-        const T* c_self = vel ? Es.Kmu + ro : Es.Dx + ro;
-        const T* c_mass = vel ? Es.M + ro : zblk;
-        const T* c_slo = !vel ? zblk : tl == F_INT ? Es.F[3] + ro : tl == F_DIR ? Es.Nb[0] + ro : zblk;
-        const T* c_shi = !vel ? zblk : tu == F_INT ? Es.F[0] + ro : tu == F_DIR ? Es.Nb[1] + ro : zblk;
-        const T* c_nlo = !vel ? Es.Dy + ro : tl == F_INT ? Es.F[2] + ro : zblk;
-        const T* c_nhi = vel && tu == F_INT ? Es.F[1] + ro : zblk;
-        const T* c_div = vel ? (comp ? Es.Dy : Es.Dx) + dd : zblk;  // column dd, stride NV
-        const T* v_self = vel ? xl + comp * NV : xl;
-        const T* v_nlo = vel ? nl : xl + NV;
-        const T* pv = xl + 2 * NV;
-        const T khh = vel ? kv[q] * hh : T(0);
-        T a = T(0), g = T(0);
-        auto term = [&](int i) {
-          a += (c_self[i] + khh * c_mass[i] + c_slo[i] + c_shi[i]) * v_self[i];
-          a += c_nlo[i] * v_nlo[i] + c_nhi[i] * nu[i];
-        };
-        if (PK) {
-          // bandwidth-bound levels: partial unrolling keeps the registers (and so the
-          // blocks per CU) of the rest of the kernel
-  #pragma unroll 2
-          for (int i = 0; i < NV; ++i) term(i);
-        } else {
-  #pragma unroll
-          for (int i = 0; i < NV; ++i) term(i);
-        }
-  #pragma unroll
-        for (int i = 0; i < NP; ++i) g += c_div[i * NV] * pv[i];
-        const T z = (vel ? a : mh * a) + mh * g;
-        zw[e] = (active && in_dom(cx, cy)) ? z : T(0);
-      }
-      wave_lds_sync();  // this wave's own LDS region only
-    }
-
-    // 3. local residual (b - A x) on the patch entries.  The layout follows from the
-    // vertex position (extended iff an outer face of the patch lies on an open
-    // side); setup checks this rule against the patch construction.
-    T xold[NT];
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int t = lane + 64 * q;
-      xold[q] = T(0);
-      if (t < NSE) {
-        T r = T(0);
-        if (gi[q] >= 0) {
-          if (ADD) {
-            r = bv[q];
-            xold[q] = xv[q];
-          } else {
-            r = bv[q] - zw[zA[q]] - (zB[q] >= 0 ? zw[zB[q]] : T(0));
-            xold[q] = (&xw[0][0])[zA[q]];
-          }
-        }
-        if (MF) {
-          rsa[w][c - c0][t] = r;
-          if (c == c0) gis[w][t] = gi[q];
-        } else {
-          rs[w][t] = r;
-        }
-      }
-    }
-    // regular rotated inverse to LDS, once (the extended ones are read from HBM below);
-    // with OVL it overwrites this wave's xs / nb / zs, whose reads are all above
-    if (OVL) __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (PK && !MC && !ext_guess) {
-      if (K <= 1) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          if (lane + 64 * q < NPR) apw[lane + 64 * q] = apk[q];
-      } else {
-        const S* A = inv + (size_t)pc * NPR;
-        for (int i = lane; i < NPR; i += 64) apw[i] = A[i];
-      }
-    }
-    wave_lds_sync();  // this wave's own LDS region only
-
-    // the next column's gather and b are issued before the product of this one
-    const bool more = MC && c + 1 < c1;
-    if (more) {
-      const T* xn = x + (int64_t)(c + 1) * ld;
-      if (!ADD) {
-#pragma unroll
-        for (int q = 0; q < NG; ++q) gx[q] = xn[gxi[q]];
-#pragma unroll
-        for (int q = 0; q < NN; ++q) gn[q] = xn[gni[q]];
-      }
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        bv[q] = b[(int64_t)(c + 1) * ld + (gi[q] >= 0 ? gi[q] : 0)];
-        if (ADD) xv[q] = xn[gi[q] >= 0 ? gi[q] : 0];
-      }
-    }
-
-    // 4. correction y = A_S^+ r, x[S] = x_old + y (no re-read of x)
-    if (active && !MF) {
-      if (PK) {
-        // rotated symmetric product: (A+ r)_t = sum_{d=0}^{n/2} R[d][t] r[(t + d) mod n]
-        //   + sum_{d=1}^{n/2-1} R[d][(t - d) mod n] r[(t - d) mod n]  (A+[t][t-d] = A+[t-d][t]);
-        // consecutive lanes read consecutive entries, so the LDS reads are conflict-free.
-        // Rows t = lane + 64 q (RT_2 patches have more than 64 entries).
-        auto rot = [&](const S* Rp, int n, int t) {
-          T acc = T(0);
-          if (K <= 1) {  // n == NSR: fully unrolled
-#pragma unroll
-            for (int d = 0; d <= NSR / 2; ++d) {
-              int u = t + d;
-              u -= u >= NSR ? NSR : 0;
-              acc += T(Rp[d * NSR + t]) * rs[w][u];
-            }
-#pragma unroll
-            for (int d = 1; d < NSR / 2; ++d) {
-              int u = t - d;
-              u += u < 0 ? NSR : 0;
-              acc += T(Rp[d * NSR + u]) * rs[w][u];
-            }
-          } else {
-#pragma unroll 8
-            for (int d = 0; d <= n / 2; ++d) {
-              int u = t + d;
-              u -= u >= n ? n : 0;
-              acc += T(Rp[d * n + t]) * rs[w][u];
-            }
-#pragma unroll 8
-            for (int d = 1; d < n / 2; ++d) {
-              int u = t - d;
-              u += u < 0 ? n : 0;
-              acc += T(Rp[d * n + u]) * rs[w][u];
-            }
-          }
-          return acc;
-        };
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          const int t = lane + 64 * q;
-          if (t < ns) {
-            T acc;
-            if (!is_ext) {
-              acc = rot(apw, NSR, t);
-            } else {
-              // extended (boundary) patches: their own rotated block, read from HBM
-              const S* Rp = invx + (size_t)ext * NPE;
-              acc = T(0);
-#pragma unroll 4
-              for (int d = 0; d <= NSE / 2; ++d) {
-                int u = t + d;
-                u -= u >= NSE ? NSE : 0;
-                acc += T(Rp[d * NSE + t]) * rs[w][u];
-              }
-#pragma unroll 4
-              for (int d = 1; d < NSE / 2; ++d) {
-                int u = t - d;
-                u += u < 0 ? NSE : 0;
-                acc += T(Rp[d * NSE + u]) * rs[w][u];
-              }
-            }
-            if (gi[q] >= 0) xc[gi[q]] = xold[q] + (ADD ? omega * acc : acc);
-          }
-        }
-      } else if (PF) {
-        // the first NSR terms from registers, the rest (extended patches) from memory
-        if (lane < ns) {
-          T acc = T(0);
-#pragma unroll
-          for (int u = 0; u < (PF ? NSR : 1); ++u) acc += T(areg[u]) * rs[w][u];
-          if (is_ext) {
-            const S* Ax = invx + (size_t)ext * NSE * NSE;
-#pragma unroll
-            for (int u = NSR; u < (PF ? NSE : NSR); ++u) acc += T(Ax[u * NSE + lane]) * rs[w][u];
-          }
-          if (gi[0] >= 0) xc[gi[0]] = xold[0] + (ADD ? omega * acc : acc);
-        }
-      } else {
-        const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          const int t = lane + 64 * q;
-          if (t < ns) {
-            T acc = T(0);
-#pragma unroll 8
-            for (int u = 0; u < ns; ++u) acc += T(A[u * ns + t]) * rs[w][u];
-            if (gi[q] >= 0) xc[gi[q]] = xold[q] + (ADD ? omega * acc : acc);
-          }
-        }
-      }
-    }
-    if (!more) break;
-    ++c;
-  }
-
-  if (MF) {
-    // Y (n x C) = A+ (n x n) R (n x C) by v_mfma_f32_16x16x4f32 tiles: A operand lane l
-    // holds A[16 rt + l % 16][4 ks + l / 16] (column-major storage: entry (row, col) at
-    // col n + row), B operand R[4 ks + l / 16][l % 16] from LDS, result lane l register
-    // v: Y[16 rt + 4 (l / 16) + v][l % 16].  n is a multiple of 4; rows past n are 0.
-    typedef float mf4 __attribute__((ext_vector_type(4)));
-    constexpr int NRT = (NSE + 15) / 16;
-    wave_lds_sync();  // this wave's own LDS region only
-    if (active) {
-      const int n = is_ext ? NSE : NSR;
-      const S* A = is_ext ? invx + (size_t)ext * NSE * NSE : inv + (size_t)p * NSR * NSR;
-      const int ncols = c1 - c0;
-      const int j = lane & 15, kq = lane >> 4;
-      mf4 acc[NRT];
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) acc[rt] = mf4{0.f, 0.f, 0.f, 0.f};
-      for (int ks = 0; ks < n / 4; ++ks) {
-        const int kk = 4 * ks + kq;
-        const float bval = j < ncols ? (float)rsa[w][j][kk] : 0.f;
-#pragma unroll
-        for (int rt = 0; rt < NRT; ++rt) {
-          const int row = 16 * rt + j;
-          const float aval = row < n ? (float)A[(size_t)kk * n + row] : 0.f;
-          acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[rt], 0, 0, 0);
-        }
-      }
-      if (j < ncols) {
-        T* xc = x + (int64_t)(c0 + j) * ld;
-#pragma unroll
-        for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * rt + 4 * kq + v;
-            if (row < n) {
-              const int g = gis[w][row];
-              // same-colour patches write disjoint entries: the read-modify-write is safe
-              if (g >= 0) xc[g] += ADD ? omega * (T)acc[rt][v] : (T)acc[rt][v];
-            }
-          }
-      }
-    }
+  } else {
+    constexpr bool INT = false;
+#include "colour_body.inc"
   }
 }
 
