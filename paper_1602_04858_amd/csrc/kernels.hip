@@ -457,12 +457,12 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   // right-hand-side columns of this block: c0 .. c1-1 (ld apart); MC = several
   const int c0 = MC ? blockIdx.y * ncol : blockIdx.y, c1 = MC ? min(c0 + ncol, nrhs) : c0 + 1;
 
-  // FP64 single-column RT_1 launches (the bandwidth-bound finest levels and the
-  // latency-bound full-storage ones of the FP64 V-cycle) carry a second copy of the
-  // body for vertices at least two cells from the boundary, with the boundary logic
-  // compiled out (a wave-uniform branch; both copies execute the same barriers).
-  // Other instantiations compile the general body alone.
-  constexpr bool FAST = K == 1 && !MC && !ADD && sizeof(T) == 8;
+  // Single-column RT_1 launches (the bandwidth-bound finest levels and the
+  // latency-bound full-storage ones) carry a second copy of the body for vertices at
+  // least two cells from the boundary, with the boundary logic compiled out (a
+  // wave-uniform branch; both copies execute the same barriers).  Other instantiations
+  // compile the general body alone.
+  constexpr bool FAST = K == 1 && !MC && !ADD;
   if constexpr (FAST) {
     if (vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2) {
       constexpr bool INT = true;
