@@ -1,6 +1,6 @@
 // Shared definitions of the HIP library: compile-time sizes of the RT_k x dQ_k
 // cell, the reference-element data the kernels consume, and the launcher
-// interface between the host driver and the kernels.
+// interface between the host code and the kernels.
 #pragma once
 #include <cstddef>
 #include <cstdint>

@@ -1,7 +1,7 @@
 // Host side of the 3-D (hexahedral) path: reference integrals of RT_1 x dQ_1 on the
 // unit cube, assembly of the level operators (CSR) with essential boundary normals,
 // vertex patches and their pseudo-inverses, the exact-embedding transfers, and the
-// FGMRES / V-cycle driver whose every vector operation runs in HIP kernels.
+// FGMRES / V-cycle loop whose every vector operation runs in HIP kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
