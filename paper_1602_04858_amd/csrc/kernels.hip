@@ -357,9 +357,12 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
   } else {
     const int e = t - nf * NB;
     int s, d;
+    // RT_0 has no interior dofs (NI = 0): the branch is dead and the divisors are
+    // kept nonzero so that it stays well defined
+    constexpr int NId = NI > 0 ? NI : 1, KNB = K > 0 ? K * NB : 1;
     if (e < 4 * NI) {
-      s = e / NI;
-      const int w2 = e % NI, comp = w2 / (K * NB), rem = w2 % (K * NB);
+      s = e / NId;
+      const int w2 = e % NId, comp = w2 / KNB, rem = w2 % KNB;
       d = comp * NV + (2 + rem / NB) * NB + rem % NB;
     } else {
       s = (e - 4 * NI) / NP;
