@@ -64,9 +64,10 @@ typedef struct {
 /* Assemble levels, transfers and patch pseudo-inverses for the fine-level kappa
  * (kappa_host[c], N^3 values >= 0, finite; coarse kappa = mean of the eight children)
  * and upload them.  hip_stream: the hipStream_t every later call uses (NULL = default).
- * Cost at N = 32: ~17 s of host time and ~14 GB of device memory (12 GB of FP64 patch
- * pseudo-inverses, half with FP32 storage); both grow 8x per refinement, so N = 64
- * needs ~100 GB of device and host memory.
+ * Cost at N = 32: ~17 s of host time and ~8 GB of device memory (6 GB of patch
+ * pseudo-inverses: FP64 storage keeps the n (n/2 + 1) rotated diagonals of each
+ * symmetric block, FP32 storage the full n x n block, about the same bytes); both
+ * grow 8x per refinement, so N = 64 needs ~65 GB of device and host memory.
  * BMG_E_ARG on invalid parameters or kappa, BMG_E_NOMEM / BMG_E_HIP on device errors,
  * BMG_E_SINGULAR if a patch or the coarse matrix cannot be inverted. */
 bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_stream, bmg3_handle* out);
@@ -95,14 +96,16 @@ bmg_status bmg3_vcycle(bmg3_handle h, const double* r_dev, double* z_dev);
  * otherwise.  info may be NULL. */
 bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
                       bmg_solve_info* info);
-/* Dofs (ascending, *n of them, at most 208) and pseudo-inverse (n x n, column-major) of
- * the patch of vertex (vx, vy, vz) on level >= 1 (host arrays; pinv_host may be NULL). */
+/* Dofs (ascending, *n of them, at most 208) and pseudo-inverse (n x n, column-major,
+ * symmetrised: the mean of the computed inverse and its transpose, as the smoother
+ * applies it) of the patch of vertex (vx, vy, vz) on level >= 1 (host arrays;
+ * pinv_host may be NULL). */
 bmg_status bmg3_export_patch(bmg3_handle h, int32_t level, int32_t vx, int32_t vy, int32_t vz, int32_t* n,
                              int32_t* dofs_host, double* pinv_host);
 /* Host-only exports (no device needed) for checking the setup against a reference:
  * the CSR matrix of level `level` (call first with rp_host = NULL to get *nnz; then
  * rp_host holds ndof + 1 entries, ci_host and v_host *nnz), and the dofs and
- * pseudo-inverse (column-major) of one vertex patch on level >= 1. */
+ * symmetrised pseudo-inverse (column-major) of one vertex patch on level >= 1. */
 bmg_status bmg3_export_level_csr(const bmg3_params* p, const double* kappa_host, int32_t level, int64_t* nnz,
                                  int32_t* rp_host, int32_t* ci_host, double* v_host);
 bmg_status bmg3_export_patch_host(const bmg3_params* p, const double* kappa_host, int32_t level, int32_t vx,

@@ -689,7 +689,7 @@ void patch_dofs3(const Num3& S, int vx, int vy, int vz, std::vector<int64_t>& ou
 
 inline int colour3(int vx, int vy, int vz) { return (vx % 3) + 3 * (vy % 3) + 9 * (vz % 3); }
 
-// Pseudo-inverse of A[D, D] (column-major into dst): the leading block of the inverse of
+// Pseudo-inverse of A[D, D] (column-major into dst, symmetrised): the leading block of the inverse of
 // [[A_D, c], [c^T, 0]] with c the normalised patch-constant pressure (every patch has it
 // in its kernel: no patch space holds a boundary normal dof).
 bool patch_pinv3(const Num3& S, const Csr& A, const std::vector<int64_t>& D, const std::vector<int>& cells,
@@ -709,9 +709,28 @@ bool patch_pinv3(const Num3& S, const Csr& A, const std::vector<int64_t>& D, con
     a[(size_t)n * m + t] = cv;
   }
   if (!gj_inverse(m, a, inv)) return false;
+  // the pseudo-inverse of the symmetric patch matrix is symmetric: the two rounded
+  // copies of each off-diagonal entry are averaged (exactly symmetric result)
   for (int t = 0; t < n; ++t)
-    for (int u = 0; u < n; ++u) dst[(size_t)u * n + t] = inv[(size_t)t * m + u];
+    for (int u = 0; u < n; ++u) dst[(size_t)u * n + t] = 0.5 * (inv[(size_t)t * m + u] + inv[(size_t)u * m + t]);
   return true;
+}
+
+// Stored form of a symmetric n x n block F (column-major): its rotated diagonals
+// R[d n + t] = F(t, (t + d) mod n), d = 0 .. n/2, n (n/2 + 1) entries; every entry of
+// F is F(t, u) or F(u, t) of one of them.
+void rotate_sym3(int n, const double* F, double* R) {
+  for (int d = 0; d <= n / 2; ++d)
+    for (int t = 0; t < n; ++t) R[(size_t)d * n + t] = F[(size_t)((t + d) % n) * n + t];
+}
+
+// Inverse of rotate_sym3 into the full column-major block.
+void unrotate_sym3(int n, const double* R, double* F) {
+  for (int d = 0; d <= n / 2; ++d)
+    for (int t = 0; t < n; ++t) {
+      const int u = (t + d) % n;
+      F[(size_t)u * n + t] = F[(size_t)t * n + u] = R[(size_t)d * n + t];
+    }
 }
 
 // Patches of one level: dofs, pseudo-inverses (bordered with the normalised patch-
@@ -745,7 +764,8 @@ bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
     const int64_t n = (int64_t)dofs[p].size();
     if (n > kMaxPatch3 || n == 0) return fail3(c, BMG_E_ARG, "patch size out of range");
     L.hpoff[p + 1] = L.hpoff[p] + n;
-    L.hioff[p + 1] = L.hioff[p] + n * n;
+    // FP64: rotated diagonals of the symmetric block; FP32: the full block
+    L.hioff[p + 1] = L.hioff[p] + (c->p.precond_prec == 1 ? n * n : n * (n / 2 + 1));
   }
   L.hpdofs.resize(L.hpoff[nvert]);
   std::vector<double> pinv(L.hioff[nvert]);
@@ -753,7 +773,13 @@ bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
   par_for(nvert, [&](int64_t p) {
     const auto& D = dofs[p];
     for (size_t t = 0; t < D.size(); ++t) L.hpdofs[L.hpoff[p] + t] = (int32_t)D[t];
-    if (!patch_pinv3(S, A, D, cells[p], &pinv[L.hioff[p]])) bad.store(1);
+    if (c->p.precond_prec == 1) {
+      if (!patch_pinv3(S, A, D, cells[p], &pinv[L.hioff[p]])) bad.store(1);
+    } else {
+      std::vector<double> full(D.size() * D.size());
+      if (!patch_pinv3(S, A, D, cells[p], full.data())) bad.store(1);
+      else rotate_sym3((int)D.size(), full.data(), &pinv[L.hioff[p]]);
+    }
   });
   if (bad.load()) return fail3(c, BMG_E_SINGULAR, "a patch matrix is singular");
   bmg_status s;
@@ -1049,15 +1075,19 @@ bmg_status bmg3_export_patch(bmg3_handle h, int32_t level, int32_t vx, int32_t v
   *n = (int32_t)cnt;
   std::memcpy(dofs_host, L.hpdofs.data() + o, cnt * sizeof(int32_t));
   if (!pinv_host) return BMG_OK;
+  const size_t stored = (size_t)(L.hioff[p + 1] - L.hioff[p]);
   if (h->p.precond_prec == 1) {
-    std::vector<float> tmp(cnt * cnt);
-    if (hipMemcpy(tmp.data(), (const float*)L.pinv + L.hioff[p], tmp.size() * sizeof(float), hipMemcpyDeviceToHost) !=
+    std::vector<float> tmp(stored);
+    if (hipMemcpy(tmp.data(), (const float*)L.pinv + L.hioff[p], stored * sizeof(float), hipMemcpyDeviceToHost) !=
         hipSuccess)
       return fail3(h, BMG_E_HIP, "hipMemcpy failed");
-    for (size_t i = 0; i < tmp.size(); ++i) pinv_host[i] = tmp[i];
-  } else if (hipMemcpy(pinv_host, (const double*)L.pinv + L.hioff[p], cnt * cnt * sizeof(double),
-                       hipMemcpyDeviceToHost) != hipSuccess) {
-    return fail3(h, BMG_E_HIP, "hipMemcpy failed");
+    for (size_t i = 0; i < stored; ++i) pinv_host[i] = tmp[i];
+  } else {
+    std::vector<double> tmp(stored);
+    if (hipMemcpy(tmp.data(), (const double*)L.pinv + L.hioff[p], stored * sizeof(double), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return fail3(h, BMG_E_HIP, "hipMemcpy failed");
+    unrotate_sym3((int)cnt, tmp.data(), pinv_host);
   }
   return BMG_OK;
 }

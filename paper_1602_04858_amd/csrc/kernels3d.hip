@@ -6,8 +6,8 @@
 //   k3_colour  one colour step of the symmetric multiplicative vertex-patch smoother
 //              (Section 3, eq. smoother-Multiplicative): a block per patch forms the
 //              local residual (b - A x) on the patch rows, applies the patch
-//              pseudo-inverse (dense, column-major, FP64 or FP32 storage, FP64
-//              arithmetic) and adds the correction into x
+//              pseudo-inverse (symmetric, stored as rotated diagonals, FP64 or FP32
+//              storage, FP64 arithmetic) and adds the correction into x
 //   k3_copy_idx  x[i] = b[i] on the essential rows (identity rows of the operator)
 #include <hip/hip_runtime.h>
 
@@ -48,13 +48,16 @@ __global__ __launch_bounds__(256) void k3_csr(int64_t nrows, const int32_t* __re
 
 // Patches of one colour are the contiguous range [p0, p0 + gridDim.x) of the level's
 // patch list; patch p has the dofs pdofs[poff[p] .. poff[p+1]) (ascending) and its
-// pseudo-inverse at pinv + ioff[p], column-major (entry (t, u) at u n + t).
+// symmetric pseudo-inverse A+ at pinv + ioff[p]: with FP64 storage as rotated
+// diagonals, R[d n + t] = A+(t, (t + d) mod n) for d = 0 .. n/2 (n (n/2 + 1) entries,
+// about half of n^2; the entry (t, (t - d) mod n) below the diagonal is R[d][(t - d)
+// mod n] by symmetry), with FP32 storage as the full column-major block.
 //
-// A patch's work is two dependent streams (the CSR rows of its dofs, then its n x n
-// pseudo-inverse, 346 KB for n = 208), so the kernel is built for loads in flight:
-// the residual rows take eight lanes each with the row loop unrolled, and in the
-// product each of the BS/64 waves takes its share of the columns for all rows, issuing
-// 4 rows x 8 columns of loads before their FMAs; the partial sums meet in LDS.  BS =
+// A patch's work is two dependent streams (the CSR rows of its dofs, then its
+// pseudo-inverse, 175 KB for n = 208 in FP64), so the kernel is built for loads in
+// flight: the residual rows take eight lanes each with the row loop unrolled, and in
+// the product each of the BS/64 waves takes its share of the diagonals (columns) for
+// all rows, issuing 32 loads before their FMAs; the partial sums meet in LDS.  BS =
 // 1024 serves levels with fewer patches in a colour than CUs (the chains get 4x
 // shorter; the CUs would idle anyway), BS = 256 the fine levels.
 template <int BS, typename S>
@@ -88,33 +91,73 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
     if (t < n && sub == 0) rs[t] = b[gi] - s;
   }
   __syncthreads();
-  // correction y = A+ r: wave w sums the columns u in [u0, u1) for rows lane + 64 i
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int q = (n + NW - 1) / NW, u0 = w * q, u1 = min(n, u0 + q);
   const S* A = pinv + ioff[p];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int ub = u0; ub < u1; ub += 8) {
-    // all 32 loads are issued before the first wait.  FP64: masked loads.  FP32:
-    // unconditional loads at clamped (in-bounds) indices, widened only in the FMAs
-    // (masked FP32 loads were each compiled into a branch with its own wait and
-    // conversion); rows t >= n are never stored and columns u >= u1 meet r = 0 below.
-    S a[4][8];
+  if constexpr (sizeof(S) == 8) {
+    // correction y = A+ r from the rotated diagonals: wave w takes the diagonals d in
+    // [d0, d1) for rows t = lane + 64 i, and for each reads both R[d][t] (entry
+    // (t, t + d)) and R[d][(t - d) mod n] (entry (t, t - d) by symmetry) in the same
+    // iteration: the second read hits the lines the first brought in, so the block's
+    // HBM stream is the stored half.  Diagonal 0 has no second entry, nor has d = n/2
+    // for even n (its entries are all (t, t + n/2)).  Loads are masked and their
+    // indices formed from min(t, n-1), inside the block; 2 x 4 x KC of them are issued
+    // before the first wait.
+    constexpr int KC = 4;
+    const int H = n >> 1, HL = n - 1 - H;
+    const int q = (H + NW) / NW, d0 = w * q, d1 = min(H + 1, d0 + q);
+    for (int db = d0; db < d1; db += KC) {
+      double au[4][KC], al[4][KC];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int t = lane + 64 * i;
+      for (int i = 0; i < 4; ++i) {
+        const int t = lane + 64 * i, tc = min(t, n - 1);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if constexpr (sizeof(S) == 8)
-          a[i][k] = (t < n && ub + k < u1) ? A[(int64_t)(ub + k) * n + t] : S(0);
-        else
-          a[i][k] = A[(int64_t)min(ub + k, u1 - 1) * n + min(t, n - 1)];
+        for (int k = 0; k < KC; ++k) {
+          const int d = min(db + k, d1 - 1);
+          const bool ok = t < n && db + k < d1;
+          int s = tc - d;
+          s += s < 0 ? n : 0;
+          au[i][k] = ok ? A[d * n + tc] : 0.0;
+          al[i][k] = (ok && d >= 1 && d <= HL) ? A[d * n + s] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int d = min(db + k, d1 - 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int tc = min(lane + 64 * i, n - 1);
+          int su = tc + d, sl = tc - d;
+          su -= su >= n ? n : 0;
+          sl += sl < 0 ? n : 0;
+          acc[i] += au[i][k] * rs[su] + al[i][k] * rs[sl];
+        }
       }
     }
+  } else {
+    // FP32 storage keeps the full column-major block (entry (t, u) at u n + t); its
+    // narrower stream was already short, and the rotated product's index arithmetic
+    // and per-lane gathers cost more than the bytes it saves.  Wave w sums the columns
+    // u in [u0, u1) for rows lane + 64 i.
+    const int q = (n + NW - 1) / NW, u0 = w * q, u1 = min(n, u0 + q);
+    for (int ub = u0; ub < u1; ub += 8) {
+      // all 32 loads are issued before the first wait, unconditionally at clamped
+      // (in-bounds) indices and widened only in the FMAs (masked FP32 loads were each
+      // compiled into a branch with its own wait and conversion); rows t >= n are
+      // never stored and columns u >= u1 meet r = 0 below.
+      S a[4][8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double r = ub + k < u1 ? rs[ub + k] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const int t = lane + 64 * i;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] += (double)a[i][k] * r;
+        for (int k = 0; k < 8; ++k) a[i][k] = A[(int64_t)min(ub + k, u1 - 1) * n + min(t, n - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double r = ub + k < u1 ? rs[ub + k] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += (double)a[i][k] * r;
+      }
     }
   }
 #pragma unroll

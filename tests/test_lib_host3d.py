@@ -51,6 +51,8 @@ def test_patch_pseudo_inverse_matches_oracle(vertex):
     po = o3.patch_pinv(A_S, lev.sp, d_o, cells, True)
     assert np.array_equal(dofs, d_o)
     assert np.abs(pinv - po).max() <= 1e-9 * np.abs(po).max()
+    # the smoother stores only the rotated diagonals of a symmetric block
+    assert np.array_equal(pinv, pinv.T)
 
 
 @pytest.mark.parametrize("change,expect", [(dict(k=2), 2), (dict(k=0), 2), (dict(n0=0), 1), (dict(levels=0), 1),
