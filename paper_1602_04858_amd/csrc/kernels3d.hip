@@ -66,7 +66,8 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
                                                  const S* __restrict__ pinv, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
                                                  double* __restrict__ x, const double* __restrict__ b) {
-  __shared__ double rs[kMaxPatch3];
+  // the local residual, twice over (rs[t + n] = rs[t]) for the rotated FP64 product
+  __shared__ double rs[2 * kMaxPatch3];
   constexpr int NW = BS / 64;
   __shared__ double part[NW][kMaxPatch3];
   __shared__ int32_t gs[kMaxPatch3];
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
       for (int e = rp[gi] + sub; e < e1; e += kRowLanes) s += v[e] * x[ci[e]];
     }
     s = lane_group_sum(s);
-    if (t < n && sub == 0) rs[t] = b[gi] - s;
+    if (t < n && sub == 0) rs[t] = rs[t + n] = b[gi] - s;
   }
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -100,9 +101,10 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
     // (t, t + d)) and R[d][(t - d) mod n] (entry (t, t - d) by symmetry) in the same
     // iteration: the second read hits the lines the first brought in, so the block's
     // HBM stream is the stored half.  Diagonal 0 has no second entry, nor has d = n/2
-    // for even n (its entries are all (t, t + n/2)).  Loads are masked and their
-    // indices formed from min(t, n-1), inside the block; 2 x 4 x KC of them are issued
-    // before the first wait.
+    // for even n (its entries are all (t, t + n/2)).  Loads are masked (rows t < n,
+    // diagonals below d1; the second index is formed from min(t, n-1), inside the
+    // block); 2 x 4 x KC of them are issued before the first wait.  The residual
+    // entries r[(t +- d) mod n] are read from the doubled copy at t + d and t - d + n.
     constexpr int KC = 4;
     const int H = n >> 1, HL = n - 1 - H;
     const int q = (H + NW) / NW, d0 = w * q, d1 = min(H + 1, d0 + q);
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
           const bool ok = t < n && db + k < d1;
           int s = tc - d;
           s += s < 0 ? n : 0;
-          au[i][k] = ok ? A[d * n + tc] : 0.0;
+          au[i][k] = ok ? A[d * n + t] : 0.0;
           al[i][k] = (ok && d >= 1 && d <= HL) ? A[d * n + s] : 0.0;
         }
       }
@@ -127,10 +129,7 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int tc = min(lane + 64 * i, n - 1);
-          int su = tc + d, sl = tc - d;
-          su -= su >= n ? n : 0;
-          sl += sl < 0 ? n : 0;
-          acc[i] += au[i][k] * rs[su] + al[i][k] * rs[sl];
+          acc[i] += au[i][k] * rs[tc + d] + al[i][k] * rs[tc - d + n];
         }
       }
     }
