@@ -903,7 +903,8 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
       c->n0dof = n;
       if (upload(c, &c->coarse_inv, ci.data(), ci.size())) return bail(BMG_E_NOMEM, "device allocation failed");
     } else {
-      if (build_patches3(c, L, A)) return bail(BMG_E_SINGULAR, "");
+      // its own status: SINGULAR for a singular patch, NOMEM / HIP for device errors
+      if (const bmg_status ps = build_patches3(c, L, A)) return bail(ps, "");
       Csr P = prolongation(c->lev[j - 1].S, L.S);
       Csr R = transpose(P);
       if (upload_csr(c, L.P, P) || upload_csr(c, L.R, R)) return bail(BMG_E_NOMEM, "device allocation failed");
