@@ -93,7 +93,8 @@ bmg_status bmg3_vcycle(bmg3_handle h, const double* r_dev, double* z_dev);
 /* Solve A x = b with FGMRES(restart) and the V-cycle, x0 = 0, until the Arnoldi
  * residual estimate <= rtol ||b|| (then refined on the true residual as in bmg_solve)
  * or maxit preconditioner applications; BMG_E_NOT_CONVERGED with x the last iterate
- * otherwise.  info may be NULL. */
+ * otherwise.  BMG_E_NONFINITE if b holds a NaN or Inf (x untouched) or the iteration
+ * produces one.  info may be NULL. */
 bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
                       bmg_solve_info* info);
 /* Dofs (ascending, *n of them, at most 208) and pseudo-inverse (n x n, column-major,

@@ -991,6 +991,7 @@ bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double 
   };
   double bn = 0.0;
   if (!norm2(b_dev, bn)) return fail3(h, BMG_E_HIP, "device error");
+  if (!std::isfinite(bn)) return fail3(h, BMG_E_NONFINITE, "right-hand side is not finite");
   launch_fill_zero(0, x_dev, n, s);
   if (info) *info = bmg_solve_info{0, 0, 0.0, 0.0};
   if (bn == 0.0) {
@@ -1005,6 +1006,7 @@ bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double 
     launch3_csr(1, n, L.A.rp, L.A.ci, L.A.v, x_dev, b_dev, h->rr, s);
     double beta = 0.0;
     if (!norm2(h->rr, beta)) return fail3(h, BMG_E_HIP, "device error");
+    if (!std::isfinite(beta)) return fail3(h, BMG_E_NONFINITE, "residual is not finite");
     if (beta <= rtol * bn) {
       conv = true;
       est = beta / bn;
@@ -1038,6 +1040,7 @@ bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double 
         H[(size_t)l * m + i] = t;
       }
       const double den = std::hypot(H[(size_t)i * m + i], hn);
+      if (!std::isfinite(den)) return fail3(h, BMG_E_NONFINITE, "Arnoldi step is not finite");
       cs[i] = den > 0 ? H[(size_t)i * m + i] / den : 1.0;
       sn[i] = den > 0 ? hn / den : 0.0;
       H[(size_t)i * m + i] = den;

@@ -177,3 +177,20 @@ def test_not_converged_and_argument_errors_3d():
     dofs = np.zeros(208, dtype=np.int32)
     assert lib.bmg3_export_patch(s.h, 2, 5, 0, 0, C.byref(n), dofs, None) == 1
     assert lib.bmg3_sizes(s.h, 3, None, None, None, None) == 1
+
+
+def test_nonfinite_rhs_3d():
+    """A NaN or Inf in b is reported as BMG_E_NONFINITE and x is left untouched."""
+    import ctypes as C
+    s, o, _ = _pair(1, 3)
+    n = o.lev[-1].sp.ndof
+    lib = bmg.lib()
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    for bad in (float("nan"), float("inf")):
+        print(f"3-D non-finite right-hand side: {bad}", flush=True)
+        b = torch.ones(n, dtype=torch.float64, device="cuda")
+        b[n // 2] = bad
+        y = torch.full_like(b, 3.0)
+        assert lib.bmg3_solve(s.h, ptr(b), ptr(y), 1e-10, 10, None) == 7
+        torch.cuda.synchronize()
+        assert bool((y == 3.0).all())
