@@ -270,8 +270,9 @@ def main():
                          "size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
+              "splitting problems, right-hand sides or the mesh across GPUs is not implemented.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
