@@ -134,6 +134,28 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+
+def _kappa_host(kappa, n_cells):
+    """kappa as a contiguous FP64 host array.  The library reads exactly n_cells values
+    (the finest mesh's cells) from the pointer it is given, so a shorter array would be
+    read past its end: any other size is refused here.  n_cells is None when the
+    parameters are out of range; the library then rejects the call itself."""
+    kap = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+    if n_cells is not None and kap.size != n_cells:
+        raise ValueError(f"kappa has {kap.size} values; the finest mesh has {n_cells} cells")
+    return kap
+
+
+def _cells2(p):
+    """Cells of the finest 2-D mesh, (n0 2^levels)^2, or None for out-of-range parameters."""
+    return (p.n0 << p.levels) ** 2 if 1 <= p.n0 <= 64 and 0 <= p.levels <= 12 else None
+
+
+def _cells3(p):
+    """Cells of the finest 3-D mesh, (n0 2^(levels-1))^3, or None for out-of-range parameters."""
+    return (p.n0 << (p.levels - 1)) ** 3 if 1 <= p.n0 <= 8 and 1 <= p.levels <= 7 else None
+
+
 class Solver:
     """One problem on the GPU (handle of the C library)."""
 
@@ -144,7 +166,7 @@ class Solver:
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        kap = np.ascontiguousarray(kappa, dtype=np.float64)
+        kap = _kappa_host(kappa, _cells2(params))
         self.stream = torch.cuda.current_stream(self.device)
         ws_ptr, ws_bytes = None, 0
         if workspace == "torch":
@@ -271,8 +293,8 @@ class Batch:
             self.device = torch.device("cuda", torch.cuda.current_device())
         n = len(params_list)
         self.params = list(params_list)
-        self._kap = [np.ascontiguousarray(kp, dtype=np.float64) for kp in kappas]
-        if len(self._kap) != n:
+        self._kap = [_kappa_host(kp, _cells2(pp)) for kp, pp in zip(kappas, self.params)]
+        if len(kappas) != n:
             raise ValueError("one kappa field per problem")
         arr = (Params * n)(*self.params)
         kptr = (_P(_D) * n)(*[kp.ctypes.data_as(_P(_D)) for kp in self._kap])
@@ -368,7 +390,7 @@ def assemble_rhs(params: Params, f, s=None, g=None):
 def autotune(params: Params, kappa, trials=5, device="cuda"):
     """(parameters with the faster colouring, {"S9": ms, "L8": ms} per V-cycle), by bmg_autotune."""
     import torch
-    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    kap = _kappa_host(kappa, _cells2(params))
     stream = torch.cuda.current_stream(torch.device(device))
     best = Params()
     ms = np.zeros(2)
@@ -397,7 +419,7 @@ def export_patch(params: Params, kappa, level, vx, vy, with_inverse=True):
     dofs = np.zeros(cap, np.int32)
     inv = np.zeros(cap * cap) if with_inverse else None
     n, col = C.c_int32(), C.c_int32()
-    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    kap = _kappa_host(kappa, _cells2(params))
     st = _lib.bmg_export_patch(C.byref(params), kap, level, vx, vy, C.byref(n), dofs,
                                inv.ctypes.data_as(C.c_void_p) if inv is not None else None, C.byref(col))
     if st:
@@ -411,7 +433,7 @@ def export_level_matrix(params: Params, kappa, level):
     k = params.k
     n = 2 * N * (N + 1) * (k + 1) + 2 * k * (k + 1) * N * N + (k + 1) ** 2 * N * N
     out = np.zeros(n * n)
-    st = _lib.bmg_export_level_matrix(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64), level, out)
+    st = _lib.bmg_export_level_matrix(C.byref(params), _kappa_host(kappa, _cells2(params)), level, out)
     if st:
         raise BmgError(st, "export_level_matrix")
     return out.reshape(n, n)
@@ -470,7 +492,7 @@ def assemble_rhs3(params: Params3, kappa, f=(0.0, 0.0, 0.0), g=(1.0, 0.0, 0.0)):
     NF = (N + 1) * N * N * nb * nb
     n = 3 * NF + 3 * nb * nb * N ** 3 + nb ** 3 * N ** 3
     out = np.zeros(n)
-    st = _lib.bmg3_assemble_rhs(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64),
+    st = _lib.bmg3_assemble_rhs(C.byref(params), _kappa_host(kappa, _cells3(params)),
                                 np.ascontiguousarray(f, dtype=np.float64), np.ascontiguousarray(g, dtype=np.float64),
                                 out)
     if st:
@@ -490,7 +512,7 @@ class Solver3:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        st = _lib.bmg3_setup(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64),
+        st = _lib.bmg3_setup(C.byref(params), _kappa_host(kappa, _cells3(params)),
                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st:
             raise BmgError(st, f"setup3: {_lib.bmg3_last_error(None).decode()}")
@@ -562,7 +584,7 @@ class Solver3:
 
 def export_level_csr3(params: Params3, kappa, level):
     """(rowptr, colidx, values) of the library's level operator (host assembly)."""
-    kap = np.ascontiguousarray(kappa, dtype=np.float64)
+    kap = _kappa_host(kappa, _cells3(params))
     nnz = C.c_int64()
     st = _lib.bmg3_export_level_csr(C.byref(params), kap, level, C.byref(nnz), None, None, None)
     if st:
@@ -584,7 +606,7 @@ def export_patch_host3(params: Params3, kappa, level, vx, vy, vz):
     n = C.c_int32()
     dofs = np.zeros(208, dtype=np.int32)
     pinv = np.zeros(208 * 208)
-    st = _lib.bmg3_export_patch_host(C.byref(params), np.ascontiguousarray(kappa, dtype=np.float64), level, vx, vy,
+    st = _lib.bmg3_export_patch_host(C.byref(params), _kappa_host(kappa, _cells3(params)), level, vx, vy,
                                      vz, C.byref(n), dofs, pinv.ctypes.data_as(C.c_void_p))
     if st:
         raise BmgError(st, f"export_patch_host3: {_lib.bmg3_last_error(None).decode()}")

@@ -272,3 +272,15 @@ def test_public_headers_compile_as_c_and_cxx():
             r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-x", lang, "-I", inc, os.path.join(inc, name)],
                                capture_output=True, text=True)
             assert r.returncode == 0, (name, lang, r.stderr)
+
+
+def test_kappa_of_the_wrong_size_is_refused_by_the_binding():
+    """The library reads (n0 2^levels)^2 values from kappa; the binding refuses any
+    other size before the call (a short array would be read past its end)."""
+    p = bmg.make_params(2, 2, 1, 1e-2, 6.0, [D, D, O, O])
+    for n in (63, 65, 16):
+        with pytest.raises(ValueError):
+            bmg.export_patch(p, np.ones(n), 1, 1, 1)
+        with pytest.raises(ValueError):
+            bmg.export_level_matrix(p, np.ones(n), 1)
+    bmg.export_patch(p, np.ones((8, 8)), 1, 1, 1)  # any shape with 64 values

@@ -92,3 +92,14 @@ def test_host_exports_reject_bad_arguments():
     nnz = C.c_int64()
     assert lib.bmg3_export_level_csr(C.byref(p), kap, 3, C.byref(nnz), None, None, None) == 1
     assert lib.bmg3_export_level_csr(C.byref(p), kap, 1, C.byref(nnz), None, None, None) == 0 and nnz.value > 0
+
+
+def test_kappa_of_the_wrong_size_is_refused_by_the_binding_3d():
+    p = bmg.make_params3(1, 3, 1e-2)
+    for n in (63, 65, 8):
+        with pytest.raises(ValueError):
+            bmg.export_patch_host3(p, np.ones(n), 2, 1, 1, 1)
+        with pytest.raises(ValueError):
+            bmg.assemble_rhs3(p, np.ones(n))
+        with pytest.raises(ValueError):
+            bmg.export_level_csr3(p, np.ones(n), 1)
