@@ -366,15 +366,23 @@ def quad_points(params: Params):
 def assemble_rhs(params: Params, f, s=None, g=None):
     """b (numpy, host) from callables f(x, y) -> (..., 2), s(x, y), g(x, y) -> (..., 2)."""
     cell, face = quad_points(params)
-    fq = np.ascontiguousarray(f(cell[:, 0], cell[:, 1]), dtype=np.float64).reshape(-1)
+
+    def values(fn, pts, per_point, what):
+        # the library reads exactly per_point values per quadrature point
+        v = np.ascontiguousarray(fn(pts[:, 0], pts[:, 1]), dtype=np.float64).reshape(-1)
+        if v.size != per_point * pts.shape[0]:
+            raise ValueError(f"{what} gave {v.size} values for {pts.shape[0]} points ({per_point} per point expected)")
+        return v
+
+    fq = values(f, cell, 2, "f")
     keep = []
     sp = gp = None
     if s is not None:
-        sq = np.ascontiguousarray(s(cell[:, 0], cell[:, 1]), dtype=np.float64).reshape(-1)
+        sq = values(s, cell, 1, "s")
         keep.append(sq)
         sp = sq.ctypes.data_as(C.c_void_p)
     if g is not None:
-        gq = np.ascontiguousarray(g(face[:, 0], face[:, 1]), dtype=np.float64).reshape(-1)
+        gq = values(g, face, 2, "g")
         keep.append(gq)
         gp = gq.ctypes.data_as(C.c_void_p)
     N = params.n0 << params.levels

@@ -284,3 +284,16 @@ def test_kappa_of_the_wrong_size_is_refused_by_the_binding():
         with pytest.raises(ValueError):
             bmg.export_level_matrix(p, np.ones(n), 1)
     bmg.export_patch(p, np.ones((8, 8)), 1, 1, 1)  # any shape with 64 values
+
+
+def test_rhs_callables_of_the_wrong_size_are_refused():
+    p = bmg.make_params(2, 1, 1, 1e-2, 6.0, [D, D, O, O])
+    with pytest.raises(ValueError):
+        bmg.assemble_rhs(p, lambda x, y: x)  # one component instead of two
+    with pytest.raises(ValueError):
+        bmg.assemble_rhs(p, lambda x, y: np.stack([x, y], -1), s=lambda x, y: np.stack([x, y], -1))
+    with pytest.raises(ValueError):
+        bmg.assemble_rhs(p, lambda x, y: np.stack([x, y], -1), g=lambda x, y: x)
+    b = bmg.assemble_rhs(p, lambda x, y: np.stack([x, y], -1), s=lambda x, y: x * y,
+                         g=lambda x, y: np.stack([0 * x, 0 * y], -1))
+    assert np.isfinite(b).all()
