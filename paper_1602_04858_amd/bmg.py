@@ -500,9 +500,11 @@ def assemble_rhs3(params: Params3, kappa, f=(0.0, 0.0, 0.0), g=(1.0, 0.0, 0.0)):
     NF = (N + 1) * N * N * nb * nb
     n = 3 * NF + 3 * nb * nb * N ** 3 + nb ** 3 * N ** 3
     out = np.zeros(n)
-    st = _lib.bmg3_assemble_rhs(C.byref(params), _kappa_host(kappa, _cells3(params)),
-                                np.ascontiguousarray(f, dtype=np.float64), np.ascontiguousarray(g, dtype=np.float64),
-                                out)
+    fv = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    gv = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+    if fv.size != 3 or gv.size != 3:
+        raise ValueError("f and g are constant 3-vectors")
+    st = _lib.bmg3_assemble_rhs(C.byref(params), _kappa_host(kappa, _cells3(params)), fv, gv, out)
     if st:
         raise BmgError(st, f"assemble_rhs3: {_lib.bmg3_last_error(None).decode()}")
     return out

@@ -103,3 +103,5 @@ def test_kappa_of_the_wrong_size_is_refused_by_the_binding_3d():
             bmg.assemble_rhs3(p, np.ones(n))
         with pytest.raises(ValueError):
             bmg.export_level_csr3(p, np.ones(n), 1)
+    with pytest.raises(ValueError):
+        bmg.assemble_rhs3(p, np.ones(64), (1.0, 0.0), (0.0, 0.0, 0.0))
