@@ -125,6 +125,9 @@ bmg_status bmg_plan(const bmg_params* p, size_t* workspace_bytes);
  *   out:        receives the handle. */
 bmg_status bmg_setup(const bmg_params* p, const double* kappa_host, void* workspace_dev, size_t bytes,
                      void* hip_stream, bmg_handle* out);
+/* Wait for the handle's stream, release its events, graph and capture stream, free
+ * the workspace if the library allocated it (a caller-supplied workspace stays the
+ * caller's), and delete the handle.  BMG_E_ARG for NULL. */
 bmg_status bmg_destroy(bmg_handle h);
 
 /* Sizes of level j (0 = coarsest, levels = finest). */
@@ -180,7 +183,10 @@ bmg_status bmg_batch_solve(bmg_batch_handle b, const double* const* b_dev, doubl
 /* The handle of problem i (sizes, single V-cycles, step entry points).  Owned by
  * the batch: do not destroy it, and do not use it while a batch call runs. */
 bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out);
+/* Message of the last failing batch call (naming the problem). */
 const char* bmg_batch_last_error(bmg_batch_handle b);
+/* Wait for the worker streams, then free every problem's handle and workspace, the
+ * worker streams and the batch.  BMG_E_ARG for NULL. */
 bmg_status bmg_batch_destroy(bmg_batch_handle b);
 
 /* ----- autotuning ----- */

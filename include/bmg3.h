@@ -71,6 +71,7 @@ typedef struct {
  * BMG_E_ARG on invalid parameters or kappa, BMG_E_NOMEM / BMG_E_HIP on device errors,
  * BMG_E_SINGULAR if a patch or the coarse matrix cannot be inverted. */
 bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_stream, bmg3_handle* out);
+/* Wait for the handle's stream, free its device memory and delete it.  BMG_E_ARG for NULL. */
 bmg_status bmg3_destroy(bmg3_handle h);
 
 /* Sizes of level `level` (0 = coarsest .. levels-1): cells per side, velocity and
