@@ -659,3 +659,121 @@ def test_rt0_patch_sizes_and_level_independent_iterations():
         assert tr < 1e-9
         its.append(it)
     assert its[-1] <= its[0] and its[1] <= its[0] + 1, its
+
+
+# --------------------------------------------------------------------------
+# V-cycle schedule (Section 3.2): B_J rebuilt in numpy from the oracle's level
+# operators, patch pseudo-inverses, prolongations and coarse inverse, with the
+# variable cycle's m(j) = m_J 2^(J-j) written here; the oracle's cycle must equal it,
+# and the standard cycle (m(j) = m_J) and the reversed exponent must not.
+# --------------------------------------------------------------------------
+def _numpy_vcycle(o, r, m_of):
+    """The recursion of Section 3.2 on the oracle's exported pieces: x = 0, m(j)
+    symmetric smoothing steps (patch projections colour 0..C-1 then C-2..0), the
+    coarse-grid correction x += P_j B_{j-1} P_j^T (b - A_j x), m(j) smoothing steps;
+    B_0 = the coarse inverse; identity rows of essential dofs inverted exactly."""
+    J = o.J
+    A = [o.csr(j).tocsr() for j in range(J + 1)]
+    P = [None] + [o.prolongation(j).tocsr() for j in range(1, J + 1)]
+    cons = [o.constrained(j) for j in range(J + 1)]
+    n0 = o.ndof(0)
+    B0 = np.column_stack([o.coarse_solve(np.eye(n0)[:, i]) for i in range(n0)])
+    patches = []
+    for j in range(J + 1):
+        byc = {}
+        if j > 0:
+            for p in range(o.npatch(j)):
+                _, _, col, dofs, _, inv = o.patch(p, j)
+                byc.setdefault(col, []).append((dofs, inv))
+        patches.append(byc)
+
+    def smooth(j, x, b):
+        C = max(patches[j]) + 1
+        for col in list(range(C)) + list(range(C - 2, -1, -1)):
+            for dofs, inv in patches[j].get(col, []):
+                rl = b[dofs] - A[j][dofs] @ x
+                x[dofs] += inv @ rl
+
+    def vc(j, b):
+        if j == 0:
+            return B0 @ b
+        x = np.zeros(A[j].shape[0])
+        for _ in range(m_of(j)):
+            smooth(j, x, b)
+        x += P[j] @ vc(j - 1, P[j].T @ (b - A[j] @ x))
+        for _ in range(m_of(j)):
+            smooth(j, x, b)
+        x[cons[j]] = b[cons[j]]
+        return x
+
+    return vc(J, np.asarray(r, dtype=float))
+
+
+@pytest.mark.parametrize("J,bc", [(2, [D, D, O, O]), (3, [D, D, O, O]), (2, [O, D, D, O])])
+def test_variable_cycle_schedule(J, bc):
+    n0, k, mJ = 2, 1, 2
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 11 + J, 1e-4, 1.0)
+    o = Oracle(n0, J, k, 1e-2, 6.0, bc, kap, 1, mJ)
+    rng = np.random.default_rng(J)
+    variable = lambda j: mJ * 2 ** (J - j)
+    for _ in range(2):
+        r = rng.standard_normal(o.ndof())
+        z = o.vcycle(r)
+        zn = _numpy_vcycle(o, r, variable)
+        assert np.abs(z - zn).max() <= 1e-12 * np.abs(zn).max()
+        # the pin discriminates: other schedules give other operators
+        for wrong in (lambda j: mJ, lambda j: mJ * 2 ** j, lambda j: mJ * 2 ** (J - j + 1)):
+            zw = _numpy_vcycle(o, r, wrong)
+            assert np.abs(z - zw).max() > 1e-6 * np.abs(zn).max()
+    # and the standard cycle of the oracle is the constant schedule
+    os_ = Oracle(n0, J, k, 1e-2, 6.0, bc, kap, 0, mJ)
+    r = rng.standard_normal(o.ndof())
+    zs = _numpy_vcycle(os_, r, lambda j: mJ)
+    assert np.abs(os_.vcycle(r) - zs).max() <= 1e-12 * np.abs(zs).max()
+
+
+# --------------------------------------------------------------------------
+# P4 (second part): the pressure rows of the right-hand side hold -(s, q) for a
+# divergence source s, so the exact discrete solution satisfies div u_h = Pi_Q s
+# (eq. Brinkman-weak: -(q, div u) = -(s, q) for every q in Q_h, and div RT_k is in
+# dQ_k).  Pi_Q s is computed here by an independent 8-point Gauss projection onto
+# the orthonormal Legendre products; div u_h by numpy evaluation of the basis.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k,mu,bc,src", [
+    (1, 1e-2, [D, D, O, O], "open"),
+    (2, 1.0, [D, D, O, O], "open"),
+    (1, 0.0, [D, D, O, O], "open"),
+    (1, 1e-2, [D, D, D, D], "mean0"),
+    (0, 1e-2, [O, D, O, D], "open"),
+])
+def test_divergence_source_is_reproduced(k, mu, bc, src):
+    n0, J = 2, 2
+    n = n0 << J
+    kap = inputs.kappa_random_cells(n, 7, 1e-3, 1.0)
+    o = Oracle(n0, J, k, mu, (k + 1) * (k + 2), bc, kap, 1, 2)
+    if src == "mean0":   # all sides Dirichlet: the source must have zero mean
+        s = lambda x, y: (x - 0.5) ** 3 + 2.0 * (y - 0.5) * x * x - (y - 0.5) / 3.0 + 0.7 * (x - 0.5) * (y - 0.5) ** 2
+    else:
+        s = lambda x, y: x ** 3 * y ** 2 + 2 * x * y - 0.3 * y ** 3 + 0.25
+    f = lambda x, y: np.stack([np.sin(np.pi * y), x * y], axis=-1)
+    b = o.rhs(f, s=s)
+    x = o.direct_solve(b)
+    sp = Space(n, k)
+    # Pi_Q s per cell, orthonormal Legendre products on the reference cell
+    t, wq = npl.leggauss(8)
+    t, wq = 0.5 * (t + 1), 0.5 * wq
+    rng = np.random.default_rng(3)
+    worst, scale = 0.0, 0.0
+    for c in rng.choice(n * n, 12, replace=False):
+        cx, cy = c % n, c // n
+        X, Y = np.meshgrid((cx + t) / n, (cy + t) / n, indexing="ij")
+        W = np.outer(wq, wq)
+        TX, TY = np.meshgrid(t, t, indexing="ij")
+        coef = {(a, bb): np.sum(W * s(X, Y) * L(a, TX) * L(bb, TY)) for a in range(k + 1) for bb in range(k + 1)}
+        xi, eta = rng.random(6), rng.random(6)
+        proj = sum(coef[(a, bb)] * L(a, xi) * L(bb, eta) for a in range(k + 1) for bb in range(k + 1))
+        _, _, div, _ = sp.evaluate(x, (cx + xi) / n, (cy + eta) / n)
+        worst = max(worst, np.abs(div - proj).max())
+        scale = max(scale, np.abs(proj).max())
+    assert worst <= 1e-10 * scale
