@@ -72,7 +72,9 @@ enum { BMG_COLOURING_S9 = 0,  /* 9 colours, (vx mod 3) + 3 (vy mod 3); a smoothi
 };
 
 typedef struct {
-  int32_t n0;            /* cells per side of the coarsest mesh T_0, 2 <= n0 <= 64 */
+  int32_t n0;            /* cells per side of the coarsest mesh T_0, 2 <= n0 <= 64, and the coarsest
+                            level has at most 4096 unknowns (its dense inverse is formed at setup):
+                            n0 <= 36 (RT_0), 18 (RT_1), 12 (RT_2); BMG_E_UNSUPPORTED above that */
   int32_t levels;        /* J >= 0 refinements; finest N = n0 << levels <= 4096 */
   int32_t k;             /* Raviart-Thomas degree, 0, 1 or 2 (RT_k x dQ_k; Section 2) */
   double mu;             /* viscosity, >= 0 (0 = Darcy) */

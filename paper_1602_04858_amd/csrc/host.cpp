@@ -4,8 +4,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <new>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -110,6 +113,7 @@ int64_t n_u_of(int N, int k) { return 2LL * N * (N + 1) * (k + 1) + 2LL * k * (k
 int64_t n_p_of(int N, int k) { return (int64_t)(k + 1) * (k + 1) * N * N; }
 
 constexpr int kMaxRhs = 16;
+constexpr int64_t kMaxCoarseDof = 4096;
 
 
 
@@ -117,6 +121,9 @@ bmg_status check_params(const bmg_params* p) {
   if (!p) return BMG_E_ARG;
   if (p->k < 0 || p->k > 2) return BMG_E_UNSUPPORTED;
   if (p->n0 < 2 || p->n0 > 64 || p->levels < 0 || p->levels > 12) return BMG_E_ARG;
+  // the coarse solve keeps A_0's dense inverse (host Gauss-Jordan at setup, the
+  // right-hand side staged in LDS when applied): at most kMaxCoarseDof unknowns
+  if (n_u_of(p->n0, p->k) + n_p_of(p->n0, p->k) > kMaxCoarseDof) return BMG_E_UNSUPPORTED;
   if ((int64_t)p->n0 << p->levels > 4096) return BMG_E_ARG;
   if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
   for (int s = 0; s < 4; ++s)
@@ -422,6 +429,8 @@ bool patch_pinv(const HostIdx& I, const PatchLayout& P, const std::vector<double
   return true;
 }
 
+// f(i) for i < n on the host threads; an exception thrown by f (a failed host
+// allocation) stops the loop and is rethrown to the caller after the join.
 template <typename F>
 void parallel_for(int n, F&& f) {
   unsigned nt = std::thread::hardware_concurrency();
@@ -429,16 +438,25 @@ void parallel_for(int n, F&& f) {
   if (nt > 32) nt = 32;
   if ((int)nt > n) nt = std::max(1, n);
   std::atomic<int> next{0};
+  std::exception_ptr first;
+  std::mutex mu;
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nt; ++t)
     th.emplace_back([&]() {
       for (;;) {
         const int i = next.fetch_add(1);
         if (i >= n) break;
-        f(i);
+        try {
+          f(i);
+        } catch (...) {
+          std::lock_guard<std::mutex> g(mu);
+          if (!first) first = std::current_exception();
+          next.store(n);
+        }
       }
     });
   for (auto& t : th) t.join();
+  if (first) std::rethrow_exception(first);
 }
 
 // --------------------------------------------------------------------------
@@ -1075,6 +1093,9 @@ bmg_status check_finite_host(const double* v, size_t n) {
   return BMG_OK;
 }
 
+bmg_status setup_into(bmg_ctx* c, const bmg_params* p, const double* kappa, void* workspace, size_t bytes,
+                      void* stream, bmg_handle* out);
+
 }  // namespace
 
 // ===========================================================================
@@ -1099,7 +1120,7 @@ const char* bmg_status_string(bmg_status s) {
 
 const char* bmg_last_error(bmg_handle h) { return h ? h->err.c_str() : g_setup_err.c_str(); }
 
-bmg_status bmg_plan(const bmg_params* p, size_t* bytes) {
+bmg_status bmg_plan(const bmg_params* p, size_t* bytes) try {
   bmg_status s = check_params(p);
   if (s) return s;
   if (!bytes) return BMG_E_ARG;
@@ -1110,15 +1131,41 @@ bmg_status bmg_plan(const bmg_params* p, size_t* bytes) {
   if (tmp.layout_mismatch) return BMG_E_STATE;
   *bytes = layout(&tmp, nullptr);
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, size_t bytes, void* stream,
-                     bmg_handle* out) {
+                     bmg_handle* out) try {
   bmg_status s = check_params(p);
   if (s) return s;
   if (!out) return BMG_E_ARG;
   if ((s = check_kappa(p, kappa))) return s;
   bmg_ctx* c = new bmg_ctx();
+  // a host allocation that fails inside setup frees what the handle holds
+  try {
+    return setup_into(c, p, kappa, workspace, bytes, stream, out);
+  } catch (const std::bad_alloc&) {
+    g_setup_err = "host memory exhausted during setup";
+    if (c->own_ws) (void)hipFree(c->ws);
+    delete c;
+    return BMG_E_NOMEM;
+  }
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
+}
+
+}  // extern "C"
+
+namespace {
+// The body of bmg_setup after argument validation; c is freed here on every
+// failure it reports.
+bmg_status setup_into(bmg_ctx* c, const bmg_params* p, const double* kappa, void* workspace, size_t bytes,
+                      void* stream, bmg_handle* out) {
   c->p = *p;
   c->stream = (hipStream_t)stream;
   setup_types(c);
@@ -1126,15 +1173,15 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   const size_t need = layout(c, nullptr);
   if (workspace) {
     if (bytes < need || ((uintptr_t)workspace % kAlign) != 0) {
-      delete c;
       g_setup_err = "workspace smaller than bmg_plan's size or not 256-byte aligned";
+      delete c;
       return BMG_E_NOMEM;
     }
     c->ws = (char*)workspace;
   } else {
     if (hipMalloc((void**)&c->ws, need) != hipSuccess) {
-      delete c;
       g_setup_err = "hipMalloc of the " + std::to_string(need >> 20) + " MiB workspace failed";
+      delete c;
       return BMG_E_NOMEM;
     }
     c->own_ws = true;
@@ -1168,8 +1215,11 @@ bmg_status bmg_setup(const bmg_params* p, const double* kappa, void* workspace, 
   *out = c;
   return BMG_OK;
 }
+}  // namespace
 
-bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) {
+extern "C" {
+
+bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) try {
   if (!h || level < -1 || level >= (int)h->lev.size() || level == 0 || max_launches < 0 || max_launches > 1 << 20)
     return BMG_E_ARG;
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1183,9 +1233,13 @@ bmg_status bmg_kernel_timing(bmg_handle h, int32_t level, int32_t max_launches) 
   h->ev.resize((size_t)2 * ((max_launches + 14) / 15));
   for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes) {
+bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total_ms, double* bytes) try {
   if (!h || !launches || !total_ms || !bytes) return BMG_E_ARG;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   double ms = 0.0;
@@ -1198,9 +1252,13 @@ bmg_status bmg_kernel_timing_read(bmg_handle h, int32_t* launches, double* total
   *total_ms = ms;
   *bytes = h->timed_bytes;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_destroy(bmg_handle h) {
+bmg_status bmg_destroy(bmg_handle h) try {
   if (!h) return BMG_E_ARG;
   (void)hipStreamSynchronize(h->stream);
   for (auto e : h->ev) (void)hipEventDestroy(e);
@@ -1213,32 +1271,48 @@ bmg_status bmg_destroy(bmg_handle h) {
   }
   delete h;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_sizes(bmg_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p) {
+bmg_status bmg_sizes(bmg_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p) try {
   if (!h || level < 0 || level >= (int)h->lev.size()) return BMG_E_ARG;
   if (N) *N = h->lev[level].N;
   if (n_u) *n_u = h->lev[level].n_u;
   if (n_p) *n_p = h->lev[level].n_p;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x, double* y) {
+bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x, double* y) try {
   if (!h || !x || !y || level < 0 || level >= (int)h->lev.size()) return BMG_E_ARG;
   apply_op64(h, level, x, y);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) {
+bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) try {
   if (!h || !r || !z) return BMG_E_ARG;
   apply_precond(h, r, z);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 // Step entry points: FP64 vectors in/out, run in the handle's arithmetic.
-bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x, const double* b) {
+bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* x, const double* b) try {
   if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || colour < 0 ||
       colour >= colour_count(h->p.colouring))
     return BMG_E_ARG;
@@ -1252,9 +1326,13 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, const double* b) {
+bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, const double* b) try {
   if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || steps < 0) return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
   const int64_t nt = L.ndof * h->R;
@@ -1264,9 +1342,13 @@ bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, con
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* bc) {
+bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* bc) try {
   if (!h || !rf || !bc || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
@@ -1275,9 +1357,13 @@ bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* b
   launch_cast(0, h->prec, C.b, bc, C.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double* xf) {
+bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double* xf) try {
   if (!h || !xc || !xf || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
@@ -1287,9 +1373,13 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
   launch_cast(0, h->prec, F.x, xf, F.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) {
+bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) try {
   if (!h || !b || !x) return BMG_E_ARG;
   LevelInfo& L = h->lev[0];
   launch_cast(h->prec, 0, b, L.b, L.ndof * h->R, h->stream);
@@ -1297,10 +1387,14 @@ bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) {
   launch_cast(0, h->prec, L.x, x, L.ndof * h->R, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int32_t maxit, const double* x0,
-                     bmg_solve_info* info) {
+                     bmg_solve_info* info) try {
   if (!h || !b || !x || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
   const int J = (int)h->lev.size() - 1;
   const int R = h->R;
@@ -1491,9 +1585,13 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
   return all ? BMG_OK
              : fail(h, BMG_E_NOT_CONVERGED,
                     stalled ? "true residual stagnates above rtol (attainable accuracy reached)" : "maxit reached");
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy) {
+bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if (!cell_xy || !face_xy) return BMG_E_ARG;
@@ -1523,10 +1621,14 @@ bmg_status bmg_quad_points(const bmg_params* p, double* cell_xy, double* face_xy
         }
       }
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg_assemble_rhs(const bmg_params* p, const double* f_qp, const double* s_qp, const double* g_qp,
-                            double* b) {
+                            double* b) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if (!f_qp || !b) return BMG_E_ARG;
@@ -1611,10 +1713,14 @@ bmg_status bmg_assemble_rhs(const bmg_params* p, const double* f_qp, const doubl
         if (I.cons(cx, cy, d)) out[I.g(cx, cy, d)] = 0.0;
   std::copy(out.begin(), out.end(), b);
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t level, int32_t vx, int32_t vy,
-                            int32_t* n, int32_t* dofs, double* inv, int32_t* colour) {
+                            int32_t* n, int32_t* dofs, double* inv, int32_t* colour) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if ((st = check_kappa(p, kappa))) return st;
@@ -1644,9 +1750,13 @@ bmg_status bmg_export_patch(const bmg_params* p, const double* kappa, int32_t le
       for (size_t j = 0; j < m; ++j) inv[i * m + j] = pinv[(size_t)idx[i] * P.ns + idx[j]];
   }
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_export_colouring(const bmg_params* p, int32_t level, int32_t* ncolours, int32_t* colour_host) {
+bmg_status bmg_export_colouring(const bmg_params* p, int32_t level, int32_t* ncolours, int32_t* colour_host) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if (level < 1 || level > p->levels) return BMG_E_ARG;
@@ -1656,9 +1766,13 @@ bmg_status bmg_export_colouring(const bmg_params* p, int32_t level, int32_t* nco
     for (int vy = 0; vy <= N; ++vy)
       for (int vx = 0; vx <= N; ++vx) colour_host[vy * (N + 1) + vx] = colour_of(p->colouring, vx, vy);
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int32_t level, double* out) {
+bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int32_t level, double* out) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if ((st = check_kappa(p, kappa))) return st;
@@ -1669,6 +1783,10 @@ bmg_status bmg_export_level_matrix(const bmg_params* p, const double* kappa, int
   std::vector<double> A = dense_level(R, p->k, bc_mask(*p), N, kappa_level(kappa, p->n0, p->levels, level, p->coarse_kappa));
   std::copy(A.begin(), A.end(), out);
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 
@@ -1685,7 +1803,7 @@ static void batch_free(bmg_batch* b) {
 }
 
 bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double* const* kappa_host,
-                           int32_t nstreams, void* hip_stream, bmg_batch_handle* out) {
+                           int32_t nstreams, void* hip_stream, bmg_batch_handle* out) try {
   if (!out || !params || !kappa_host || nprob < 1 || nprob > 4096 || nstreams < 0 || nstreams > 16)
     return BMG_E_ARG;
   for (int i = 0; i < nprob; ++i) {
@@ -1723,16 +1841,24 @@ bmg_status bmg_batch_setup(int32_t nprob, const bmg_params* params, const double
   }
   *out = b;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out) {
+bmg_status bmg_batch_handle_of(bmg_batch_handle b, int32_t i, bmg_handle* out) try {
   if (!b || !out || i < 0 || i >= (int)b->h.size()) return BMG_E_ARG;
   *out = b->h[i];
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg_batch_solve(bmg_batch_handle b, const double* const* b_dev, double* const* x_dev, double rtol,
-                           int32_t maxit, bmg_solve_info* info) {
+                           int32_t maxit, bmg_solve_info* info) try {
   if (!b || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
   const int n = (int)b->h.size(), S = (int)b->streams.size();
   std::vector<int64_t> info_off(n + 1, 0);
@@ -1770,21 +1896,29 @@ bmg_status bmg_batch_solve(bmg_batch_handle b, const double* const* b_dev, doubl
   if (pick < 0) return BMG_OK;
   b->err = "problem " + std::to_string(pick) + ": " + b->h[pick]->err;
   return st[pick];
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 const char* bmg_batch_last_error(bmg_batch_handle b) { return b ? b->err.c_str() : "null batch"; }
 
-bmg_status bmg_batch_destroy(bmg_batch_handle b) {
+bmg_status bmg_batch_destroy(bmg_batch_handle b) try {
   if (!b) return BMG_E_ARG;
   for (auto s : b->streams) (void)hipStreamSynchronize(s);
   batch_free(b);
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 
 // ----- autotuning of the smoother schedule -----
 bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
-                        bmg_params* best, double* ms_per_vcycle) {
+                        bmg_params* best, double* ms_per_vcycle) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if (!best || trials < 1 || trials > 1000) return BMG_E_ARG;
@@ -1829,6 +1963,10 @@ bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip
     }
   }
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 }  // extern "C"

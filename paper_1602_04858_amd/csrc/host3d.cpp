@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <new>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -850,7 +851,7 @@ bool sync_ok(bmg3_ctx* c) { return hipStreamSynchronize(c->s) == hipSuccess; }
 
 extern "C" {
 
-bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_stream, bmg3_handle* out) {
+bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_stream, bmg3_handle* out) try {
   if (!out) return fail3(nullptr, BMG_E_ARG, "out is NULL");
   *out = nullptr;
   bmg_status st = check3(p);
@@ -920,18 +921,26 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
     return bail(BMG_E_HIP, "hipMemcpy failed");
   *out = c;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg3_destroy(bmg3_handle h) {
+bmg_status bmg3_destroy(bmg3_handle h) try {
   if (!h) return BMG_E_ARG;
   if (h->s) (void)hipStreamSynchronize(h->s);
   else (void)hipDeviceSynchronize();
   for (void* q : h->allocs) (void)hipFree(q);
   delete h;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg3_sizes(bmg3_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p, int64_t* npatch) {
+bmg_status bmg3_sizes(bmg3_handle h, int32_t level, int32_t* N, int64_t* n_u, int64_t* n_p, int64_t* npatch) try {
   if (!h || level < 0 || level >= (int)h->lev.size()) return BMG_E_ARG;
   const Level3& L = h->lev[level];
   if (N) *N = L.S.N;
@@ -939,10 +948,14 @@ bmg_status bmg3_sizes(bmg3_handle h, int32_t level, int32_t* N, int64_t* n_u, in
   if (n_p) *n_p = L.S.n_p;
   if (npatch) *npatch = level ? L.npatch : 0;
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg3_assemble_rhs(const bmg3_params* p, const double* kappa_host, const double* f, const double* g,
-                             double* b_host) {
+                             double* b_host) try {
   bmg_status st = check3(p);
   if (st) return fail3(nullptr, st, "invalid parameters");
   if (!kappa_host || !f || !g || !b_host) return fail3(nullptr, BMG_E_ARG, "NULL argument");
@@ -952,29 +965,45 @@ bmg_status bmg3_assemble_rhs(const bmg3_params* p, const double* kappa_host, con
   std::vector<double> b = rhs3(S, p->mu, p->sigma, kap, f, g);
   std::memcpy(b_host, b.data(), b.size() * sizeof(double));
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg3_apply(bmg3_handle h, int32_t level, const double* x_dev, double* y_dev) {
+bmg_status bmg3_apply(bmg3_handle h, int32_t level, const double* x_dev, double* y_dev) try {
   if (!h || level < 0 || level >= (int)h->lev.size() || !x_dev || !y_dev) return BMG_E_ARG;
   const Level3& L = h->lev[level];
   launch3_csr(0, L.S.ndof, L.A.rp, L.A.ci, L.A.v, x_dev, nullptr, y_dev, h->s);
   return hipGetLastError() == hipSuccess ? BMG_OK : fail3(h, BMG_E_HIP, "launch failed");
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg3_smooth(bmg3_handle h, int32_t level, int32_t steps, double* x_dev, const double* b_dev) {
+bmg_status bmg3_smooth(bmg3_handle h, int32_t level, int32_t steps, double* x_dev, const double* b_dev) try {
   if (!h || level < 1 || level >= (int)h->lev.size() || steps < 0 || !x_dev || !b_dev) return BMG_E_ARG;
   for (int k = 0; k < steps; ++k) smooth_step3(h, h->lev[level], x_dev, b_dev);
   return hipGetLastError() == hipSuccess ? BMG_OK : fail3(h, BMG_E_HIP, "launch failed");
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
-bmg_status bmg3_vcycle(bmg3_handle h, const double* r_dev, double* z_dev) {
+bmg_status bmg3_vcycle(bmg3_handle h, const double* r_dev, double* z_dev) try {
   if (!h || !r_dev || !z_dev) return BMG_E_ARG;
   vcycle3(h, (int)h->lev.size() - 1, r_dev, z_dev);
   return hipGetLastError() == hipSuccess ? BMG_OK : fail3(h, BMG_E_HIP, "launch failed");
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
-                      bmg_solve_info* info) {
+                      bmg_solve_info* info) try {
   if (!h || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) return BMG_E_ARG;
   Level3& L = h->lev.back();
   const int64_t n = L.S.ndof;
@@ -1066,10 +1095,14 @@ bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double 
   if (tr <= rtol * bn) conv = true;
   if (info) *info = bmg_solve_info{its, conv ? 1 : 0, est, tr / bn};
   return conv ? BMG_OK : fail3(h, BMG_E_NOT_CONVERGED, "not converged");
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg3_export_patch(bmg3_handle h, int32_t level, int32_t vx, int32_t vy, int32_t vz, int32_t* n,
-                             int32_t* dofs_host, double* pinv_host) {
+                             int32_t* dofs_host, double* pinv_host) try {
   if (!h || level < 1 || level >= (int)h->lev.size() || !n || !dofs_host) return BMG_E_ARG;
   const Level3& L = h->lev[level];
   const int nv = L.S.N + 1;
@@ -1094,10 +1127,14 @@ bmg_status bmg3_export_patch(bmg3_handle h, int32_t level, int32_t vx, int32_t v
     unrotate_sym3((int)cnt, tmp.data(), pinv_host);
   }
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg3_export_level_csr(const bmg3_params* p, const double* kappa_host, int32_t level, int64_t* nnz,
-                                 int32_t* rp_host, int32_t* ci_host, double* v_host) {
+                                 int32_t* rp_host, int32_t* ci_host, double* v_host) try {
   bmg_status st = check3(p);
   if (st) return fail3(nullptr, st, "invalid parameters");
   if (!kappa_host || !nnz || level < 0 || level >= p->levels) return fail3(nullptr, BMG_E_ARG, "bad argument");
@@ -1114,10 +1151,14 @@ bmg_status bmg3_export_level_csr(const bmg3_params* p, const double* kappa_host,
   std::memcpy(ci_host, A.ci.data(), A.ci.size() * sizeof(int32_t));
   std::memcpy(v_host, A.v.data(), A.v.size() * sizeof(double));
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 bmg_status bmg3_export_patch_host(const bmg3_params* p, const double* kappa_host, int32_t level, int32_t vx,
-                                  int32_t vy, int32_t vz, int32_t* n, int32_t* dofs_host, double* pinv_host) {
+                                  int32_t vy, int32_t vz, int32_t* n, int32_t* dofs_host, double* pinv_host) try {
   bmg_status st = check3(p);
   if (st) return fail3(nullptr, st, "invalid parameters");
   if (!kappa_host || !n || !dofs_host || level < 1 || level >= p->levels) return fail3(nullptr, BMG_E_ARG, "bad argument");
@@ -1134,6 +1175,10 @@ bmg_status bmg3_export_patch_host(const bmg3_params* p, const double* kappa_host
   for (size_t t = 0; t < D.size(); ++t) dofs_host[t] = (int32_t)D[t];
   if (pinv_host && !patch_pinv3(S, A, D, cells, pinv_host)) return fail3(nullptr, BMG_E_SINGULAR, "singular patch");
   return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
 }
 
 const char* bmg3_last_error(bmg3_handle h) { return h ? h->err.c_str() : g_err3.c_str(); }

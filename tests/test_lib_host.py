@@ -43,7 +43,10 @@ def test_status_strings():
     (dict(sigma=0.0), 1), (dict(m_fine=0), 1), (dict(restart=0), 1), (dict(cycle=5), 1),
     (dict(n0=2, levels=12), 1), (dict(prec=7), 1), (dict(dense=-1), 1), (dict(dense=70000), 1),
     (dict(n_rhs=-1), 1), (dict(n_rhs=17), 1), (dict(smoother=2), 1), (dict(smoother=1, omega=0.0), 1),
-    (dict(smoother=1, omega=1.5), 1), (dict(colouring=3), 1), (dict(coarse_kappa=3), 1)])
+    (dict(smoother=1, omega=1.5), 1), (dict(colouring=3), 1), (dict(coarse_kappa=3), 1),
+    # coarsest level above 4096 unknowns: its dense inverse is not formed (n0 = 64 would need
+    # a 98 GB host matrix for RT_2)
+    (dict(n0=19, levels=0), 2), (dict(n0=64, levels=0, k=2), 2), (dict(n0=13, levels=1, k=2), 2)])
 def test_parameter_validation(change, expect):
     args = dict(n0=2, levels=2, k=1, mu=1.0, sigma=6.0, bc=[D, D, O, O], prec=0)
     args.update(change)
@@ -68,6 +71,12 @@ def test_smoother_layout_rule_matches_patch_construction(n0):
         for J in (1, 2, 3):
             bmg.plan(bmg.make_params(n0, J, 1, 1e-2, 6.0, bc, restart=4))
             bmg.plan(bmg.make_params(n0, J, 2, 1e-2, 12.0, bc, restart=4))
+
+
+@pytest.mark.parametrize("n0,k", [(18, 1), (12, 2), (36, 0)])
+def test_largest_supported_coarse_mesh(n0, k):
+    """The largest coarsest meshes within the 4096-unknown limit are accepted."""
+    assert bmg.plan(bmg.make_params(n0, 0, k, 1e-2, (k + 1) * (k + 2), [D, D, O, O], restart=4)) > 0
 
 
 def test_plan_grows_with_levels():
