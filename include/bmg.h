@@ -143,6 +143,21 @@ bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x_dev, double* y
  * FP64 in and out, canonical layout of the finest level, n_rhs columns. */
 bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): z = B_J r as bmg_vcycle, with
+ * the same kernels launched one by one on the handle's stream (no graph), and the
+ * level vectors of the cycle (x_j, b_j, r_j of every level, n_rhs columns) kept
+ * in a static device array of 256 MiB instead of the handle's workspace.  The
+ * array exists once per device, from the library's load until the process ends,
+ * and is shared by every handle on that device: calls that overlap on one device
+ * (other streams, other threads) race on it.  Every level vector is written
+ * before it is read, so nothing from an earlier call is used.  The call itself
+ * allocates nothing (no hipMalloc, hipFree or graph); the first call on a device
+ * looks up the array's device address (hipGetSymbolAddress).  BMG_E_NOMEM (with a
+ * message) if 3 * sum_j ndof_j * n_rhs * (8 for BMG_P_FP64, else 4) bytes exceed
+ * 256 MiB. */
+bmg_status bmg_vcycle_noalloc(bmg_handle h, const double* r_dev, double* z_dev);
+
 /* Solve A_J x = b by right-preconditioned flexible GMRES(restart) in FP64 with B_J
  * as preconditioner (Section 3.2), until ||b - A x||_2 <= rtol ||b||_2 (Section 4.1
  * stopping rule with rtol as given).  A cycle ends when the Arnoldi estimate reaches

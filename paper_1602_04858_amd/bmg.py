@@ -60,6 +60,7 @@ _sig = {
     "bmg_sizes": [_VP, _I32, _P(_I32), _P(_I64), _P(_I64)],
     "bmg_apply": [_VP, _I32, _VP, _VP],
     "bmg_vcycle": [_VP, _VP, _VP],
+    "bmg_vcycle_noalloc": [_VP, _VP, _VP],
     "bmg_solve": [_VP, _VP, _VP, _D, _I32, _VP, _P(SolveInfo)],
     "bmg_quad_points": [_P(Params), _dp, _dp],
     "bmg_assemble_rhs": [_P(Params), _dp, _VP, _VP, _dp],
@@ -233,6 +234,11 @@ class Solver:
     def vcycle(self, r):
         z = self.zeros()
         self._check(_lib.bmg_vcycle(self.h, self._vec(r), _ptr(z)), "vcycle")
+        return z
+
+    def vcycle_noalloc(self, r, z):
+        """z = B_J r into the caller's z, level vectors in the library's static scratch."""
+        self._check(_lib.bmg_vcycle_noalloc(self.h, self._vec(r), self._vec(z)), "vcycle_noalloc")
         return z
 
     def solve(self, b, rtol=1e-10, maxit=500, x0=None, x=None):

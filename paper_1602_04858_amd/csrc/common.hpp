@@ -153,4 +153,12 @@ void launch_scale(double* dst, const double* src, const double* denom, int64_t d
 void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s);
 int dots_partial_count();
 
+// Static device scratch of the allocation-free entry point (bmg_vcycle_noalloc):
+// kStaticScratchBytes per device, in a file-scope __device__ array of kernels.hip.
+// static_scratch() returns its device address on the current device (looked up
+// with hipGetSymbolAddress on the first call per device, then cached).
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t static_scratch(void** ptr, size_t* bytes);
+
 }  // namespace bmg

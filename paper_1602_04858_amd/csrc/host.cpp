@@ -1300,6 +1300,41 @@ bmg_status bmg_apply(bmg_handle h, int32_t level, const double* x, double* y) tr
   return BMG_E_STATE;
 }
 
+bmg_status bmg_vcycle_noalloc(bmg_handle h, const double* r, double* z) try {
+  if (!h || !r || !z) return BMG_E_ARG;
+  void* base = nullptr;
+  size_t cap = 0;
+  HIPCHK(h, static_scratch(&base, &cap));
+  // the level vectors x_j, b_j, r_j of every level (n_rhs columns, preconditioner
+  // arithmetic) in the static scratch instead of the handle's workspace
+  Vecs v;
+  v.nrhs = h->R;
+  Bump B((char*)base);
+  for (const LevelInfo& L : h->lev) {
+    const size_t bytes = (size_t)L.ndof * h->R * h->tsize;
+    v.x.push_back(B.take(bytes));
+    v.b.push_back(B.take(bytes));
+    v.r.push_back(B.take(bytes));
+  }
+  if (B.off > cap)
+    return fail(h, BMG_E_NOMEM, "bmg_vcycle_noalloc: the level vectors need " + std::to_string(B.off >> 20) +
+                                    " MiB, the static scratch holds " + std::to_string(cap >> 20) + " MiB");
+  const int J = (int)h->lev.size() - 1;
+  const int64_t n = h->lev[J].ndof * h->R;
+  // eager launches on the handle's stream (no graph: its nodes hold the workspace's
+  // vectors); every level vector is written before it is read
+  launch_cast(h->prec, 0, r, v.b[J], n, h->stream);
+  vcycle_level(h, J, v, true);
+  launch_cast(0, h->prec, v.x[J], z, n, h->stream);
+  launch_copy_constrained(h->K, h->lev[J].N, h->bcm, r, z, 0, h->R, h->lev[J].ndof, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
+}
+
 bmg_status bmg_vcycle(bmg_handle h, const double* r, double* z) try {
   if (!h || !r || !z) return BMG_E_ARG;
   apply_precond(h, r, z);

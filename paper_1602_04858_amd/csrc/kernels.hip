@@ -18,6 +18,7 @@
 //   k_coarse   x_0 = A_0^{-1} b_0 with the precomputed FP64 inverse.
 //   Krylov     FP64 multi-dot (deterministic two-stage reduction), multi-axpy.
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -1097,6 +1098,40 @@ void launch_scale(double* dst, const double* src, const double* denom, int64_t d
 
 void launch_sub(double* r, const double* b, const double* ax, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, ax, n);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free V-cycle entry point: one array per device,
+// held from the moment the code object is loaded until the process ends.  Host code
+// must not pass `scratch` itself to a kernel (in host code it names a host-side
+// stand-in): its device address is looked up once per device and cached.
+// ---------------------------------------------------------------------------
+}  // namespace bmg
+
+static __device__ __align__(256) unsigned char scratch[bmg::kStaticScratchBytes];
+
+namespace bmg {
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  *ptr = nullptr;
+  if (bytes) *bytes = kStaticScratchBytes;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = a;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace bmg
