@@ -101,6 +101,9 @@ typedef struct {
                             used in the tests); ignored by the multiplicative one */
   int32_t coarse_kappa;  /* BMG_KAPPA_*: kappa of a coarse cell from its four children; Section 4.1
                             uses the arithmetic mean (default) and notes that other choices are possible */
+  int32_t setup_on_host; /* 0 (default): the patch pseudo-inverses are computed on the device (FP64
+                            Gauss-Jordan, one workgroup per patch); 1: on the host (FP64 Gauss-Jordan on
+                            every host thread).  The same matrices up to rounding */
 } bmg_params;
 
 typedef struct {

@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
                 ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32),
                 ("n_rhs", C.c_int32), ("colouring", C.c_int32), ("smoother", C.c_int32), ("omega", C.c_double),
-                ("coarse_kappa", C.c_int32)]
+                ("coarse_kappa", C.c_int32), ("setup_on_host", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -108,7 +108,7 @@ DENSE_COARSE_DEFAULT = 16384
 
 def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
                 dense_coarse_max=0, n_rhs=1, colouring=COLOURING_S9, smoother=SMOOTHER_MULTIPLICATIVE, omega=0.25,
-                coarse_kappa=KAPPA_ARITHMETIC):
+                coarse_kappa=KAPPA_ARITHMETIC, setup_on_host=0):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
@@ -120,6 +120,7 @@ def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, pr
     p.smoother = smoother
     p.omega = float(omega)
     p.coarse_kappa = coarse_kappa
+    p.setup_on_host = setup_on_host
     return p
 
 

@@ -128,6 +128,11 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
                    bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s);
+// Setup: the pseudo-inverses of every vertex patch of one colour of a level, FP64 on the
+// device, written in the level's storage (sprec; full column-major or rotated); extidx
+// as for launch_colour; L.kap is the FP64 kappa of the level; *status |= 1 on a zero pivot
+void launch_patch_pinv(int K, int sprec, const void* elem64, const LevelArgs& L, int colour, int npatch, bool rotated,
+                       void* inv, void* invx, const int32_t* extidx, int32_t* status, hipStream_t s);
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
                      int64_t ldf, int64_t ldc, hipStream_t s);
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
@@ -146,6 +151,12 @@ void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst
 // V + k ldv + r n; per-right-hand-side results ostride / cstride / dstride apart
 void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_t n, double* partial,
                  double* out, int nrhs, int64_t ostride, hipStream_t s);
+// w += sign * sum_v coef_v V_v with FP32-stored V (the preconditioned vectors Z of FGMRES)
+void launch_axpys_f32(double* w, const float* V, int nvec, int64_t ldv, const double* coef, int64_t cstride,
+                      double sign, int64_t n, int nrhs, hipStream_t s);
+// y = A_j x in FP64 for FP32-stored x (the FP64 operator applied to a vector of Z)
+void launch_op64_f32x(int K, const void* elem64, const LevelArgs& L, const float* x, double* y, int nrhs, int64_t ld,
+                      hipStream_t s);
 void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, int64_t cstride,
                   double sign, int64_t n, int nrhs, hipStream_t s);
 void launch_scale(double* dst, const double* src, const double* denom, int64_t dstride, const int32_t* live,

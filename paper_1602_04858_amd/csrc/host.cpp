@@ -63,8 +63,12 @@ struct bmg_ctx {
   // setup batch (unit vectors through the V-cycle of level jc), overlapping the Krylov storage
   int batch_chunk = 0;
   char* region = nullptr;
-  // FP64 Krylov storage
-  double *V = nullptr, *Z = nullptr, *w = nullptr, *rr = nullptr, *ax = nullptr, *t0 = nullptr, *t1 = nullptr;
+  // Krylov storage: V (restart + 1 FP64 vectors of R columns) and Z (restart vectors,
+  // FP64 for the FP64 V-cycle, FP32 otherwise: the V-cycle's output is FP32 then, so
+  // storing it as FP32 is exact); zsize = bytes per entry of Z
+  double* V = nullptr;
+  void* Z = nullptr;
+  size_t zsize = 8;
   double *hdev = nullptr, *partial = nullptr;
   int32_t* live = nullptr;  // per right-hand side: 1 while its Arnoldi process runs
   // V-cycle captured as a graph (captured on a private stream, launched on `stream`)
@@ -139,6 +143,7 @@ bmg_status check_params(const bmg_params* p) {
   if (p->coarse_kappa < BMG_KAPPA_ARITHMETIC || p->coarse_kappa > BMG_KAPPA_GEOMETRIC) return BMG_E_ARG;
   if (p->smoother != BMG_SMOOTHER_MULTIPLICATIVE && p->smoother != BMG_SMOOTHER_ADDITIVE) return BMG_E_ARG;
   if (p->smoother == BMG_SMOOTHER_ADDITIVE && !(p->omega > 0.0 && p->omega <= 1.0)) return BMG_E_ARG;
+  if (p->setup_on_host != 0 && p->setup_on_host != 1) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -546,8 +551,10 @@ size_t layout(bmg_ctx* c, char* base) {
   c->xferT = B.take(c->prec == 0 ? xfer_bytes<double>(K) : xfer_bytes<float>(K));
   const int64_t n = c->lev.back().ndof * c->R;  // all columns of one Krylov vector
   const int m = c->p.restart;
-  // one region shared by the Krylov vectors (solve) and the setup batch
-  const size_t kry = ((size_t)(2 * m + 4) * n + 64) * sizeof(double);
+  c->zsize = c->prec == 0 ? sizeof(double) : sizeof(float);
+  // one region shared by the Krylov vectors (solve) and the setup batch; the residual
+  // of a cycle start and A z_i are formed in the next free slot of V
+  const size_t kry = (size_t)(m + 1) * n * sizeof(double) + (size_t)m * n * c->zsize + 4 * kAlign;
   size_t per_col = 0;
   for (int j = 0; j <= c->jc; ++j) per_col += 3 * (size_t)c->lev[j].ndof * ts;
   int64_t chunk = 0;
@@ -562,11 +569,7 @@ size_t layout(bmg_ctx* c, char* base) {
   {
     Bump R(c->region);
     c->V = (double*)R.take((size_t)(m + 1) * n * sizeof(double));
-    c->Z = (double*)R.take((size_t)m * n * sizeof(double));
-    c->w = (double*)R.take(n * sizeof(double));
-    c->rr = (double*)R.take(n * sizeof(double));
-    c->ax = (double*)R.take(n * sizeof(double));
-    c->t0 = c->t1 = nullptr;
+    c->Z = R.take((size_t)m * n * c->zsize);
   }
   c->hdev = (double*)B.take((size_t)hd_stride(c) * c->R * sizeof(double));
   c->partial = (double*)B.take((size_t)dots_partial_count() * (m + 2) * c->R * sizeof(double));
@@ -804,6 +807,17 @@ bmg_status build_coarse(bmg_ctx* c) {
   return BMG_OK;
 }
 
+// Arguments of the level kernels for level j (kappa in FP64 or the preconditioner's arithmetic).
+LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
+  LevelArgs a;
+  a.N = c->lev[j].N;
+  a.bcm = c->bcm;
+  a.h = c->lev[j].h;
+  a.kap = fp64 ? (const void*)c->lev[j].kap64 : c->lev[j].kap;
+  a.colouring = c->p.colouring;
+  return a;
+}
+
 // Patch pseudo-inverses of level j, colour by colour, uploaded column-major.
 bmg_status build_patches(bmg_ctx* c, int j) {
   LevelInfo& L = c->lev[j];
@@ -822,6 +836,14 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       if (near && needs_ext(I, vx, vy)) ext[p] = ne++;
     }
     const bool pk = packed_level(c, L.N);
+    HIPCHK(c, hipMemcpy(L.extidx[col], ext.data(), np * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!c->p.setup_on_host) {
+      // FP64 Gauss-Jordan on the device, one block per patch (zero pivots flagged in c->live[0])
+      launch_patch_pinv(c->K, c->sprec, c->elem64, largs(c, j, true), col, np, pk, L.inv[col], L.invx[col],
+                        L.extidx[col], c->live, c->stream);
+      HIPCHK(c, hipGetLastError());
+      continue;
+    }
     const int64_t er = inv_entries(pk, nsr), ee = inv_entries(pk, nse);
     std::vector<double> reg((size_t)np * er, 0.0), exd((size_t)std::max(ne, 1) * ee, 0.0);
     std::atomic<int> bad{0};
@@ -857,23 +879,23 @@ bmg_status build_patches(bmg_ctx* c, int j) {
       s = upload_converted(c, L.invx[col], exd.data(), (size_t)ne * ee, c->sprec);
       if (s) return s;
     }
-    HIPCHK(c, hipMemcpy(L.extidx[col], ext.data(), np * sizeof(int32_t), hipMemcpyHostToDevice));
   }
+  return BMG_OK;
+}
+
+// Outcome of the device builds of the patch pseudo-inverses (all levels).
+bmg_status check_patch_status(bmg_ctx* c) {
+  if (c->p.setup_on_host) return BMG_OK;
+  int32_t flag = 0;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&flag, c->live, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) return fail(c, BMG_E_SINGULAR, "a patch matrix is singular");
   return BMG_OK;
 }
 
 // --------------------------------------------------------------------------
 // Cycle
 // --------------------------------------------------------------------------
-LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
-  LevelArgs a;
-  a.N = c->lev[j].N;
-  a.bcm = c->bcm;
-  a.h = c->lev[j].h;
-  a.kap = fp64 ? (const void*)c->lev[j].kap64 : c->lev[j].kap;
-  a.colouring = c->p.colouring;
-  return a;
-}
 
 // Bytes one colour launch must move: every patch's stored pseudo-inverse, the
 // gathered x of its cells and of the tangential components across its outer faces,
@@ -1025,10 +1047,10 @@ bool capture_vcycle(bmg_ctx* c) {
   return ok;
 }
 
-// z = B_J r with FP64 r, z (device); the essential rows are inverted exactly.
-// z = B_J r for all R columns (FP64 r, z on the device); the essential rows are
-// inverted exactly.
-void apply_precond(bmg_ctx* c, const double* r, double* z) {
+// z = B_J r for all R columns (FP64 r on the device; z FP64, or FP32 with
+// z_prec = 1, which is exact for the FP32 V-cycle); the essential rows are inverted
+// exactly.
+void apply_precond(bmg_ctx* c, const double* r, void* z, int z_prec = 0) {
   LevelInfo& L = c->lev.back();
   launch_cast(c->prec, 0, r, L.b, L.ndof * c->R, c->stream);
   // the captured graph (eager launches while kernel timing is on, or if the graph
@@ -1038,12 +1060,25 @@ void apply_precond(bmg_ctx* c, const double* r, double* z) {
     if (c->timing_level < 0) (void)hipGetLastError();  // a failed graph launch is replaced, not reported
     vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
   }
-  launch_cast(0, c->prec, L.x, z, L.ndof * c->R, c->stream);
-  launch_copy_constrained(c->K, L.N, c->bcm, r, z, 0, c->R, L.ndof, c->stream);
+  launch_cast(z_prec, c->prec, L.x, z, L.ndof * c->R, c->stream);
+  launch_copy_constrained(c->K, L.N, c->bcm, r, z, z_prec, c->R, L.ndof, c->stream);
 }
 
 void apply_op64(bmg_ctx* c, int j, const double* x, double* y) {
   launch_op(c->K, 0, c->elem64, largs(c, j, true), x, nullptr, y, false, c->R, c->lev[j].ndof, c->stream);
+}
+
+// y = b - A_J x in FP64 (one fused launch)
+void residual64(bmg_ctx* c, const double* b, const double* x, double* y) {
+  const int J = (int)c->lev.size() - 1;
+  launch_op(c->K, 0, c->elem64, largs(c, J, true), x, b, y, true, c->R, c->lev[J].ndof, c->stream);
+}
+
+// y = A_J z for a vector of Z (FP64 or FP32-stored)
+void apply_op64_z(bmg_ctx* c, const void* z, double* y) {
+  const int J = (int)c->lev.size() - 1;
+  if (c->zsize == sizeof(double)) apply_op64(c, J, (const double*)z, y);
+  else launch_op64_f32x(c->K, c->elem64, largs(c, J, true), (const float*)z, y, c->R, c->lev[J].ndof, c->stream);
 }
 
 // kappa of level j from the finest field, each coarse cell from its 4 children:
@@ -1197,12 +1232,18 @@ bmg_status setup_into(bmg_ctx* c, const bmg_params* p, const double* kappa, void
   // kappa hierarchy: arithmetic mean of the four children (Section 4.1)
   for (int j = 0; j <= p->levels; ++j) c->lev[j].kappa = kappa_level(kappa, p->n0, p->levels, j, p->coarse_kappa);
   bmg_status st = upload_all_consts(c);
+  if (!st) {
+    const int32_t zero = 0;  // status word of the device patch builds
+    if (hipMemcpy(c->live, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+      st = fail(c, BMG_E_HIP, "hipMemcpy of the setup status failed");
+  }
   for (size_t j = 0; !st && j < c->lev.size(); ++j) {
     LevelInfo& L = c->lev[j];
     st = upload_converted(c, L.kap, L.kappa.data(), L.kappa.size(), c->prec);
     if (!st) st = upload_converted(c, L.kap64, L.kappa.data(), L.kappa.size(), 0);
     if (!st && j > 0) st = build_patches(c, (int)j);
   }
+  if (!st) st = check_patch_status(c);
   if (!st) st = build_coarse(c);
   if (!st) st = build_dense(c);
   if (!st && hipDeviceSynchronize() != hipSuccess) st = fail(c, BMG_E_HIP, "setup synchronisation failed");
@@ -1488,14 +1529,15 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
   // ||b - A x|| itself (iterative refinement when the Arnoldi estimate has drifted
   // from it); a cycle that reduces the true residual by less than 10% ends the
   // column's solve.
+  const int zprec = h->zsize == sizeof(double) ? 0 : 1;
+  auto zvec = [&](int i) { return (char*)h->Z + (size_t)i * ldv * h->zsize; };
   for (;;) {
     bool any_open = false;
     for (auto& c : col) any_open |= c.open;
     if (!any_open) break;
-    // r = b - A x, ||r||
-    apply_op64(h, J, x, h->ax);
-    launch_sub(h->rr, b, h->ax, ldv, s);
-    launch_dots(h->rr, 1, ldv, h->rr, n, h->partial, hd + NS, R, HS, s);
+    // r = b - A x in V_0, ||r||
+    residual64(h, b, x, h->V);
+    launch_dots(h->V, 1, ldv, h->V, n, h->partial, hd + NS, R, HS, s);
     if ((st = readback())) return st;
     std::vector<int32_t> act(R, 0);
     bool any = false;
@@ -1525,23 +1567,25 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       }
     }
     if (!any) break;
-    // V_0 = r / beta on the running columns, 0 on the others
+    // V_0 = r / beta on the running columns, 0 on the others (in place)
     if ((st = upload())) return st;
     if ((st = set_live(act))) return st;
-    launch_scale(h->V, h->rr, hd + NS, HS, h->live, false, n, R, s);
+    launch_scale(h->V, h->V, hd + NS, HS, h->live, false, n, R, s);
     std::vector<int32_t> run = act;
     std::vector<int> icount(R, 0);
     for (int i = 0; i < m; ++i) {
       double* vi = h->V + (size_t)i * ldv;
-      double* zi = h->Z + (size_t)i * ldv;
-      apply_precond(h, vi, zi);
-      apply_op64(h, J, zi, h->w);
+      void* zi = zvec(i);
+      // w = A z_i is formed in V_{i+1} and orthogonalised there
+      double* w = h->V + (size_t)(i + 1) * ldv;
+      apply_precond(h, vi, zi, zprec);
+      apply_op64_z(h, zi, w);
       // classical Gram-Schmidt, two passes
-      launch_dots(h->V, i + 1, ldv, h->w, n, h->partial, hd, R, HS, s);
-      launch_axpys(h->w, h->V, i + 1, ldv, hd, HS, -1.0, n, R, s);
-      launch_dots(h->V, i + 1, ldv, h->w, n, h->partial, hd + (m + 2), R, HS, s);
-      launch_axpys(h->w, h->V, i + 1, ldv, hd + (m + 2), HS, -1.0, n, R, s);
-      launch_dots(h->w, 1, ldv, h->w, n, h->partial, hd + NS, R, HS, s);
+      launch_dots(h->V, i + 1, ldv, w, n, h->partial, hd, R, HS, s);
+      launch_axpys(w, h->V, i + 1, ldv, hd, HS, -1.0, n, R, s);
+      launch_dots(h->V, i + 1, ldv, w, n, h->partial, hd + (m + 2), R, HS, s);
+      launch_axpys(w, h->V, i + 1, ldv, hd + (m + 2), HS, -1.0, n, R, s);
+      launch_dots(w, 1, ldv, w, n, h->partial, hd + NS, R, HS, s);
       if ((st = readback())) return st;
       bool still = false;
       for (int r = 0; r < R; ++r) {
@@ -1578,7 +1622,7 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       }
       if (!still || i + 1 == m) break;
       if ((st = set_live(run))) return st;
-      launch_scale(h->V + (size_t)(i + 1) * ldv, h->w, hd + NS, HS, h->live, true, n, R, s);
+      launch_scale(w, w, hd + NS, HS, h->live, true, n, R, s);
     }
     // x_r += Z_r y_r with y_r from the triangular system of column r
     int imax = 0;
@@ -1596,13 +1640,13 @@ bmg_status bmg_solve(bmg_handle h, const double* b, double* x, double rtol, int3
       for (int q = 0; q < ic; ++q) up[(size_t)r * HS + q] = y[q];
     }
     if ((st = upload())) return st;
-    launch_axpys(x, h->Z, imax, ldv, hd, HS, 1.0, n, R, s);
+    if (zprec == 0) launch_axpys(x, (const double*)h->Z, imax, ldv, hd, HS, 1.0, n, R, s);
+    else launch_axpys_f32(x, (const float*)h->Z, imax, ldv, hd, HS, 1.0, n, R, s);
     HIPCHK(h, hipStreamSynchronize(s));  // hd and up are reused by the next cycle
   }
-  // true residuals
-  apply_op64(h, J, x, h->ax);
-  launch_sub(h->rr, b, h->ax, ldv, s);
-  launch_dots(h->rr, 1, ldv, h->rr, n, h->partial, hd + NS, R, HS, s);
+  // true residuals (in V_0, whose basis vector is no longer needed)
+  residual64(h, b, x, h->V);
+  launch_dots(h->V, 1, ldv, h->V, n, h->partial, hd + NS, R, HS, s);
   if ((st = readback())) return st;
   HIPCHK(h, hipGetLastError());
   bool all = true, stalled = false;

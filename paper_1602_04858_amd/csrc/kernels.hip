@@ -87,22 +87,22 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // one velocity component (NV values, comp 0 = u_x, 1 = u_y) of a cell; essential dofs read as 0
-template <int K, typename T>
-__device__ __forceinline__ void load_comp(const T* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
+template <int K, typename T, typename XT>
+__device__ __forceinline__ void load_comp(const XT* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
   using D = Dims<K>;
 #pragma unroll
   for (int d = 0; d < D::NV; ++d) {
     const int dd = comp * D::NV + d;
-    out[d] = Idx<K>::cons(N, bcm, cx, cy, dd) ? T(0) : x[Idx<K>::g(N, cx, cy, dd)];
+    out[d] = Idx<K>::cons(N, bcm, cx, cy, dd) ? T(0) : T(x[Idx<K>::g(N, cx, cy, dd)]);
   }
 }
 
-template <int K, typename T>
-__device__ __forceinline__ void load_pres(const T* __restrict__ x, int N, int cx, int cy, T* out) {
+template <int K, typename T, typename XT>
+__device__ __forceinline__ void load_pres(const XT* __restrict__ x, int N, int cx, int cy, T* out) {
   using D = Dims<K>;
   const int base = Idx<K>::pres(N, cy * N + cx, 0);
 #pragma unroll
-  for (int q = 0; q < D::NP; ++q) out[q] = x[base + q];
+  for (int q = 0; q < D::NP; ++q) out[q] = T(x[base + q]);
 }
 
 // Row d of one velocity component of a cell: cell block, divergence coupling and
@@ -147,9 +147,11 @@ __device__ __forceinline__ T pres_row(const Elem<T, K>& E, int q, const T* ux, c
 // ---------------------------------------------------------------------------
 // Level operator
 // ---------------------------------------------------------------------------
-template <typename T, int K, bool RES>
+// XT: element type of x (T, or float for the FP64 operator applied to FP32-stored
+// Krylov vectors; loads are widened to T)
+template <typename T, int K, bool RES, typename XT = T>
 __global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
-                                            const T* __restrict__ kap, const T* __restrict__ x,
+                                            const T* __restrict__ kap, const XT* __restrict__ x,
                                             const T* __restrict__ b, T* __restrict__ y, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
@@ -171,8 +173,8 @@ __global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, i
     else y[gi] = v;
   };
   auto ident = [&](int gi) {
-    if (RES) y[gi] = b[gi] - x[gi];
-    else y[gi] = x[gi];
+    if (RES) y[gi] = b[gi] - T(x[gi]);
+    else y[gi] = T(x[gi]);
   };
 
   T ux[NV], uy[NV], p[NP], n0[NV], n1[NV];
@@ -479,6 +481,268 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
     constexpr bool INT = false;
 #include "colour_body.inc"
   }
+}
+
+// ---------------------------------------------------------------------------
+// Setup: vertex-patch pseudo-inverses on the device (Section 3.3: the local Ritz
+// projection of every vertex patch), one 256-thread block per patch, FP64 throughout.
+//   1. the slot layout of the patch (the same decode as the colour step) and the
+//      patch matrix A_S = A_j[S, S], assembled from the cell and face blocks: entry
+//      (t, u) sums the couplings between the (at most two) cell-local positions of
+//      slot t and those of slot u;
+//   2. if no free normal dof of the patch lies on the domain boundary, the constant
+//      patch pressure (the (0,0) Legendre coefficient of every patch cell,
+//      normalised) spans the kernel of A_S: the matrix is bordered with it, and the
+//      leading block of the bordered inverse is the pseudo-inverse with zero patch
+//      mean pressure;
+//   3. Gauss-Jordan elimination in place in LDS with partial (row) pivoting, the
+//      row interchanges undone on the columns at the end;
+//   4. the inverse written in the storage of the level: full column-major blocks, or
+//      the rotated diagonals of its symmetric part, in the storage precision (S).
+// A zero pivot sets *status (the host reports BMG_E_SINGULAR).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(double d) {
+  const float f = (float)d;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename S>
+__device__ __forceinline__ S store_as(double v);
+template <>
+__device__ __forceinline__ double store_as<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ float store_as<float>(double v) { return (float)v; }
+template <>
+__device__ __forceinline__ bf16 store_as<bf16>(double v) { return bf16{bf16_rne(v)}; }
+
+// Coupling of cell-local position pa = s NL + d (test) with pb = s2 NL + e (trial)
+// inside the patch around (vx, vy): the cell block, the divergence blocks, the face
+// self terms (interior face, Dirichlet Nitsche face, nothing on an open face) and
+// the neighbour block across a face shared by two patch cells.
+template <int K>
+__device__ double patch_coupling(const Elem<double, K>& E, int pa, int pb, int vx, int vy, int N, int bcm, double h,
+                                 const double* __restrict__ kap) {
+  using D = Dims<K>;
+  constexpr int NV = D::NV, NL = D::NL;
+  const int s = pa / NL, d = pa % NL, s2 = pb / NL, e = pb % NL;
+  const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+  const bool vd = d < 2 * NV, ve = e < 2 * NV;
+  if (s == s2) {
+    if (vd && ve) {
+      const int comp = d / NV;
+      if (e / NV != comp) return 0.0;
+      const int dd = d % NV, ee = e % NV;
+      double v = E.Kmu[dd * NV + ee] + kap[cy * N + cx] * h * h * E.M[dd * NV + ee];
+      for (int up = 0; up < 2; ++up) {
+        int ncx = cx, ncy = cy, side;
+        if (comp == 0) {
+          ncy += up ? 1 : -1;
+          side = up ? 3 : 2;
+        } else {
+          ncx += up ? 1 : -1;
+          side = up ? 1 : 0;
+        }
+        if (ncx >= 0 && ncx < N && ncy >= 0 && ncy < N) v += E.F[up ? 0 : 3][dd * NV + ee];
+        else if ((bcm >> side) & 1) v += E.Nb[up][dd * NV + ee];
+      }
+      return v;
+    }
+    if (vd && !ve) {
+      const int comp = d / NV;
+      return -h * (comp ? E.Dy : E.Dx)[(e - 2 * NV) * NV + d % NV];
+    }
+    if (!vd && ve) {
+      const int comp = e / NV;
+      return -h * (comp ? E.Dy : E.Dx)[(d - 2 * NV) * NV + e % NV];
+    }
+    return 0.0;
+  }
+  if (!vd || !ve) return 0.0;
+  const int comp = d / NV;
+  if (e / NV != comp) return 0.0;
+  const int cx2 = vx - 1 + (s2 & 1), cy2 = vy - 1 + (s2 >> 1);
+  const int dd = d % NV, ee = e % NV;
+  // the component is tangential across horizontal faces (u_x) or vertical ones (u_y)
+  if (comp == 0 && cx2 == cx && cy2 == cy + 1) return E.F[1][dd * NV + ee];
+  if (comp == 0 && cx2 == cx && cy2 == cy - 1) return E.F[2][dd * NV + ee];
+  if (comp == 1 && cy2 == cy && cx2 == cx + 1) return E.F[1][dd * NV + ee];
+  if (comp == 1 && cy2 == cy && cx2 == cx - 1) return E.F[2][dd * NV + ee];
+  return 0.0;
+}
+
+// Face slot t of the layout lies on the domain boundary (its face has one cell in
+// the domain); meaningful for slots that belong to the patch space.
+template <int K>
+__device__ __forceinline__ bool slot_on_boundary(int t, bool ext, int vx, int vy, int N) {
+  using D = Dims<K>;
+  const int nf = ext ? 12 : 4;
+  if (t >= nf * D::NB) return false;
+  const int grp = ext ? t / D::NB : (int)((kRegularGroups >> (4 * (t / D::NB))) & 0xfu);
+  int sA, kA, sB, kB;
+  group_info(grp, sA, kA, sB, kB);
+  if (sB < 0) return true;  // outer face: in the patch space only on the domain boundary
+  const int axA = vx - 1 + (sA & 1), ayA = vy - 1 + (sA >> 1);
+  const int axB = vx - 1 + (sB & 1), ayB = vy - 1 + (sB >> 1);
+  const bool inA = axA >= 0 && axA < N && ayA >= 0 && ayA < N;
+  const bool inB = axB >= 0 && axB < N && ayB >= 0 && ayB < N;
+  return inA != inB;
+}
+
+template <int K, typename S, bool ROT>
+__global__ __launch_bounds__(256) void k_patch_pinv(const Elem<double, K>* __restrict__ Ep, int N, int bcm, double h,
+                                                    const double* __restrict__ kap, int colour, int scheme,
+                                                    S* __restrict__ inv, S* __restrict__ invx,
+                                                    const int32_t* __restrict__ extidx, int32_t* __restrict__ status) {
+  using D = Dims<K>;
+  constexpr int NSR = D::NSR, NSE = D::NSE, NL = D::NL, NV = D::NV, NP = D::NP;
+  constexpr int MM = NSE + 1;  // largest bordered size
+  __shared__ double a[MM * MM];
+  __shared__ double fcol[MM], prow[MM];
+  __shared__ int zA[NSE], zB[NSE], gis[NSE], cidx[NSE], slot[MM];
+  __shared__ int s_n, s_sing, s_piv, s_bad;
+  __shared__ int pv[MM];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  int vx, vy;
+  patch_vertex(scheme, N, colour, p, vx, vy);
+  const int ext = extidx[p];
+  const bool isx = ext >= 0;
+  const int ns = isx ? NSE : NSR;
+  const Elem<double, K>& E = *Ep;
+  // 1. layout
+  for (int t = tid; t < ns; t += blockDim.x) {
+    int g, za, zb;
+    decode_slot<K, false>(t, isx, vx, vy, N, bcm, g, za, zb);
+    gis[t] = g;
+    zA[t] = za;
+    zB[t] = zb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int n = 0;
+    bool bnd = false;
+    for (int t = 0; t < ns; ++t) {
+      if (gis[t] >= 0) {
+        slot[n] = t;
+        cidx[t] = n++;
+        bnd = bnd || slot_on_boundary<K>(t, isx, vx, vy, N);
+      } else {
+        cidx[t] = -1;
+      }
+    }
+    s_n = n;
+    s_sing = bnd ? 0 : 1;
+    s_bad = 0;
+  }
+  __syncthreads();
+  const int n = s_n, m = n + s_sing;
+  // constant patch pressure: the (0,0) coefficient of every patch cell's pressure
+  int cnt = 0;
+  for (int i = 0; i < n; ++i) {
+    const int za = zA[slot[i]];
+    cnt += (za % NL) == 2 * NV;
+  }
+  const double cval = cnt > 0 ? 1.0 / sqrt((double)cnt) : 0.0;
+  for (int q = tid; q < m * m; q += blockDim.x) {
+    const int i = q / m, j = q % m;
+    double v = 0.0;
+    if (i < n && j < n) {
+      const int ti = slot[i], tj = slot[j];
+      const int pa[2] = {zA[ti], zB[ti]}, pb[2] = {zA[tj], zB[tj]};
+      for (int x1 = 0; x1 < 2; ++x1)
+        for (int x2 = 0; x2 < 2; ++x2)
+          if (pa[x1] >= 0 && pb[x2] >= 0) v += patch_coupling<K>(E, pa[x1], pb[x2], vx, vy, N, bcm, h, kap);
+    } else if (i < n || j < n) {
+      const int ii = i < n ? i : j;
+      v = (zA[slot[ii]] % NL) == 2 * NV ? cval : 0.0;
+    }
+    a[i * m + j] = v;
+  }
+  __syncthreads();
+  // 3. Gauss-Jordan in place, partial pivoting
+  for (int k = 0; k < m; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < m; i += 64) {
+        const double v = fabs(a[i * m + k]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_down(best, o, 64);
+        const int oi = __shfl_down(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv = bi;
+        if (!(best > 0.0)) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const int pr = s_piv;
+    if (tid == 0) pv[k] = pr;
+    if (pr != k)
+      for (int j = tid; j < m; j += blockDim.x) {
+        const double t0 = a[k * m + j];
+        a[k * m + j] = a[pr * m + j];
+        a[pr * m + j] = t0;
+      }
+    __syncthreads();
+    const double dinv = 1.0 / a[k * m + k];
+    for (int i = tid; i < m; i += blockDim.x) {
+      fcol[i] = a[i * m + k];
+      prow[i] = (i == k ? 1.0 : a[k * m + i]) * dinv;
+    }
+    __syncthreads();
+    for (int q = tid; q < m * m; q += blockDim.x) {
+      const int i = q / m, j = q % m;
+      if (i == k) a[q] = prow[j];
+      else a[q] = (j == k ? 0.0 : a[q]) - fcol[i] * prow[j];
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) atomicOr(status, 1);
+    return;
+  }
+  // undo the row interchanges on the columns, last first
+  for (int k = m - 1; k >= 0; --k) {
+    const int pr = pv[k];
+    if (pr != k)
+      for (int i = tid; i < m; i += blockDim.x) {
+        const double t0 = a[i * m + k];
+        a[i * m + k] = a[i * m + pr];
+        a[i * m + pr] = t0;
+      }
+    __syncthreads();
+  }
+  // 4. the leading n x n block in the layout of the level
+  S* dst = isx ? invx + (size_t)ext * (ROT ? NSE * (NSE / 2 + 1) : NSE * NSE)
+               : inv + (size_t)p * (ROT ? NSR * (NSR / 2 + 1) : NSR * NSR);
+  if (ROT) {
+    const int ne = ns * (ns / 2 + 1);
+    for (int q = tid; q < ne; q += blockDim.x) {
+      const int dg = q / ns, t = q % ns, u = (t + dg) % ns;
+      const int ci = cidx[t], cj = cidx[u];
+      const double v = (ci >= 0 && cj >= 0) ? 0.5 * (a[ci * m + cj] + a[cj * m + ci]) : 0.0;
+      dst[q] = store_as<S>(v);
+    }
+  } else {
+    for (int q = tid; q < ns * ns; q += blockDim.x) {
+      const int u = q / ns, t = q % ns;  // column-major: entry (t, u) at u ns + t
+      const int ci = cidx[t], cj = cidx[u];
+      dst[q] = store_as<S>((ci >= 0 && cj >= 0) ? a[ci * m + cj] : 0.0);
+    }
+  }
+  (void)NP;
 }
 
 // ---------------------------------------------------------------------------
@@ -818,7 +1082,8 @@ __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ p
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const double* __restrict__ V, int nvec,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const VT* __restrict__ V, int nvec,
                                                int64_t ldv, const double* __restrict__ coef, int64_t cstride,
                                                double sign, int64_t n) {
   w += blockIdx.y * n;
@@ -826,7 +1091,7 @@ __global__ __launch_bounds__(256) void k_axpys(double* __restrict__ w, const dou
   coef += blockIdx.y * cstride;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int v = 0; v < nvec; ++v) s += coef[v] * V[(int64_t)v * ldv + i];
+    for (int v = 0; v < nvec; ++v) s += coef[v] * (double)V[(int64_t)v * ldv + i];
     w[i] += sign * s;
   }
 }
@@ -873,6 +1138,22 @@ static void op_t(const void* elem, const LevelArgs& L, const void* x, const void
   else
     hipLaunchKernelGGL((k_op<T, K, false>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
                        (const T*)L.kap, (const T*)x, (const T*)b, (T*)y, ld);
+}
+
+template <int K>
+static void op64_f32x_t(const void* elem, const LevelArgs& L, const float* x, double* y, int nrhs, int64_t ld,
+                        hipStream_t s) {
+  const int n = L.N * L.N;
+  hipLaunchKernelGGL((k_op<double, K, false, float>), dim3((n + 255) / 256, nrhs), dim3(256), 0, s,
+                     (const Elem<double, K>*)elem, L.N, L.bcm, L.h, (const double*)L.kap, x, (const double*)nullptr,
+                     y, ld);
+}
+
+void launch_op64_f32x(int K, const void* elem64, const LevelArgs& L, const float* x, double* y, int nrhs, int64_t ld,
+                      hipStream_t s) {
+  if (K == 0) op64_f32x_t<0>(elem64, L, x, y, nrhs, ld, s);
+  else if (K == 1) op64_f32x_t<1>(elem64, L, x, y, nrhs, ld, s);
+  else op64_f32x_t<2>(elem64, L, x, y, nrhs, ld, s);
 }
 
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
@@ -932,6 +1213,34 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
     else BMG_KC(0, false, false, false);
   }
 #undef BMG_KC
+}
+
+template <int K, typename S>
+static void pinv_t(const void* elem64, const LevelArgs& L, int colour, int npatch, bool rotated, void* inv, void* invx,
+                   const int32_t* extidx, int32_t* status, hipStream_t s) {
+  if (npatch <= 0) return;
+  if (rotated)
+    hipLaunchKernelGGL((k_patch_pinv<K, S, true>), dim3(npatch), dim3(256), 0, s, (const Elem<double, K>*)elem64,
+                       L.N, L.bcm, L.h, (const double*)L.kap, colour, L.colouring, (S*)inv, (S*)invx, extidx, status);
+  else
+    hipLaunchKernelGGL((k_patch_pinv<K, S, false>), dim3(npatch), dim3(256), 0, s, (const Elem<double, K>*)elem64,
+                       L.N, L.bcm, L.h, (const double*)L.kap, colour, L.colouring, (S*)inv, (S*)invx, extidx, status);
+}
+
+void launch_patch_pinv(int K, int sprec, const void* elem64, const LevelArgs& L, int colour, int npatch, bool rotated,
+                       void* inv, void* invx, const int32_t* extidx, int32_t* status, hipStream_t s) {
+#define BMG_PI(KK)                                                                                         \
+  if (sprec == 0) pinv_t<KK, double>(elem64, L, colour, npatch, rotated, inv, invx, extidx, status, s);    \
+  else if (sprec == 1) pinv_t<KK, float>(elem64, L, colour, npatch, rotated, inv, invx, extidx, status, s); \
+  else pinv_t<KK, bf16>(elem64, L, colour, npatch, rotated, inv, invx, extidx, status, s);
+  if (K == 0) {
+    BMG_PI(0)
+  } else if (K == 1) {
+    BMG_PI(1)
+  } else {
+    BMG_PI(2)
+  }
+#undef BMG_PI
 }
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
@@ -1087,7 +1396,14 @@ void launch_dots(const double* V, int nvec, int64_t ldv, const double* w, int64_
 
 void launch_axpys(double* w, const double* V, int nvec, int64_t ldv, const double* coef, int64_t cstride, double sign,
                   int64_t n, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpys, dim3(grid_for(n), nrhs), dim3(256), 0, s, w, V, nvec, ldv, coef, cstride, sign, n);
+  hipLaunchKernelGGL(k_axpys<double>, dim3(grid_for(n), nrhs), dim3(256), 0, s, w, V, nvec, ldv, coef, cstride,
+                     sign, n);
+}
+
+void launch_axpys_f32(double* w, const float* V, int nvec, int64_t ldv, const double* coef, int64_t cstride,
+                      double sign, int64_t n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpys<float>, dim3(grid_for(n), nrhs), dim3(256), 0, s, w, V, nvec, ldv, coef, cstride,
+                     sign, n);
 }
 
 void launch_scale(double* dst, const double* src, const double* denom, int64_t dstride, const int32_t* live,

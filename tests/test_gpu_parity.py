@@ -136,6 +136,21 @@ def test_transfers_and_coarse(torch, bmg, case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_device_setup_matches_host_setup(torch, bmg, case, prec):
+    """Patch pseudo-inverses computed on the device (FP64 Gauss-Jordan per patch) and on
+    the host give the same V-cycle: the stored matrices differ only by rounding."""
+    n0, J, k, mu, sigma, bc = case
+    kap = inputs.kappa_lognormal_channels(n0 << J, 1, channels=3, width=2 if (n0 << J) >= 16 else 1)
+    args = dict(cycle=1, m_fine=2, prec=prec, restart=20, dense_coarse_max=1000)
+    sd = bmg.Solver(bmg.make_params(n0, J, k, mu, sigma, bc, setup_on_host=0, **args), kap)
+    sh = bmg.Solver(bmg.make_params(n0, J, k, mu, sigma, bc, setup_on_host=1, **args), kap)
+    r = _dev(torch, inputs.random_vector(sd.ndof(), 83))
+    zd, zh = _np(sd.vcycle(r)), _np(sh.vcycle(r))
+    assert _rel(zd, zh) <= (1e-12 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_vcycle(torch, bmg, case):
     o, s, _ = _setup(bmg, case)
     r = _vec(o, o.J, 80, zero_cons=False)
