@@ -46,6 +46,27 @@ struct Elem {
   T Nb[2][D::NV * D::NV];
 };
 
+// The cell operator of a cell whose four faces are interior (every cell of an
+// interior vertex patch), FP32, for the several-column colour step: Kint = Kmu + F[0]
+// + F[3] (the stiffness and both faces' self blocks of the tangential component), the
+// mass block M (times kappa h^2), the neighbour blocks F1 = F[1] (upper / right) and
+// F2 = F[2] (lower / left), the divergence blocks by columns (DxT[d][q] = Dx[q][d],
+// for the velocity rows) and by rows (Dx, Dy, for the pressure rows).  Rows are padded
+// to multiples of four entries (zeros) so that the kernel reads them four at a time.
+template <typename T, int K>
+struct ElemInt {
+  using D = Dims<K>;
+  static constexpr int NVP = (D::NV + 3) / 4 * 4, NPP = (D::NP + 3) / 4 * 4;
+  T Kint[D::NV][NVP];
+  T M[D::NV][NVP];
+  T F1[D::NV][NVP];
+  T F2[D::NV][NVP];
+  T DxT[D::NV][NPP];
+  T DyT[D::NV][NPP];
+  T Dx[D::NP][NVP];
+  T Dy[D::NP][NVP];
+};
+
 // 1-D re-expansion of a coarse function on child interval s (s = 0 left, 1 right):
 // fine coefficient a' of coarse psi_a is Ppsi[s][a'*NA + a], of coarse L_b is
 // PL[s][b'*NB + b].
@@ -125,9 +146,29 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
                bool residual, int nrhs, int64_t ld, hipStream_t s);
 // omega == 0: one colour step of the multiplicative smoother (b = right-hand side);
 // omega > 0: the colour's share of an additive step, x[S] += omega A_S^+ b[S] (b = residual)
+// plist: NULL, or the colour-class indices of the npatch patches to apply (a subset)
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
-                   bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s);
+                   bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s,
+                   const int32_t* plist = nullptr);
+// columns one block of the colour kernel serves (for the byte count of a launch)
+int colour_columns_per_block(int N, bool packed, int npatch, int nrhs);
+// The colour step on the interior patches of a level (K = 1 or 2) for 2..16 FP32 columns
+// with bfloat16 rotated inverses; the other patches of the colour are left alone
+// (launch_colour with their list does them).  elem_int: ElemInt<float, K>
+//   tab: the level's template table (mr_table_entries(K) int4 entries, see below)
+void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
+                      const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s);
+// Template table of a level for launch_colour_mr (int4 entries): first, for each of the
+// NE = 4 NL + 8 NV + NSR gathered entries of one column (the dofs of the 4 cells, the
+// tangential components of the 8 outside neighbours, the patch slots), {global index at
+// the interior vertex (2, 2), stream (0 x-faces, 1 y-faces, 2 interiors, 3 pressure),
+// position in the column's LDS block, 1 if it is read from b}; then for each slot
+// {LDS position of its first row contribution, of its second or -1, 0, 0}.  Positions
+// use the kernel's LDS layout (mr_layout: padded cell width cw, x part xs, column cs).
+int mr_table_entries(int K);
+void mr_steps(int K, int N, int* ax, int* ay);
+void mr_layout(int K, int* cw, int* xs, int* cs);
 // Setup: the pseudo-inverses of every vertex patch of one colour of a level, FP64 on the
 // device, written in the level's storage (sprec; full column-major or rotated); extidx
 // as for launch_colour; L.kap is the FP64 kappa of the level; *status |= 1 on a zero pivot

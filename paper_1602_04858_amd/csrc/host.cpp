@@ -38,6 +38,11 @@ struct LevelInfo {
   void* inv[9] = {nullptr};
   void* invx[9] = {nullptr};
   int32_t* extidx[9] = {nullptr};
+  // levels whose interior patches run the several-column kernel: the other patches
+  // of each colour (colour-class indices; host copy and device copy)
+  std::vector<int32_t> hblist[9];
+  int32_t* blist[9] = {nullptr};
+  int32_t* mrtab = nullptr;  // template table of the several-column kernel (levels with N >= 4)
 };
 
 }  // namespace
@@ -54,6 +59,7 @@ struct bmg_ctx {
   std::vector<LevelInfo> lev;
   RefData ref;
   void* elemT = nullptr;
+  void* elemInt = nullptr;  // ElemInt<float, K> of the several-column colour step (or null)
   void* elem64 = nullptr;
   void* xferT = nullptr;
   double* coarse_inv = nullptr;
@@ -494,14 +500,23 @@ int nse_of(int k) { return 12 * (k + 1) + 8 * k * (k + 1) + 4 * (k + 1) * (k + 1
 // with N >= 192, where the smoother is bandwidth-bound; R[d n + t] = A+[t][(t + d)
 // mod n] for d = 0 .. n/2, n even) or full column-major block.
 bool packed_level(const bmg_ctx* c, int N) {
-  // Several columns in FP32 arithmetic keep full blocks: the colour kernel multiplies
-  // a block by all columns at once on the matrix cores (each entry read once), which
-  // beats the rotated per-column products.  RT_2 keeps full blocks always (its rotated
-  // LDS-staged path stays in the kernel but is not chosen: FP32 entries need 89 KB of
-  // LDS per block).
-  if (c->R > 1 && c->prec != 0) return false;
-  return c->K <= 1 && N >= 192;
+  // Several columns in FP32 arithmetic keep full blocks where the colour kernel
+  // multiplies a block by all columns at once on the matrix cores from memory (FP32
+  // entries, and RT_0 bfloat16 entries); RT_1 / RT_2 with bfloat16 entries and several
+  // columns are stored rotated on every level (half the memory: 2048^2 RT_2 with 16
+  // columns only fits that way), staged per patch in LDS for the product.
+  if (c->R > 1 && c->prec != 0) return c->K >= 1 && c->sprec == 2;
+  // one column (or FP64): rotated on the bandwidth-bound levels; RT_2 in FP64 reads its
+  // rotated blocks from memory in the product
+  return N >= 192 && (c->K <= 1 || c->prec == 0);
 }
+// Interior patches of level j run the several-column kernel (k_colour_mr): 2..16
+// FP32 columns, bfloat16 rotated inverses, RT_1 or RT_2, multiplicative smoother.
+bool mr_handle(const bmg_ctx* c) {
+  return c->R > 1 && c->prec != 0 && c->sprec == 2 && c->K >= 1 && c->p.smoother == BMG_SMOOTHER_MULTIPLICATIVE;
+}
+bool mr_level(const bmg_ctx* c, int N, int nrhs) { return mr_handle(c) && packed_level(c, N) && nrhs >= 2 && nrhs <= 16; }
+
 int64_t inv_entries(bool packed, int ns) { return packed ? (int64_t)ns * (ns / 2 + 1) : (int64_t)ns * ns; }
 
 // Coarse sub-cycle applied as one dense matrix: the finest level jc >= 1 whose
@@ -537,6 +552,9 @@ size_t layout(bmg_ctx* c, char* base) {
         L.inv[col] = B.take((size_t)L.npatch[col] * inv_entries(pk, nsr) * ss);
         L.invx[col] = B.take((size_t)std::max(L.next[col], 1) * inv_entries(pk, nse) * ss);
         L.extidx[col] = (int32_t*)B.take((size_t)std::max(L.npatch[col], 1) * sizeof(int32_t));
+        if (mr_handle(c))
+          L.blist[col] = (int32_t*)B.take((size_t)std::max<size_t>(L.hblist[col].size(), 1) * sizeof(int32_t));
+      if (mr_handle(c) && L.N >= 4) L.mrtab = (int32_t*)B.take((size_t)mr_table_entries(K) * 4 * sizeof(int32_t));
       }
   }
   const int64_t n0 = c->lev[0].ndof;
@@ -548,6 +566,9 @@ size_t layout(bmg_ctx* c, char* base) {
   }
   c->elemT = B.take(c->prec == 0 ? elem_bytes<double>(K) : elem_bytes<float>(K));
   c->elem64 = B.take(elem_bytes<double>(K));
+  c->elemInt = nullptr;
+  if (mr_handle(c))
+    c->elemInt = B.take(K == 1 ? sizeof(ElemInt<float, 1>) : sizeof(ElemInt<float, 2>));
   c->xferT = B.take(c->prec == 0 ? xfer_bytes<double>(K) : xfer_bytes<float>(K));
   const int64_t n = c->lev.back().ndof * c->R;  // all columns of one Krylov vector
   const int m = c->p.restart;
@@ -600,6 +621,7 @@ void init_levels(bmg_ctx* c) {
           const bool e = near && needs_ext(I, vx, vy);
           if (e != ext_rule(I, vx, vy) || colour_of(p.colouring, vx, vy) != col) c->layout_mismatch = true;
           if (e) ++ne;
+          if (mr_handle(c) && !(vx >= 2 && vx <= L.N - 2 && vy >= 2 && vy <= L.N - 2)) L.hblist[col].push_back(q);
         }
         L.next[col] = ne;
       }
@@ -668,7 +690,37 @@ bmg_status upload_consts(bmg_ctx* c, void* dst, bool elem, bool as_double) {
   return BMG_OK;
 }
 
+template <int K>
+bmg_status upload_elem_int(bmg_ctx* c) {
+  using D = Dims<K>;
+  constexpr int NV = D::NV, NP = D::NP;
+  const RefData& R = c->ref;
+  ElemInt<float, K> E;
+  std::memset(&E, 0, sizeof(E));
+  for (int d = 0; d < NV; ++d)
+    for (int e = 0; e < NV; ++e) {
+      const int i = d * NV + e;
+      E.Kint[d][e] = (float)(R.Kmu[i] + R.F[0][i] + R.F[3][i]);
+      E.M[d][e] = (float)R.M[i];
+      E.F1[d][e] = (float)R.F[1][i];
+      E.F2[d][e] = (float)R.F[2][i];
+    }
+  for (int q = 0; q < NP; ++q)
+    for (int d = 0; d < NV; ++d) {
+      E.DxT[d][q] = (float)R.Dx[q * NV + d];
+      E.DyT[d][q] = (float)R.Dy[q * NV + d];
+      E.Dx[q][d] = (float)R.Dx[q * NV + d];
+      E.Dy[q][d] = (float)R.Dy[q * NV + d];
+    }
+  HIPCHK(c, hipMemcpy(c->elemInt, &E, sizeof(E), hipMemcpyHostToDevice));
+  return BMG_OK;
+}
+
 bmg_status upload_all_consts(bmg_ctx* c) {
+  if (c->elemInt) {
+    const bmg_status se = c->K == 1 ? upload_elem_int<1>(c) : upload_elem_int<2>(c);
+    if (se) return se;
+  }
   bmg_status s;
   if (c->K == 0) {
     s = c->prec == 0 ? upload_consts<double, 0>(c, c->elemT, true, false) : upload_consts<float, 0>(c, c->elemT, true, false);
@@ -883,6 +935,61 @@ bmg_status build_patches(bmg_ctx* c, int j) {
   return BMG_OK;
 }
 
+// Template table of level j for the several-column kernel (see launch_colour_mr): the
+// regular patch of the interior vertex (2, 2).
+bmg_status upload_mr_table(bmg_ctx* c, int j) {
+  LevelInfo& L = c->lev[j];
+  if (!L.mrtab) return BMG_OK;
+  const int K = c->K, N = L.N;
+  HostIdx I(N, K, c->bcm);
+  const int NV = I.NV, NL = I.NL, nsr = nsr_of(K);
+  int cw, xs, cs;
+  mr_layout(K, &cw, &xs, &cs);
+  (void)cs;
+  const PatchLayout P = build_layout(I, 2, 2, false);
+  const int ne = 4 * NL + 8 * NV + nsr;
+  std::vector<int32_t> tab((size_t)mr_table_entries(K) * 4, 0);
+  const int64_t nux = (int64_t)N * (N + 1) * I.NB, nu = n_u_of(N, K);
+  auto stream = [&](int64_t g) { return g < nux ? 0 : g < 2 * nux ? 1 : g < nu ? 2 : 3; };
+  for (int e = 0; e < ne; ++e) {
+    int64_t g;
+    int pos, fb = 0;
+    if (e < 4 * NL) {
+      const int sl = e / NL, d = e % NL;
+      g = I.g(1 + (sl & 1), 1 + (sl >> 1), d);
+      pos = sl * cw + d;
+    } else if (e < 4 * NL + 8 * NV) {
+      const int e2 = e - 4 * NL, sl = e2 / (2 * NV), r = e2 % (2 * NV), which = r / NV, d = r % NV;
+      const int cx = 1 + (sl & 1), cy = 1 + (sl >> 1);
+      const int ncx = which == 0 ? cx : ((sl & 1) ? cx + 1 : cx - 1);
+      const int ncy = which == 0 ? ((sl < 2) ? cy - 1 : cy + 1) : cy;
+      g = I.g(ncx, ncy, which * NV + d);
+      pos = 4 * cw + e2;
+    } else {
+      const int t = e - 4 * NL - 8 * NV;
+      g = P.g[t];
+      pos = xs + t;
+      fb = 1;
+      if (g < 0) return fail(c, BMG_E_STATE, "interior template patch has an empty slot");
+      int pa = -1, pb = -1;
+      for (int sl = 0; sl < 4; ++sl)
+        for (int d = 0; d < NL; ++d)
+          if (P.lane[sl * NL + d] == t) {
+            if (pa < 0) pa = sl * cw + d;
+            else pb = sl * cw + d;
+          }
+      tab[(size_t)(ne + t) * 4 + 0] = pa;
+      tab[(size_t)(ne + t) * 4 + 1] = pb;
+    }
+    tab[(size_t)e * 4 + 0] = (int32_t)g;
+    tab[(size_t)e * 4 + 1] = stream(g);
+    tab[(size_t)e * 4 + 2] = pos;
+    tab[(size_t)e * 4 + 3] = fb;
+  }
+  HIPCHK(c, hipMemcpy(L.mrtab, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return BMG_OK;
+}
+
 // Outcome of the device builds of the patch pseudo-inverses (all levels).
 bmg_status check_patch_status(bmg_ctx* c) {
   if (c->p.setup_on_host) return BMG_OK;
@@ -897,19 +1004,48 @@ bmg_status check_patch_status(bmg_ctx* c) {
 // Cycle
 // --------------------------------------------------------------------------
 
-// Bytes one colour launch must move: every patch's stored pseudo-inverse, the
+// Bytes one colour step of level j (nrhs columns) must move: every patch's stored
+// pseudo-inverse (once per block of columns a launch serves), and per column the
 // gathered x of its cells and of the tangential components across its outer faces,
 // kappa of its cells, b on the patch and the read-modify-write of x on the patch.
-double colour_bytes(const bmg_ctx* c, int j, int col) {
+double colour_bytes(const bmg_ctx* c, int j, int col, int nrhs) {
   const LevelInfo& L = c->lev[j];
   const int K = c->K, NB = K + 1, NI = 2 * K * NB, NP = NB * NB, NV = (K + 2) * NB;
   const int nsr = nsr_of(K), nse = nse_of(K);
   const double gather = 12.0 * NB + 4.0 * NI + 4.0 * NP + 8.0 * NV + 4.0;
   const double reg = L.npatch[col] - L.next[col], ext = L.next[col];
-  // x on the patch is written once (its old values come with the gather)
   const bool pk = packed_level(c, L.N);
-  return reg * ((double)inv_entries(pk, nsr) * c->ssize + (gather + 2.0 * nsr) * c->tsize) +
-         ext * ((double)inv_entries(pk, nse) * c->ssize + (gather + 2.0 * nse) * c->tsize);
+  // passes over the inverses: one for the several-column kernel, otherwise one per
+  // block of columns
+  double inv_bytes = (reg * (double)inv_entries(pk, nsr) + ext * (double)inv_entries(pk, nse)) * c->ssize;
+  if (mr_level(c, L.N, nrhs)) {
+    // the listed boundary patches read their inverse once per column
+    const double nb = (double)L.hblist[col].size(), np = std::max(1, L.npatch[col]);
+    inv_bytes *= 1.0 + (nrhs - 1) * nb / np;
+  } else {
+    const int ncol = colour_columns_per_block(L.N, pk, L.npatch[col], nrhs);
+    inv_bytes *= (double)((nrhs + ncol - 1) / ncol);
+  }
+  // x on the patch is written once (its old values come with the gather)
+  return inv_bytes + nrhs * (reg * (gather + 2.0 * nsr) + ext * (gather + 2.0 * nse)) * c->tsize;
+}
+
+// One colour step of level j on nrhs columns (ld apart) of x, b: the several-column
+// kernel on the interior patches plus the general kernel on the listed others, or
+// the general kernel on every patch of the colour.  omega > 0: additive share.
+void colour_launch(bmg_ctx* c, int j, int col, void* x, const void* b, int nrhs, double omega) {
+  LevelInfo& L = c->lev[j];
+  const LevelArgs a = largs(c, j, c->prec == 0);
+  const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c, L.N);
+  if (omega == 0.0 && mr_level(c, L.N, nrhs)) {
+    if (L.mrtab)
+      launch_colour_mr(c->K, c->elemInt, a, x, b, L.inv[col], L.mrtab, col, L.npatch[col], nrhs, L.ndof, c->stream);
+    launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
+                  (int)L.hblist[col].size(), finest, pk, nrhs, L.ndof, 0.0, c->stream, L.blist[col]);
+    return;
+  }
+  launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
+                L.npatch[col], finest, pk, nrhs, L.ndof, omega, c->stream);
 }
 
 // `steps` smoothing steps on level j (nrhs columns; r: scratch of the same shape).
@@ -923,7 +1059,6 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
   const bool additive = c->p.smoother == BMG_SMOOTHER_ADDITIVE;
   const int C = colour_count(c->p.colouring);
   const int nl = additive ? C : 2 * C - 1;
-  const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c, L.N);
   for (int st = 0; st < steps; ++st) {
     if (additive) launch_op(c->K, c->prec, c->elemT, a, x, b, r, true, nrhs, L.ndof, c->stream);
     // one event pair around the back-to-back colour launches of a smoothing step, so
@@ -932,13 +1067,9 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
     if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
     for (int i = 0; i < nl; ++i) {
       const int col = i < C ? i : 2 * C - 2 - i;
-      if (additive)
-        launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, r, L.inv[col], L.invx[col], L.extidx[col], col,
-                      L.npatch[col], finest, pk, nrhs, L.ndof, c->p.omega, c->stream);
-      else
-        launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
-                      L.npatch[col], finest, pk, nrhs, L.ndof, 0.0, c->stream);
-      if (rec) c->timed_bytes += colour_bytes(c, j, col) * nrhs;
+      if (additive) colour_launch(c, j, col, x, r, nrhs, c->p.omega);
+      else colour_launch(c, j, col, x, b, nrhs, 0.0);
+      if (rec) c->timed_bytes += colour_bytes(c, j, col, nrhs);
     }
     if (rec) {
       (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
@@ -1242,6 +1373,12 @@ bmg_status setup_into(bmg_ctx* c, const bmg_params* p, const double* kappa, void
     st = upload_converted(c, L.kap, L.kappa.data(), L.kappa.size(), c->prec);
     if (!st) st = upload_converted(c, L.kap64, L.kappa.data(), L.kappa.size(), 0);
     if (!st && j > 0) st = build_patches(c, (int)j);
+    for (int col = 0; !st && j > 0 && col < 9; ++col)
+      if (L.blist[col] && !L.hblist[col].empty() &&
+          hipMemcpy(L.blist[col], L.hblist[col].data(), L.hblist[col].size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        st = fail(c, BMG_E_HIP, "hipMemcpy of a boundary patch list failed");
+    if (!st && j > 0) st = upload_mr_table(c, (int)j);
   }
   if (!st) st = check_patch_status(c);
   if (!st) st = build_coarse(c);
@@ -1396,9 +1533,7 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
   const int64_t nt = L.ndof * h->R;
   launch_cast(h->prec, 0, x, L.x, nt, h->stream);
   launch_cast(h->prec, 0, b, L.b, nt, h->stream);
-  launch_colour(h->K, h->prec, h->sprec, h->elemT, largs(h, level, h->prec == 0), L.x, L.b, L.inv[colour],
-                L.invx[colour], L.extidx[colour], colour, L.npatch[colour], level == (int)h->lev.size() - 1,
-                packed_level(h, L.N), h->R, L.ndof, 0.0, h->stream);
+  colour_launch(h, level, colour, L.x, L.b, h->R, 0.0);
   launch_cast(0, h->prec, L.x, x, nt, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;

@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 const T* __restrict__ b, const S* __restrict__ inv,
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
                                                 int colour, int scheme, int npatch, int64_t ld, int nrhs,
-                                                int ncol, T omega) {
+                                                int ncol, T omega, const int32_t* __restrict__ plist) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
@@ -406,6 +406,9 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   //   otherwise (RT_2): full blocks streamed from HBM in the product.
   // (RT_2 rotated blocks only with 4- or 2-byte entries: four of them fit in LDS)
   constexpr bool PK = PKD && (K <= 1 || sizeof(S) <= 4);
+  // PKG: rotated blocks read from memory in the product (RT_2 with FP64 entries, 37.6 KB
+  // per patch: not staged)
+  constexpr bool PKG = PKD && !PK;
   // MF: several columns in FP32 arithmetic with full-storage inverses -- the residuals
   // of all columns are formed first, then one MFMA product Y = A+ [r_1 .. r_C] reads
   // every inverse entry once for all columns
@@ -449,11 +452,15 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   // of `ext` below is still seen as reading unmodified memory.)
   int gdim;
   asm("" : "=s"(gdim) : "0"((int)gridDim.x), "s"(N), "s"(bcm), "s"(colour), "s"(scheme), "s"(npatch), "s"(ld),
-      "s"(Ep), "s"(kap), "s"(x), "s"(b), "s"(inv), "s"(invx), "s"(extidx), "s"(h));
+      "s"(Ep), "s"(kap), "s"(x), "s"(b), "s"(inv), "s"(invx), "s"(extidx), "s"(h), "s"(plist));
   const int lb = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
-  const int p = lb * 4 + w;
-  const bool active = p < npatch;
-  const int pc = active ? p : npatch - 1;  // in-bounds stand-in for idle waves
+  // the wave's patch: the (lb * 4 + w)-th of the colour, or of the given list of patches
+  // (the boundary patches of a level whose interior ones run k_colour_mr)
+  const int q = lb * 4 + w;
+  const bool active = q < npatch;
+  const int qc = active ? q : npatch - 1;  // in-bounds stand-in for idle waves
+  const int pc = plist ? plist[qc] : qc;
+  const int p = pc;
   int vx, vy;
   patch_vertex(scheme, N, colour, pc, vx, vy);
   const T mh = -h, hh = h * h;
@@ -480,6 +487,307 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   } else {
     constexpr bool INT = false;
 #include "colour_body.inc"
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Colour step for several right-hand sides (up to 16 columns, FP32 arithmetic,
+// bfloat16 rotated patch inverses), interior vertices only: the patch cells and their
+// neighbours are all in the domain and hold no essential dof, so every coefficient of
+// the local operator is the same for the whole wave (LDS broadcasts), and the global
+// index of every gathered entry is that of the level's template patch (vertex (2, 2),
+// table from setup) shifted linearly with the vertex.  One wave per patch:
+//   1. x of the 4 cells and of the 8 neighbouring components, and b on the patch, of
+//      every column, gathered column by column (coalesced over the entries) into LDS;
+//   2. lane (cell s, column c) computes the NL local rows of its cell for its column
+//      from registers: the cell-local operator of eq. (ipbrinkman) / (Brinkman-weak)
+//      with the interior-face blocks summed into one self block;
+//   3. the residual of the patch rows, split into bfloat16 hi + lo parts, is the B
+//      operand of v_mfma_f32_16x16x32_bf16; the A operand is gathered from the
+//      rotated inverse staged in LDS (A+[i][k] = R[(k - i) mod n][i] for
+//      (k - i) mod n <= n/2, else R[(i - k) mod n][k]); Y = A+ (r_hi + r_lo) accumulates
+//      in FP32;
+//   4. Y goes through LDS to coalesced read-modify-writes x[S] += Y.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+}  // namespace
+
+template <int K>
+struct MrDims {
+  using D = Dims<K>;
+  static constexpr int CW = (D::NL + 3) / 4 * 4;             // padded cell width in LDS
+  static constexpr int XS = 4 * CW + 8 * D::NV;              // x of one column: cells, then neighbours
+  static constexpr int CS = XS + D::NSR;                     // one column: x part, then b on the slots
+  static constexpr int NE = 4 * D::NL + 8 * D::NV + D::NSR;  // gathered entries per column
+  static constexpr int NPR = D::NSR * (D::NSR / 2 + 1);      // stored rotated entries
+  static constexpr int NKS = (D::NSR + 31) / 32;             // k-steps of the product
+  static constexpr int NRT = (D::NSR + 15) / 16;             // row tiles of the product
+};
+
+// stream of a global index (0 x-faces, 1 y-faces, 2 cell interiors, 3 pressure) and the
+// per-stream change of the index when the vertex moves by one in x / in y
+template <int K>
+__host__ __device__ inline void mr_stream_steps(int N, int* ax, int* ay) {
+  using D = Dims<K>;
+  ax[0] = D::NB;
+  ay[0] = (N + 1) * D::NB;
+  ax[1] = D::NB;
+  ay[1] = N * D::NB;
+  ax[2] = D::NI;
+  ay[2] = N * D::NI;
+  ax[3] = D::NP;
+  ay[3] = N * D::NP;
+}
+
+namespace {
+
+template <int K>
+__global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* __restrict__ Ei, int N, float h,
+                                                  const float* __restrict__ kap, float* __restrict__ x,
+                                                  const float* __restrict__ b, const bf16* __restrict__ inv,
+                                                  const int4* __restrict__ tab, int colour, int scheme, int npatch,
+                                                  int64_t ld, int nrhs) {
+  using D = Dims<K>;
+  using M = MrDims<K>;
+  using EI = ElemInt<float, K>;
+  constexpr int NV = D::NV, NP = D::NP, NL = D::NL, NSR = D::NSR, CW = M::CW, XS = M::XS, CS = M::CS, NE = M::NE;
+  constexpr int NPR = M::NPR, NKS = M::NKS, NRT = M::NRT, NVP = EI::NVP, NPP = EI::NPP;
+  constexpr int NEQ = (NE + 255) / 256;       // gather entries per thread and column
+  constexpr int NST = (16 * NSR + 255) / 256;  // (slot, column) pairs per thread in the store
+  constexpr int NH = NV / 2;                   // velocity rows per wave (NV is even)
+  // x | b per column (x later holds the rows, b the correction), and one spare word for
+  // the writes of idle threads
+  __shared__ __attribute__((aligned(16))) float buf[16 * CS + 4];
+  __shared__ __attribute__((aligned(16))) uint16_t apw[(NPR + 7) / 8 * 8];
+  __shared__ __attribute__((aligned(16))) EI Es;  // coefficients, read as broadcasts
+  __shared__ int sgi[NSR], spa[NSR], spb[NSR];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int p = blockIdx.x;
+  if (p >= npatch) return;
+  int vx, vy;
+  patch_vertex(scheme, N, colour, p, vx, vy);
+  if (!(vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2)) return;  // boundary patches: the general kernel
+  const int R = nrhs < 16 ? nrhs : 16;
+  int ax[4], ay[4];
+  mr_stream_steps<K>(N, ax, ay);
+  const int dvx = vx - 2, dvy = vy - 2;
+
+  // gather entries of this thread: table entry e = tid + 256 q holds {index at the
+  // template vertex, stream, LDS position, 1 for b}; the patch slots also carry the
+  // positions of their row contributions
+  int ge[NEQ], pe[NEQ];
+  const float* src[NEQ];
+#pragma unroll
+  for (int q = 0; q < NEQ; ++q) {
+    const int e = tid + 256 * q;
+    const int4 t = tab[e < NE ? e : 0];
+    ge[q] = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
+    pe[q] = e < NE ? t.z : 16 * CS;  // idle threads write the spare word
+    src[q] = t.w != 0 ? b : (const float*)x;
+    if (e >= NE - NSR && e < NE) {
+      const int4 u = tab[NE + (e - (NE - NSR))];
+      sgi[e - (NE - NSR)] = ge[q];
+      spa[e - (NE - NSR)] = u.x;
+      spb[e - (NE - NSR)] = u.y;
+    }
+  }
+  // 1. gather, column by column (all loads of the thread before its first LDS write),
+  // the rotated inverse of the patch and the coefficients (16-byte pieces) meanwhile
+  {
+    float v[16][NEQ];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      if (cc < R) {
+#pragma unroll
+        for (int q = 0; q < NEQ; ++q) v[cc][q] = src[q][(int64_t)cc * ld + ge[q]];
+      }
+    const uint4* ai = reinterpret_cast<const uint4*>(inv + (size_t)p * NPR);
+    uint4* ad = reinterpret_cast<uint4*>(apw);
+    for (int i = tid; i < NPR / 8; i += 256) ad[i] = ai[i];
+    constexpr int NEI = (int)(sizeof(EI) / 16);
+    const uint4* es = reinterpret_cast<const uint4*>(Ei);
+    uint4* ed = reinterpret_cast<uint4*>(&Es);
+    for (int i = tid; i < NEI; i += 256) ed[i] = es[i];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      if (cc < R) {
+#pragma unroll
+        for (int q = 0; q < NEQ; ++q) buf[pe[q] < 16 * CS ? cc * CS + pe[q] : 16 * CS] = v[cc][q];
+      }
+  }
+  __syncthreads();
+
+  // the old x on the (slot, column) pairs this thread stores at the end (the x part of
+  // LDS is overwritten by the rows)
+  float xold[NST];
+#pragma unroll
+  for (int k2 = 0; k2 < NST; ++k2) {
+    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
+    xold[k2] = idx < 16 * NSR ? buf[cc * CS + spa[t]] : 0.f;
+  }
+
+  // 2. rows: wave w takes half of the rows of one velocity component (comp = w / 2,
+  // rows (w % 2) NV/2 .. + NV/2 - 1) and the pressure rows q = w, w + 4, ...; lane
+  // (cell s, column c)
+  const int s = lane >> 4, c = lane & 15;
+  const int comp = w >> 1, d0 = (w & 1) * NH;
+  {
+    const float* col = buf + c * CS;
+    const float* own = col + s * CW;
+    float u0[NVP], u1[NVP], pr[NPP], lo[NVP], hi[NVP];
+#pragma unroll
+    for (int i = 0; i < NVP; ++i) {
+      u0[i] = i < NV ? own[i] : 0.f;
+      u1[i] = i < NV ? own[NV + i] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NPP; ++i) pr[i] = i < NP ? own[2 * NV + i] : 0.f;
+    // tangential neighbours of this wave's component: u_x below / above, u_y left / right
+    const float* nbo = col + 4 * CW + s * 2 * NV + comp * NV;  // the neighbour outside the patch
+    const float* lp = comp == 0 ? (s >= 2 ? col + (s - 2) * CW : nbo) : ((s & 1) ? col + (s - 1) * CW + NV : nbo);
+    const float* hp = comp == 0 ? (s < 2 ? col + (s + 2) * CW : nbo) : ((s & 1) ? nbo : col + (s + 1) * CW + NV);
+#pragma unroll
+    for (int i = 0; i < NVP; ++i) {
+      lo[i] = i < NV ? lp[i] : 0.f;
+      hi[i] = i < NV ? hp[i] : 0.f;
+    }
+    float ucv[NVP];
+#pragma unroll
+    for (int i = 0; i < NVP; ++i) ucv[i] = comp == 0 ? u0[i] : u1[i];
+    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
+    const float khh = kap[cy * N + cx] * (h * h), mh = -h;
+    const float* Dt = comp == 0 ? &Es.DxT[0][0] : &Es.DyT[0][0];
+    float* zc = buf + c * CS + s * CW;
+    // every thread holds its inputs: the rows overwrite the x part of LDS from here
+    __syncthreads();
+    // one row at a time (the coefficient reads of all rows at once would not fit in
+    // registers)
+#pragma unroll 1
+    for (int r = 0; r < NH; ++r) {
+      const int d = d0 + r;
+      float a = 0.f, m = 0.f, g = 0.f;
+#pragma unroll
+      for (int e4 = 0; e4 < NVP / 4; ++e4) {
+        const float4 kf = reinterpret_cast<const float4*>(Es.Kint[d])[e4];
+        const float4 mm = reinterpret_cast<const float4*>(Es.M[d])[e4];
+        const float4 f1 = reinterpret_cast<const float4*>(Es.F1[d])[e4];
+        const float4 f2 = reinterpret_cast<const float4*>(Es.F2[d])[e4];
+        const float kv4[4] = {kf.x, kf.y, kf.z, kf.w}, mv4[4] = {mm.x, mm.y, mm.z, mm.w};
+        const float f14[4] = {f1.x, f1.y, f1.z, f1.w}, f24[4] = {f2.x, f2.y, f2.z, f2.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = 4 * e4 + u;
+          a = fmaf(kv4[u], ucv[e], a);
+          a = fmaf(f24[u], lo[e], a);
+          a = fmaf(f14[u], hi[e], a);
+          m = fmaf(mv4[u], ucv[e], m);
+        }
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < NPP / 4; ++q4) {
+        const float4 dv = reinterpret_cast<const float4*>(Dt + d * NPP)[q4];
+        const float dv4[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g = fmaf(dv4[u], pr[4 * q4 + u], g);
+      }
+      zc[comp * NV + d] = fmaf(mh, g, fmaf(khh, m, a));
+    }
+#pragma unroll 1
+    for (int qi = 0; qi < (NP + 3) / 4; ++qi) {
+      const int q = w + 4 * qi;
+      float a = 0.f;
+      if (q < NP) {
+#pragma unroll
+        for (int e4 = 0; e4 < NVP / 4; ++e4) {
+          const float4 dx = reinterpret_cast<const float4*>(Es.Dx[q])[e4];
+          const float4 dy = reinterpret_cast<const float4*>(Es.Dy[q])[e4];
+          const float dx4[4] = {dx.x, dx.y, dx.z, dx.w}, dy4[4] = {dy.x, dy.y, dy.z, dy.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a = fmaf(dx4[u], u0[4 * e4 + u], a);
+            a = fmaf(dy4[u], u1[4 * e4 + u], a);
+          }
+        }
+      }
+      if (q < NP) zc[2 * NV + q] = mh * a;
+    }
+  }
+  __syncthreads();
+
+  // 3. residual of the patch rows as hi + lo bfloat16 B operands: lane (kg, c) holds
+  // rows t = 32 ks + 8 kg + j, j = 0..7, of column c (every wave forms all of them)
+  const int kg = lane >> 4, li = lane & 15;
+  bf16x8 bhi[NKS], blo[NKS];
+  {
+    const float* col = buf + li * CS;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        // rows past the patch size (RT_1) read slot 0 and are zeroed
+        const int t = 32 * ks + 8 * kg + j, tc = (NSR % 32 == 0 || t < NSR) ? t : 0;
+        const int pb = spb[tc];
+        const float zb = col[pb >= 0 ? pb : 0];
+        float r = col[XS + tc] - col[spa[tc]] - (pb >= 0 ? zb : 0.f);
+        r = (NSR % 32 == 0 || t < NSR) ? r : 0.f;
+        const __bf16 hv = (__bf16)r;
+        bhi[ks][j] = hv;
+        blo[ks][j] = (__bf16)(r - (float)hv);
+      }
+  }
+  // A operand of row tile rt (rt = w, w + 4, ...), k-step ks: lane (kg, i) holds
+  // A+[16 rt + i][32 ks + 8 kg + j]
+  constexpr int NRW = (NRT + 3) / 4;
+  fx4 acc[NRW];
+#pragma unroll
+  for (int ri = 0; ri < NRW; ++ri) {
+    acc[ri] = fx4{0.f, 0.f, 0.f, 0.f};
+    const int rt = w + 4 * ri;
+    if (rt < NRT) {
+      const int row = 16 * rt + li;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        bf16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          // entries past the patch size (RT_1) read entry 0 and are zeroed
+          const int cl = 32 * ks + 8 * kg + j;
+          const bool in = (NSR % 32 == 0) || (row < NSR && cl < NSR);
+          int d1 = cl - row;
+          d1 += d1 < 0 ? NSR : 0;
+          const int idx = d1 <= NSR / 2 ? d1 * NSR + row : (NSR - d1) * NSR + cl;
+          const uint16_t bits = apw[in ? idx : 0];
+          a[j] = __builtin_bit_cast(__bf16, in ? bits : (uint16_t)0);
+        }
+        acc[ri] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bhi[ks], acc[ri], 0, 0, 0);
+        acc[ri] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo[ks], acc[ri], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();  // every wave has read b and the rows: the b part takes the correction
+  // 4. Y[t][c] (lane (rg, c) of row tile rt: rows 16 rt + 4 rg + v) to LDS, then
+  // x[S] = x_old + Y, coalesced over the slots of a column
+  {
+    float* yc = buf + li * CS + XS;
+#pragma unroll
+    for (int ri = 0; ri < NRW; ++ri) {
+      const int rt = w + 4 * ri;
+      if (rt < NRT)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int t = 16 * rt + 4 * kg + v;
+          if (t < NSR) yc[t] = acc[ri][v];
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < NST; ++k2) {
+    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
+    if (idx < 16 * NSR && cc < R) x[(int64_t)cc * ld + sgi[t]] = xold[k2] + buf[cc * CS + XS + t];
   }
 }
 
@@ -1170,20 +1478,25 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
   }
 }
 
+// Columns one block of k_colour serves: all of them on the bandwidth-bound levels
+// (N >= 192, or rotated storage: the inverse is read once per patch for all
+// columns); elsewhere enough blocks to fill the device come first.
+int colour_columns_per_block(int N, bool packed, int npatch, int nrhs) {
+  if (nrhs <= 1) return 1;
+  if (packed || N >= 192) return std::min(nrhs, 16);
+  const int nblk = (npatch + 3) / 4;
+  return std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
+}
+
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
-                     const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs,
-                     int64_t ld, double omega, hipStream_t s) {
+              const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs, int64_t ld,
+              double omega, const int32_t* plist, hipStream_t s) {
   if (npatch <= 0) return;
-  // columns per block: all of them on the bandwidth-bound levels (N >= 192: the inverse
-  // is read once per patch for all columns); elsewhere enough blocks to fill the
-  // device come first
   const int nblk = (npatch + 3) / 4;
-  int ncol = 1;
-  if (nrhs > 1) {
-    if (packed || L.N >= 192) ncol = std::min(nrhs, 16);
-    else ncol = std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
-  }
+  // a short list of patches (the boundary patches beside the several-column kernel):
+  // one column per block, so that the columns run in parallel
+  const int ncol = plist ? 1 : colour_columns_per_block(L.N, packed, npatch, nrhs);
   // large grids: a multiple of the 8 XCDs (the kernel then maps blocks to strips);
   // small ones (coarse levels, setup batches): one block per 4 patches, plain order
   // (a count that happens to be a multiple of 8 gets one idle block more)
@@ -1192,7 +1505,7 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
 #define BMG_KC(TAG, PKD, MC, ADD)                                                                               \
   hipLaunchKernelGGL((k_colour<T, S, K, TAG, PKD, MC, ADD>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm,  \
                      (T)L.h, (const T*)L.kap, (T*)x, (const T*)b, (const S*)inv, (const S*)invx, extidx, colour,  \
-                     L.colouring, npatch, ld, nrhs, ncol, (T)omega)
+                     L.colouring, npatch, ld, nrhs, ncol, (T)omega, plist)
   if (omega > 0.0) {
     // additive step: b is the residual of x
     if (packed) {
@@ -1243,11 +1556,47 @@ void launch_patch_pinv(int K, int sprec, const void* elem64, const LevelArgs& L,
 #undef BMG_PI
 }
 
+template <int K>
+static void colour_mr_t(const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
+                        const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s) {
+  if (npatch <= 0) return;
+  hipLaunchKernelGGL((k_colour_mr<K>), dim3(npatch), dim3(256), 0, s, (const ElemInt<float, K>*)elem_int, L.N,
+                     (float)L.h, (const float*)L.kap, (float*)x, (const float*)b, (const bf16*)inv,
+                     (const int4*)tab, colour, L.colouring, npatch, ld, nrhs);
+}
+
+void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
+                      const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s) {
+  if (K == 1) colour_mr_t<1>(elem_int, L, x, b, inv, tab, colour, npatch, nrhs, ld, s);
+  else if (K == 2) colour_mr_t<2>(elem_int, L, x, b, inv, tab, colour, npatch, nrhs, ld, s);
+}
+
+int mr_table_entries(int K) {
+  return K == 1 ? MrDims<1>::NE + Dims<1>::NSR : MrDims<2>::NE + Dims<2>::NSR;
+}
+
+void mr_steps(int K, int N, int* ax, int* ay) {
+  if (K == 1) mr_stream_steps<1>(N, ax, ay);
+  else mr_stream_steps<2>(N, ax, ay);
+}
+
+void mr_layout(int K, int* cw, int* xs, int* cs) {
+  if (K == 1) {
+    *cw = MrDims<1>::CW;
+    *xs = MrDims<1>::XS;
+    *cs = MrDims<1>::CS;
+  } else {
+    *cw = MrDims<2>::CW;
+    *xs = MrDims<2>::XS;
+    *cs = MrDims<2>::CS;
+  }
+}
+
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
-                   bool packed, int nrhs, int64_t ld, double omega, hipStream_t s) {
+                   bool packed, int nrhs, int64_t ld, double omega, hipStream_t s, const int32_t* plist) {
 #define BMG_COL(T, S, KK) \
-  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, s)
+  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, plist, s)
   if (K == 0) {
     if (prec == 0) BMG_COL(double, double, 0);
     else if (sprec == 0) BMG_COL(float, double, 0);
