@@ -717,22 +717,30 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
   }
   __syncthreads();
 
-  // 3. residual of the patch rows as hi + lo bfloat16 B operands: lane (kg, c) holds
-  // rows t = 32 ks + 8 kg + j, j = 0..7, of column c (every wave forms all of them)
+  // 3. residual of the patch rows, each (slot, column) pair once, in place of b; then
+  // the hi + lo bfloat16 B operands: lane (kg, c) holds rows t = 32 ks + 8 kg + j, j =
+  // 0..7, of column c
+#pragma unroll
+  for (int k2 = 0; k2 < NST; ++k2) {
+    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
+    if (idx < 16 * NSR) {
+      const float* col = buf + cc * CS;
+      const int pb = spb[t];
+      const float zb = col[pb >= 0 ? pb : 0];
+      buf[cc * CS + XS + t] = col[XS + t] - col[spa[t]] - (pb >= 0 ? zb : 0.f);
+    }
+  }
+  __syncthreads();
   const int kg = lane >> 4, li = lane & 15;
   bf16x8 bhi[NKS], blo[NKS];
   {
-    const float* col = buf + li * CS;
+    const float* rc = buf + li * CS + XS;
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        // rows past the patch size (RT_1) read slot 0 and are zeroed
-        const int t = 32 * ks + 8 * kg + j, tc = (NSR % 32 == 0 || t < NSR) ? t : 0;
-        const int pb = spb[tc];
-        const float zb = col[pb >= 0 ? pb : 0];
-        float r = col[XS + tc] - col[spa[tc]] - (pb >= 0 ? zb : 0.f);
-        r = (NSR % 32 == 0 || t < NSR) ? r : 0.f;
+        const int t = 32 * ks + 8 * kg + j;
+        const float r = (NSR % 32 == 0 || t < NSR) ? rc[(NSR % 32 == 0 || t < NSR) ? t : 0] : 0.f;
         const __bf16 hv = (__bf16)r;
         bhi[ks][j] = hv;
         blo[ks][j] = (__bf16)(r - (float)hv);
@@ -899,13 +907,14 @@ __device__ __forceinline__ bool slot_on_boundary(int t, bool ext, int vx, int vy
 }
 
 template <int K, typename S, bool ROT>
-__global__ __launch_bounds__(256) void k_patch_pinv(const Elem<double, K>* __restrict__ Ep, int N, int bcm, double h,
+__global__ __launch_bounds__(512) void k_patch_pinv(const Elem<double, K>* __restrict__ Ep, int N, int bcm, double h,
                                                     const double* __restrict__ kap, int colour, int scheme,
                                                     S* __restrict__ inv, S* __restrict__ invx,
                                                     const int32_t* __restrict__ extidx, int32_t* __restrict__ status) {
   using D = Dims<K>;
   constexpr int NSR = D::NSR, NSE = D::NSE, NL = D::NL, NV = D::NV, NP = D::NP;
   constexpr int MM = NSE + 1;  // largest bordered size
+  static_assert(MM <= 128, "the update loop covers columns l and l + 64");
   __shared__ double a[MM * MM];
   __shared__ double fcol[MM], prow[MM];
   __shared__ int zA[NSE], zB[NSE], gis[NSE], cidx[NSE], slot[MM];
@@ -1010,10 +1019,21 @@ __global__ __launch_bounds__(256) void k_patch_pinv(const Elem<double, K>* __res
       prow[i] = (i == k ? 1.0 : a[k * m + i]) * dinv;
     }
     __syncthreads();
-    for (int q = tid; q < m * m; q += blockDim.x) {
-      const int i = q / m, j = q % m;
-      if (i == k) a[q] = prow[j];
-      else a[q] = (j == k ? 0.0 : a[q]) - fcol[i] * prow[j];
+    // wave wv updates rows wv, wv + NWV, ...; lane l columns l, l + 64 (no index division)
+    {
+      const int nwv = blockDim.x >> 6, wv = tid >> 6, l = tid & 63;
+      const double p0 = l < m ? prow[l] : 0.0, p1 = l + 64 < m ? prow[l + 64] : 0.0;
+      for (int i = wv; i < m; i += nwv) {
+        const double f = fcol[i];
+        double* ar = a + i * m;
+        if (i == k) {
+          if (l < m) ar[l] = p0;
+          if (l + 64 < m) ar[l + 64] = p1;
+        } else {
+          if (l < m) ar[l] = (l == k ? 0.0 : ar[l]) - f * p0;
+          if (l + 64 < m) ar[l + 64] = (l + 64 == k ? 0.0 : ar[l + 64]) - f * p1;
+        }
+      }
     }
     __syncthreads();
   }
@@ -1533,10 +1553,10 @@ static void pinv_t(const void* elem64, const LevelArgs& L, int colour, int npatc
                    const int32_t* extidx, int32_t* status, hipStream_t s) {
   if (npatch <= 0) return;
   if (rotated)
-    hipLaunchKernelGGL((k_patch_pinv<K, S, true>), dim3(npatch), dim3(256), 0, s, (const Elem<double, K>*)elem64,
+    hipLaunchKernelGGL((k_patch_pinv<K, S, true>), dim3(npatch), dim3(512), 0, s, (const Elem<double, K>*)elem64,
                        L.N, L.bcm, L.h, (const double*)L.kap, colour, L.colouring, (S*)inv, (S*)invx, extidx, status);
   else
-    hipLaunchKernelGGL((k_patch_pinv<K, S, false>), dim3(npatch), dim3(256), 0, s, (const Elem<double, K>*)elem64,
+    hipLaunchKernelGGL((k_patch_pinv<K, S, false>), dim3(npatch), dim3(512), 0, s, (const Elem<double, K>*)elem64,
                        L.N, L.bcm, L.h, (const double*)L.kap, colour, L.colouring, (S*)inv, (S*)invx, extidx, status);
 }
 
