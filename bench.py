@@ -1,16 +1,19 @@
 #!/usr/bin/env python
 """Benchmark: V-cycle-preconditioned FGMRES solves of the H(div)-DG Brinkman problem.
 
-One step = one complete solve (FGMRES in FP64 to a 1e-10 relative residual, the
-V-cycle of Section 3.2 as preconditioner: level operators, colour-ordered vertex-
-patch smoother, transfers, coarse solve) of the 256 x 256, 8-level RT_1 Brinkman
-problem (mu = 1e-2, seeded log-normal kappa with channels, contrast 1e6, f = (1,0),
-no-slip left/right, open top/bottom), right-hand side already in HBM.
+Default workload (C5, the largest configuration): 2048 x 2048 quads, 11 levels,
+RT_2 x dQ_2, Brinkman mu = 1e-2, 85 log-normal permeability layers with channels,
+16 smooth random right-hand sides, right-hand sides already in HBM.  One step = one
+complete solve of the 16 right-hand sides (FP64 flexible GMRES per column to a 1e-10
+relative residual, the variable V-cycle of Section 3.2 as preconditioner in FP32 with
+bfloat16-stored patch inverses: level operators, colour-ordered vertex-patch
+smoother, transfers, coarse solve).
 
-Prints one JSON line: solves/s of the plain FP64 path, DoF*iterations/s, the
-mixed-precision (FP32 V-cycle) path beside it, the roofline of the finest-level
-smoother kernel (HIP events around its launches) and the CPU oracle timed on a
-bounded sample of the same solve.
+Prints one JSON line: right-hand sides solved per second (whole job), DoF*iterations/s,
+the plain FP64 V-cycle beside it, the roofline of the finest-level colour step (HIP
+events around its launches), a measured device copy and the CPU oracle timed on a
+bounded sample.  --workload C2 runs the 256^2 RT_1 configuration (FP64, FP32 and
+bfloat16 V-cycles, standard cycle, 16-column batch).
 """
 import argparse
 import json
@@ -109,56 +112,154 @@ def bench_c4(args, torch, bmg, inputs):
     print(json.dumps(out), flush=True)
 
 
+def c5_cpu_baseline(nfull, its_full, n_sample=128, sample_its=10):
+    """The oracle (plain FP64 CPU) on the C5 generator (RT_2, layered kappa, smooth
+    source) at n_sample^2, one right-hand side: setup untimed, the first sample_its FGMRES
+    iterations timed; the time per iteration and unknown is scaled to one right-hand side
+    of the full workload at its iteration count (the full 2048^2 hierarchy does not fit
+    the oracle's host memory)."""
+    from oracle import Oracle
+    from paper_1602_04858_amd import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    w = inputs.scaled_workload("C5", n_sample)
+    t0 = time.perf_counter()
+    o = Oracle.from_workload(w)
+    b = o.rhs(w.source)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its, _, _ = o.fgmres(b, rtol=1e-10, maxit=sample_its, restart=8)
+    dt = time.perf_counter() - t0
+    per_it_dof = dt / abs(its) / o.ndof()
+    solve_s = per_it_dof * nfull * its_full
+    return {"value": 1.0 / solve_s, "unit": "right-hand sides solved/s", "cores": threads, "kind": "oracle",
+            "sample": f"C5 generator at {n_sample}x{n_sample} ({o.ndof()} unknowns), first {abs(its)} FGMRES(8) "
+                      f"iterations ({dt:.1f} s; setup {t_setup:.1f} s untimed), time per iteration and unknown "
+                      f"scaled to {nfull} unknowns x {its_full} iterations",
+            "seconds_per_iteration_per_unknown": per_it_dof}
+
+
 def bench_c5(args, torch, bmg, inputs):
+    """C5 (the largest configuration): 2048^2 quads, 11 levels, RT_2 x dQ_2, Brinkman
+    mu = 1e-2, 85 log-normal layers + channels, 16 smooth random right-hand sides solved
+    together (FP64 FGMRES per column, lockstep), variable V-cycle with FP32 arithmetic
+    and bfloat16-stored patch inverses; the patch products of the interior patches are
+    MFMA tiles.  One step = one solve of all 16 right-hand sides to 1e-10.  Beside it:
+    the plain FP64 V-cycle on one right-hand side (a 16-column FP64 Krylov basis does not
+    fit in HBM at this size), the finest-level colour step's roofline, a device copy and
+    the CPU oracle on a bounded sample."""
     import numpy as np
-    """C5 generator (RT_2, layered kappa, 16 smooth right-hand sides) at --n cells per
-    side: the n_rhs columns solved together (FP64 FGMRES(8) per column, lockstep), with
-    the FP32 and BF16-inverse V-cycles, and the FP64 V-cycle beside them."""
-    w = inputs.scaled_workload("C5", args.n)
-    R = args.rhs
+    from concurrent.futures import ThreadPoolExecutor
+    n, R = args.n, args.rhs
+    w = inputs.workload("C5") if n == 2048 else inputs.scaled_workload("C5", n)
+    restart = args.restart
+    log(f"bench: C5 at {w.n}^2, k=2, {R} right-hand sides, FGMRES({restart}), bf16 inverses, fp32 V-cycle")
+    p = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_BF16, restart,
+                        args.dense_coarse_max, R)
     srcs = [inputs.smooth_source(5100 + c) for c in range(R)]
-    res = {}
-    B = None
-    for key, prec in (("fp32", bmg.P_FP32), ("bf16", bmg.P_BF16), ("fp64", bmg.P_FP64)):
-        p = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 8,
-                            args.dense_coarse_max, R)
+    with ThreadPoolExecutor(min(16, R)) as ex:
+        cols = list(ex.map(lambda f: bmg.assemble_rhs(p, f), srcs))
+    B = torch.as_tensor(np.stack(cols), dtype=torch.float64, device="cuda")
+    del cols
+    t0 = time.perf_counter()
+    s = bmg.Solver(p, w.kappa)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    ndof = s.ndof()
+    log(f"bench: setup {setup:.1f} s, {ndof} unknowns per right-hand side")
+    x = s.zeros()
+    for i in range(args.warmup):
+        x, infos = s.solve(B, rtol=args.rtol, maxit=200, x=x)
+        log(f"bench: warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_all = []
+    for i in range(args.steps):
+        x, infos = s.solve(B, rtol=args.rtol, maxit=200, x=x)
+        its_all.append([inf.iterations for inf in infos])
+        log(f"bench: step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = its_all[-1]
+    worst = max(inf.rel_residual_true for inf in infos)
+    conv = all(inf.converged == 1 for inf in infos)
+    value = args.steps * R / dt
+    log(f"bench: mixed {value:.3f} right-hand sides/s ({dt / args.steps:.2f} s per step), iterations "
+        f"{min(its)}..{max(its)}, worst true residual {worst:.2e}")
+    # roofline of the finest-level colour step: HIP events around its launches (one V-cycle)
+    J = w.levels
+    s.kernel_timing(J, 34 * 4)
+    s.vcycle(B)
+    nl, ms, by = s.kernel_timing_read()
+    s.kernel_timing(-1, 0)
+    avg_s = ms * 1e-3 / nl
+    achieved = by / nl / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_colour_mr<2> (interior patches, MFMA) + k_colour boundary list, finest-level colour step",
+            "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
+    log(f"bench: finest colour step {achieved:.0f} GB/s, {avg_s * 1e6:.0f} us per step")
+    x0 = x[0].clone()
+    s.close()
+    del s, x
+    torch.cuda.empty_cache()
+    # a STREAM-style device copy (2 GiB read + 2 GiB written, HIP events)
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roof["measured_copy_gbs"] = copy_gbs
+    roof["frac_of_measured_copy"] = achieved / copy_gbs
+    out = {"metric": METRIC, "value": value, "unit": "right-hand sides solved/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 V-cycle with bf16-stored patch inverses (bf16 MFMA, f32 accumulate), f64 FGMRES",
+           "data": "synthetic",
+           "config": {"workload": f"C5: {w.n}x{w.n} quads, {w.levels + 1} levels (2x2 coarsest), RT_2 x dQ_2 "
+                                  "H(div)-DG Brinkman mu=0.01, 85 log-normal kappa layers (log10 in [-6,1]) + "
+                                  f"meandering channels, {R} smooth random right-hand sides solved together, "
+                                  "no-slip left/right, open top/bottom; variable V-cycle m=2, multiplicative "
+                                  f"vertex-patch smoother, FP64 FGMRES({restart}) per right-hand side, rtol "
+                                  f"{args.rtol:g}",
+                      "N": w.n, "levels": w.levels + 1, "k": w.k, "mu": w.mu, "n_rhs": R, "restart": restart,
+                      "rtol": args.rtol},
+           "ndof_per_rhs": ndof, "iterations_min": min(its), "iterations_max": max(its),
+           "dof_iters_per_s": ndof * sum(sum(i) for i in its_all) / dt, "worst_true_rel_residual": worst,
+           "converged": conv, "setup_s": setup}
+    # the plain FP64 path beside it: FP64 V-cycle (FP64 rotated inverses), one right-hand side
+    if not args.no_mixed:
+        p64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, restart,
+                              args.dense_coarse_max, 1)
         t0 = time.perf_counter()
-        s = bmg.Solver(p, w.kappa)
-        setup = time.perf_counter() - t0
-        if B is None:
-            B = torch.as_tensor(np.stack([bmg.assemble_rhs(p, f) for f in srcs]), dtype=torch.float64, device="cuda")
-            ndof = s.ndof()
-            log(f"bench: C5@{w.n} k=2, {R} right-hand sides x {ndof} dofs")
-        x = s.zeros()
-        for _ in range(args.warmup):
-            x, infos = s.solve(B, rtol=args.rtol, maxit=1000, x=x)
+        s64 = bmg.Solver(p64, w.kappa)
         torch.cuda.synchronize()
+        setup64 = time.perf_counter() - t0
+        b0 = B[0].contiguous()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            x, infos = s.solve(B, rtol=args.rtol, maxit=1000, x=x)
+        x64, i64 = s64.solve(b0, rtol=args.rtol, maxit=200)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        its = [i.iterations for i in infos]
-        res[key] = {"solves_per_s": args.steps * R / dt, "iterations_min": min(its), "iterations_max": max(its),
-                    "worst_true_rel_residual": max(i.rel_residual_true for i in infos), "setup_s": setup,
-                    "dof_iters_per_s": ndof * sum(its) * args.steps / dt, "x": x}
-        log(f"bench: C5 {key} {res[key]['solves_per_s']:.2f} solves/s, iterations {min(its)}..{max(its)}, "
-            f"setup {setup:.1f} s")
-        s.close()
-        del s
-    ref = res["fp64"]["x"]
-    for key in res:
-        res[key]["rel_diff_vs_fp64"] = (torch.linalg.norm(res[key].pop("x") - ref) / torch.linalg.norm(ref)).item()
-    out = {"metric": f"C5 multi-RHS: right-hand sides solved/s to {args.rtol:g} rel resid",
-           "value": res["fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
-           "config": {"workload": f"C5 generator at {w.n}x{w.n}: RT_2 x dQ_2, mu=1e-2, 85 log-normal layers + "
-                                  f"channels, {R} smooth random right-hand sides solved together, FGMRES(8)",
-                      "N": w.n, "levels": w.levels + 1, "k": w.k, "n_rhs": R, "rtol": args.rtol},
-           "ndof_per_rhs": ndof, "paths": res,
-           "speedup_fp32_vs_fp64": res["fp32"]["solves_per_s"] / res["fp64"]["solves_per_s"],
-           "speedup_bf16_vs_fp64": res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"]}
+        dt64 = time.perf_counter() - t0
+        diff = (torch.linalg.norm(x0 - x64) / torch.linalg.norm(x64)).item()
+        out["fp64"] = {"value": 1.0 / dt64, "unit": "right-hand sides solved/s", "n_rhs": 1,
+                       "precond": "fp64 V-cycle, fp64 rotated patch inverses", "iterations": i64.iterations,
+                       "true_rel_residual": i64.rel_residual_true, "setup_s": setup64}
+        out["speedup_mixed_vs_fp64"] = value * dt64
+        out["rel_diff_mixed_vs_fp64_column0"] = diff
+        log(f"bench: FP64 {1.0 / dt64:.3f} right-hand sides/s ({i64.iterations} iterations, setup {setup64:.1f} s), "
+            f"mixed/fp64 {value * dt64:.2f}x, column 0 difference {diff:.1e}")
+        s64.close()
+        del s64, x64
+    out["roofline"] = roof
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle sample")
+        out["cpu_baseline"] = c5_cpu_baseline(ndof, max(its))
+        out["cpu_baseline"]["note"] = "per right-hand side; the GPU value counts all 16 solved together"
     print(json.dumps(out), flush=True)
 
 
@@ -270,12 +371,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3"],
-                    help="C2 (default, the benchmark configuration), the 1024^2 precision study, or the "
-                         "48-problem batch")
+    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3"],
+                    help="C5 (default: 2048^2 RT_2, 16 right-hand sides, the largest configuration), C2 (256^2 "
+                         "RT_1), the 1024^2 precision study, the 48-problem batch or the 3-D solver")
     ap.add_argument("--streams", type=int, default=4, help="C4: worker streams of the batch")
     ap.add_argument("--problems", type=int, default=48, help="C4: problems in the batch")
-    ap.add_argument("--n", type=int, default=512, help="C5: cells per side (the 2048^2 generator at this size)")
+    ap.add_argument("--n", type=int, default=2048, help="C5: cells per side (the 2048^2 generator at this size)")
+    ap.add_argument("--restart", type=int, default=7,
+                    help="C5: FGMRES restart (16 FP64 basis columns of 113 M unknowns: 7 fits in HBM)")
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--n3", type=int, default=32, help="D3: cells per side of the 3-D mesh (a power of two)")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,

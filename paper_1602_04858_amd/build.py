@@ -9,6 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbmg.so")
+RUNNER = os.path.join(HERE, "bmg_run")  # command-line driver (no Python in the process)
 SOURCES = ["kernels.hip", "host.cpp", "refelem.cpp", "kernels3d.hip", "host3d.cpp"]
 ARCH = os.environ.get("BMG_OFFLOAD_ARCH", "gfx950")
 
@@ -43,8 +44,16 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
     os.replace(tmp, LIB)
+    tmp = RUNNER + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + COMMON + [os.path.join(CSRC, "bmg_run.hip"), "-o", tmp, "-L" + HERE, "-lbmg",
+                            "-Wl,-rpath,$ORIGIN", "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("bmg_run build failed")
+    os.replace(tmp, RUNNER)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", RUNNER)
     return LIB
 
 

@@ -565,7 +565,12 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
   __shared__ int sgi[NSR], spa[NSR], spb[NSR];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int p = blockIdx.x;
+  // XCD-aware order (grids padded to a multiple of 8): the hardware hands consecutive
+  // blocks to the 8 XCDs in turn, so block b takes the (b mod 8)-th contiguous range of
+  // the colour's patches; neighbouring patches of a mesh row then share cache lines
+  // and pages in one XCD's L2 and translation caches
+  const int gdim = gridDim.x;
+  const int p = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
   if (p >= npatch) return;
   int vx, vy;
   patch_vertex(scheme, N, colour, p, vx, vy);
@@ -1499,11 +1504,15 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 }
 
 // Columns one block of k_colour serves: all of them on the bandwidth-bound levels
-// (N >= 192, or rotated storage: the inverse is read once per patch for all
-// columns); elsewhere enough blocks to fill the device come first.
+// (N >= 192: the inverse is read once per patch for all columns) and with rotated
+// storage (up to 16 columns); elsewhere enough blocks to fill the device come first.
 int colour_columns_per_block(int N, bool packed, int npatch, int nrhs) {
   if (nrhs <= 1) return 1;
-  if (packed || N >= 192) return std::min(nrhs, 16);
+  if (N >= 192) return std::min(nrhs, 16);
+  // rotated storage on a small level with many columns (the setup batch of unit vectors
+  // that builds the dense coarse operator): one column per block, the columns in parallel
+  if (packed && nrhs > 16) return 1;
+  if (packed) return std::min(nrhs, 16);
   const int nblk = (npatch + 3) / 4;
   return std::max(1, std::min(16, (int)((int64_t)nblk * nrhs / 4096)));
 }
@@ -1580,7 +1589,7 @@ template <int K>
 static void colour_mr_t(const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
                         const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s) {
   if (npatch <= 0) return;
-  hipLaunchKernelGGL((k_colour_mr<K>), dim3(npatch), dim3(256), 0, s, (const ElemInt<float, K>*)elem_int, L.N,
+  hipLaunchKernelGGL((k_colour_mr<K>), dim3((npatch + 7) & ~7), dim3(256), 0, s, (const ElemInt<float, K>*)elem_int, L.N,
                      (float)L.h, (const float*)L.kap, (float*)x, (const float*)b, (const bf16*)inv,
                      (const int4*)tab, colour, L.colouring, npatch, ld, nrhs);
 }
