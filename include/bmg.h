@@ -157,8 +157,9 @@ bmg_status bmg_vcycle(bmg_handle h, const double* r_dev, double* z_dev);
  * before it is read, so nothing from an earlier call is used.  The call itself
  * allocates nothing (no hipMalloc, hipFree or graph); the first call on a device
  * looks up the array's device address (hipGetSymbolAddress).  BMG_E_NOMEM (with a
- * message) if 3 * sum_j ndof_j * n_rhs * (8 for BMG_P_FP64, else 4) bytes exceed
- * 256 MiB. */
+ * message) if 3 * sum_j ndof_j * w * (8 for BMG_P_FP64, else 4) bytes exceed 256 MiB,
+ * where w = n_rhs, or for BMG_P_BF16 handles with n_rhs >= 2 and k >= 1 (whose level
+ * vectors are interleaved records) n_rhs rounded up to a power of two >= 4. */
 bmg_status bmg_vcycle_noalloc(bmg_handle h, const double* r_dev, double* z_dev);
 
 /* Solve A_J x = b by right-preconditioned flexible GMRES(restart) in FP64 with B_J

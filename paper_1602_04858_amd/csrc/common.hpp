@@ -141,24 +141,27 @@ __host__ __device__ inline void patch_vertex(int scheme, int N, int colour, int 
   vx = ((vy + m) & 3) + 4 * (rem < nA ? rem : rem - nA);
 }
 
-// Level kernels work on nrhs vectors stored ld elements apart (grid.y = vector).
+// Level kernels work on nrhs vectors stored ld elements apart (grid.y = vector), or,
+// with il > 0 (FP32, K >= 1), on interleaved records of il values (a power of two,
+// 4..16): entry g of column c at g * il + c, the il - nrhs trailing columns zero.
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
-               bool residual, int nrhs, int64_t ld, hipStream_t s);
+               bool residual, int nrhs, int64_t ld, hipStream_t s, int il = 0);
 // omega == 0: one colour step of the multiplicative smoother (b = right-hand side);
 // omega > 0: the colour's share of an additive step, x[S] += omega A_S^+ b[S] (b = residual)
 // plist: NULL, or the colour-class indices of the npatch patches to apply (a subset)
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
                    bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s,
-                   const int32_t* plist = nullptr);
+                   const int32_t* plist = nullptr, int il = 0);
 // columns one block of the colour kernel serves (for the byte count of a launch)
 int colour_columns_per_block(int N, bool packed, int npatch, int nrhs);
-// The colour step on the interior patches of a level (K = 1 or 2) for 2..16 FP32 columns
-// with bfloat16 rotated inverses; the other patches of the colour are left alone
-// (launch_colour with their list does them).  elem_int: ElemInt<float, K>
+// The colour step on the interior patches of a level (K = 1 or 2) for FP32 columns in
+// interleaved records of rp = 4, 8 or 16 values, with bfloat16 rotated inverses; the
+// other patches of the colour are left alone (launch_colour with their list does
+// them).  elem_int: ElemInt<float, K>
 //   tab: the level's template table (mr_table_entries(K) int4 entries, see below)
 void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
-                      const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s);
+                      const int32_t* tab, int colour, int npatch, int rp, hipStream_t s);
 // Template table of a level for launch_colour_mr (int4 entries): first, for each of the
 // NE = 4 NL + 8 NV + NSR gathered entries of one column (the dofs of the 4 cells, the
 // tangential components of the 8 outside neighbours, the patch slots), {global index at
@@ -175,15 +178,20 @@ void mr_layout(int K, int* cw, int* xs, int* cs);
 void launch_patch_pinv(int K, int sprec, const void* elem64, const LevelArgs& L, int colour, int npatch, bool rotated,
                        void* inv, void* invx, const int32_t* extidx, int32_t* status, hipStream_t s);
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
-                     int64_t ldf, int64_t ldc, hipStream_t s);
+                     int64_t ldf, int64_t ldc, hipStream_t s, int il = 0);
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
-                    int64_t ldc, int64_t ldf, hipStream_t s);
-void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s);
+                    int64_t ldc, int64_t ldf, hipStream_t s, int il = 0);
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s, int il = 0);
 void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s);
 void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipStream_t s);
 // Y = B X for a dense symmetric n x n matrix and nrhs columns of n entries
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s);
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s,
+                       int il = 0);
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s);
+// nrhs column-major vectors of n entries (ld apart) -> FP32 interleaved records of w values
+// (to_il; the w - nrhs trailing columns zero), or back (to_prec 0: FP64, 1: FP32)
+void launch_cast_il(int to_prec, int from_prec, const void* src, void* dst, int64_t n, int64_t ld, int nrhs, int w,
+                    bool to_il, hipStream_t s);
 // dst = src on the essential (constrained) rows, nrhs columns ld apart
 void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, int nrhs, int64_t ld,
                              hipStream_t s);

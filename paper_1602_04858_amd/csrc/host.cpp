@@ -77,6 +77,10 @@ struct bmg_ctx {
   size_t zsize = 8;
   double *hdev = nullptr, *partial = nullptr;
   int32_t* live = nullptr;  // per right-hand side: 1 while its Arnoldi process runs
+  // several-column bfloat16 handles keep the V-cycle's level vectors as interleaved
+  // records of il values (n_rhs rounded up to a power of two >= 4; the extra columns
+  // zero): entry g of column r at g * il + r.  0: n_rhs column-major blocks
+  int il = 0;
   // V-cycle captured as a graph (captured on a private stream, launched on `stream`)
   hipStream_t cap_stream = nullptr;
   hipGraph_t vgraph = nullptr;
@@ -543,9 +547,10 @@ size_t layout(bmg_ctx* c, char* base) {
     const int64_t nc = (int64_t)L.N * L.N;
     L.kap = B.take(nc * ts);
     L.kap64 = (double*)B.take(nc * sizeof(double));
-    L.x = B.take(L.ndof * c->R * ts);
-    L.b = B.take(L.ndof * c->R * ts);
-    L.r = B.take(L.ndof * c->R * ts);
+    const int64_t w = c->il > 0 ? c->il : c->R;  // columns (record width) of a level vector
+    L.x = B.take(L.ndof * w * ts);
+    L.b = B.take(L.ndof * w * ts);
+    L.r = B.take(L.ndof * w * ts);
     if (j > 0)
       for (int col = 0; col < 9; ++col) {
         const bool pk = packed_level(c, L.N);
@@ -649,6 +654,11 @@ void setup_types(bmg_ctx* c) {
   c->ssize = c->sprec == 0 ? 8 : c->sprec == 1 ? 4 : 2;
   c->bcm = bc_mask(c->p);
   c->R = std::max(1, c->p.n_rhs);
+  c->il = 0;
+  if (mr_handle(c)) {
+    c->il = 4;
+    while (c->il < c->R) c->il *= 2;
+  }
 }
 
 template <typename T, int K>
@@ -1030,18 +1040,19 @@ double colour_bytes(const bmg_ctx* c, int j, int col, int nrhs) {
   return inv_bytes + nrhs * (reg * (gather + 2.0 * nsr) + ext * (gather + 2.0 * nse)) * c->tsize;
 }
 
-// One colour step of level j on nrhs columns (ld apart) of x, b: the several-column
-// kernel on the interior patches plus the general kernel on the listed others, or
-// the general kernel on every patch of the colour.  omega > 0: additive share.
-void colour_launch(bmg_ctx* c, int j, int col, void* x, const void* b, int nrhs, double omega) {
+// One colour step of level j on nrhs columns of x, b (ld = level ndof apart, or with
+// il > 0 interleaved records of il values): the several-column kernel on the interior
+// patches plus the general kernel on the listed others, or the general kernel on
+// every patch of the colour.  omega > 0: additive share.
+void colour_launch(bmg_ctx* c, int j, int col, void* x, const void* b, int nrhs, double omega, int il) {
   LevelInfo& L = c->lev[j];
   const LevelArgs a = largs(c, j, c->prec == 0);
   const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c, L.N);
-  if (omega == 0.0 && mr_level(c, L.N, nrhs)) {
-    if (L.mrtab)
-      launch_colour_mr(c->K, c->elemInt, a, x, b, L.inv[col], L.mrtab, col, L.npatch[col], nrhs, L.ndof, c->stream);
+  if (il > 0) {
+    // interleaved records: the several-column handle's own vectors (multiplicative)
+    if (L.mrtab) launch_colour_mr(c->K, c->elemInt, a, x, b, L.inv[col], L.mrtab, col, L.npatch[col], il, c->stream);
     launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
-                  (int)L.hblist[col].size(), finest, pk, nrhs, L.ndof, 0.0, c->stream, L.blist[col]);
+                  (int)L.hblist[col].size(), finest, pk, nrhs, L.ndof, 0.0, c->stream, L.blist[col], il);
     return;
   }
   launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
@@ -1052,7 +1063,7 @@ void colour_launch(bmg_ctx* c, int j, int col, void* x, const void* b, int nrhs,
 // Multiplicative: colours 0..C-1 then C-2..0, each one launch.  Additive: the
 // residual of x once, then every colour adds its damped patch corrections computed
 // from that residual (colour by colour, so that the updates of a launch are disjoint).
-void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r, int nrhs) {
+void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r, int nrhs, int il) {
   LevelInfo& L = c->lev[j];
   LevelArgs a = largs(c, j, c->prec == 0);
   const bool timed = (c->timing_level == j);
@@ -1060,15 +1071,15 @@ void smooth_level(bmg_ctx* c, int j, int steps, void* x, const void* b, void* r,
   const int C = colour_count(c->p.colouring);
   const int nl = additive ? C : 2 * C - 1;
   for (int st = 0; st < steps; ++st) {
-    if (additive) launch_op(c->K, c->prec, c->elemT, a, x, b, r, true, nrhs, L.ndof, c->stream);
+    if (additive) launch_op(c->K, c->prec, c->elemT, a, x, b, r, true, nrhs, L.ndof, c->stream, il);
     // one event pair around the back-to-back colour launches of a smoothing step, so
     // that no marker sits between two colour kernels
     const bool rec = timed && c->ev_used + 2 <= c->ev.size();
     if (rec) (void)hipEventRecord(c->ev[c->ev_used], c->stream);
     for (int i = 0; i < nl; ++i) {
       const int col = i < C ? i : 2 * C - 2 - i;
-      if (additive) colour_launch(c, j, col, x, r, nrhs, c->p.omega);
-      else colour_launch(c, j, col, x, b, nrhs, 0.0);
+      if (additive) colour_launch(c, j, col, x, r, nrhs, c->p.omega, il);
+      else colour_launch(c, j, col, x, b, nrhs, 0.0, il);
       if (rec) c->timed_bytes += colour_bytes(c, j, col, nrhs);
     }
     if (rec) {
@@ -1088,11 +1099,13 @@ int smoothing_steps(const bmg_ctx* c, int j) {
 struct Vecs {
   std::vector<void*> x, b, r;
   int nrhs = 1;
+  int il = 0;  // > 0: interleaved records of il values (the handle's own level vectors)
 };
 
 Vecs level_vecs(bmg_ctx* c) {
   Vecs v;
   v.nrhs = c->R;
+  v.il = c->il;
   for (auto& L : c->lev) {
     v.x.push_back(L.x);
     v.b.push_back(L.b);
@@ -1107,23 +1120,23 @@ void vcycle_level(bmg_ctx* c, int j, const Vecs& v, bool use_dense) {
   LevelInfo& L = c->lev[j];
   const int nr = v.nrhs;
   if (use_dense && c->jc > 0 && j == c->jc) {
-    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], v.x[j], nr, c->stream);
+    launch_dense_gemv(c->prec, c->dense, L.ndof, v.b[j], v.x[j], nr, c->stream, v.il);
     return;
   }
   if (j == 0) {
-    launch_coarse(c->prec, (int)L.ndof, c->coarse_inv, v.b[0], v.x[0], nr, c->stream);
+    launch_coarse(c->prec, (int)L.ndof, c->coarse_inv, v.b[0], v.x[0], nr, c->stream, v.il);
     return;
   }
   const int m = smoothing_steps(c, j);
-  launch_fill_zero(c->prec, v.x[j], L.ndof * nr, c->stream);
-  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr);
+  launch_fill_zero(c->prec, v.x[j], L.ndof * (v.il > 0 ? v.il : nr), c->stream);
+  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr, v.il);
   LevelArgs a = largs(c, j, c->prec == 0);
-  launch_op(c->K, c->prec, c->elemT, a, v.x[j], v.b[j], v.r[j], true, nr, L.ndof, c->stream);
+  launch_op(c->K, c->prec, c->elemT, a, v.x[j], v.b[j], v.r[j], true, nr, L.ndof, c->stream, v.il);
   LevelInfo& C = c->lev[j - 1];
-  launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, v.r[j], v.b[j - 1], nr, L.ndof, C.ndof, c->stream);
+  launch_restrict(c->K, c->prec, c->xferT, C.N, c->bcm, v.r[j], v.b[j - 1], nr, L.ndof, C.ndof, c->stream, v.il);
   vcycle_level(c, j - 1, v, use_dense);
-  launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, v.x[j - 1], v.x[j], nr, C.ndof, L.ndof, c->stream);
-  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr);
+  launch_prolong(c->K, c->prec, c->xferT, C.N, c->bcm, v.x[j - 1], v.x[j], nr, C.ndof, L.ndof, c->stream, v.il);
+  smooth_level(c, j, m, v.x[j], v.b[j], v.r[j], nr, v.il);
 }
 
 // Dense B_jc: the V-cycle of level jc applied to the unit vectors, a chunk of
@@ -1178,12 +1191,25 @@ bool capture_vcycle(bmg_ctx* c) {
   return ok;
 }
 
+// FP64 user vectors (R columns of level j, column-major) into a level vector of the
+// handle's arithmetic and layout, and back (to_prec 0: FP64, 1: FP32)
+void cast_in(bmg_ctx* c, int j, const double* src, void* dst) {
+  const int64_t n = c->lev[j].ndof;
+  if (c->il > 0) launch_cast_il(1, 0, src, dst, n, n, c->R, c->il, true, c->stream);
+  else launch_cast(c->prec, 0, src, dst, n * c->R, c->stream);
+}
+void cast_out(bmg_ctx* c, int j, const void* src, void* dst, int to_prec) {
+  const int64_t n = c->lev[j].ndof;
+  if (c->il > 0) launch_cast_il(to_prec, 1, src, dst, n, n, c->R, c->il, false, c->stream);
+  else launch_cast(to_prec, c->prec, src, dst, n * c->R, c->stream);
+}
+
 // z = B_J r for all R columns (FP64 r on the device; z FP64, or FP32 with
 // z_prec = 1, which is exact for the FP32 V-cycle); the essential rows are inverted
 // exactly.
 void apply_precond(bmg_ctx* c, const double* r, void* z, int z_prec = 0) {
   LevelInfo& L = c->lev.back();
-  launch_cast(c->prec, 0, r, L.b, L.ndof * c->R, c->stream);
+  cast_in(c, (int)c->lev.size() - 1, r, L.b);
   // the captured graph (eager launches while kernel timing is on, or if the graph
   // cannot be built or launched)
   const bool graphed = c->timing_level < 0 && capture_vcycle(c) && hipGraphLaunch(c->vexec, c->stream) == hipSuccess;
@@ -1191,7 +1217,7 @@ void apply_precond(bmg_ctx* c, const double* r, void* z, int z_prec = 0) {
     if (c->timing_level < 0) (void)hipGetLastError();  // a failed graph launch is replaced, not reported
     vcycle_level(c, (int)c->lev.size() - 1, level_vecs(c), true);
   }
-  launch_cast(z_prec, c->prec, L.x, z, L.ndof * c->R, c->stream);
+  cast_out(c, (int)c->lev.size() - 1, L.x, z, z_prec);
   launch_copy_constrained(c->K, L.N, c->bcm, r, z, z_prec, c->R, L.ndof, c->stream);
 }
 
@@ -1487,9 +1513,10 @@ bmg_status bmg_vcycle_noalloc(bmg_handle h, const double* r, double* z) try {
   // arithmetic) in the static scratch instead of the handle's workspace
   Vecs v;
   v.nrhs = h->R;
+  v.il = h->il;
   Bump B((char*)base);
   for (const LevelInfo& L : h->lev) {
-    const size_t bytes = (size_t)L.ndof * h->R * h->tsize;
+    const size_t bytes = (size_t)L.ndof * (h->il > 0 ? h->il : h->R) * h->tsize;
     v.x.push_back(B.take(bytes));
     v.b.push_back(B.take(bytes));
     v.r.push_back(B.take(bytes));
@@ -1498,12 +1525,11 @@ bmg_status bmg_vcycle_noalloc(bmg_handle h, const double* r, double* z) try {
     return fail(h, BMG_E_NOMEM, "bmg_vcycle_noalloc: the level vectors need " + std::to_string(B.off >> 20) +
                                     " MiB, the static scratch holds " + std::to_string(cap >> 20) + " MiB");
   const int J = (int)h->lev.size() - 1;
-  const int64_t n = h->lev[J].ndof * h->R;
   // eager launches on the handle's stream (no graph: its nodes hold the workspace's
   // vectors); every level vector is written before it is read
-  launch_cast(h->prec, 0, r, v.b[J], n, h->stream);
+  cast_in(h, J, r, v.b[J]);
   vcycle_level(h, J, v, true);
-  launch_cast(0, h->prec, v.x[J], z, n, h->stream);
+  cast_out(h, J, v.x[J], z, 0);
   launch_copy_constrained(h->K, h->lev[J].N, h->bcm, r, z, 0, h->R, h->lev[J].ndof, h->stream);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
@@ -1530,11 +1556,10 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
       colour >= colour_count(h->p.colouring))
     return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
-  const int64_t nt = L.ndof * h->R;
-  launch_cast(h->prec, 0, x, L.x, nt, h->stream);
-  launch_cast(h->prec, 0, b, L.b, nt, h->stream);
-  colour_launch(h, level, colour, L.x, L.b, h->R, 0.0);
-  launch_cast(0, h->prec, L.x, x, nt, h->stream);
+  cast_in(h, level, x, L.x);
+  cast_in(h, level, b, L.b);
+  colour_launch(h, level, colour, L.x, L.b, h->R, 0.0, h->il);
+  cast_out(h, level, L.x, x, 0);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 } catch (const std::bad_alloc&) {
@@ -1546,11 +1571,10 @@ bmg_status bmg_colour_step(bmg_handle h, int32_t level, int32_t colour, double* 
 bmg_status bmg_smooth(bmg_handle h, int32_t level, int32_t steps, double* x, const double* b) try {
   if (!h || !x || !b || level < 1 || level >= (int)h->lev.size() || steps < 0) return BMG_E_ARG;
   LevelInfo& L = h->lev[level];
-  const int64_t nt = L.ndof * h->R;
-  launch_cast(h->prec, 0, x, L.x, nt, h->stream);
-  launch_cast(h->prec, 0, b, L.b, nt, h->stream);
-  smooth_level(h, level, steps, L.x, L.b, L.r, h->R);
-  launch_cast(0, h->prec, L.x, x, nt, h->stream);
+  cast_in(h, level, x, L.x);
+  cast_in(h, level, b, L.b);
+  smooth_level(h, level, steps, L.x, L.b, L.r, h->R, h->il);
+  cast_out(h, level, L.x, x, 0);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 } catch (const std::bad_alloc&) {
@@ -1563,9 +1587,9 @@ bmg_status bmg_restrict(bmg_handle h, int32_t level, const double* rf, double* b
   if (!h || !rf || !bc || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
-  launch_cast(h->prec, 0, rf, F.r, F.ndof * h->R, h->stream);
-  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, h->R, F.ndof, C.ndof, h->stream);
-  launch_cast(0, h->prec, C.b, bc, C.ndof * h->R, h->stream);
+  cast_in(h, level, rf, F.r);
+  launch_restrict(h->K, h->prec, h->xferT, C.N, h->bcm, F.r, C.b, h->R, F.ndof, C.ndof, h->stream, h->il);
+  cast_out(h, level - 1, C.b, bc, 0);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 } catch (const std::bad_alloc&) {
@@ -1578,10 +1602,10 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
   if (!h || !xc || !xf || level < 1 || level >= (int)h->lev.size()) return BMG_E_ARG;
   LevelInfo& F = h->lev[level];
   LevelInfo& C = h->lev[level - 1];
-  launch_cast(h->prec, 0, xc, C.x, C.ndof * h->R, h->stream);
-  launch_cast(h->prec, 0, xf, F.x, F.ndof * h->R, h->stream);
-  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, h->R, C.ndof, F.ndof, h->stream);
-  launch_cast(0, h->prec, F.x, xf, F.ndof * h->R, h->stream);
+  cast_in(h, level - 1, xc, C.x);
+  cast_in(h, level, xf, F.x);
+  launch_prolong(h->K, h->prec, h->xferT, C.N, h->bcm, C.x, F.x, h->R, C.ndof, F.ndof, h->stream, h->il);
+  cast_out(h, level, F.x, xf, 0);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 } catch (const std::bad_alloc&) {
@@ -1593,9 +1617,9 @@ bmg_status bmg_prolong_add(bmg_handle h, int32_t level, const double* xc, double
 bmg_status bmg_coarse_solve(bmg_handle h, const double* b, double* x) try {
   if (!h || !b || !x) return BMG_E_ARG;
   LevelInfo& L = h->lev[0];
-  launch_cast(h->prec, 0, b, L.b, L.ndof * h->R, h->stream);
-  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, h->R, h->stream);
-  launch_cast(0, h->prec, L.x, x, L.ndof * h->R, h->stream);
+  cast_in(h, 0, b, L.b);
+  launch_coarse(h->prec, (int)L.ndof, h->coarse_inv, L.b, L.x, h->R, h->stream, h->il);
+  cast_out(h, 0, L.x, x, 0);
   HIPCHK(h, hipGetLastError());
   return BMG_OK;
 } catch (const std::bad_alloc&) {

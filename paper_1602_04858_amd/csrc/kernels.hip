@@ -19,6 +19,7 @@
 //   Krylov     FP64 multi-dot (deterministic two-stage reduction), multi-axpy.
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -87,8 +88,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // one velocity component (NV values, comp 0 = u_x, 1 = u_y) of a cell; essential dofs read as 0
-template <int K, typename T, typename XT>
-__device__ __forceinline__ void load_comp(const XT* __restrict__ x, int N, int bcm, int cx, int cy, int comp, T* out) {
+// One column of a vector in interleaved records: entry g at p[g * s] (p already points
+// at the column's first entry).  Column-major vectors are read through plain pointers.
+template <typename T>
+struct Rec {
+  T* p;
+  int64_t s;
+  __device__ __forceinline__ T& operator[](int64_t g) const { return p[g * s]; }
+};
+// the view of a column: IL records of width s, or the plain pointer
+template <bool IL, typename T>
+__device__ __forceinline__ auto col_view(T* p, int64_t s) {
+  if constexpr (IL) return Rec<T>{p, s};
+  else return p;
+}
+
+template <int K, typename T, typename XA>
+__device__ __forceinline__ void load_comp(XA x, int N, int bcm, int cx, int cy, int comp, T* out) {
   using D = Dims<K>;
 #pragma unroll
   for (int d = 0; d < D::NV; ++d) {
@@ -97,8 +113,8 @@ __device__ __forceinline__ void load_comp(const XT* __restrict__ x, int N, int b
   }
 }
 
-template <int K, typename T, typename XT>
-__device__ __forceinline__ void load_pres(const XT* __restrict__ x, int N, int cx, int cy, T* out) {
+template <int K, typename T, typename XA>
+__device__ __forceinline__ void load_pres(XA x, int N, int cx, int cy, T* out) {
   using D = Dims<K>;
   const int base = Idx<K>::pres(N, cy * N + cx, 0);
 #pragma unroll
@@ -149,18 +165,30 @@ __device__ __forceinline__ T pres_row(const Elem<T, K>& E, int q, const T* ux, c
 // ---------------------------------------------------------------------------
 // XT: element type of x (T, or float for the FP64 operator applied to FP32-stored
 // Krylov vectors; loads are widened to T)
-template <typename T, int K, bool RES, typename XT = T>
+// IL: the vectors are interleaved records of ld values (a power of two); thread ->
+// (cell, column), column fastest, so that the lanes of a cell read whole records.
+// Otherwise one thread per cell and blockIdx.y = column (ld apart).
+template <typename T, int K, bool RES, typename XT = T, bool IL = false>
 __global__ __launch_bounds__(256) void k_op(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
-                                            const T* __restrict__ kap, const XT* __restrict__ x,
-                                            const T* __restrict__ b, T* __restrict__ y, int64_t ld) {
+                                            const T* __restrict__ kap, const XT* __restrict__ x_,
+                                            const T* __restrict__ b_, T* __restrict__ y_, int64_t ld) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NV = D::NV, NP = D::NP, NA = D::NA, NB = D::NB;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int c;
+  int64_t co;
+  if constexpr (IL) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    c = (int)(t >> __builtin_ctzll(ld));
+    co = t & (ld - 1);
+  } else {
+    c = blockIdx.x * blockDim.x + threadIdx.x;
+    co = blockIdx.y * ld;
+  }
   if (c >= N * N) return;
-  x += blockIdx.y * ld;
-  y += blockIdx.y * ld;
-  if (RES) b += blockIdx.y * ld;
+  const auto x = col_view<IL>(x_ + co, ld);
+  const auto y = col_view<IL>(y_ + co, ld);
+  const auto b = col_view<IL>(RES ? b_ + co : b_, ld);
   const Elem<T, K>& E = *Ep;
   const int cx = c % N, cy = c / N;
   const T mh = -h, hh = h * h;
@@ -387,7 +415,7 @@ __device__ __forceinline__ void decode_slot(int t, bool ext, int vx, int vy, int
 // prefetched into registers (RT_1, regular layout), the patch layout is decoded
 // arithmetically and b on the patch is loaded -- so the dependent chain is one
 // gather of x, the local residual in LDS, an FMA chain on registers and the store.
-template <typename T, typename S, int K, int TAG, bool PKD, bool MC, bool ADD>
+template <typename T, typename S, int K, int TAG, bool PKD, bool MC, bool ADD, bool IL = false>
 __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ Ep, int N, int bcm, T h,
                                                 const T* __restrict__ kap, T* __restrict__ x,
                                                 const T* __restrict__ b, const S* __restrict__ inv,
@@ -397,6 +425,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
+  // Layout of the right-hand-side columns: ld-strided blocks (column c at c * ld), or
+  // with IL interleaved records of ld values (entry g of column c at g * ld + c)
+  const int64_t cst = IL ? 1 : ld;
+  auto ix = [&](int g) {
+    if constexpr (IL) return (int64_t)g * ld;
+    else return g;
+  };
   // Storage of the pseudo-inverses (chosen per level by the host):
   //   PK (RT_1, bandwidth-bound levels): symmetric "rotated diagonal" blocks,
   //       R[d n + t] = A+[t][(t + d) mod n] for d = 0 .. n/2 (n (n/2 + 1) entries,
@@ -475,7 +510,7 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
   // least two cells from the boundary, with the boundary logic compiled out (a
   // wave-uniform branch; both copies execute the same barriers).  Other instantiations
   // compile the general body alone.
-  constexpr bool FAST = K == 1 && !MC && !ADD;
+  constexpr bool FAST = K == 1 && !MC && !ADD && !IL;
   if constexpr (FAST) {
     if (vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2) {
       constexpr bool INT = true;
@@ -548,18 +583,19 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
                                                   const float* __restrict__ kap, float* __restrict__ x,
                                                   const float* __restrict__ b, const bf16* __restrict__ inv,
                                                   const int4* __restrict__ tab, int colour, int scheme, int npatch,
-                                                  int64_t ld, int nrhs) {
+                                                  int rp) {
   using D = Dims<K>;
   using M = MrDims<K>;
   using EI = ElemInt<float, K>;
   constexpr int NV = D::NV, NP = D::NP, NL = D::NL, NSR = D::NSR, CW = M::CW, XS = M::XS, CS = M::CS, NE = M::NE;
   constexpr int NPR = M::NPR, NKS = M::NKS, NRT = M::NRT, NVP = EI::NVP, NPP = EI::NPP;
-  constexpr int NEQ = (NE + 255) / 256;       // gather entries per thread and column
-  constexpr int NST = (16 * NSR + 255) / 256;  // (slot, column) pairs per thread in the store
+  constexpr int NGI = (4 * NE + 255) / 256;   // gather items (entry, 4 columns) per thread
+  constexpr int NSI = (4 * NSR + 255) / 256;  // store items (slot, 4 columns) per thread
+  constexpr int NST = (16 * NSR + 255) / 256;  // (slot, column) pairs per thread in the residual
   constexpr int NH = NV / 2;                   // velocity rows per wave (NV is even)
   // x | b per column (x later holds the rows, b the correction), and one spare word for
   // the writes of idle threads
-  __shared__ __attribute__((aligned(16))) float buf[16 * CS + 4];
+  __shared__ __attribute__((aligned(16))) float buf[16 * CS + 4];  // + 4 spare words
   __shared__ __attribute__((aligned(16))) uint16_t apw[(NPR + 7) / 8 * 8];
   __shared__ __attribute__((aligned(16))) EI Es;  // coefficients, read as broadcasts
   __shared__ int sgi[NSR], spa[NSR], spb[NSR];
@@ -575,40 +611,36 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
   int vx, vy;
   patch_vertex(scheme, N, colour, p, vx, vy);
   if (!(vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2)) return;  // boundary patches: the general kernel
-  const int R = nrhs < 16 ? nrhs : 16;
+  // columns: records of rp = 4, 8 or 16 values (entry g of column c at g * rp + c),
+  // read and written 4 columns (16 bytes) at a time; nq pieces per record
+  const int lq = rp >= 16 ? 2 : rp >= 8 ? 1 : 0, nq = 1 << lq;
   int ax[4], ay[4];
   mr_stream_steps<K>(N, ax, ay);
   const int dvx = vx - 2, dvy = vy - 2;
 
-  // gather entries of this thread: table entry e = tid + 256 q holds {index at the
-  // template vertex, stream, LDS position, 1 for b}; the patch slots also carry the
-  // positions of their row contributions
-  int ge[NEQ], pe[NEQ];
-  const float* src[NEQ];
-#pragma unroll
-  for (int q = 0; q < NEQ; ++q) {
-    const int e = tid + 256 * q;
-    const int4 t = tab[e < NE ? e : 0];
-    ge[q] = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
-    pe[q] = e < NE ? t.z : 16 * CS;  // idle threads write the spare word
-    src[q] = t.w != 0 ? b : (const float*)x;
-    if (e >= NE - NSR && e < NE) {
-      const int4 u = tab[NE + (e - (NE - NSR))];
-      sgi[e - (NE - NSR)] = ge[q];
-      spa[e - (NE - NSR)] = u.x;
-      spb[e - (NE - NSR)] = u.y;
-    }
+  // the patch slots: global index and the positions of their row contributions (table
+  // entry e holds {index at the template vertex (2, 2), stream, LDS position, 1 for b})
+  if (tid < NSR) {
+    const int4 t = tab[NE - NSR + tid], u = tab[NE + tid];
+    sgi[tid] = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
+    spa[tid] = u.x;
+    spb[tid] = u.y;
   }
-  // 1. gather, column by column (all loads of the thread before its first LDS write),
-  // the rotated inverse of the patch and the coefficients (16-byte pieces) meanwhile
+  // 1. gather: item i = (entry i >> lq, columns 4 (i & (nq - 1)) .. + 3), one 16-byte load
+  // each, every load of the thread issued before its first LDS write; the rotated
+  // inverse of the patch and the coefficients (16-byte pieces) meanwhile
   {
-    float v[16][NEQ];
+    float4 v[NGI];
+    int pv[NGI];
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc)
-      if (cc < R) {
-#pragma unroll
-        for (int q = 0; q < NEQ; ++q) v[cc][q] = src[q][(int64_t)cc * ld + ge[q]];
-      }
+    for (int k = 0; k < NGI; ++k) {
+      const int i = tid + 256 * k, e = i >> lq, c4 = 4 * (i & (nq - 1));
+      const bool ok = e < NE;
+      const int4 t = tab[ok ? e : 0];
+      const int64_t g = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
+      v[k] = *reinterpret_cast<const float4*>((t.w != 0 ? b : (const float*)x) + g * rp + c4);
+      pv[k] = ok ? c4 * CS + t.z : 16 * CS;  // idle items write the spare words
+    }
     const uint4* ai = reinterpret_cast<const uint4*>(inv + (size_t)p * NPR);
     uint4* ad = reinterpret_cast<uint4*>(apw);
     for (int i = tid; i < NPR / 8; i += 256) ad[i] = ai[i];
@@ -617,21 +649,24 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
     uint4* ed = reinterpret_cast<uint4*>(&Es);
     for (int i = tid; i < NEI; i += 256) ed[i] = es[i];
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc)
-      if (cc < R) {
-#pragma unroll
-        for (int q = 0; q < NEQ; ++q) buf[pe[q] < 16 * CS ? cc * CS + pe[q] : 16 * CS] = v[cc][q];
-      }
+    for (int k = 0; k < NGI; ++k) {
+      const bool ok = pv[k] < 16 * CS;
+      buf[pv[k]] = v[k].x;
+      buf[ok ? pv[k] + CS : 16 * CS + 1] = v[k].y;
+      buf[ok ? pv[k] + 2 * CS : 16 * CS + 2] = v[k].z;
+      buf[ok ? pv[k] + 3 * CS : 16 * CS + 3] = v[k].w;
+    }
   }
   __syncthreads();
 
-  // the old x on the (slot, column) pairs this thread stores at the end (the x part of
-  // LDS is overwritten by the rows)
-  float xold[NST];
+  // the old x on the (slot, 4 columns) items this thread stores at the end (the x part
+  // of LDS is overwritten by the rows)
+  float4 xold[NSI];
 #pragma unroll
-  for (int k2 = 0; k2 < NST; ++k2) {
-    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
-    xold[k2] = idx < 16 * NSR ? buf[cc * CS + spa[t]] : 0.f;
+  for (int k = 0; k < NSI; ++k) {
+    const int i = tid + 256 * k, t = i >> lq, c4 = 4 * (i & (nq - 1));
+    const int o = t < NSR ? c4 * CS + spa[t] : 0;
+    xold[k] = make_float4(buf[o], buf[o + CS], buf[o + 2 * CS], buf[o + 3 * CS]);
   }
 
   // 2. rows: wave w takes half of the rows of one velocity component (comp = w / 2,
@@ -798,9 +833,14 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
   }
   __syncthreads();
 #pragma unroll
-  for (int k2 = 0; k2 < NST; ++k2) {
-    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
-    if (idx < 16 * NSR && cc < R) x[(int64_t)cc * ld + sgi[t]] = xold[k2] + buf[cc * CS + XS + t];
+  for (int k = 0; k < NSI; ++k) {
+    const int i = tid + 256 * k, t = i >> lq, c4 = 4 * (i & (nq - 1));
+    if (t < NSR) {
+      const float* yc = buf + c4 * CS + XS + t;
+      const float4 o = xold[k];
+      *reinterpret_cast<float4*>(x + (int64_t)sgi[t] * rp + c4) =
+          make_float4(o.x + yc[0], o.y + yc[CS], o.z + yc[2 * CS], o.w + yc[3 * CS]);
+    }
   }
 }
 
@@ -1083,9 +1123,9 @@ __global__ __launch_bounds__(512) void k_patch_pinv(const Elem<double, K>* __res
 // ---------------------------------------------------------------------------
 // Sums over the fine dofs strictly inside coarse cell (cxc, cyc) of P[f][coarse dof]
 // * r_f, for one velocity component; only rows with psi index `arow` if arow >= 0.
-template <typename T, int K>
-__device__ __forceinline__ void inside_comp(const Xfer<T, K>& X, int Nf, int cxc, int cyc, int comp,
-                                            const T* __restrict__ rf, T* out, int arow) {
+template <typename T, int K, typename RA>
+__device__ __forceinline__ void inside_comp(const Xfer<T, K>& X, int Nf, int cxc, int cyc, int comp, RA rf, T* out,
+                                            int arow) {
   using D = Dims<K>;
   constexpr int NA = D::NA, NB = D::NB, NV = D::NV;
 #pragma unroll
@@ -1114,17 +1154,29 @@ __device__ __forceinline__ void inside_comp(const Xfer<T, K>& X, int Nf, int cxc
   }
 }
 
-template <typename T, int K>
+// IL: interleaved records of ldf (= ldc) values, thread -> (coarse cell, column) with
+// the column fastest; otherwise one thread per coarse cell, blockIdx.y = column
+template <typename T, int K, bool IL = false>
 __global__ __launch_bounds__(256) void k_restrict(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
-                                                  const T* __restrict__ rf, T* __restrict__ bc, int64_t ldf,
+                                                  const T* __restrict__ rf_, T* __restrict__ bc_, int64_t ldf,
                                                   int64_t ldc) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int c;
+  int64_t cof, coc;
+  if constexpr (IL) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    c = (int)(t >> __builtin_ctzll(ldf));
+    cof = coc = t & (ldf - 1);
+  } else {
+    c = blockIdx.x * blockDim.x + threadIdx.x;
+    cof = blockIdx.y * ldf;
+    coc = blockIdx.y * ldc;
+  }
   if (c >= Nc * Nc) return;
-  rf += blockIdx.y * ldf;
-  bc += blockIdx.y * ldc;
+  const auto rf = col_view<IL>(rf_ + cof, ldf);
+  const auto bc = col_view<IL>(bc_ + coc, ldc);
   const Xfer<T, K>& X = *Xp;
   const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
   T in_x[NV], in_y[NV], tmp[NV];
@@ -1201,17 +1253,28 @@ __global__ __launch_bounds__(256) void k_restrict(const Xfer<T, K>* __restrict__
   }
 }
 
-template <typename T, int K>
+// IL: as k_restrict
+template <typename T, int K, bool IL = false>
 __global__ __launch_bounds__(256) void k_prolong(const Xfer<T, K>* __restrict__ Xp, int Nc, int bcm,
-                                                 const T* __restrict__ xc, T* __restrict__ xf, int64_t ldc,
+                                                 const T* __restrict__ xc_, T* __restrict__ xf_, int64_t ldc,
                                                  int64_t ldf) {
   using D = Dims<K>;
   using I = Idx<K>;
   constexpr int NA = D::NA, NB = D::NB, NV = D::NV, NP = D::NP;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int c;
+  int64_t coc, cof;
+  if constexpr (IL) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    c = (int)(t >> __builtin_ctzll(ldf));
+    coc = cof = t & (ldf - 1);
+  } else {
+    c = blockIdx.x * blockDim.x + threadIdx.x;
+    coc = blockIdx.y * ldc;
+    cof = blockIdx.y * ldf;
+  }
   if (c >= Nc * Nc) return;
-  xc += blockIdx.y * ldc;
-  xf += blockIdx.y * ldf;
+  const auto xc = col_view<IL>(xc_ + coc, ldc);
+  const auto xf = col_view<IL>(xf_ + cof, ldf);
   const Xfer<T, K>& X = *Xp;
   const int cx = c % Nc, cy = c / Nc, Nf = 2 * Nc;
   T zx[NV], zy[NV], zp[NP];
@@ -1265,18 +1328,20 @@ __global__ __launch_bounds__(256) void k_prolong(const Xfer<T, K>* __restrict__ 
 // ---------------------------------------------------------------------------
 // Coarse solve, casts, constrained copy
 // ---------------------------------------------------------------------------
+// one block per column; entry i of column c at c * cs + i * es (column-major: cs = n,
+// es = 1; interleaved records of width w: cs = 1, es = w)
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(int n, const double* __restrict__ inv, const T* __restrict__ b,
-                                                T* __restrict__ x) {
+                                                T* __restrict__ x, int64_t cs, int64_t es) {
   extern __shared__ double sb[];
-  b += (int64_t)blockIdx.x * n;
-  x += (int64_t)blockIdx.x * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
+  b += (int64_t)blockIdx.x * cs;
+  x += (int64_t)blockIdx.x * cs;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i * es];
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double s = 0.0;
     for (int j = 0; j < n; ++j) s += inv[(size_t)j * n + i] * sb[j];
-    x[i] = (T)s;
+    x[i * es] = (T)s;
   }
 }
 
@@ -1302,7 +1367,7 @@ __global__ __launch_bounds__(256) void k_identity(T* __restrict__ x, int64_t n, 
 // column (the summation order of a column does not depend on NR).
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_dense_rows(const T* __restrict__ B, int64_t n, const T* __restrict__ x,
-                                                    T* __restrict__ y) {
+                                                    T* __restrict__ y, int64_t cs, int64_t es) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
@@ -1316,23 +1381,23 @@ __global__ __launch_bounds__(256) void k_dense_rows(const T* __restrict__ B, int
     const T b2 = __builtin_nontemporal_load(r + j + 128), b3 = __builtin_nontemporal_load(r + j + 192);
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-      const T* xc = x + c * n;
-      a0[c] += b0 * xc[j];
-      a1[c] += b1 * xc[j + 64];
-      a2[c] += b2 * xc[j + 128];
-      a3[c] += b3 * xc[j + 192];
+      const T* xc = x + c * cs;
+      a0[c] += b0 * xc[j * es];
+      a1[c] += b1 * xc[(j + 64) * es];
+      a2[c] += b2 * xc[(j + 128) * es];
+      a3[c] += b3 * xc[(j + 192) * es];
     }
   }
   for (; j < n; j += 64) {
     const T b0 = __builtin_nontemporal_load(r + j);
 #pragma unroll
-    for (int c = 0; c < NR; ++c) a0[c] += b0 * x[c * n + j];
+    for (int c = 0; c < NR; ++c) a0[c] += b0 * x[c * cs + j * es];
   }
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     T s = (a0[c] + a1[c]) + (a2[c] + a3[c]);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if (lane == 0) y[c * n + row] = s;
+    if (lane == 0) y[c * cs + row * es] = s;
   }
 }
 
@@ -1340,6 +1405,49 @@ template <typename TO, typename TI>
 __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __restrict__ dst, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = (TO)src[i];
+}
+
+// Interleaved records of w values (w a power of two, at most 16) <-> column-major
+// blocks ld apart: to_il writes dst[g w + c] = src[c ld + g] for c < nrhs and 0 for
+// nrhs <= c < w; from_il writes dst[c ld + g] = src[g w + c] for c < nrhs.  A block
+// moves 64 consecutive entries g of every column through LDS, so that the blocks are
+// read / written along g and the records as whole contiguous runs.
+template <typename TO, typename TI>
+__global__ __launch_bounds__(256) void k_to_il(const TI* __restrict__ src, TO* __restrict__ dst, int64_t n,
+                                               int64_t ld, int nrhs, int w) {
+  __shared__ TO tile[16][65];
+  const int64_t g0 = (int64_t)blockIdx.x * 64;
+  const int gl = threadIdx.x & 63;
+  for (int c = threadIdx.x >> 6; c < w; c += 4) {
+    const int64_t g = g0 + gl;
+    tile[c][gl] = (c < nrhs && g < n) ? (TO)src[c * ld + g] : TO(0);
+  }
+  __syncthreads();
+  const int lw = __builtin_ctz(w);
+  for (int i = threadIdx.x; i < 64 * w; i += 256) {
+    const int gi = i >> lw, c = i & (w - 1);
+    const int64_t g = g0 + gi;
+    if (g < n) dst[g * w + c] = tile[c][gi];
+  }
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(256) void k_from_il(const TI* __restrict__ src, TO* __restrict__ dst, int64_t n,
+                                                 int64_t ld, int nrhs, int w) {
+  __shared__ TI tile[16][65];
+  const int64_t g0 = (int64_t)blockIdx.x * 64;
+  const int lw = __builtin_ctz(w);
+  for (int i = threadIdx.x; i < 64 * w; i += 256) {
+    const int gi = i >> lw, c = i & (w - 1);
+    const int64_t g = g0 + gi;
+    tile[c][gi] = g < n ? src[g * w + c] : TI(0);
+  }
+  __syncthreads();
+  const int gl = threadIdx.x & 63;
+  for (int c = threadIdx.x >> 6; c < nrhs; c += 4) {
+    const int64_t g = g0 + gl;
+    if (g < n) dst[c * ld + g] = (TO)tile[c][gl];
+  }
 }
 
 template <typename TO, int K>
@@ -1462,8 +1570,20 @@ inline unsigned grid_for(int64_t n, int bs = 256, int64_t cap = 8192) {
 // ---------------------------------------------------------------------------
 template <typename T, int K>
 static void op_t(const void* elem, const LevelArgs& L, const void* x, const void* b, void* y, bool res, int nrhs,
-                 int64_t ld, hipStream_t s) {
+                 int64_t ld, int il, hipStream_t s) {
   const int n = L.N * L.N;
+  if constexpr (K >= 1 && std::is_same<T, float>::value)
+    if (il > 0) {
+      // interleaved records of il values: one thread per (cell, column)
+      const dim3 gi((unsigned)(((int64_t)n * il + 255) / 256)), bi(256);
+      if (res)
+        hipLaunchKernelGGL((k_op<T, K, true, T, true>), gi, bi, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                           (const T*)L.kap, (const T*)x, (const T*)b, (T*)y, (int64_t)il);
+      else
+        hipLaunchKernelGGL((k_op<T, K, false, T, true>), gi, bi, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
+                           (const T*)L.kap, (const T*)x, (const T*)b, (T*)y, (int64_t)il);
+      return;
+    }
   dim3 g((n + 255) / 256, nrhs), bl(256);
   if (res)
     hipLaunchKernelGGL((k_op<T, K, true>), g, bl, 0, s, (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h,
@@ -1490,16 +1610,16 @@ void launch_op64_f32x(int K, const void* elem64, const LevelArgs& L, const float
 }
 
 void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void* x, const void* b, void* y,
-               bool residual, int nrhs, int64_t ld, hipStream_t s) {
+               bool residual, int nrhs, int64_t ld, hipStream_t s, int il) {
   if (K == 0) {
-    if (prec == 0) op_t<double, 0>(elem, L, x, b, y, residual, nrhs, ld, s);
-    else op_t<float, 0>(elem, L, x, b, y, residual, nrhs, ld, s);
+    if (prec == 0) op_t<double, 0>(elem, L, x, b, y, residual, nrhs, ld, il, s);
+    else op_t<float, 0>(elem, L, x, b, y, residual, nrhs, ld, il, s);
   } else if (K == 1) {
-    if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
-    else op_t<float, 1>(elem, L, x, b, y, residual, nrhs, ld, s);
+    if (prec == 0) op_t<double, 1>(elem, L, x, b, y, residual, nrhs, ld, il, s);
+    else op_t<float, 1>(elem, L, x, b, y, residual, nrhs, ld, il, s);
   } else {
-    if (prec == 0) op_t<double, 2>(elem, L, x, b, y, residual, nrhs, ld, s);
-    else op_t<float, 2>(elem, L, x, b, y, residual, nrhs, ld, s);
+    if (prec == 0) op_t<double, 2>(elem, L, x, b, y, residual, nrhs, ld, il, s);
+    else op_t<float, 2>(elem, L, x, b, y, residual, nrhs, ld, il, s);
   }
 }
 
@@ -1520,9 +1640,21 @@ int colour_columns_per_block(int N, bool packed, int npatch, int nrhs) {
 template <typename T, typename S, int K>
 static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* b, const void* inv, const void* invx,
               const int32_t* extidx, int colour, int npatch, bool finest, bool packed, int nrhs, int64_t ld,
-              double omega, const int32_t* plist, hipStream_t s) {
+              double omega, const int32_t* plist, int il, hipStream_t s) {
   if (npatch <= 0) return;
   const int nblk = (npatch + 3) / 4;
+  if constexpr (K >= 1 && std::is_same<T, float>::value && std::is_same<S, bf16>::value) {
+    if (il > 0) {
+      // the listed patches of a level whose columns are interleaved records of il values
+      // (rotated inverses, one column per block)
+      const int gx = nblk >= 64 ? (nblk + 7) / 8 * 8 : (nblk % 8 == 0 ? nblk + 1 : nblk);
+      hipLaunchKernelGGL((k_colour<T, S, K, 0, true, false, false, true>), dim3(gx, nrhs), dim3(256), 0, s,
+                         (const Elem<T, K>*)elem, L.N, L.bcm, (T)L.h, (const T*)L.kap, (T*)x, (const T*)b,
+                         (const S*)inv, (const S*)invx, extidx, colour, L.colouring, npatch, (int64_t)il, nrhs, 1,
+                         (T)omega, plist);
+      return;
+    }
+  }
   // a short list of patches (the boundary patches beside the several-column kernel):
   // one column per block, so that the columns run in parallel
   const int ncol = plist ? 1 : colour_columns_per_block(L.N, packed, npatch, nrhs);
@@ -1587,17 +1719,17 @@ void launch_patch_pinv(int K, int sprec, const void* elem64, const LevelArgs& L,
 
 template <int K>
 static void colour_mr_t(const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
-                        const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s) {
+                        const int32_t* tab, int colour, int npatch, int rp, hipStream_t s) {
   if (npatch <= 0) return;
   hipLaunchKernelGGL((k_colour_mr<K>), dim3((npatch + 7) & ~7), dim3(256), 0, s, (const ElemInt<float, K>*)elem_int, L.N,
                      (float)L.h, (const float*)L.kap, (float*)x, (const float*)b, (const bf16*)inv,
-                     (const int4*)tab, colour, L.colouring, npatch, ld, nrhs);
+                     (const int4*)tab, colour, L.colouring, npatch, rp);
 }
 
 void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, const void* b, const void* inv,
-                      const int32_t* tab, int colour, int npatch, int nrhs, int64_t ld, hipStream_t s) {
-  if (K == 1) colour_mr_t<1>(elem_int, L, x, b, inv, tab, colour, npatch, nrhs, ld, s);
-  else if (K == 2) colour_mr_t<2>(elem_int, L, x, b, inv, tab, colour, npatch, nrhs, ld, s);
+                      const int32_t* tab, int colour, int npatch, int rp, hipStream_t s) {
+  if (K == 1) colour_mr_t<1>(elem_int, L, x, b, inv, tab, colour, npatch, rp, s);
+  else if (K == 2) colour_mr_t<2>(elem_int, L, x, b, inv, tab, colour, npatch, rp, s);
 }
 
 int mr_table_entries(int K) {
@@ -1623,9 +1755,9 @@ void mr_layout(int K, int* cw, int* xs, int* cs) {
 
 void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs& L, void* x, const void* b,
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch, bool finest,
-                   bool packed, int nrhs, int64_t ld, double omega, hipStream_t s, const int32_t* plist) {
+                   bool packed, int nrhs, int64_t ld, double omega, hipStream_t s, const int32_t* plist, int il) {
 #define BMG_COL(T, S, KK) \
-  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, plist, s)
+  colour_t<T, S, KK>(elem, L, x, b, inv, invx, extidx, colour, npatch, finest, packed, nrhs, ld, omega, plist, il, s)
   if (K == 0) {
     if (prec == 0) BMG_COL(double, double, 0);
     else if (sprec == 0) BMG_COL(float, double, 0);
@@ -1647,52 +1779,65 @@ void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs
 
 template <typename T, int K>
 static void restrict_t(const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs, int64_t ldf,
-                       int64_t ldc, hipStream_t s) {
-  const int n = Nc * Nc;
-  hipLaunchKernelGGL((k_restrict<T, K>), dim3((n + 255) / 256, nrhs), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc,
-                     bcm, (const T*)rf, (T*)bc, ldf, ldc);
+                       int64_t ldc, int il, hipStream_t s) {
+  const int64_t n = (int64_t)Nc * Nc;
+  if constexpr (K >= 1 && std::is_same<T, float>::value)
+    if (il > 0) {
+      hipLaunchKernelGGL((k_restrict<T, K, true>), dim3((unsigned)((n * il + 255) / 256)), dim3(256), 0, s,
+                         (const Xfer<T, K>*)xfer, Nc, bcm, (const T*)rf, (T*)bc, (int64_t)il, (int64_t)il);
+      return;
+    }
+  hipLaunchKernelGGL((k_restrict<T, K>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s,
+                     (const Xfer<T, K>*)xfer, Nc, bcm, (const T*)rf, (T*)bc, ldf, ldc);
 }
 void launch_restrict(int K, int prec, const void* xfer, int Nc, int bcm, const void* rf, void* bc, int nrhs,
-                     int64_t ldf, int64_t ldc, hipStream_t s) {
+                     int64_t ldf, int64_t ldc, hipStream_t s, int il) {
   if (K == 0) {
-    if (prec == 0) restrict_t<double, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
-    else restrict_t<float, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    if (prec == 0) restrict_t<double, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
+    else restrict_t<float, 0>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
   } else if (K == 1) {
-    if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
-    else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    if (prec == 0) restrict_t<double, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
+    else restrict_t<float, 1>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
   } else {
-    if (prec == 0) restrict_t<double, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
-    else restrict_t<float, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, s);
+    if (prec == 0) restrict_t<double, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
+    else restrict_t<float, 2>(xfer, Nc, bcm, rf, bc, nrhs, ldf, ldc, il, s);
   }
 }
 
 template <typename T, int K>
 static void prolong_t(const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs, int64_t ldc,
-                      int64_t ldf, hipStream_t s) {
-  const int n = Nc * Nc;
-  hipLaunchKernelGGL((k_prolong<T, K>), dim3((n + 255) / 256, nrhs), dim3(256), 0, s, (const Xfer<T, K>*)xfer, Nc,
-                     bcm, (const T*)xc, (T*)xf, ldc, ldf);
+                      int64_t ldf, int il, hipStream_t s) {
+  const int64_t n = (int64_t)Nc * Nc;
+  if constexpr (K >= 1 && std::is_same<T, float>::value)
+    if (il > 0) {
+      hipLaunchKernelGGL((k_prolong<T, K, true>), dim3((unsigned)((n * il + 255) / 256)), dim3(256), 0, s,
+                         (const Xfer<T, K>*)xfer, Nc, bcm, (const T*)xc, (T*)xf, (int64_t)il, (int64_t)il);
+      return;
+    }
+  hipLaunchKernelGGL((k_prolong<T, K>), dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s,
+                     (const Xfer<T, K>*)xfer, Nc, bcm, (const T*)xc, (T*)xf, ldc, ldf);
 }
 void launch_prolong(int K, int prec, const void* xfer, int Nc, int bcm, const void* xc, void* xf, int nrhs,
-                    int64_t ldc, int64_t ldf, hipStream_t s) {
+                    int64_t ldc, int64_t ldf, hipStream_t s, int il) {
   if (K == 0) {
-    if (prec == 0) prolong_t<double, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
-    else prolong_t<float, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    if (prec == 0) prolong_t<double, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
+    else prolong_t<float, 0>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
   } else if (K == 1) {
-    if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
-    else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    if (prec == 0) prolong_t<double, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
+    else prolong_t<float, 1>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
   } else {
-    if (prec == 0) prolong_t<double, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
-    else prolong_t<float, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, s);
+    if (prec == 0) prolong_t<double, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
+    else prolong_t<float, 2>(xfer, Nc, bcm, xc, xf, nrhs, ldc, ldf, il, s);
   }
 }
 
-void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s) {
+void launch_coarse(int prec, int n, const double* inv, const void* b, void* x, int nrhs, hipStream_t s, int il) {
   const size_t sh = (size_t)n * sizeof(double);
+  const int64_t cs = il > 0 ? 1 : n, es = il > 0 ? il : 1;
   if (prec == 0)
-    hipLaunchKernelGGL((k_coarse<double>), dim3(nrhs), dim3(256), sh, s, n, inv, (const double*)b, (double*)x);
+    hipLaunchKernelGGL((k_coarse<double>), dim3(nrhs), dim3(256), sh, s, n, inv, (const double*)b, (double*)x, cs, es);
   else
-    hipLaunchKernelGGL((k_coarse<float>), dim3(nrhs), dim3(256), sh, s, n, inv, (const float*)b, (float*)x);
+    hipLaunchKernelGGL((k_coarse<float>), dim3(nrhs), dim3(256), sh, s, n, inv, (const float*)b, (float*)x, cs, es);
 }
 
 void launch_fill_zero(int prec, void* x, int64_t n, hipStream_t s) {
@@ -1708,32 +1853,34 @@ void launch_identity(int prec, void* x, int64_t n, int64_t col0, int nrhs, hipSt
 }
 
 template <typename T, int NR>
-static void dense_t(const void* B, int64_t n, const void* x, void* y, hipStream_t s) {
+static void dense_t(const void* B, int64_t n, const void* x, void* y, int64_t cs, int64_t es, hipStream_t s) {
   const unsigned g = (unsigned)((n + 3) / 4);
-  hipLaunchKernelGGL((k_dense_rows<T, NR>), dim3(g), dim3(256), 0, s, (const T*)B, n, (const T*)x, (T*)y);
+  hipLaunchKernelGGL((k_dense_rows<T, NR>), dim3(g), dim3(256), 0, s, (const T*)B, n, (const T*)x, (T*)y, cs, es);
 }
 template <typename T>
-static void dense_nr(const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s) {
-  // columns in groups of at most 8 (registers of the partial sums)
+static void dense_nr(const void* B, int64_t n, const void* x, void* y, int nrhs, int il, hipStream_t s) {
+  // columns in groups of at most 8 (registers of the partial sums); column c at c * cs,
+  // entries es apart
   const size_t ts = sizeof(T);
+  const int64_t cs = il > 0 ? 1 : n, es = il > 0 ? il : 1;
   for (int c0 = 0; c0 < nrhs; c0 += 8) {
-    const void* xc = (const char*)x + (size_t)c0 * n * ts;
-    void* yc = (char*)y + (size_t)c0 * n * ts;
+    const void* xc = (const char*)x + (size_t)c0 * cs * ts;
+    void* yc = (char*)y + (size_t)c0 * cs * ts;
     switch (std::min(8, nrhs - c0)) {
-      case 1: dense_t<T, 1>(B, n, xc, yc, s); break;
-      case 2: dense_t<T, 2>(B, n, xc, yc, s); break;
-      case 3: dense_t<T, 3>(B, n, xc, yc, s); break;
-      case 4: dense_t<T, 4>(B, n, xc, yc, s); break;
-      case 5: dense_t<T, 5>(B, n, xc, yc, s); break;
-      case 6: dense_t<T, 6>(B, n, xc, yc, s); break;
-      case 7: dense_t<T, 7>(B, n, xc, yc, s); break;
-      default: dense_t<T, 8>(B, n, xc, yc, s); break;
+      case 1: dense_t<T, 1>(B, n, xc, yc, cs, es, s); break;
+      case 2: dense_t<T, 2>(B, n, xc, yc, cs, es, s); break;
+      case 3: dense_t<T, 3>(B, n, xc, yc, cs, es, s); break;
+      case 4: dense_t<T, 4>(B, n, xc, yc, cs, es, s); break;
+      case 5: dense_t<T, 5>(B, n, xc, yc, cs, es, s); break;
+      case 6: dense_t<T, 6>(B, n, xc, yc, cs, es, s); break;
+      case 7: dense_t<T, 7>(B, n, xc, yc, cs, es, s); break;
+      default: dense_t<T, 8>(B, n, xc, yc, cs, es, s); break;
     }
   }
 }
-void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s) {
-  if (prec == 0) dense_nr<double>(B, n, x, y, nrhs, s);
-  else dense_nr<float>(B, n, x, y, nrhs, s);
+void launch_dense_gemv(int prec, const void* B, int64_t n, const void* x, void* y, int nrhs, hipStream_t s, int il) {
+  if (prec == 0) dense_nr<double>(B, n, x, y, nrhs, il, s);
+  else dense_nr<float>(B, n, x, y, nrhs, il, s);
 }
 
 void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t n, hipStream_t s) {
@@ -1746,6 +1893,27 @@ void launch_cast(int to_prec, int from_prec, const void* src, void* dst, int64_t
     hipLaunchKernelGGL((k_cast<double, double>), dim3(g), dim3(256), 0, s, (const double*)src, (double*)dst, n);
   else
     hipLaunchKernelGGL((k_cast<float, float>), dim3(g), dim3(256), 0, s, (const float*)src, (float*)dst, n);
+}
+
+void launch_cast_il(int to_prec, int from_prec, const void* src, void* dst, int64_t n, int64_t ld, int nrhs, int w,
+                    bool to_il, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 63) / 64);
+  if (to_il) {
+    // the interleaved side is FP32 (the arithmetic of a several-column V-cycle)
+    if (from_prec == 0)
+      hipLaunchKernelGGL((k_to_il<float, double>), dim3(g), dim3(256), 0, s, (const double*)src, (float*)dst, n, ld,
+                         nrhs, w);
+    else
+      hipLaunchKernelGGL((k_to_il<float, float>), dim3(g), dim3(256), 0, s, (const float*)src, (float*)dst, n, ld,
+                         nrhs, w);
+  } else {
+    if (to_prec == 0)
+      hipLaunchKernelGGL((k_from_il<double, float>), dim3(g), dim3(256), 0, s, (const float*)src, (double*)dst, n,
+                         ld, nrhs, w);
+    else
+      hipLaunchKernelGGL((k_from_il<float, float>), dim3(g), dim3(256), 0, s, (const float*)src, (float*)dst, n, ld,
+                         nrhs, w);
+  }
 }
 
 void launch_copy_constrained(int K, int N, int bcm, const double* src, void* dst, int dst_prec, int nrhs, int64_t ld,
