@@ -33,6 +33,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernels_sha16():
+    """First 16 hex digits of the sha256 of the 2-D kernel sources (kernels.hip, then
+    colour_body.inc): the version of the kernels a stored counter reading belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "colour_body.inc"):
+        with open(os.path.join(ROOT, "paper_1602_04858_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(profile):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in
+    profiles/ (KiB per dispatch, each scaled by what the counter reads for a plain copy
+    of known size), or None if the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("counters:"):
+            kv = dict(t.split("=") for t in line.split()[1:])
+            if kv.get("kernels_sha16") != kernels_sha16():
+                return None
+            return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+                    float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+    return None
+
+
 def timed_solves(torch, s, b, steps, warmup, rtol):
     x = s.zeros()
     info = None
@@ -193,10 +222,15 @@ def bench_c5(args, torch, bmg, inputs):
     s.kernel_timing(-1, 0)
     avg_s = ms * 1e-3 / nl
     achieved = by / nl / avg_s / 1e9
+    traffic = stored_traffic("colour_step_c5_counters.md") if w.n == 2048 and R == 16 else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_colour_mr<2> (interior patches, MFMA) + k_colour boundary list, finest-level colour step",
             "launches": nl, "avg_us": avg_s * 1e6, "bytes_per_launch": by / nl}
+    if traffic is not None:
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["traffic_over_algorithmic"] = traffic / (by / nl)
+        roof["traffic_source"] = "profiles/colour_step_c5_counters.md"
     log(f"bench: finest colour step {achieved:.0f} GB/s, {avg_s * 1e6:.0f} us per step")
     x0 = x[0].clone()
     s.close()
