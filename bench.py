@@ -396,6 +396,46 @@ def bench_d3(args, torch, bmg, inputs):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args, torch, bmg, inputs):
+    """Robustness study standing in for the paper's Tables 1-2 (Section 4, characteristic
+    permeability fields): GMRES iterations to a 1e-6 reduction of the residual for
+    two-phase fields (foam walls, disjoint inclusions, connected inclusions; seeded
+    128 x 128 images) with kappa = 1 / 10^-e (e = 4, 5, 6) in case (a) and the phases
+    reversed in case (b), Darcy (mu = 0) and Brinkman (mu = 1e-2), h = 1/128, 1/256,
+    1/512 (the image resolved by 1, 4, 16 cells per pixel).  RT_1 x dQ_1, variable V-cycle
+    (m_J = 2), FP64 FGMRES(100), f = (1, 0), no-slip left / right, open top / bottom."""
+    import numpy as np
+    sizes = [int(v) for v in args.sweep_sizes.split(",")]
+    rows = []
+    t0 = time.perf_counter()
+    for ki, kind in enumerate(inputs.PHASE_KINDS):
+        for case in ("a", "b"):
+            for model, mu in (("darcy", 0.0), ("brinkman", 1e-2)):
+                for e in (4, 5, 6):
+                    its = {}
+                    for n in sizes:
+                        kap = inputs.kappa_two_phase(kind, 7100 + ki, n, e, reverse=(case == "b"))
+                        levels = int(round(math.log2(n // 2)))
+                        p = bmg.make_params(2, levels, 1, mu, 6.0, (0, 0, 1, 1), 1, 2, bmg.P_FP64, 100, 16384)
+                        s = bmg.Solver(p, kap)
+                        b = torch.as_tensor(bmg.assemble_rhs(p, inputs.constant_source(1.0, 0.0)), device="cuda")
+                        _, info = s.solve(b, rtol=1e-6, maxit=400)
+                        its[n] = info.iterations if info.converged else -info.iterations
+                        s.close()
+                        del s
+                    rows.append({"field": kind, "case": case, "model": model, "contrast": f"1e{e}",
+                                 "iterations": {str(n): its[n] for n in sizes}})
+                    log(f"bench: sweep {kind:10s} ({case}) {model:8s} 1e{e}: " +
+                        " ".join(f"h=1/{n}: {its[n]}" for n in sizes) + f"  [{time.perf_counter() - t0:.0f} s]")
+    out = {"metric": "GMRES iterations to 1e-6 residual reduction (robustness in h and contrast)",
+           "unit": "iterations", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "two-phase kappa stand-ins for the foam / inclusion / connected-inclusion "
+                                  "fields, RT_1, variable V-cycle m=2, FP64 FGMRES(100), rtol 1e-6",
+                      "sizes": sizes},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,9 +445,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
-    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3"],
+    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3", "sweep"],
                     help="C5 (default: 2048^2 RT_2, 16 right-hand sides, the largest configuration), C2 (256^2 "
-                         "RT_1), the 1024^2 precision study, the 48-problem batch or the 3-D solver")
+                         "RT_1), the 1024^2 precision study, the 48-problem batch, the 3-D solver, or the "
+                         "robustness sweep over two-phase fields (iteration counts)")
+    ap.add_argument("--sweep-sizes", default="128,256,512", help="sweep: cells per side")
     ap.add_argument("--streams", type=int, default=4, help="C4: worker streams of the batch")
     ap.add_argument("--problems", type=int, default=48, help="C4: problems in the batch")
     ap.add_argument("--n", type=int, default=2048, help="C5: cells per side (the 2048^2 generator at this size)")
@@ -455,6 +497,8 @@ def main():
         return bench_c5(args, torch, bmg, inputs)
     if args.workload == "D3":
         return bench_d3(args, torch, bmg, inputs)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, bmg, inputs)
 
     w = inputs.workload(args.workload)
     log(f"bench: workload {w.name} N={w.n} levels={w.levels + 1} k={w.k} mu={w.mu}")

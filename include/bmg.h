@@ -104,6 +104,15 @@ typedef struct {
   int32_t setup_on_host; /* 0 (default): the patch pseudo-inverses are computed on the device (FP64
                             Gauss-Jordan, one workgroup per patch); 1: on the host (FP64 Gauss-Jordan on
                             every host thread).  The same matrices up to rounding */
+  /* Tile parameters (performance only: the same method and results up to rounding; set
+     by bmg_autotune_tiles, 0 = the built-in choice): */
+  int32_t rotated_min_n;  /* one-column and FP64 handles: levels with at least this many cells per
+                             side store their patch pseudo-inverses as rotated symmetric blocks
+                             (about half the bytes, staged through LDS), smaller levels as full
+                             blocks; 0 = 192; 0..4096 */
+  int32_t columns_per_block; /* several-column handles on levels without the several-column
+                                bfloat16 kernel: columns one block of the colour kernel applies a
+                                patch inverse to; 0 = automatic; 0..16 */
 } bmg_params;
 
 typedef struct {
@@ -220,6 +229,18 @@ bmg_status bmg_batch_destroy(bmg_batch_handle b);
  * Allocates and frees its own device memory; costs two setups. */
 bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
                         bmg_params* best, double* ms_per_vcycle);
+/* Pick the colouring and the tile parameters (rotated_min_n, columns_per_block) for p by
+ * coordinate descent: the colourings first, then the storage threshold (192, 64, 4096),
+ * then, for several columns outside the several-column bfloat16 kernel, the columns per
+ * block (automatic, 1, 4, 16); every candidate is one setup timed over `trials` V-cycles
+ * (graph replay, HIP events) on hip_stream.  The result is kept for the process, keyed
+ * by (k, finest N, levels, precision, n_rhs, smoother, cycle, dense_coarse_max): a later
+ * call with the same key returns it without timing (*n_report = 0).  report: NULL or
+ * room for 4 * max_report doubles, one (colouring, rotated_min_n, columns_per_block,
+ * ms per V-cycle) row per timed candidate; *n_report (may be NULL) the rows written.
+ * Allocates and frees its own device memory. */
+bmg_status bmg_autotune_tiles(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
+                              bmg_params* best, double* report, int32_t max_report, int32_t* n_report);
 
 /* ----- setup-side host calls (no handle, no device) ----- */
 /* Quadrature points of bmg_assemble_rhs on the finest mesh of p (host arrays).

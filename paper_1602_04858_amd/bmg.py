@@ -41,7 +41,8 @@ class Params(C.Structure):
                 ("sigma", C.c_double), ("bc", C.c_int32 * 4), ("cycle", C.c_int32), ("m_fine", C.c_int32),
                 ("precond_prec", C.c_int32), ("restart", C.c_int32), ("dense_coarse_max", C.c_int32),
                 ("n_rhs", C.c_int32), ("colouring", C.c_int32), ("smoother", C.c_int32), ("omega", C.c_double),
-                ("coarse_kappa", C.c_int32), ("setup_on_host", C.c_int32)]
+                ("coarse_kappa", C.c_int32), ("setup_on_host", C.c_int32), ("rotated_min_n", C.c_int32),
+                ("columns_per_block", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -73,6 +74,7 @@ _sig = {
     "bmg_export_level_matrix": [_P(Params), _dp, _I32, _dp],
     "bmg_export_colouring": [_P(Params), _I32, _P(_I32), _VP],
     "bmg_autotune": [_P(Params), _dp, _VP, _I32, _P(Params), _VP],
+    "bmg_autotune_tiles": [_P(Params), _dp, _VP, _I32, _P(Params), _VP, _I32, _P(_I32)],
     "bmg_kernel_timing": [_VP, _I32, _I32],
     "bmg_kernel_timing_read": [_VP, _P(_I32), _P(_D), _P(_D)],
     "bmg_batch_setup": [_I32, _P(Params), _P(_P(_D)), _I32, _VP, _P(_VP)],
@@ -108,7 +110,7 @@ DENSE_COARSE_DEFAULT = 16384
 
 def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, prec=P_FP64, restart=100,
                 dense_coarse_max=0, n_rhs=1, colouring=COLOURING_S9, smoother=SMOOTHER_MULTIPLICATIVE, omega=0.25,
-                coarse_kappa=KAPPA_ARITHMETIC, setup_on_host=0):
+                coarse_kappa=KAPPA_ARITHMETIC, setup_on_host=0, rotated_min_n=0, columns_per_block=0):
     p = Params()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     for i in range(4):
@@ -121,6 +123,8 @@ def make_params(n0, levels, k, mu, sigma, bc, cycle=CYCLE_VARIABLE, m_fine=2, pr
     p.omega = float(omega)
     p.coarse_kappa = coarse_kappa
     p.setup_on_host = setup_on_host
+    p.rotated_min_n = rotated_min_n
+    p.columns_per_block = columns_per_block
     return p
 
 
@@ -414,6 +418,24 @@ def autotune(params: Params, kappa, trials=5, device="cuda"):
     if st:
         raise BmgError(st, f"autotune: {_lib.bmg_last_error(None).decode()}")
     return best, {"S9": float(ms[0]), "L8": float(ms[1])}
+
+
+def autotune_tiles(params: Params, kappa, trials=5, device="cuda"):
+    """(parameters with the chosen colouring, rotated_min_n and columns_per_block, list of
+    (colouring, rotated_min_n, columns_per_block, ms per V-cycle) rows of the timed
+    candidates -- empty when the choice came from the per-process cache), by
+    bmg_autotune_tiles."""
+    import torch
+    kap = _kappa_host(kappa, _cells2(params))
+    stream = torch.cuda.current_stream(torch.device(device))
+    best = Params()
+    rep = np.zeros((16, 4))
+    nrep = C.c_int32()
+    st = _lib.bmg_autotune_tiles(C.byref(params), kap, C.c_void_p(stream.cuda_stream), trials, C.byref(best),
+                                 rep.ctypes.data_as(C.c_void_p), 16, C.byref(nrep))
+    if st:
+        raise BmgError(st, f"autotune_tiles: {_lib.bmg_last_error(None).decode()}")
+    return best, [tuple(r) for r in rep[:nrep.value]]
 
 
 def export_colouring(params: Params, level):

@@ -97,6 +97,7 @@ struct LevelArgs {
   double h;
   const void* kap;  // kappa of the level, arithmetic `prec`
   int colouring;    // COLOURING_S9 or COLOURING_L8
+  int cpb = 0;      // columns per block of several-column colour launches (0: automatic)
 };
 
 // Vertex colourings of the smoother: S9, colour (vx mod 3) + 3 (vy mod 3); L8, the
@@ -153,8 +154,9 @@ void launch_colour(int K, int prec, int sprec, const void* elem, const LevelArgs
                    const void* inv, const void* invx, const int32_t* extidx, int colour, int npatch,
                    bool finest, bool packed, int nrhs, int64_t ld, double omega, hipStream_t s,
                    const int32_t* plist = nullptr, int il = 0);
-// columns one block of the colour kernel serves (for the byte count of a launch)
-int colour_columns_per_block(int N, bool packed, int npatch, int nrhs);
+// columns one block of the colour kernel serves (for the byte count of a launch);
+// cpb > 0 (a tile parameter) overrides the automatic choice
+int colour_columns_per_block(int N, bool packed, int npatch, int nrhs, int cpb = 0);
 // The colour step on the interior patches of a level (K = 1 or 2) for FP32 columns in
 // interleaved records of rp = 4, 8 or 16 values, with bfloat16 rotated inverses; the
 // other patches of the colour are left alone (launch_colour with their list does

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -154,6 +155,8 @@ bmg_status check_params(const bmg_params* p) {
   if (p->smoother != BMG_SMOOTHER_MULTIPLICATIVE && p->smoother != BMG_SMOOTHER_ADDITIVE) return BMG_E_ARG;
   if (p->smoother == BMG_SMOOTHER_ADDITIVE && !(p->omega > 0.0 && p->omega <= 1.0)) return BMG_E_ARG;
   if (p->setup_on_host != 0 && p->setup_on_host != 1) return BMG_E_ARG;
+  if (p->rotated_min_n < 0 || p->rotated_min_n > 4096) return BMG_E_ARG;
+  if (p->columns_per_block < 0 || p->columns_per_block > 16) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -510,9 +513,11 @@ bool packed_level(const bmg_ctx* c, int N) {
   // columns are stored rotated on every level (half the memory: 2048^2 RT_2 with 16
   // columns only fits that way), staged per patch in LDS for the product.
   if (c->R > 1 && c->prec != 0) return c->K >= 1 && c->sprec == 2;
-  // one column (or FP64): rotated on the bandwidth-bound levels; RT_2 in FP64 reads its
-  // rotated blocks from memory in the product
-  return N >= 192 && (c->K <= 1 || c->prec == 0);
+  // one column (or FP64): rotated on the bandwidth-bound levels (N >= 192 unless the
+  // tile parameter says otherwise); RT_2 in FP64 reads its rotated blocks from memory
+  // in the product
+  const int nmin = c->p.rotated_min_n > 0 ? c->p.rotated_min_n : 192;
+  return N >= nmin && (c->K <= 1 || c->prec == 0);
 }
 // Interior patches of level j run the several-column kernel (k_colour_mr): 2..16
 // FP32 columns, bfloat16 rotated inverses, RT_1 or RT_2, multiplicative smoother.
@@ -877,6 +882,7 @@ LevelArgs largs(bmg_ctx* c, int j, bool fp64) {
   a.h = c->lev[j].h;
   a.kap = fp64 ? (const void*)c->lev[j].kap64 : c->lev[j].kap;
   a.colouring = c->p.colouring;
+  a.cpb = c->p.columns_per_block;
   return a;
 }
 
@@ -1033,7 +1039,7 @@ double colour_bytes(const bmg_ctx* c, int j, int col, int nrhs) {
     const double nb = (double)L.hblist[col].size(), np = std::max(1, L.npatch[col]);
     inv_bytes *= 1.0 + (nrhs - 1) * nb / np;
   } else {
-    const int ncol = colour_columns_per_block(L.N, pk, L.npatch[col], nrhs);
+    const int ncol = colour_columns_per_block(L.N, pk, L.npatch[col], nrhs, c->p.columns_per_block);
     inv_bytes *= (double)((nrhs + ncol - 1) / ncol);
   }
   // x on the patch is written once (its old values come with the gather)
@@ -2155,51 +2161,152 @@ bmg_status bmg_batch_destroy(bmg_batch_handle b) try {
 
 
 // ----- autotuning of the smoother schedule -----
+}  // extern "C"
+
+namespace {
+
+// Time `trials` preconditioner applications (graph replay) of a handle set up with q.
+bmg_status time_vcycles(const bmg_params* q, const double* kappa_host, void* hip_stream, int32_t trials,
+                        double* ms_per) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  bmg_handle h = nullptr;
+  bmg_status st = bmg_setup(q, kappa_host, nullptr, 0, hip_stream, &h);
+  if (st) return st;
+  LevelInfo& L = h->lev.back();
+  const int64_t n = L.ndof * h->R;
+  double* r = nullptr;
+  double* z = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.0f;
+  bool ok = hipMalloc((void**)&r, n * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&z, n * sizeof(double)) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+            hipEventCreate(&e1) == hipSuccess;
+  if (ok) {
+    // constant 1 as input (the timing does not depend on the values)
+    std::vector<double> one(n, 1.0);
+    ok = hipMemcpyAsync(r, one.data(), n * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess;
+    apply_precond(h, r, z);  // captures the graph
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    for (int t = 0; ok && t < trials; ++t) apply_precond(h, r, z);
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (r) (void)hipFree(r);
+  if (z) (void)hipFree(z);
+  bmg_destroy(h);
+  if (!ok) return BMG_E_HIP;
+  *ms_per = ms / trials;
+  return BMG_OK;
+}
+
+// tile choices found so far in this process, by problem shape
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, bmg_params> g_tune_cache;
+
+std::vector<int64_t> tune_key(const bmg_params* p) {
+  return {p->k, (int64_t)p->n0 << p->levels, p->levels, p->precond_prec, std::max(1, p->n_rhs), p->smoother,
+          p->cycle, p->dense_coarse_max};
+}
+
+}  // namespace
+
+extern "C" {
+
 bmg_status bmg_autotune(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
                         bmg_params* best, double* ms_per_vcycle) try {
   bmg_status st = check_params(p);
   if (st) return st;
   if (!best || trials < 1 || trials > 1000) return BMG_E_ARG;
   if ((st = check_kappa(p, kappa_host))) return st;
-  hipStream_t s = (hipStream_t)hip_stream;
   double best_ms = -1.0;
   for (int cand = 0; cand < 2; ++cand) {
     bmg_params q = *p;
     q.colouring = cand == 0 ? BMG_COLOURING_S9 : BMG_COLOURING_L8;
-    bmg_handle h = nullptr;
-    if ((st = bmg_setup(&q, kappa_host, nullptr, 0, hip_stream, &h))) return st;
-    LevelInfo& L = h->lev.back();
-    const int64_t n = L.ndof * h->R;
-    double* r = nullptr;
-    double* z = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    float ms = 0.0f;
-    bool ok = hipMalloc((void**)&r, n * sizeof(double)) == hipSuccess &&
-              hipMalloc((void**)&z, n * sizeof(double)) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
-              hipEventCreate(&e1) == hipSuccess;
-    if (ok) {
-      // a smooth-free input: constant 1 on the free rows (the timing does not depend on the values)
-      std::vector<double> one(n, 1.0);
-      ok = hipMemcpyAsync(r, one.data(), n * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess;
-      apply_precond(h, r, z);  // captures the graph
-      ok = ok && hipEventRecord(e0, s) == hipSuccess;
-      for (int t = 0; ok && t < trials; ++t) apply_precond(h, r, z);
-      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (r) (void)hipFree(r);
-    if (z) (void)hipFree(z);
-    bmg_destroy(h);
-    if (!ok) return BMG_E_HIP;
-    const double per = ms / trials;
+    double per = 0.0;
+    if ((st = time_vcycles(&q, kappa_host, hip_stream, trials, &per))) return st;
     if (ms_per_vcycle) ms_per_vcycle[cand] = per;
     if (best_ms < 0.0 || per < best_ms) {
       best_ms = per;
       *best = q;
     }
   }
+  return BMG_OK;
+} catch (const std::bad_alloc&) {
+  return BMG_E_NOMEM;
+} catch (...) {
+  return BMG_E_STATE;
+}
+
+bmg_status bmg_autotune_tiles(const bmg_params* p, const double* kappa_host, void* hip_stream, int32_t trials,
+                              bmg_params* best, double* report, int32_t max_report, int32_t* n_report) try {
+  bmg_status st = check_params(p);
+  if (st) return st;
+  if (!best || trials < 1 || trials > 1000 || max_report < 0 || (max_report > 0 && !report)) return BMG_E_ARG;
+  if ((st = check_kappa(p, kappa_host))) return st;
+  if (n_report) *n_report = 0;
+  const std::vector<int64_t> key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best = *p;
+      best->colouring = it->second.colouring;
+      best->rotated_min_n = it->second.rotated_min_n;
+      best->columns_per_block = it->second.columns_per_block;
+      return BMG_OK;
+    }
+  }
+  int rows = 0;
+  bmg_params cur = *p;
+  double cur_ms = -1.0;
+  // one coordinate at a time: each candidate differs from the best so far in one parameter
+  auto trial = [&](bmg_params q) -> bmg_status {
+    double per = 0.0;
+    bmg_status s2 = time_vcycles(&q, kappa_host, hip_stream, trials, &per);
+    if (s2) return s2;
+    if (rows < max_report) {
+      report[4 * rows + 0] = q.colouring;
+      report[4 * rows + 1] = q.rotated_min_n;
+      report[4 * rows + 2] = q.columns_per_block;
+      report[4 * rows + 3] = per;
+    }
+    ++rows;
+    if (cur_ms < 0.0 || per < cur_ms) {
+      cur_ms = per;
+      cur = q;
+    }
+    return BMG_OK;
+  };
+  for (int col : {BMG_COLOURING_S9, BMG_COLOURING_L8}) {
+    bmg_params q = cur;
+    q.colouring = col;
+    if ((st = trial(q))) return st;
+  }
+  {
+    const bmg_params base = cur;
+    for (int nmin : {64, 4096}) {
+      bmg_params q = base;
+      q.rotated_min_n = nmin;
+      if ((st = trial(q))) return st;
+    }
+  }
+  bmg_ctx probe;
+  probe.p = *p;
+  setup_types(&probe);
+  if (probe.R > 1 && !mr_handle(&probe)) {
+    const bmg_params base = cur;
+    for (int cpb : {1, 4, 16}) {
+      bmg_params q = base;
+      q.columns_per_block = cpb;
+      if ((st = trial(q))) return st;
+    }
+  }
+  *best = cur;
+  if (n_report) *n_report = std::min(rows, max_report);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = cur;
   return BMG_OK;
 } catch (const std::bad_alloc&) {
   return BMG_E_NOMEM;

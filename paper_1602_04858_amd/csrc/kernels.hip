@@ -1626,8 +1626,11 @@ void launch_op(int K, int prec, const void* elem, const LevelArgs& L, const void
 // Columns one block of k_colour serves: all of them on the bandwidth-bound levels
 // (N >= 192: the inverse is read once per patch for all columns) and with rotated
 // storage (up to 16 columns); elsewhere enough blocks to fill the device come first.
-int colour_columns_per_block(int N, bool packed, int npatch, int nrhs) {
+int colour_columns_per_block(int N, bool packed, int npatch, int nrhs, int cpb) {
   if (nrhs <= 1) return 1;
+  // the tile parameter applies to a handle's own columns (at most 16), not to the setup
+  // batches of unit vectors
+  if (cpb > 0 && nrhs <= 16) return std::min(nrhs, cpb);
   if (N >= 192) return std::min(nrhs, 16);
   // rotated storage on a small level with many columns (the setup batch of unit vectors
   // that builds the dense coarse operator): one column per block, the columns in parallel
@@ -1657,7 +1660,7 @@ static void colour_t(const void* elem, const LevelArgs& L, void* x, const void* 
   }
   // a short list of patches (the boundary patches beside the several-column kernel):
   // one column per block, so that the columns run in parallel
-  const int ncol = plist ? 1 : colour_columns_per_block(L.N, packed, npatch, nrhs);
+  const int ncol = plist ? 1 : colour_columns_per_block(L.N, packed, npatch, nrhs, L.cpb);
   // large grids: a multiple of the 8 XCDs (the kernel then maps blocks to strips);
   // small ones (coarse levels, setup batches): one block per 4 patches, plain order
   // (a count that happens to be a multiple of 8 gets one idle block more)

@@ -141,6 +141,100 @@ def kappa_layered3(n: int, seed: int, layers: int = 85) -> np.ndarray:
     return np.power(10.0, np.clip(g, -6.0, 1.0)).reshape(-1)
 
 
+# ---------------------------------------------------------------------------
+# Two-phase fields (stand-ins for the open-foam / inclusion / connected-inclusion
+# images of the robustness tests of Section 4: kappa = 1 in one phase, 10^-e in the
+# other, given on a 128 x 128 pixel grid and resolved by finer meshes)
+# ---------------------------------------------------------------------------
+PHASE_KINDS = ("foam", "inclusions", "connected")
+
+
+def _disks(st: _Stream, m: int, target: float, rmin: float, rmax: float, overlap: bool) -> list:
+    """Random disks (cx, cy, r) in pixel units on an m x m grid until the covered
+    fraction of the area reaches `target`; without `overlap` a disk is kept only if it
+    keeps a gap of 2 pixels to every kept disk."""
+    disks, covered, tries = [], 0.0, 0
+    while covered < target and tries < 20000:
+        u = st.uniform(3)
+        tries += 1
+        r = rmin + (rmax - rmin) * u[2]
+        cx, cy = r + (m - 2 * r) * u[0], r + (m - 2 * r) * u[1]
+        if not overlap and any((cx - a) ** 2 + (cy - b) ** 2 < (r + q + 2.0) ** 2 for a, b, q in disks):
+            continue
+        disks.append((cx, cy, r))
+        covered += math.pi * r * r / (m * m)
+    return disks
+
+
+def _paint_disks(disks: list, m: int) -> np.ndarray:
+    yy, xx = np.mgrid[0:m, 0:m] + 0.5
+    out = np.zeros((m, m), dtype=bool)
+    for cx, cy, r in disks:
+        out |= (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+    return out
+
+
+def _paint_segment(img: np.ndarray, a: tuple, b: tuple, width: int) -> None:
+    """A straight band of `width` pixels from point a to point b."""
+    m = img.shape[0]
+    steps = int(2 * max(abs(b[0] - a[0]), abs(b[1] - a[1]))) + 1
+    for t in np.linspace(0.0, 1.0, steps):
+        x, y = a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])
+        x0, y0 = int(x - width / 2 + 0.5), int(y - width / 2 + 0.5)
+        img[max(y0, 0):min(y0 + width, m), max(x0, 0):min(x0 + width, m)] = True
+
+
+def phase_image(kind: str, seed: int, m: int = 128) -> np.ndarray:
+    """m x m boolean image of the structure phase (row = y pixel, column = x pixel).
+
+    foam: the walls of a Voronoi tessellation of 40 random sites, 2 pixels thick -- a
+          connected skeleton spanning the domain, open pores between;
+    inclusions: disjoint disks of radius 3..8 pixels (2-pixel gaps), 20% of the area;
+    connected: the inclusions joined into chains: every disk is linked to its nearest
+          neighbour by a 2-pixel band, and the chain of disks nearest the left edge to
+          the right edge, so that the structure phase spans the domain.
+    """
+    st = _Stream(seed)
+    if kind == "foam":
+        sites = st.uniform(80).reshape(40, 2) * m
+        yy, xx = np.mgrid[0:m, 0:m] + 0.5
+        d = np.sqrt((xx[..., None] - sites[:, 0]) ** 2 + (yy[..., None] - sites[:, 1]) ** 2)
+        d.sort(axis=-1)
+        return (d[..., 1] - d[..., 0]) < 2.0
+    disks = _disks(st, m, 0.20, 3.0, 8.0, overlap=False)
+    img = _paint_disks(disks, m)
+    if kind == "inclusions":
+        return img
+    if kind != "connected":
+        raise KeyError(kind)
+    for i, (x, y, _) in enumerate(disks):
+        j = min((k for k in range(len(disks)) if k != i),
+                key=lambda k: (disks[k][0] - x) ** 2 + (disks[k][1] - y) ** 2)
+        _paint_segment(img, (x, y), (disks[j][0], disks[j][1]), 2)
+    # a spanning path: from the left edge through the disks ordered by x to the right edge
+    order = sorted(range(len(disks)), key=lambda k: disks[k][0])
+    band = sorted(order, key=lambda k: abs(disks[k][1] - m / 2))[: max(2, len(disks) // 4)]
+    band.sort(key=lambda k: disks[k][0])
+    pts = [(0.0, disks[band[0]][1])] + [(disks[k][0], disks[k][1]) for k in band] + [(float(m), disks[band[-1]][1])]
+    for a, b in zip(pts[:-1], pts[1:]):
+        _paint_segment(img, a, b, 2)
+    return img
+
+
+def kappa_two_phase(kind: str, seed: int, n: int, exponent: int, reverse: bool = False,
+                    m: int = 128) -> np.ndarray:
+    """Cellwise kappa on an n x n mesh (n a multiple of m) from the m x m phase image:
+    the matrix phase kappa = 1 and the structure 10^-exponent (case (a)), or the reverse
+    (case (b)); every pixel covers (n/m)^2 cells."""
+    if n % m:
+        raise ValueError("n must be a multiple of the image size")
+    img = phase_image(kind, seed, m)
+    low = img if not reverse else ~img
+    k = np.where(low, 10.0 ** (-exponent), 1.0)
+    r = n // m
+    return np.repeat(np.repeat(k, r, axis=0), r, axis=1).reshape(-1)
+
+
 def kappa_constant(n: int, value: float = 1.0) -> np.ndarray:
     return np.full(n * n, float(value))
 

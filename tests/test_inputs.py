@@ -5,6 +5,7 @@ range, contrast, channels that cross the domain, layers."""
 from collections import deque
 
 import numpy as np
+import pytest
 
 from paper_1602_04858_amd import inputs
 
@@ -104,3 +105,54 @@ def test_workloads_are_deterministic_and_distinct():
     assert np.array_equal(a.kappa, b.kappa)
     c0, c1 = inputs.workload("C4", 0), inputs.workload("C4", 1)
     assert c0.kappa.size != c1.kappa.size or not np.array_equal(c0.kappa, c1.kappa)
+
+
+def _components(img):
+    from scipy import ndimage
+    lab, n = ndimage.label(img)
+    return lab, n
+
+
+def _spans(lab, n, axis):
+    """Some component touches both edges across `axis` (1: left to right)."""
+    first = set(np.unique(np.take(lab, 0, axis=axis))) - {0}
+    last = set(np.unique(np.take(lab, -1, axis=axis))) - {0}
+    return bool(first & last)
+
+
+def test_two_phase_images_recipe():
+    """Foam: Voronoi walls that span the domain both ways; inclusions: disjoint disks
+    (one component per disk, about 20% of the area, none touching another); connected
+    inclusions: the same disks joined so that the structure spans left to right."""
+    m = 128
+    foam = inputs.phase_image("foam", 7100, m)
+    lab, n = _components(foam)
+    assert 0.15 < foam.mean() < 0.35
+    assert _spans(lab, n, 1) and _spans(lab, n, 0)
+    inc = inputs.phase_image("inclusions", 7100, m)
+    st = inputs._Stream(7100)
+    disks = inputs._disks(st, m, 0.20, 3.0, 8.0, overlap=False)
+    lab, n = _components(inc)
+    assert n == len(disks) and 0.15 < inc.mean() < 0.25
+    assert not _spans(lab, n, 1) and not _spans(lab, n, 0)
+    con = inputs.phase_image("connected", 7100, m)
+    lab, n = _components(con)
+    assert np.all(con[inc])                    # the disks are kept, bands added
+    assert n < len(disks) // 3 and _spans(lab, n, 1)
+
+
+def test_two_phase_kappa_values_and_refinement():
+    m, e = 128, 5
+    img = inputs.phase_image("connected", 7200, m)
+    for n in (128, 256):
+        ka = inputs.kappa_two_phase("connected", 7200, n, e).reshape(n, n)
+        kb = inputs.kappa_two_phase("connected", 7200, n, e, reverse=True).reshape(n, n)
+        r = n // m
+        assert set(np.unique(ka)) == {10.0 ** -e, 1.0}
+        # every pixel covers an r x r block of cells carrying its value
+        assert np.array_equal(ka[::r, ::r] == 10.0 ** -e, img)
+        assert np.array_equal(ka, np.repeat(np.repeat(ka[::r, ::r], r, 0), r, 1))
+        # case (b) swaps the phases
+        assert np.array_equal(kb == 1.0, ka == 10.0 ** -e)
+    with pytest.raises(ValueError):
+        inputs.kappa_two_phase("foam", 1, 100, 4)

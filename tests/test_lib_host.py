@@ -306,3 +306,16 @@ def test_rhs_callables_of_the_wrong_size_are_refused():
     b = bmg.assemble_rhs(p, lambda x, y: np.stack([x, y], -1), s=lambda x, y: x * y,
                          g=lambda x, y: np.stack([0 * x, 0 * y], -1))
     assert np.isfinite(b).all()
+
+
+def test_tile_parameters_validated():
+    """rotated_min_n in 0..4096 and columns_per_block in 0..16 (0: built-in choice);
+    the plan does not depend on them beyond the storage of the inverses."""
+    from paper_1602_04858_amd import bmg
+    base = dict(n0=2, levels=5, k=1, mu=1e-2, sigma=6.0, bc=(0, 0, 1, 1))
+    assert bmg.plan(bmg.make_params(**base)) > 0
+    assert bmg.plan(bmg.make_params(**base, rotated_min_n=16, columns_per_block=4)) > 0
+    for bad in (dict(rotated_min_n=5000), dict(rotated_min_n=-1), dict(columns_per_block=17),
+                dict(columns_per_block=-2)):
+        with pytest.raises(bmg.BmgError):
+            bmg.plan(bmg.make_params(**base, **bad))
