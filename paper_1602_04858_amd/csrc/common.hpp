@@ -171,6 +171,12 @@ void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, 
 // position in the column's LDS block, 1 if it is read from b}; then for each slot
 // {LDS position of its first row contribution, of its second or -1, 0, 0}.  Positions
 // use the kernel's LDS layout (mr_layout: padded cell width cw, x part xs, column cs).
+// Both launches of a several-column colour step (launch_colour_mr on the npatch_mr
+// interior patches, launch_colour on the nlist listed ones with records of rp values)
+// as one launch (K = 1 or 2, FP32 with bfloat16 rotated inverses); for small levels.
+void launch_colour_fused(int K, const void* elem_int, const void* elem, const LevelArgs& L, void* x, const void* b,
+                         const void* inv, const void* invx, const int32_t* extidx, const int32_t* tab, int colour,
+                         int npatch_mr, int nlist, const int32_t* plist, int nrhs, int rp, hipStream_t s);
 int mr_table_entries(int K);
 void mr_steps(int K, int N, int* ax, int* ay);
 void mr_layout(int K, int* cw, int* xs, int* cs);

@@ -1046,6 +1046,8 @@ double colour_bytes(const bmg_ctx* c, int j, int col, int nrhs) {
   return inv_bytes + nrhs * (reg * (gather + 2.0 * nsr) + ext * (gather + 2.0 * nse)) * c->tsize;
 }
 
+constexpr int kFusedColourMaxN = 256;
+
 // One colour step of level j on nrhs columns of x, b (ld = level ndof apart, or with
 // il > 0 interleaved records of il values): the several-column kernel on the interior
 // patches plus the general kernel on the listed others, or the general kernel on
@@ -1055,7 +1057,16 @@ void colour_launch(bmg_ctx* c, int j, int col, void* x, const void* b, int nrhs,
   const LevelArgs a = largs(c, j, c->prec == 0);
   const bool finest = j == (int)c->lev.size() - 1, pk = packed_level(c, L.N);
   if (il > 0) {
-    // interleaved records: the several-column handle's own vectors (multiplicative)
+    // interleaved records: the several-column handle's own vectors (multiplicative).
+    // Levels up to kFusedColourMaxN cells per side, where a launch is a few dozen to a few
+    // thousand blocks and its latency dominates, do interior and listed patches in one
+    // launch; larger ones in two (the several-column kernel keeps its own, smaller LDS
+    // and four blocks per CU there)
+    if (L.mrtab && L.N <= kFusedColourMaxN) {
+      launch_colour_fused(c->K, c->elemInt, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], L.mrtab, col,
+                          L.npatch[col], (int)L.hblist[col].size(), L.blist[col], nrhs, il, c->stream);
+      return;
+    }
     if (L.mrtab) launch_colour_mr(c->K, c->elemInt, a, x, b, L.inv[col], L.mrtab, col, L.npatch[col], il, c->stream);
     launch_colour(c->K, c->prec, c->sprec, c->elemT, a, x, b, L.inv[col], L.invx[col], L.extidx[col], col,
                   (int)L.hblist[col].size(), finest, pk, nrhs, L.ndof, 0.0, c->stream, L.blist[col], il);

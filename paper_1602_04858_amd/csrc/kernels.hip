@@ -422,107 +422,13 @@ __global__ __launch_bounds__(256) void k_colour(const Elem<T, K>* __restrict__ E
                                                 const S* __restrict__ invx, const int32_t* __restrict__ extidx,
                                                 int colour, int scheme, int npatch, int64_t ld, int nrhs,
                                                 int ncol, T omega, const int32_t* __restrict__ plist) {
-  using D = Dims<K>;
-  using I = Idx<K>;
-  constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
-  // Layout of the right-hand-side columns: ld-strided blocks (column c at c * ld), or
-  // with IL interleaved records of ld values (entry g of column c at g * ld + c)
-  const int64_t cst = IL ? 1 : ld;
-  auto ix = [&](int g) {
-    if constexpr (IL) return (int64_t)g * ld;
-    else return g;
-  };
-  // Storage of the pseudo-inverses (chosen per level by the host):
-  //   PK (RT_1, bandwidth-bound levels): symmetric "rotated diagonal" blocks,
-  //       R[d n + t] = A+[t][(t + d) mod n] for d = 0 .. n/2 (n (n/2 + 1) entries,
-  //       about half the full block), staged through LDS for the product;
-  //   PF (RT_1, latency-bound levels): full column-major blocks, the column of this
-  //       lane prefetched into registers;
-  //   otherwise (RT_2): full blocks streamed from HBM in the product.
-  // (RT_2 rotated blocks only with 4- or 2-byte entries: four of them fit in LDS)
-  constexpr bool PK = PKD && (K <= 1 || sizeof(S) <= 4);
-  // PKG: rotated blocks read from memory in the product (RT_2 with FP64 entries, 37.6 KB
-  // per patch: not staged)
-  constexpr bool PKG = PKD && !PK;
-  // MF: several columns in FP32 arithmetic with full-storage inverses -- the residuals
-  // of all columns are formed first, then one MFMA product Y = A+ [r_1 .. r_C] reads
-  // every inverse entry once for all columns
-  constexpr bool MF = MC && !PK && sizeof(T) == 4;
-  constexpr bool PF = (K <= 1) && !PKD && !MF;
-  constexpr int NPR = NSR * (NSR / 2 + 1), NPE = NSE * (NSE / 2 + 1);  // rotated entries
-  static_assert(NSR % 2 == 0 && NSE % 2 == 0, "rotated storage needs an even patch size");
-  constexpr int NQ = (PK && K <= 1) ? (NPR + 63) / 64 : 1;  // rotated entries per lane (regular layout)
-  constexpr int NT = (NSE + 63) / 64;            // layout entries per lane
-  __shared__ Elem<T, K> Es;
-  __shared__ T zblk[NP * NV];  // zero coefficients / values for absent terms
-  __shared__ T rs[4][NSE];
-  __shared__ T rsa[MF ? 4 : 1][MF ? 16 : 1][MF ? NSE : 1];  // MF: residuals of every column
-  __shared__ int gis[MF ? 4 : 1][MF ? NSE : 1];              // MF: global index of every slot
-  // Per-wave region: the gathered cell values xs[slot][NL], the neighbour values
-  // nb[slot][0: u_x of the cell across the outer horizontal face, 1: u_y of the cell
-  // across the outer vertical face][NV], the row contributions zs[4 NL], and the staged
-  // rotated inverse aps[NPR].  With one column the wave stages its inverse only after
-  // its last read of xs / nb / zs, so the inverse overlays them (OVL): that keeps an
-  // FP64 RT_1 block under 32 KB of LDS, five blocks per CU instead of four.
-  constexpr bool OVL = PK && !MC;
-  constexpr int WSB = (int)sizeof(T) * (4 * NL + 8 * NV + 4 * NL);
-  constexpr int APB = (int)sizeof(S) * (PK ? NPR : 1);
-  constexpr int RB = ((OVL ? (WSB > APB ? WSB : APB) : WSB + APB) + 15) / 16 * 16;
-  __shared__ __attribute__((aligned(16))) unsigned char wpool[4 * RB];
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  unsigned char* const wreg = wpool + w * RB;
-  T(*const xw)[NL] = reinterpret_cast<T(*)[NL]>(wreg);
-  T(*const nbw)[2][NV] = reinterpret_cast<T(*)[2][NV]>(wreg + sizeof(T) * 4 * NL);
-  T* const zw = reinterpret_cast<T*>(wreg + sizeof(T) * (4 * NL + 8 * NV));
-  S* const apw = reinterpret_cast<S*>(wreg + (OVL ? 0 : WSB));
-  // XCD-aware order: the hardware hands consecutive blocks to the 8 XCDs in turn, so
-  // block b works on the (b mod 8)-th contiguous range of patches (a horizontal strip
-  // of the mesh, the same in every colour launch); values a neighbouring patch of the
-  // strip wrote in the previous colour step are then likely in this XCD's L2
-  // (only on grids the host padded to a multiple of 8; small grids keep the plain order)
-  // every kernel argument is wanted in the first microseconds: take them in one batch
-  // of scalar loads (one memory round trip for the first wave on a CU) rather than
-  // the several dependent batches the scheduler would otherwise place near each use.
-  // (A pass-through of the grid size, without side effects, so that the scalar load
-  // of `ext` below is still seen as reading unmodified memory.)
-  int gdim;
-  asm("" : "=s"(gdim) : "0"((int)gridDim.x), "s"(N), "s"(bcm), "s"(colour), "s"(scheme), "s"(npatch), "s"(ld),
-      "s"(Ep), "s"(kap), "s"(x), "s"(b), "s"(inv), "s"(invx), "s"(extidx), "s"(h), "s"(plist));
-  const int lb = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
-  // the wave's patch: the (lb * 4 + w)-th of the colour, or of the given list of patches
-  // (the boundary patches of a level whose interior ones run k_colour_mr)
-  const int q = lb * 4 + w;
-  const bool active = q < npatch;
-  const int qc = active ? q : npatch - 1;  // in-bounds stand-in for idle waves
-  const int pc = plist ? plist[qc] : qc;
-  const int p = pc;
-  int vx, vy;
-  patch_vertex(scheme, N, colour, pc, vx, vy);
-  const T mh = -h, hh = h * h;
-  // index of the extended inverse (pc is in bounds for every wave).  Unconditional, so
-  // that the wave does not wait for it before the gathers
-  const int ext = extidx[pc];
-  // right-hand-side columns of this block: c0 .. c1-1 (ld apart); MC = several
-  const int c0 = MC ? blockIdx.y * ncol : blockIdx.y, c1 = MC ? min(c0 + ncol, nrhs) : c0 + 1;
-
-  // Single-column RT_1 launches (the bandwidth-bound finest levels and the
-  // latency-bound full-storage ones) carry a second copy of the body for vertices at
-  // least two cells from the boundary, with the boundary logic compiled out (a
-  // wave-uniform branch; both copies execute the same barriers).  Other instantiations
-  // compile the general body alone.
-  constexpr bool FAST = K == 1 && !MC && !ADD && !IL;
-  if constexpr (FAST) {
-    if (vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2) {
-      constexpr bool INT = true;
-#include "colour_body.inc"
-    } else {
-      constexpr bool INT = false;
-#include "colour_body.inc"
-    }
-  } else {
-    constexpr bool INT = false;
-#include "colour_body.inc"
-  }
+#define BMG_BX (blockIdx.x)
+#define BMG_BY (blockIdx.y)
+#define BMG_GDIM ((int)gridDim.x)
+#include "colour_kernel.inc"
+#undef BMG_BX
+#undef BMG_BY
+#undef BMG_GDIM
 }
 
 // ---------------------------------------------------------------------------
@@ -584,263 +490,94 @@ __global__ __launch_bounds__(256, 4) void k_colour_mr(const ElemInt<float, K>* _
                                                   const float* __restrict__ b, const bf16* __restrict__ inv,
                                                   const int4* __restrict__ tab, int colour, int scheme, int npatch,
                                                   int rp) {
-  using D = Dims<K>;
+#define BMG_MR_BX (blockIdx.x)
+#define BMG_MR_GDIM ((int)gridDim.x)
+#include "colour_mr_kernel.inc"
+#undef BMG_MR_BX
+#undef BMG_MR_GDIM
+}
+
+// ---------------------------------------------------------------------------
+// One colour step of a small level in one launch: the blocks below mr_blocks run the
+// several-column body on the interior patches, the others the general body (one
+// column per block, interleaved records) on the listed boundary patches of the same
+// colour.  The two sets of patches share no dof (same colour), so they may run at
+// once; on the latency-bound small levels this halves the launches of a smoothing
+// step.  The two bodies' LDS share one union.
+// ---------------------------------------------------------------------------
+template <int K>
+struct MrShared {
   using M = MrDims<K>;
-  using EI = ElemInt<float, K>;
-  constexpr int NV = D::NV, NP = D::NP, NL = D::NL, NSR = D::NSR, CW = M::CW, XS = M::XS, CS = M::CS, NE = M::NE;
-  constexpr int NPR = M::NPR, NKS = M::NKS, NRT = M::NRT, NVP = EI::NVP, NPP = EI::NPP;
-  constexpr int NGI = (4 * NE + 255) / 256;   // gather items (entry, 4 columns) per thread
-  constexpr int NSI = (4 * NSR + 255) / 256;  // store items (slot, 4 columns) per thread
-  constexpr int NST = (16 * NSR + 255) / 256;  // (slot, column) pairs per thread in the residual
-  constexpr int NH = NV / 2;                   // velocity rows per wave (NV is even)
-  // x | b per column (x later holds the rows, b the correction), and one spare word for
-  // the writes of idle threads
-  __shared__ __attribute__((aligned(16))) float buf[16 * CS + 4];  // + 4 spare words
-  __shared__ __attribute__((aligned(16))) uint16_t apw[(NPR + 7) / 8 * 8];
-  __shared__ __attribute__((aligned(16))) EI Es;  // coefficients, read as broadcasts
-  __shared__ int sgi[NSR], spa[NSR], spb[NSR];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // XCD-aware order (grids padded to a multiple of 8): the hardware hands consecutive
-  // blocks to the 8 XCDs in turn, so block b takes the (b mod 8)-th contiguous range of
-  // the colour's patches; neighbouring patches of a mesh row then share cache lines
-  // and pages in one XCD's L2 and translation caches
-  const int gdim = gridDim.x;
-  const int p = (gdim & 7) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (gdim / 8) + (int)blockIdx.x / 8;
-  if (p >= npatch) return;
-  int vx, vy;
-  patch_vertex(scheme, N, colour, p, vx, vy);
-  if (!(vx >= 2 && vx <= N - 2 && vy >= 2 && vy <= N - 2)) return;  // boundary patches: the general kernel
-  // columns: records of rp = 4, 8 or 16 values (entry g of column c at g * rp + c),
-  // read and written 4 columns (16 bytes) at a time; nq pieces per record
-  const int lq = rp >= 16 ? 2 : rp >= 8 ? 1 : 0, nq = 1 << lq;
-  int ax[4], ay[4];
-  mr_stream_steps<K>(N, ax, ay);
-  const int dvx = vx - 2, dvy = vy - 2;
+  __attribute__((aligned(16))) float buf[16 * M::CS + 4];
+  __attribute__((aligned(16))) uint16_t apw[(M::NPR + 7) / 8 * 8];
+  __attribute__((aligned(16))) ElemInt<float, K> Es;
+  int sgi[Dims<K>::NSR], spa[Dims<K>::NSR], spb[Dims<K>::NSR];
+};
 
-  // the patch slots: global index and the positions of their row contributions (table
-  // entry e holds {index at the template vertex (2, 2), stream, LDS position, 1 for b})
-  if (tid < NSR) {
-    const int4 t = tab[NE - NSR + tid], u = tab[NE + tid];
-    sgi[tid] = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
-    spa[tid] = u.x;
-    spb[tid] = u.y;
-  }
-  // 1. gather: item i = (entry i >> lq, columns 4 (i & (nq - 1)) .. + 3), one 16-byte load
-  // each, every load of the thread issued before its first LDS write; the rotated
-  // inverse of the patch and the coefficients (16-byte pieces) meanwhile
-  {
-    float4 v[NGI];
-    int pv[NGI];
-#pragma unroll
-    for (int k = 0; k < NGI; ++k) {
-      const int i = tid + 256 * k, e = i >> lq, c4 = 4 * (i & (nq - 1));
-      const bool ok = e < NE;
-      const int4 t = tab[ok ? e : 0];
-      const int64_t g = t.x + dvx * ax[t.y & 3] + dvy * ay[t.y & 3];
-      v[k] = *reinterpret_cast<const float4*>((t.w != 0 ? b : (const float*)x) + g * rp + c4);
-      pv[k] = ok ? c4 * CS + t.z : 16 * CS;  // idle items write the spare words
-    }
-    const uint4* ai = reinterpret_cast<const uint4*>(inv + (size_t)p * NPR);
-    uint4* ad = reinterpret_cast<uint4*>(apw);
-    for (int i = tid; i < NPR / 8; i += 256) ad[i] = ai[i];
-    constexpr int NEI = (int)(sizeof(EI) / 16);
-    const uint4* es = reinterpret_cast<const uint4*>(Ei);
-    uint4* ed = reinterpret_cast<uint4*>(&Es);
-    for (int i = tid; i < NEI; i += 256) ed[i] = es[i];
-#pragma unroll
-    for (int k = 0; k < NGI; ++k) {
-      const bool ok = pv[k] < 16 * CS;
-      buf[pv[k]] = v[k].x;
-      buf[ok ? pv[k] + CS : 16 * CS + 1] = v[k].y;
-      buf[ok ? pv[k] + 2 * CS : 16 * CS + 2] = v[k].z;
-      buf[ok ? pv[k] + 3 * CS : 16 * CS + 3] = v[k].w;
-    }
-  }
-  __syncthreads();
+template <typename T, typename S, int K, bool PKD, bool MC>
+struct ColourShared {
+  using D = Dims<K>;
+  static constexpr int NL = D::NL, NV = D::NV, NP = D::NP, NSR = D::NSR, NSE = D::NSE;
+  static constexpr bool PK = PKD && (K <= 1 || sizeof(S) <= 4);
+  static constexpr bool MF = MC && !PK && sizeof(T) == 4;
+  static constexpr int NPR = NSR * (NSR / 2 + 1);
+  static constexpr bool OVL = PK && !MC;
+  static constexpr int WSB = (int)sizeof(T) * (4 * NL + 8 * NV + 4 * NL);
+  static constexpr int APB = (int)sizeof(S) * (PK ? NPR : 1);
+  static constexpr int RB = ((OVL ? (WSB > APB ? WSB : APB) : WSB + APB) + 15) / 16 * 16;
+  Elem<T, K> Es;
+  T zblk[NP * NV];
+  T rs[4][NSE];
+  T rsa[MF ? 4 : 1][MF ? 16 : 1][MF ? NSE : 1];
+  int gis[MF ? 4 : 1][MF ? NSE : 1];
+  __attribute__((aligned(16))) unsigned char wpool[4 * RB];
+};
 
-  // the old x on the (slot, 4 columns) items this thread stores at the end (the x part
-  // of LDS is overwritten by the rows)
-  float4 xold[NSI];
-#pragma unroll
-  for (int k = 0; k < NSI; ++k) {
-    const int i = tid + 256 * k, t = i >> lq, c4 = 4 * (i & (nq - 1));
-    const int o = t < NSR ? c4 * CS + spa[t] : 0;
-    xold[k] = make_float4(buf[o], buf[o + CS], buf[o + 2 * CS], buf[o + 3 * CS]);
-  }
-
-  // 2. rows: wave w takes half of the rows of one velocity component (comp = w / 2,
-  // rows (w % 2) NV/2 .. + NV/2 - 1) and the pressure rows q = w, w + 4, ...; lane
-  // (cell s, column c)
-  const int s = lane >> 4, c = lane & 15;
-  const int comp = w >> 1, d0 = (w & 1) * NH;
-  {
-    const float* col = buf + c * CS;
-    const float* own = col + s * CW;
-    float u0[NVP], u1[NVP], pr[NPP], lo[NVP], hi[NVP];
-#pragma unroll
-    for (int i = 0; i < NVP; ++i) {
-      u0[i] = i < NV ? own[i] : 0.f;
-      u1[i] = i < NV ? own[NV + i] : 0.f;
+template <int K>
+__global__ __launch_bounds__(256) void k_colour_fused(const ElemInt<float, K>* __restrict__ Ei,
+                                                      const int4* __restrict__ tab, int mr_npatch, int mr_blocks,
+                                                      const Elem<float, K>* __restrict__ Ep, int N, int bcm, float h,
+                                                      const float* __restrict__ kap, float* __restrict__ x,
+                                                      const float* __restrict__ b, const bf16* __restrict__ inv,
+                                                      const bf16* __restrict__ invx,
+                                                      const int32_t* __restrict__ extidx, int colour, int scheme,
+                                                      int npatch, int64_t ld, int nrhs,
+                                                      const int32_t* __restrict__ plist, int nbx) {
+  union FusedShared {
+    MrShared<K> m;
+    ColourShared<float, bf16, K, true, false> c;
+  };
+  __shared__ FusedShared fsh;
+  if ((int)blockIdx.x < mr_blocks) {
+    const int rp = (int)ld;
+    const int npatch_all = npatch;
+    (void)npatch_all;
+    {
+      const int npatch = mr_npatch;
+#define BMG_MR_SHARED fsh.m
+#define BMG_MR_BX (blockIdx.x)
+#define BMG_MR_GDIM (mr_blocks)
+#include "colour_mr_kernel.inc"
+#undef BMG_MR_SHARED
+#undef BMG_MR_BX
+#undef BMG_MR_GDIM
     }
-#pragma unroll
-    for (int i = 0; i < NPP; ++i) pr[i] = i < NP ? own[2 * NV + i] : 0.f;
-    // tangential neighbours of this wave's component: u_x below / above, u_y left / right
-    const float* nbo = col + 4 * CW + s * 2 * NV + comp * NV;  // the neighbour outside the patch
-    const float* lp = comp == 0 ? (s >= 2 ? col + (s - 2) * CW : nbo) : ((s & 1) ? col + (s - 1) * CW + NV : nbo);
-    const float* hp = comp == 0 ? (s < 2 ? col + (s + 2) * CW : nbo) : ((s & 1) ? nbo : col + (s + 1) * CW + NV);
-#pragma unroll
-    for (int i = 0; i < NVP; ++i) {
-      lo[i] = i < NV ? lp[i] : 0.f;
-      hi[i] = i < NV ? hp[i] : 0.f;
-    }
-    float ucv[NVP];
-#pragma unroll
-    for (int i = 0; i < NVP; ++i) ucv[i] = comp == 0 ? u0[i] : u1[i];
-    const int cx = vx - 1 + (s & 1), cy = vy - 1 + (s >> 1);
-    const float khh = kap[cy * N + cx] * (h * h), mh = -h;
-    const float* Dt = comp == 0 ? &Es.DxT[0][0] : &Es.DyT[0][0];
-    float* zc = buf + c * CS + s * CW;
-    // every thread holds its inputs: the rows overwrite the x part of LDS from here
-    __syncthreads();
-    // one row at a time (the coefficient reads of all rows at once would not fit in
-    // registers)
-#pragma unroll 1
-    for (int r = 0; r < NH; ++r) {
-      const int d = d0 + r;
-      float a = 0.f, m = 0.f, g = 0.f;
-#pragma unroll
-      for (int e4 = 0; e4 < NVP / 4; ++e4) {
-        const float4 kf = reinterpret_cast<const float4*>(Es.Kint[d])[e4];
-        const float4 mm = reinterpret_cast<const float4*>(Es.M[d])[e4];
-        const float4 f1 = reinterpret_cast<const float4*>(Es.F1[d])[e4];
-        const float4 f2 = reinterpret_cast<const float4*>(Es.F2[d])[e4];
-        const float kv4[4] = {kf.x, kf.y, kf.z, kf.w}, mv4[4] = {mm.x, mm.y, mm.z, mm.w};
-        const float f14[4] = {f1.x, f1.y, f1.z, f1.w}, f24[4] = {f2.x, f2.y, f2.z, f2.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = 4 * e4 + u;
-          a = fmaf(kv4[u], ucv[e], a);
-          a = fmaf(f24[u], lo[e], a);
-          a = fmaf(f14[u], hi[e], a);
-          m = fmaf(mv4[u], ucv[e], m);
-        }
-      }
-#pragma unroll
-      for (int q4 = 0; q4 < NPP / 4; ++q4) {
-        const float4 dv = reinterpret_cast<const float4*>(Dt + d * NPP)[q4];
-        const float dv4[4] = {dv.x, dv.y, dv.z, dv.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) g = fmaf(dv4[u], pr[4 * q4 + u], g);
-      }
-      zc[comp * NV + d] = fmaf(mh, g, fmaf(khh, m, a));
-    }
-#pragma unroll 1
-    for (int qi = 0; qi < (NP + 3) / 4; ++qi) {
-      const int q = w + 4 * qi;
-      float a = 0.f;
-      if (q < NP) {
-#pragma unroll
-        for (int e4 = 0; e4 < NVP / 4; ++e4) {
-          const float4 dx = reinterpret_cast<const float4*>(Es.Dx[q])[e4];
-          const float4 dy = reinterpret_cast<const float4*>(Es.Dy[q])[e4];
-          const float dx4[4] = {dx.x, dx.y, dx.z, dx.w}, dy4[4] = {dy.x, dy.y, dy.z, dy.w};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            a = fmaf(dx4[u], u0[4 * e4 + u], a);
-            a = fmaf(dy4[u], u1[4 * e4 + u], a);
-          }
-        }
-      }
-      if (q < NP) zc[2 * NV + q] = mh * a;
-    }
-  }
-  __syncthreads();
-
-  // 3. residual of the patch rows, each (slot, column) pair once, in place of b; then
-  // the hi + lo bfloat16 B operands: lane (kg, c) holds rows t = 32 ks + 8 kg + j, j =
-  // 0..7, of column c
-#pragma unroll
-  for (int k2 = 0; k2 < NST; ++k2) {
-    const int idx = tid + 256 * k2, cc = idx / NSR, t = idx % NSR;
-    if (idx < 16 * NSR) {
-      const float* col = buf + cc * CS;
-      const int pb = spb[t];
-      const float zb = col[pb >= 0 ? pb : 0];
-      buf[cc * CS + XS + t] = col[XS + t] - col[spa[t]] - (pb >= 0 ? zb : 0.f);
-    }
-  }
-  __syncthreads();
-  const int kg = lane >> 4, li = lane & 15;
-  bf16x8 bhi[NKS], blo[NKS];
-  {
-    const float* rc = buf + li * CS + XS;
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int t = 32 * ks + 8 * kg + j;
-        const float r = (NSR % 32 == 0 || t < NSR) ? rc[(NSR % 32 == 0 || t < NSR) ? t : 0] : 0.f;
-        const __bf16 hv = (__bf16)r;
-        bhi[ks][j] = hv;
-        blo[ks][j] = (__bf16)(r - (float)hv);
-      }
-  }
-  // A operand of row tile rt (rt = w, w + 4, ...), k-step ks: lane (kg, i) holds
-  // A+[16 rt + i][32 ks + 8 kg + j]
-  constexpr int NRW = (NRT + 3) / 4;
-  fx4 acc[NRW];
-#pragma unroll
-  for (int ri = 0; ri < NRW; ++ri) {
-    acc[ri] = fx4{0.f, 0.f, 0.f, 0.f};
-    const int rt = w + 4 * ri;
-    if (rt < NRT) {
-      const int row = 16 * rt + li;
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        bf16x8 a;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          // entries past the patch size (RT_1) read entry 0 and are zeroed
-          const int cl = 32 * ks + 8 * kg + j;
-          const bool in = (NSR % 32 == 0) || (row < NSR && cl < NSR);
-          int d1 = cl - row;
-          d1 += d1 < 0 ? NSR : 0;
-          const int idx = d1 <= NSR / 2 ? d1 * NSR + row : (NSR - d1) * NSR + cl;
-          const uint16_t bits = apw[in ? idx : 0];
-          a[j] = __builtin_bit_cast(__bf16, in ? bits : (uint16_t)0);
-        }
-        acc[ri] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bhi[ks], acc[ri], 0, 0, 0);
-        acc[ri] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo[ks], acc[ri], 0, 0, 0);
-      }
-    }
-  }
-  __syncthreads();  // every wave has read b and the rows: the b part takes the correction
-  // 4. Y[t][c] (lane (rg, c) of row tile rt: rows 16 rt + 4 rg + v) to LDS, then
-  // x[S] = x_old + Y, coalesced over the slots of a column
-  {
-    float* yc = buf + li * CS + XS;
-#pragma unroll
-    for (int ri = 0; ri < NRW; ++ri) {
-      const int rt = w + 4 * ri;
-      if (rt < NRT)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int t = 16 * rt + 4 * kg + v;
-          if (t < NSR) yc[t] = acc[ri][v];
-        }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NSI; ++k) {
-    const int i = tid + 256 * k, t = i >> lq, c4 = 4 * (i & (nq - 1));
-    if (t < NSR) {
-      const float* yc = buf + c4 * CS + XS + t;
-      const float4 o = xold[k];
-      *reinterpret_cast<float4*>(x + (int64_t)sgi[t] * rp + c4) =
-          make_float4(o.x + yc[0], o.y + yc[CS], o.z + yc[2 * CS], o.w + yc[3 * CS]);
-    }
+  } else {
+    using T = float;
+    using S = bf16;
+    constexpr bool PKD = true, MC = false, ADD = false, IL = true;
+    const int ncol = 1;
+    const T omega = 0.0f;
+    const unsigned vb = blockIdx.x - (unsigned)mr_blocks;
+#define BMG_COLOUR_SHARED fsh.c
+#define BMG_BX (vb % (unsigned)nbx)
+#define BMG_BY (vb / (unsigned)nbx)
+#define BMG_GDIM (nbx)
+#include "colour_kernel.inc"
+#undef BMG_COLOUR_SHARED
+#undef BMG_BX
+#undef BMG_BY
+#undef BMG_GDIM
   }
 }
 
@@ -1733,6 +1470,30 @@ void launch_colour_mr(int K, const void* elem_int, const LevelArgs& L, void* x, 
                       const int32_t* tab, int colour, int npatch, int rp, hipStream_t s) {
   if (K == 1) colour_mr_t<1>(elem_int, L, x, b, inv, tab, colour, npatch, rp, s);
   else if (K == 2) colour_mr_t<2>(elem_int, L, x, b, inv, tab, colour, npatch, rp, s);
+}
+
+template <int K>
+static void colour_fused_t(const void* elem_int, const void* elem, const LevelArgs& L, void* x, const void* b,
+                           const void* inv, const void* invx, const int32_t* extidx, const int32_t* tab, int colour,
+                           int npatch_mr, int nlist, const int32_t* plist, int nrhs, int rp, hipStream_t s) {
+  const int mr_blocks = (npatch_mr + 7) & ~7;
+  const int nblk = (nlist + 3) / 4;
+  const int nbx = nlist <= 0 ? 0 : nblk >= 64 ? (nblk + 7) / 8 * 8 : (nblk % 8 == 0 ? nblk + 1 : nblk);
+  const int64_t grid = (int64_t)mr_blocks + (int64_t)nbx * nrhs;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_colour_fused<K>), dim3((unsigned)grid), dim3(256), 0, s, (const ElemInt<float, K>*)elem_int,
+                     (const int4*)tab, npatch_mr, mr_blocks, (const Elem<float, K>*)elem, L.N, L.bcm, (float)L.h,
+                     (const float*)L.kap, (float*)x, (const float*)b, (const bf16*)inv, (const bf16*)invx, extidx,
+                     colour, L.colouring, nlist, (int64_t)rp, nrhs, plist, nbx > 0 ? nbx : 1);
+}
+
+void launch_colour_fused(int K, const void* elem_int, const void* elem, const LevelArgs& L, void* x, const void* b,
+                         const void* inv, const void* invx, const int32_t* extidx, const int32_t* tab, int colour,
+                         int npatch_mr, int nlist, const int32_t* plist, int nrhs, int rp, hipStream_t s) {
+  if (K == 1)
+    colour_fused_t<1>(elem_int, elem, L, x, b, inv, invx, extidx, tab, colour, npatch_mr, nlist, plist, nrhs, rp, s);
+  else if (K == 2)
+    colour_fused_t<2>(elem_int, elem, L, x, b, inv, invx, extidx, tab, colour, npatch_mr, nlist, plist, nrhs, rp, s);
 }
 
 int mr_table_entries(int K) {
