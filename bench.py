@@ -34,11 +34,12 @@ def log(msg):
 
 
 def kernels_sha16():
-    """First 16 hex digits of the sha256 of the 2-D kernel sources (kernels.hip, then
-    colour_body.inc): the version of the kernels a stored counter reading belongs to."""
+    """First 16 hex digits of the sha256 of the 2-D kernel sources (kernels.hip, then the
+    colour-step bodies it includes): the version of the kernels a stored counter reading
+    belongs to."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "colour_body.inc"):
+    for f in ("kernels.hip", "colour_body.inc", "colour_kernel.inc", "colour_mr_kernel.inc"):
         with open(os.path.join(ROOT, "paper_1602_04858_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -445,6 +446,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=10)
+    ap.add_argument("--oracle-check", action="store_true",
+                    help="C2: also solve the workload with the oracle (about a minute on the host) and report "
+                         "every leg's relative difference from its solution")
     ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C3darcy", "C4", "C5", "D3", "sweep"],
                     help="C5 (default: 2048^2 RT_2, 16 right-hand sides, the largest configuration), C2 (256^2 "
                          "RT_1), the 1024^2 precision study, the 48-problem batch, the 3-D solver, or the "
@@ -587,6 +591,7 @@ def main():
            "ndof": ndof, "iterations": its64[-1], "dof_iters_per_s": ndof * sum(its64) / dt64,
            "true_rel_residual": info64.rel_residual_true, "setup_s": setup64}
 
+    sols = {"fp64": x64}  # the solutions compared with the oracle's (--oracle-check)
     if not args.no_mixed:
         for key, prec in (("mixed", bmg.P_FP32), ("mixed_bf16", bmg.P_BF16)):
             p32 = choose(bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, prec, 100,
@@ -608,6 +613,7 @@ def main():
                 f"finest smoother {by32 / (ms32 * 1e-3) / 1e9:.0f} GB/s")
             s32.close()
             del s32
+            sols[key] = x32
 
     if not args.no_mixed and args.workload == "C2":
         # batched: 16 right-hand sides of the same problem solved together with the FP32
@@ -622,14 +628,29 @@ def main():
         xb, infb, dtb, _ = timed_solves(torch, sb, B, args.steps, args.warmup, args.rtol)
         itsb = [i.iterations for i in infb]
         errb = (torch.linalg.norm(xb[0] - x64) / torch.linalg.norm(x64)).item()
+        sols["mixed_batched_column0"] = xb[0].clone()
+        sb.close()
+        del sb
+        # the same 16 columns with the FP64 V-cycle: the like-for-like FP64 rate
+        pb64 = bmg.make_params(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.cycle, w.m_fine, bmg.P_FP64, 100,
+                               args.dense_coarse_max, R, p64.colouring, smoother, args.omega)
+        sb64 = bmg.Solver(pb64, w.kappa)
+        xb64, infb64, dtb64, _ = timed_solves(torch, sb64, B, args.steps, args.warmup, args.rtol)
+        sb64.close()
+        del sb64
+        errb64 = max((torch.linalg.norm(xb[c] - xb64[c]) / torch.linalg.norm(xb64[c])).item() for c in range(R))
         out["mixed_batched"] = {"value": args.steps * R / dtb, "unit": "right-hand sides solved/s", "n_rhs": R,
                                 "precond": "fp32", "iterations_min": min(itsb), "iterations_max": max(itsb),
                                 "worst_true_rel_residual": max(i.rel_residual_true for i in infb),
-                                "rel_diff_vs_fp64_column0": errb, "speedup_vs_fp64": (args.steps * R / dtb) / value}
+                                "rel_diff_vs_fp64_column0": errb,
+                                "fp64_batched": {"value": args.steps * R / dtb64, "unit": "right-hand sides solved/s",
+                                                 "iterations_max": max(i.iterations for i in infb64)},
+                                "speedup_vs_fp64_batched": dtb64 / dtb,
+                                "worst_rel_diff_vs_fp64_batched": errb64,
+                                "speedup_vs_fp64_single": (args.steps * R / dtb) / value}
         log(f"bench: mixed batched ({R} right-hand sides) {args.steps * R / dtb:.2f} solves/s, iterations "
-            f"{min(itsb)}..{max(itsb)}")
-        sb.close()
-        del sb
+            f"{min(itsb)}..{max(itsb)}; FP64 batched {args.steps * R / dtb64:.2f} ({dtb64 / dtb:.2f}x)")
+        xb, xb64 = None, None
     if std_cycle:
         out["standard_vcycle"] = std_cycle
     if tuned:
@@ -638,6 +659,15 @@ def main():
     if not args.no_cpu_baseline and args.workload == "C2":
         log("bench: CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(w, its64[-1], args.cpu_sample_its, p64.colouring)
+        if args.oracle_check:
+            # every path's solution against a tightly converged oracle solve of the same workload
+            from oracle import Oracle
+            o = Oracle(w.n0, w.levels, w.k, w.mu, w.sigma, w.bc, w.kappa, w.cycle, w.m_fine, p64.colouring)
+            xo, _, _, _ = o.fgmres(o.rhs(w.source), rtol=1e-13, maxit=400, restart=100)
+            xo = torch.as_tensor(xo, device="cuda")
+            out["rel_diff_vs_oracle"] = {k: (torch.linalg.norm(v - xo) / torch.linalg.norm(xo)).item()
+                                         for k, v in sols.items()}
+            log(f"bench: solutions vs oracle {out['rel_diff_vs_oracle']}")
     print(json.dumps(out), flush=True)
 
 
