@@ -510,7 +510,6 @@ struct MrShared {
   using M = MrDims<K>;
   __attribute__((aligned(16))) float buf[16 * M::CS + 4];
   __attribute__((aligned(16))) uint16_t apw[(M::NPR + 7) / 8 * 8];
-  __attribute__((aligned(16))) ElemInt<float, K> Es;
   int sgi[Dims<K>::NSR], spa[Dims<K>::NSR], spb[Dims<K>::NSR];
 };
 
