@@ -3,8 +3,11 @@
  * solver (Kanschat, Lazarov, Mao, arXiv 1602.04858).
  *
  * Problem (Section 2, d = 3): -mu Lap u + kappa u + grad p = f, div u = 0 on the unit
- * cube, mu > 0, kappa >= 0 cellwise constant, u = g on all six sides.
- * Discretisation (Section 2): RT_1 velocity x discontinuous Q_1 pressure on a uniform
+ * cube, mu >= 0 (mu = 0: the Darcy limit, eq. (Darcy-weak)), kappa >= 0 cellwise
+ * constant, u = g on all six sides (for mu = 0 only the normal component counts).
+ * Discretisation (Section 2): RT_k velocity x discontinuous Q_k pressure, k = 0 (the
+ * lowest order, Section 2.3: one normal-flux dof per face, one pressure per cell) or
+ * k = 1, on a uniform
  * N x N x N hexahedral mesh, interior-penalty form a_h (eq. ipbrinkman) with face
  * penalty 2 mu sigma / h, saddle-point form (eq. Brinkman-weak).  The normal velocity
  * on the boundary is an essential condition (boundary normal face dofs fixed, identity
@@ -18,13 +21,13 @@
  * coarsest mesh.  Level operators, transfers and patch pseudo-inverses are assembled
  * on the host at setup; every step of a solve runs in the library's HIP kernels.
  *
- * Vector layout, with nb = 2, cell c = (cz N + cy) N + cx, velocity component d with
+ * Vector layout, with nb = k + 1, cell c = (cz N + cy) N + cx, velocity component d with
  * transverse axes (d1, d2) = the other two in increasing order, basis
  * psi_a(xi_d) L_b(xi_d1) L_c(xi_d2) (L_b orthonormal Legendre on [0,1], psi_0 = 1 - t,
  * psi_1 = t, psi_2 = int_0^t L_1) and pressure L_a(x) L_b(y) L_c(z):
  *   face dofs (a = 0/1, face index i = c_d + a along d):
  *       d NF + ((t2 N + t1)(N + 1) + i) nb^2 + b + nb c,   NF = (N + 1) N^2 nb^2
- *   interior dofs (a = 2):  3 NF + c NI + d nb^2 + b + nb c,  NI = 3 nb^2
+ *   interior dofs (a = 2, k = 1 only):  3 NF + c NI + d nb^2 + b + nb c,  NI = 3 k nb^2
  *   pressure:               n_u + c nb^3 + a + nb b + nb^2 c
  * with n_u = 3 NF + NI N^3 and n_p = nb^3 N^3; a full vector is velocity then pressure.
  *
@@ -50,8 +53,8 @@ typedef struct bmg3_ctx* bmg3_handle;
 typedef struct {
   int32_t n0;      /* coarsest mesh n0^3 cells, 1 .. 8 */
   int32_t levels;  /* >= 1; finest N = n0 2^(levels-1) <= 64 */
-  int32_t k;       /* RT degree: 1 */
-  double mu;       /* viscosity > 0 */
+  int32_t k;       /* RT degree: 0 or 1 */
+  double mu;       /* viscosity >= 0 (0: Darcy) */
   double sigma;    /* penalty parameter > 0 (sigma_h = sigma / h); Section 4.1 uses (k+1)(k+2) */
   int32_t cycle;   /* 0: m_fine smoothing steps on every level; 1: variable, m_fine 2^(J-j) */
   int32_t m_fine;  /* >= 1 */

@@ -522,13 +522,16 @@ def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, rest
     return p
 
 
+def _ndof3(N, k):
+    """Unknowns of the 3-D level with N cells per side (the layout of bmg3.h)."""
+    nb = k + 1
+    return 3 * (N + 1) * N * N * nb * nb + 3 * k * nb * nb * N ** 3 + nb ** 3 * N ** 3
+
+
 def assemble_rhs3(params: Params3, kappa, f=(0.0, 0.0, 0.0), g=(1.0, 0.0, 0.0)):
     """Right-hand side for constant body force f and constant boundary data g (host)."""
     N = params.n0 << (params.levels - 1)
-    nb = 2
-    NF = (N + 1) * N * N * nb * nb
-    n = 3 * NF + 3 * nb * nb * N ** 3 + nb ** 3 * N ** 3
-    out = np.zeros(n)
+    out = np.zeros(_ndof3(N, params.k))
     fv = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
     gv = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
     if fv.size != 3 or gv.size != 3:
@@ -628,8 +631,7 @@ def export_level_csr3(params: Params3, kappa, level):
     st = _lib.bmg3_export_level_csr(C.byref(params), kap, level, C.byref(nnz), None, None, None)
     if st:
         raise BmgError(st, f"export_level_csr3: {_lib.bmg3_last_error(None).decode()}")
-    N = params.n0 << level
-    n = 3 * (N + 1) * N * N * 4 + 12 * N ** 3 + 8 * N ** 3
+    n = _ndof3(params.n0 << level, params.k)
     rp = np.zeros(n + 1, dtype=np.int32)
     ci = np.zeros(nnz.value, dtype=np.int32)
     v = np.zeros(nnz.value)

@@ -1,5 +1,5 @@
-// Host side of the 3-D (hexahedral) path: reference integrals of RT_1 x dQ_1 on the
-// unit cube, assembly of the level operators (CSR) with essential boundary normals,
+// Host side of the 3-D (hexahedral) path: reference integrals of RT_k x dQ_k (k = 0, the
+// lowest order of Section 2.3, or 1) on the unit cube, assembly of the level operators (CSR) with essential boundary normals,
 // vertex patches and their pseudo-inverses, the exact-embedding transfers, and the
 // FGMRES / V-cycle loop whose every vector operation runs in HIP kernels.
 #include <hip/hip_runtime.h>
@@ -21,11 +21,19 @@
 namespace bmg {
 namespace {
 
-constexpr int K3 = 1, NA3 = K3 + 2, NB3 = K3 + 1;
-constexpr int NU3 = 3 * NA3 * NB3 * NB3;  // local velocity dofs of a cell (36)
-constexpr int NP3 = NB3 * NB3 * NB3;      // local pressure dofs (8)
-constexpr int NL3 = NU3 + NP3;
-constexpr int NQ1 = K3 + 2;               // Gauss points per direction
+// Sizes of RT_K x dQ_K on one hexahedron (K = 0: 6 face dofs + 1 pressure; K = 1: 36 + 8)
+template <int K>
+struct Dims3 {
+  static constexpr int NA = K + 2, NB = K + 1;
+  static constexpr int NU = 3 * NA * NB * NB;  // local velocity dofs of a cell
+  static constexpr int NP = NB * NB * NB;      // local pressure dofs
+  static constexpr int NL = NU + NP;
+  static constexpr int NQ = K + 2;             // Gauss points per direction
+};
+#define BMG_DIMS3(K)                                                                         \
+  constexpr int NA3 = Dims3<K>::NA, NB3 = Dims3<K>::NB, NU3 = Dims3<K>::NU, NP3 = Dims3<K>::NP, \
+                NL3 = Dims3<K>::NL, NQ1 = Dims3<K>::NQ;                                     \
+  (void)NA3, (void)NB3, (void)NU3, (void)NP3, (void)NL3, (void)NQ1
 
 // transverse axes of component d
 inline void axes(int d, int& d1, int& d2) {
@@ -33,14 +41,17 @@ inline void axes(int d, int& d1, int& d2) {
   d2 = d == 2 ? 1 : 2;
 }
 // local velocity index of (d, a, b, c): (d NA + a) NB^2 + b + NB c; pressure a + NB b + NB^2 c
-inline int lu(int d, int a, int b, int c) { return (d * NA3 + a) * NB3 * NB3 + b + NB3 * c; }
+inline int lu(int NA, int NB, int d, int a, int b, int c) { return (d * NA + a) * NB * NB + b + NB * c; }
 
-struct Num3 {  // global numbering of one level (the layout documented in bmg3.h)
-  int N;
+struct Num3 {  // global numbering of one level (the layout documented in bmg3.h), degree k
+  int N, k, NA3, NB3, NU3, NP3, NL3;
   int64_t NF, NI, n_u, n_p, ndof;
-  explicit Num3(int n) : N(n) {
+  Num3(int n, int deg) : N(n), k(deg), NA3(deg + 2), NB3(deg + 1) {
+    NU3 = 3 * NA3 * NB3 * NB3;
+    NP3 = NB3 * NB3 * NB3;
+    NL3 = NU3 + NP3;
     NF = (int64_t)(N + 1) * N * N * NB3 * NB3;
-    NI = 3 * K3 * NB3 * NB3;
+    NI = 3 * k * NB3 * NB3;
     n_u = 3 * NF + NI * N * N * N;
     n_p = (int64_t)NP3 * N * N * N;
     ndof = n_u + n_p;
@@ -58,7 +69,7 @@ struct Num3 {  // global numbering of one level (the layout documented in bmg3.h
       axes(d, d1, d2);
       return face(d, cc[d] + a, cc[d1], cc[d2], bc % NB3, bc / NB3);
     }
-    return 3 * NF + cell(cc[0], cc[1], cc[2]) * NI + (d * K3 + a - 2) * NB3 * NB3 + bc;
+    return 3 * NF + cell(cc[0], cc[1], cc[2]) * NI + (d * k + a - 2) * NB3 * NB3 + bc;
   }
   // essential: a normal face dof on a boundary face
   bool essential(int64_t gi) const {
@@ -69,9 +80,11 @@ struct Num3 {  // global numbering of one level (the layout documented in bmg3.h
   }
 };
 
-// Local basis on the reference cube: values and gradients of the 36 velocity
-// functions, values of the 8 pressure functions.
+// Local basis on the reference cube: values and gradients of the NU velocity
+// functions, values of the NP pressure functions.
+template <int K>
 struct Basis3 {
+  static constexpr int NA3 = Dims3<K>::NA, NB3 = Dims3<K>::NB, NU3 = Dims3<K>::NU, NP3 = Dims3<K>::NP;
   Poly L[NB3], dL[NB3], P[NA3], dP[NA3];
   Basis3() {
     for (int b = 0; b < NB3; ++b) {
@@ -92,7 +105,7 @@ struct Basis3 {
       for (int a = 0; a < NA3; ++a)
         for (int c = 0; c < NB3; ++c)
           for (int b = 0; b < NB3; ++b) {
-            const int l = lu(d, a, b, c);
+            const int l = lu(NA3, NB3, d, a, b, c);
             const double pa = P[a](X[d]), lb = L[b](X[d1]), lc = L[c](X[d2]);
             val[l][d] = pa * lb * lc;
             grad[l][d][d] = dP[a](X[d]) * lb * lc;
@@ -109,12 +122,14 @@ struct Basis3 {
 };
 
 // Reference integrals (unit cube / unit faces); physical blocks are scaled per level.
+template <int KD>
 struct Ref3 {
+  static constexpr int NU3 = Dims3<KD>::NU, NP3 = Dims3<KD>::NP, NQ1 = Dims3<KD>::NQ;
   std::vector<double> K, M, D;           // NU x NU, NU x NU, NP x NU
   std::vector<double> J[3], C[3];        // interior faces: 2NU x 2NU jumps / consistency
   std::vector<double> Jb[3][2], Cb[3][2];  // boundary faces (low, high): NU x NU
   double gx[NQ1], gw[NQ1];
-  Basis3 B;
+  Basis3<KD> B;
   Ref3() {
     gauss_points(NQ1, gx, gw);
     K.assign(NU3 * NU3, 0.0);
@@ -197,8 +212,9 @@ struct Ref3 {
   }
 };
 
-const Ref3& ref3() {
-  static const Ref3 R;
+template <int K>
+const Ref3<K>& ref3() {
+  static const Ref3<K> R;
   return R;
 }
 
@@ -313,8 +329,10 @@ Csr transpose(const Csr& A) {
 
 // Level operator: the full interior-penalty matrix (eq. ipbrinkman, Brinkman-weak),
 // then identity rows and columns on the essential dofs.
-Csr assemble_level(const Num3& S, double mu, double sigma, const std::vector<double>& kap, Csr* full_out) {
-  const Ref3& R = ref3();
+template <int K>
+Csr assemble_level_k(const Num3& S, double mu, double sigma, const std::vector<double>& kap, Csr* full_out) {
+  BMG_DIMS3(K);
+  const Ref3<K>& R = ref3<K>();
   const int N = S.N;
   const double h = 1.0 / N;
   std::vector<Trip> t;
@@ -404,9 +422,11 @@ Csr assemble_level(const Num3& S, double mu, double sigma, const std::vector<dou
 // Local transfer of the exact embedding: T[o] (NL x NL) = coefficients on the child
 // with offset o (ox + 2 oy + 4 oz) of the parent's local functions, by local L2
 // projection (velocity and pressure blocks; the rest zero).
+template <int K>
 std::vector<double> local_transfers() {
-  const Ref3& R = ref3();
-  const Basis3& B = R.B;
+  BMG_DIMS3(K);
+  const Ref3<K>& R = ref3<K>();
+  const Basis3<K>& B = R.B;
   std::vector<double> Mu(NU3 * NU3, 0.0), Mp(NP3 * NP3, 0.0), T(8 * NL3 * NL3, 0.0);
   double vf[NU3][3], gf[NU3][3][3], vc[NU3][3], gc[NU3][3][3];
   double pf[NP3], pc[NP3];
@@ -465,8 +485,10 @@ std::vector<double> local_transfers() {
 // P (fine x coarse): every free fine dof takes its value from the first child cell
 // that holds it (the coarse function is continuous in the normal component, so every
 // holder gives the same value); essential rows and columns are left out.
-Csr prolongation(const Num3& C, const Num3& F) {
-  static const std::vector<double> T = local_transfers();
+template <int K>
+Csr prolongation_k(const Num3& C, const Num3& F) {
+  BMG_DIMS3(K);
+  static const std::vector<double> T = local_transfers<K>();
   std::vector<char> done(F.ndof, 0);
   std::vector<Trip> t;
   for (int cz = 0; cz < C.N; ++cz)
@@ -494,10 +516,12 @@ Csr prolongation(const Num3& C, const Num3& F) {
 
 // Right-hand side of eq. (BCh) for constant f and g (free rows), with the lifting of
 // the essential values, and the essential values on the essential rows.
-std::vector<double> rhs3(const Num3& S, double mu, double sigma, const std::vector<double>& kap, const double f[3],
-                         const double g[3]) {
-  const Ref3& R = ref3();
-  const Basis3& B = R.B;
+template <int K>
+std::vector<double> rhs3_k(const Num3& S, double mu, double sigma, const std::vector<double>& kap, const double f[3],
+                           const double g[3]) {
+  BMG_DIMS3(K);
+  const Ref3<K>& R = ref3<K>();
+  const Basis3<K>& B = R.B;
   const int N = S.N;
   const double h = 1.0 / N;
   // reference integrals of each velocity function against constant vectors
@@ -551,7 +575,7 @@ std::vector<double> rhs3(const Num3& S, double mu, double sigma, const std::vect
       for (int t1 = 0; t1 < N; ++t1)
         for (int i : {0, N}) ge[S.face(d, i, t1, t2, 0, 0)] = g[d];
   Csr Af;
-  assemble_level(S, mu, sigma, kap, &Af);
+  assemble_level_k<K>(S, mu, sigma, kap, &Af);
   for (int64_t i = 0; i < S.ndof; ++i) {
     if (S.essential(i)) {
       b[i] = ge[i];
@@ -562,6 +586,16 @@ std::vector<double> rhs3(const Num3& S, double mu, double sigma, const std::vect
     b[i] -= s;
   }
   return b;
+}
+
+// the degree is a run-time parameter of the handle: dispatch to the instantiation
+Csr assemble_level(const Num3& S, double mu, double sigma, const std::vector<double>& kap, Csr* full_out) {
+  return S.k == 0 ? assemble_level_k<0>(S, mu, sigma, kap, full_out) : assemble_level_k<1>(S, mu, sigma, kap, full_out);
+}
+Csr prolongation(const Num3& C, const Num3& F) { return F.k == 0 ? prolongation_k<0>(C, F) : prolongation_k<1>(C, F); }
+std::vector<double> rhs3(const Num3& S, double mu, double sigma, const std::vector<double>& kap, const double f[3],
+                         const double g[3]) {
+  return S.k == 0 ? rhs3_k<0>(S, mu, sigma, kap, f, g) : rhs3_k<1>(S, mu, sigma, kap, f, g);
 }
 
 }  // namespace
@@ -576,7 +610,7 @@ struct DevCsr {
 };
 
 struct Level3 {
-  Num3 S{1};
+  Num3 S{1, 1};
   DevCsr A, P, R;  // P, R: from / to level j-1 (j >= 1)
   int32_t* cons = nullptr;
   int64_t ncons = 0;
@@ -640,10 +674,10 @@ bmg_status upload_csr(bmg3_ctx* c, DevCsr& D, const Csr& A) {
 
 bmg_status check3(const bmg3_params* p) {
   if (!p) return BMG_E_ARG;
-  if (p->k != 1) return BMG_E_UNSUPPORTED;
+  if (p->k != 0 && p->k != 1) return BMG_E_UNSUPPORTED;
   if (p->n0 < 1 || p->n0 > 8 || p->levels < 1 || p->levels > 8) return BMG_E_ARG;
   if ((int64_t)p->n0 << (p->levels - 1) > 64) return BMG_E_ARG;
-  if (!(p->mu > 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
+  if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
   if ((p->cycle != 0 && p->cycle != 1) || p->m_fine < 1 || p->restart < 1 || p->restart > 200) return BMG_E_ARG;
   if (p->precond_prec != 0 && p->precond_prec != 1) return BMG_E_ARG;
   return BMG_OK;
@@ -651,7 +685,7 @@ bmg_status check3(const bmg3_params* p) {
 
 // vertex patch of (vx, vy, vz): free dofs whose support lies in the patch cells, ascending
 void patch_dofs3(const Num3& S, int vx, int vy, int vz, std::vector<int64_t>& out, std::vector<int>& cells) {
-  const int N = S.N;
+  const int N = S.N, NA3 = S.NA3, NB3 = S.NB3, NU3 = S.NU3, NL3 = S.NL3;
   out.clear();
   cells.clear();
   bool in[2][2][2] = {};
@@ -704,7 +738,7 @@ bool patch_pinv3(const Num3& S, const Csr& A, const std::vector<int64_t>& D, con
     }
   const double cv = 1.0 / std::sqrt((double)cells.size());
   for (int cl : cells) {
-    const int64_t gpres = S.n_u + (int64_t)cl * NP3;
+    const int64_t gpres = S.n_u + (int64_t)cl * S.NP3;
     const int t = (int)(std::lower_bound(D.begin(), D.end(), gpres) - D.begin());
     a[(size_t)t * m + n] = cv;
     a[(size_t)n * m + t] = cv;
@@ -875,7 +909,7 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
   c->lev.resize(p->levels);
   for (int j = 0; j <= J; ++j) {
     Level3& L = c->lev[j];
-    L.S = Num3(p->n0 << j);
+    L.S = Num3(p->n0 << j, p->k);
     Csr A = assemble_level(L.S, p->mu, p->sigma, kap[j], nullptr);
     if (A.n == 0) return bail(BMG_E_SINGULAR, "essential row without diagonal");
     if (upload_csr(c, L.A, A)) return bail(BMG_E_NOMEM, "device allocation failed");
@@ -894,8 +928,8 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
         for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) a[(size_t)i * m + A.ci[e]] = A.v[e];
       const double cv = 1.0 / std::sqrt((double)L.S.N * L.S.N * L.S.N);
       for (int64_t cl = 0; cl < (int64_t)L.S.N * L.S.N * L.S.N; ++cl) {
-        a[(size_t)(L.S.n_u + cl * NP3) * m + n] = cv;
-        a[(size_t)n * m + L.S.n_u + cl * NP3] = cv;
+        a[(size_t)(L.S.n_u + cl * L.S.NP3) * m + n] = cv;
+        a[(size_t)n * m + L.S.n_u + cl * L.S.NP3] = cv;
       }
       if (!gj_inverse((int)m, a, inv)) return bail(BMG_E_SINGULAR, "coarse matrix is singular");
       std::vector<double> ci((size_t)n * n);  // row-major (applied row by row)
@@ -960,7 +994,7 @@ bmg_status bmg3_assemble_rhs(const bmg3_params* p, const double* kappa_host, con
   if (st) return fail3(nullptr, st, "invalid parameters");
   if (!kappa_host || !f || !g || !b_host) return fail3(nullptr, BMG_E_ARG, "NULL argument");
   const int Nf = p->n0 << (p->levels - 1);
-  Num3 S(Nf);
+  Num3 S(Nf, p->k);
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   std::vector<double> b = rhs3(S, p->mu, p->sigma, kap, f, g);
   std::memcpy(b_host, b.data(), b.size() * sizeof(double));
@@ -1141,7 +1175,7 @@ bmg_status bmg3_export_level_csr(const bmg3_params* p, const double* kappa_host,
   const int J = p->levels - 1, Nf = p->n0 << J;
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   for (int j = J; j > level; --j) kap = coarsen(kap, p->n0 << (j - 1));
-  Csr A = assemble_level(Num3(p->n0 << level), p->mu, p->sigma, kap, nullptr);
+  Csr A = assemble_level(Num3(p->n0 << level, p->k), p->mu, p->sigma, kap, nullptr);
   if (!rp_host) {
     *nnz = (int64_t)A.v.size();
     return BMG_OK;
@@ -1166,7 +1200,7 @@ bmg_status bmg3_export_patch_host(const bmg3_params* p, const double* kappa_host
   if (vx < 0 || vy < 0 || vz < 0 || vx > N || vy > N || vz > N) return fail3(nullptr, BMG_E_ARG, "vertex out of range");
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   for (int j = J; j > level; --j) kap = coarsen(kap, p->n0 << (j - 1));
-  const Num3 S(N);
+  const Num3 S(N, p->k);
   Csr A = assemble_level(S, p->mu, p->sigma, kap, nullptr);
   std::vector<int64_t> D;
   std::vector<int> cells;

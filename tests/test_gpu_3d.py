@@ -19,16 +19,24 @@ def _kappa(n, seed):
 _cache = {}
 
 
-def _pair(n0, levels, seed=1, cycle=1, m_fine=2):
-    key = (n0, levels, seed, cycle, m_fine)
+def _pair(n0, levels, seed=1, cycle=1, m_fine=2, k=1, mu=MU):
+    key = (n0, levels, seed, cycle, m_fine, k, mu)
     if key not in _cache:
         N = n0 << (levels - 1)
         kap = _kappa(N, seed)
-        print(f"3-D case n0={n0} levels={levels} N={N} seed={seed}", flush=True)
-        s = bmg.Solver3(bmg.make_params3(n0, levels, MU, cycle=cycle, m_fine=m_fine), kap)
-        o = o3.Oracle3D(n0, levels, 1, MU, 6.0, kap, cycle=cycle, m_fine=m_fine)
+        sigma = (k + 1) * (k + 2)  # the penalty of Section 4.1
+        print(f"3-D case k={k} mu={mu} n0={n0} levels={levels} N={N} seed={seed}", flush=True)
+        s = bmg.Solver3(bmg.make_params3(n0, levels, mu, sigma=sigma, cycle=cycle, m_fine=m_fine, k=k), kap)
+        o = o3.Oracle3D(n0, levels, k, mu, sigma, kap, cycle=cycle, m_fine=m_fine)
         _cache[key] = (s, o, kap)
     return _cache[key]
+
+
+def _oracle_iterate(o, b, its):
+    """The oracle's FGMRES iterate after exactly `its` iterations."""
+    x, n, _ = o.fgmres(b, rtol=1e-30, maxit=its)
+    assert abs(n) == its
+    return x
 
 
 def _dev(a):
@@ -80,10 +88,13 @@ def test_solve_3d_matches_oracle(n0, levels):
     xo, its, tr = o.fgmres(b, rtol=1e-10, maxit=100)
     assert info.converged and info.rel_residual_true <= 1e-10
     assert abs(info.iterations - its) <= 1
+    if info.iterations != its:
+        xo = _oracle_iterate(o, b, info.iterations)
     xg = x.cpu().numpy()
     d = xg - xo
     d[lev.sp.n_u:] -= o.pressure_mean(xg) - o.pressure_mean(xo)
-    assert np.abs(d).max() <= 1e-7 * np.abs(xo).max()
+    # the iterate after the same number of iterations, pressures compared with zero mean
+    assert np.abs(d).max() <= 1e-10 * np.abs(xo).max(), np.abs(d).max() / np.abs(xo).max()
     # the library's own right-hand side gives the same solve
     b2 = bmg.assemble_rhs3(s.params, kap, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0))
     assert np.abs(b2 - b).max() <= 1e-13 * np.abs(b).max()
@@ -194,3 +205,95 @@ def test_nonfinite_rhs_3d():
         assert lib.bmg3_solve(s.h, ptr(b), ptr(y), 1e-10, 10, None) == 7
         torch.cuda.synchronize()
         assert bool((y == 3.0).all())
+
+
+# ---------------------------------------------------------------------------------
+# RT_0 x dQ_0 (k = 0): Brinkman and the Darcy limit mu = 0
+# ---------------------------------------------------------------------------------
+KMU0 = [(0, MU), (0, 0.0)]
+
+
+@pytest.mark.parametrize("k,mu", KMU0)
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_apply_rt0_3d(level, k, mu):
+    s, o, _ = _pair(1, 3, k=k, mu=mu)
+    n = o.lev[level].sp.ndof
+    x = np.random.default_rng(level).standard_normal(n)
+    y = s.apply(_dev(x), level).cpu().numpy()
+    yo = o.lev[level].A @ x
+    assert np.abs(y - yo).max() <= 1e-13 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("k,mu", KMU0)
+@pytest.mark.parametrize("level", [1, 2])
+def test_smoothing_step_rt0_3d(level, k, mu):
+    s, o, _ = _pair(1, 3, k=k, mu=mu)
+    L = o.lev[level]
+    rng = np.random.default_rng(10 + level)
+    x = rng.standard_normal(L.sp.ndof)
+    x[L.sp.cons] = 0.0
+    b = rng.standard_normal(L.sp.ndof)
+    xg = _dev(x)
+    s.smooth(level, 1, xg, _dev(b))
+    xo = x.copy()
+    o.sm[level].step(xo, b)
+    assert np.abs(xg.cpu().numpy() - xo).max() <= 1e-11 * np.abs(xo).max()
+
+
+@pytest.mark.parametrize("k,mu", KMU0)
+@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4), (2, 3)])
+def test_vcycle_rt0_3d(n0, levels, k, mu):
+    s, o, _ = _pair(n0, levels, k=k, mu=mu)
+    n = o.lev[-1].sp.ndof
+    r = np.random.default_rng(5).standard_normal(n)
+    r[o.lev[-1].sp.cons] = 0.0
+    z = s.vcycle(_dev(r)).cpu().numpy()
+    zo = o.vcycle(r)
+    assert np.abs(z - zo).max() <= 1e-10 * np.abs(zo).max()
+
+
+@pytest.mark.parametrize("k,mu", KMU0)
+@pytest.mark.parametrize("n0,levels", [(1, 3), (1, 4), (2, 3)])
+def test_solve_rt0_3d_matches_oracle(n0, levels, k, mu):
+    """FP64 solve: iteration count within +-1 of the oracle's, the iterate after the
+    same count within 1e-10 (max norm, zero-mean pressures)."""
+    s, o, kap = _pair(n0, levels, k=k, mu=mu)
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    f = lambda x, y, z: np.array([0 * x, np.ones_like(x), 0 * x])
+    b = lev.rhs(f, g)
+    b2 = bmg.assemble_rhs3(s.params, kap, (0.0, 1.0, 0.0), (1.0, 0.0, 0.0))
+    assert np.abs(b2 - b).max() <= 1e-13 * np.abs(b).max()
+    x, info = s.solve(_dev(b), rtol=1e-10, maxit=200)
+    xo, its, tr = o.fgmres(b, rtol=1e-10, maxit=200)
+    assert info.converged and info.rel_residual_true <= 1e-10
+    assert abs(info.iterations - its) <= 1, (info.iterations, its)
+    if info.iterations != its:
+        xo = _oracle_iterate(o, b, info.iterations)
+    xg = x.cpu().numpy()
+    d = xg - xo
+    d[lev.sp.n_u:] -= o.pressure_mean(xg) - o.pressure_mean(xo)
+    print(f"RT_0 3-D mu={mu} n0={n0} levels={levels}: {info.iterations} iterations (oracle {its}), "
+          f"max diff {np.abs(d).max() / np.abs(xo).max():.2e}")
+    assert np.abs(d).max() <= 1e-10 * np.abs(xo).max()
+
+
+def test_rt0_3d_at_n32_sampled():
+    """RT_0 Darcy at N = 32 (6 levels), the contrast-1e6 field: converged solve, the
+    operator against the oracle's assembly at this size, the true residual recomputed
+    on the host."""
+    N = 32
+    kap = _kappa(N, 8)
+    print("3-D case k=0 mu=0 N=32 levels=6 seed=8", flush=True)
+    s = bmg.Solver3(bmg.make_params3(1, 6, 0.0, sigma=2.0, k=0), kap)
+    lev = o3.Level(N, 0, 0.0, 2.0, kap)
+    b = bmg.assemble_rhs3(s.params, kap, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0))
+    x, info = s.solve(_dev(b), rtol=1e-10, maxit=200)
+    xg = x.cpu().numpy()
+    assert info.converged
+    assert np.linalg.norm(b - lev.A @ xg) <= 2e-10 * np.linalg.norm(b)
+    xr = np.random.default_rng(1).standard_normal(lev.sp.ndof)
+    y = s.apply(_dev(xr)).cpu().numpy()
+    assert np.abs(y - lev.A @ xr).max() <= 1e-13 * np.abs(y).max()
+    print(f"RT_0 3-D Darcy N=32: {info.iterations} iterations", flush=True)
+    s.close()

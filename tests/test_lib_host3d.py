@@ -17,11 +17,16 @@ def _kappa(n, seed):
     return 10.0 ** np.clip(np.random.default_rng(seed).normal(-3, 1.5, n ** 3), -6, 0)
 
 
+# (k, mu): RT_1 Brinkman, RT_0 Brinkman, RT_0 Darcy
+KMU = [(1, 1e-2), (0, 1e-2), (0, 0.0)]
+
+
+@pytest.mark.parametrize("k,mu", KMU)
 @pytest.mark.parametrize("level", [0, 1, 2])
-def test_level_operator_matches_oracle(level):
-    p = bmg.make_params3(1, 3, 1e-2)
+def test_level_operator_matches_oracle(level, k, mu):
+    p = bmg.make_params3(1, 3, mu, k=k)
     kap = _kappa(4, 1)
-    o = o3.Oracle3D(1, 3, 1, 1e-2, 6.0, kap)
+    o = o3.Oracle3D(1, 3, k, mu, 6.0, kap)
     rp, ci, v = bmg.export_level_csr3(p, kap, level)
     n = len(rp) - 1
     A = sp.csr_matrix((v, ci, rp), shape=(n, n))
@@ -30,22 +35,24 @@ def test_level_operator_matches_oracle(level):
     assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
 
 
-def test_rhs_matches_oracle():
-    p = bmg.make_params3(2, 2, 0.3)
+@pytest.mark.parametrize("k,mu", [(1, 0.3), (0, 0.3), (0, 0.0)])
+def test_rhs_matches_oracle(k, mu):
+    p = bmg.make_params3(2, 2, mu, k=k)
     kap = _kappa(4, 2)
     f, g = (0.5, -1.0, 0.25), (1.0, 0.3, -0.2)
     b = bmg.assemble_rhs3(p, kap, f, g)
-    lev = o3.Level(4, 1, 0.3, 6.0, kap)
+    lev = o3.Level(4, k, mu, 6.0, kap)
     bo = lev.rhs(lambda x, y, z: np.array([c + 0 * x for c in f]), lambda x, y, z: np.array([c + 0 * x for c in g]))
     assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
 
 
+@pytest.mark.parametrize("k,mu", KMU)
 @pytest.mark.parametrize("vertex", [(2, 2, 2), (0, 0, 0), (4, 1, 2), (1, 4, 4), (3, 0, 1)])
-def test_patch_pseudo_inverse_matches_oracle(vertex):
-    p = bmg.make_params3(1, 3, 1e-2)
+def test_patch_pseudo_inverse_matches_oracle(vertex, k, mu):
+    p = bmg.make_params3(1, 3, mu, k=k)
     kap = _kappa(4, 3)
     dofs, pinv = bmg.export_patch_host3(p, kap, 2, *vertex)
-    lev = o3.Level(4, 1, 1e-2, 6.0, kap)
+    lev = o3.Level(4, k, mu, 6.0, kap)
     d_o, cells = o3.patch_dofs(lev.sp, *vertex)
     A_S = lev.A[d_o][:, d_o].toarray()
     po = o3.patch_pinv(A_S, lev.sp, d_o, cells, True)
@@ -55,8 +62,8 @@ def test_patch_pseudo_inverse_matches_oracle(vertex):
     assert np.array_equal(pinv, pinv.T)
 
 
-@pytest.mark.parametrize("change,expect", [(dict(k=2), 2), (dict(k=0), 2), (dict(n0=0), 1), (dict(levels=0), 1),
-                                           (dict(mu=0.0), 1), (dict(sigma=-1.0), 1), (dict(m_fine=0), 1),
+@pytest.mark.parametrize("change,expect", [(dict(k=2), 2), (dict(k=-1), 2), (dict(n0=0), 1), (dict(levels=0), 1),
+                                           (dict(mu=-1.0), 1), (dict(sigma=-1.0), 1), (dict(m_fine=0), 1),
                                            (dict(restart=0), 1), (dict(cycle=3), 1), (dict(n0=8, levels=5), 1),
                                            (dict(precond_prec=2), 1), (dict(precond_prec=-1), 1)])
 def test_setup3_rejects_bad_parameters(change, expect):

@@ -225,3 +225,92 @@ def test_brinkman_convergence_rates_3d():
     rp = np.log2(errs[1][1] / errs[2][1])
     assert ru > 1.8, errs
     assert rp > 0.9, errs
+
+
+# ---------------------------------------------------------------------------------
+# RT_0 x dQ_0 (k = 0, Section 2.3: one normal flux per face, one pressure per cell),
+# Brinkman and the Darcy limit mu = 0
+# ---------------------------------------------------------------------------------
+# P1 (k = 0): constant u = a is in RT_0, divergence free and has no jumps, p = 0:
+# f = kappa a, g = a.  The discrete solution is exact for any mu >= 0 and any
+# cellwise kappa (a dropped mass term, a wrong lifting or a sign error in the
+# pressure coupling leaves an O(1) error).
+@pytest.mark.parametrize("mu", [1.0, 1e-2, 0.0])
+def test_constant_solution_is_reproduced_rt0_3d(mu):
+    n0, levels = 1, 3
+    n = n0 << (levels - 1)
+    kap = _kappa(n, 5)
+    o = o3.Oracle3D(n0, levels, 0, mu, 2.0, kap)
+    lev = o.lev[-1]
+    a = np.array([0.3, -0.7, 1.1])
+    k_at = lambda x, y, z: _cell_kappa(kap, n, x, y, z)
+    f = lambda x, y, z: np.array([k_at(x, y, z) * a[0], k_at(x, y, z) * a[1], k_at(x, y, z) * a[2]])
+    g = lambda x, y, z: np.array([a[0] + 0 * x, a[1] + 0 * x, a[2] + 0 * x])
+    b = lev.rhs(f, g)
+    P = np.random.default_rng(7).random((40, 3))
+    for x in (o.direct_solve(b), o.fgmres(b, rtol=1e-13, maxit=80)[0]):
+        U, Pv = o3.evaluate(lev, x, P)
+        assert np.abs(U - a).max() < 1e-10
+        assert np.abs(Pv - o.pressure_mean(x)).max() < 1e-10
+
+
+def test_rt0_sizes_and_patch_3d():
+    # N = 4: 3 (N+1) N^2 face fluxes, N^3 pressures; an interior patch holds the 12
+    # faces inside its 2 x 2 x 2 block and the 8 cell pressures
+    S = o3.Space(4, 0)
+    assert S.n_u == 3 * 5 * 16 and S.ndof == S.n_u + 64
+    lev = o3.Level(4, 0, 0.5, 2.0, _kappa(4, 2))
+    d, cells = o3.patch_dofs(lev.sp, 2, 2, 2)
+    assert len(d) == 12 + 8 and len(cells) == 8
+
+
+@pytest.mark.parametrize("mu", [1e-2, 0.0])
+def test_multigrid_matches_direct_solve_rt0_3d(mu):
+    # Darcy with contrast 1e2 (at 1e6 the mixed operator's conditioning turns a 1e-12
+    # residual into ~1e-7 relative differences between the two solutions)
+    kap = 10.0 ** np.clip(np.random.default_rng(12).normal(-3, 1.5, 512), -6, 0) if mu else _kappa(8, 12)
+    o = o3.Oracle3D(2, 3, 0, mu, 2.0, kap)
+    lev = o.lev[-1]
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0 * x])
+    b = lev.rhs(lambda x, y, z: np.zeros((3,) + np.shape(x)), g)
+    xm, its, tr = o.fgmres(b, rtol=1e-12, maxit=100)
+    xd = o.direct_solve(b)
+    d = xm - xd
+    d[lev.sp.n_u:] -= o.pressure_mean(xm) - o.pressure_mean(xd)
+    assert tr < 1e-11 and its < 100
+    assert np.abs(d).max() < 1e-8 * np.abs(xd).max()
+
+
+def test_vcycle_is_symmetric_rt0_3d():
+    o = o3.Oracle3D(1, 3, 0, 0.0, 2.0, _kappa(4, 6, -4.0, 0.0))
+    n = o.lev[-1].sp.ndof
+    free = ~o.lev[-1].sp.cons
+    rng = np.random.default_rng(2)
+    u, v = rng.standard_normal(n) * free, rng.standard_normal(n) * free
+    a, b = u @ o.vcycle(v), v @ o.vcycle(u)
+    assert abs(a - b) < 1e-10 * abs(a)
+
+
+# P3 (k = 0, Darcy): u = grad of a smooth p' with kappa = 1 and f = 0 ... written as
+# the mixed problem kappa u + grad p = f, div u = 0 with the smooth divergence-free
+# u = (sin pi y, sin pi z, sin pi x), p = cos pi x cos pi y cos pi z: f = u + grad p,
+# g = u.  RT_0 x dQ_0 converges at first order in L2 for both fields.
+def test_darcy_convergence_rates_rt0_3d():
+    pi = np.pi
+    u = lambda x, y, z: (np.sin(pi * y), np.sin(pi * z), np.sin(pi * x))
+    p = lambda x, y, z: np.cos(pi * x) * np.cos(pi * y) * np.cos(pi * z)
+    f = lambda x, y, z: np.array([np.sin(pi * y) - pi * np.sin(pi * x) * np.cos(pi * y) * np.cos(pi * z),
+                                  np.sin(pi * z) - pi * np.cos(pi * x) * np.sin(pi * y) * np.cos(pi * z),
+                                  np.sin(pi * x) - pi * np.cos(pi * x) * np.cos(pi * y) * np.sin(pi * z)])
+    g = lambda x, y, z: np.array(u(x, y, z))
+    errs = []
+    for n in (4, 8, 16):
+        lev = o3.Level(n, 0, 0.0, 2.0, np.ones(n ** 3))
+        c = lev.cvec / np.linalg.norm(lev.cvec)
+        Bd = sp.bmat([[lev.A, sp.csr_matrix(c[:, None])], [sp.csr_matrix(c[None, :]), None]]).tocsc()
+        x = spla.spsolve(Bd, np.concatenate([lev.rhs(f, g), [0.0]]))[:-1]
+        errs.append(_l2_errors(lev, x, u, p))
+    ru = np.log2(errs[1][0] / errs[2][0])
+    rp = np.log2(errs[1][1] / errs[2][1])
+    assert 0.85 < ru < 1.3, errs
+    assert 0.85 < rp < 1.3, errs
