@@ -6,13 +6,14 @@ links or runs anything here, and nothing here calls the library.
 It follows the method's definitions as written, for d = 3:
   * discretisation (Section 2): RT_k x dQ_k on a uniform hexahedral mesh of the unit
     cube, the interior-penalty Brinkman form (eq. ipbrinkman) with sigma_h = sigma / h,
-    pressure coupling -(p, div v) - (q, div u) (eq. Brinkman-weak), Dirichlet data on
-    all six sides: the normal velocity essential (boundary normal face dofs fixed to
-    the face projection of g.n, identity rows and columns, lifting into the
-    right-hand side), the tangential velocity by the Nitsche terms of eq. (BCh), and
-    the pressure in L2_0 (the reading the two-dimensional path takes for Dirichlet
-    sides: with a weak normal component the form misses <p, v.n> and the polynomial
-    patch test fails);
+    pressure coupling -(p, div v) - (q, div u) (eq. Brinkman-weak); on a Dirichlet
+    side the normal velocity is essential (boundary normal face dofs fixed to the face
+    projection of g.n, identity rows and columns, lifting into the right-hand side) and
+    the tangential velocity is imposed by the Nitsche terms of eq. (BCh) (the reading
+    the two-dimensional path takes: with a weak normal component the form misses
+    <p, v.n> and the polynomial patch test fails); an open side carries the natural
+    condition mu d_n u - p n = 0 (no boundary term, no data); with every side
+    Dirichlet the pressure is taken in L2_0;
   * mesh hierarchy (Section 3): N_j = N_0 2^j, kappa of a coarse cell = mean of its
     eight children (the arithmetic average used in the experiments);
   * transfers (Section 3): the exact embedding of the nested coarse space, computed
@@ -21,13 +22,14 @@ It follows the method's definitions as written, for d = 3:
     fine dof; restriction is its transpose;
   * smoother (Section 3): vertex patches of up to eight cells (each cell lies in at
     most eight patches in 3-D), S = dofs whose support lies in the patch cells,
-    local Ritz projection through the patch pseudo-inverse (every patch has the
-    patch-constant pressure in its kernel: no free boundary normal dof), symmetric
+    local Ritz projection through the patch pseudo-inverse (a patch without a free
+    boundary normal dof, i.e. one not touching an open side, has the patch-constant
+    pressure in its kernel), symmetric
     multiplicative sweep over 27 colours (vx mod 3) + 3 (vy mod 3) + 9 (vz mod 3),
     order 0..26, 25..0;
   * V-cycle with the coarse-grid correction x += P B_{j-1} P^T (b - A x), variable
     smoothing m_j = m_J 2^(J-j) (or fixed), exact coarse solve (bordered with the
-    constant pressure), identity rows of the essential dofs inverted exactly; right-preconditioned
+    constant pressure when every side is Dirichlet), identity rows of the essential dofs inverted exactly; right-preconditioned
     FGMRES with modified Gram-Schmidt (the Krylov method of the experiments).
 Integrals use Gauss-Legendre rules with k + 2 points per direction, exact for every
 integrand here (cellwise constant kappa, polynomial data of low degree).
@@ -43,6 +45,7 @@ Numbering (a specification the library follows in code of its own):
       (t1, t2) = the cell indices along d1, d2;
   interior dofs (a >= 2): 3 NF + c NI + (d k + a - 2) NB^2 + b + NB c, NI = 3 k NB^2;
   pressure L_a(x) L_b(y) L_c(z): n_u + c NB^3 + a + NB b + NB^2 c.
+Sides: bc[s] for s = 2 d + (0 at x_d = 0, 1 at x_d = 1), 0 Dirichlet, 1 open.
 """
 from __future__ import annotations
 
@@ -78,11 +81,15 @@ def gauss01(q: int):
 
 
 # ---------------------------------------------------------------- discretisation
-class Space:
-    """Sizes and the dof numbering of one level (N cells per side, degree k)."""
+DIRICHLET = (0, 0, 0, 0, 0, 0)
 
-    def __init__(self, N: int, k: int):
+
+class Space:
+    """Sizes and the dof numbering of one level (N cells per side, degree k, sides bc)."""
+
+    def __init__(self, N: int, k: int, bc=DIRICHLET):
         self.N, self.k, self.NB = N, k, k + 1
+        self.bc = tuple(int(v) for v in bc)
         NB = self.NB
         self.NF = (N + 1) * N * N * NB * NB
         self.NI = 3 * k * NB * NB
@@ -92,14 +99,18 @@ class Space:
         # local velocity dofs (d, a, b, c) and pressure dofs (a, b, c)
         self.lu = [(d, a, b, c) for d in range(3) for a in range(k + 2) for c in range(NB) for b in range(NB)]
         self.lp = [(a, b, c) for c in range(NB) for b in range(NB) for a in range(NB)]
-        # essential dofs: the normal face dofs on the boundary faces (i = 0 or N)
+        # essential dofs: the normal face dofs on the boundary faces (i = 0 or N) of the
+        # Dirichlet sides; the normal face dofs of the open sides are free
         self.cons = np.zeros(self.ndof, dtype=bool)
+        self.open_normal = np.zeros(self.ndof, dtype=bool)
         for d in range(3):
             for t2 in range(N):
                 for t1 in range(N):
-                    for i in (0, N):
+                    for side, i in ((0, 0), (1, N)):
                         base = d * self.NF + ((t2 * N + t1) * (N + 1) + i) * NB * NB
-                        self.cons[base:base + NB * NB] = True
+                        mask = self.open_normal if self.bc[2 * d + side] else self.cons
+                        mask[base:base + NB * NB] = True
+        self.all_dirichlet = not any(self.bc)
 
     def cell(self, cx, cy, cz):
         return (cz * self.N + cy) * self.N + cx
@@ -177,8 +188,8 @@ def face_rule(q, d, xi_d):
 class Level:
     """Assembled FP64 operator of one level (CSR), with its reference matrices."""
 
-    def __init__(self, N, k, mu, sigma, kappa):
-        self.sp = S = Space(N, k)
+    def __init__(self, N, k, mu, sigma, kappa, bc=DIRICHLET):
+        self.sp = S = Space(N, k, bc)
         self.N, self.k, self.mu, self.sigma = N, k, mu, sigma
         self.kappa = np.asarray(kappa, dtype=np.float64).reshape(N ** 3)
         h = 1.0 / N
@@ -238,9 +249,10 @@ class Level:
                     t2 = S.cell(*up)
                     gl = np.concatenate([du[t], du[t2]])
                     rows.append(np.repeat(gl, 2 * nu)); cols.append(np.tile(gl, 2 * nu)); vals.append(F.ravel())
-                if cc[d] == 0:
+                # Nitsche terms on Dirichlet sides only (an open side has no boundary term)
+                if cc[d] == 0 and not S.bc[2 * d]:
                     rows.append(np.repeat(du[t], nu)); cols.append(np.tile(du[t], nu)); vals.append(Fb_lo.ravel())
-                if cc[d] == N - 1:
+                if cc[d] == N - 1 and not S.bc[2 * d + 1]:
                     rows.append(np.repeat(du[t], nu)); cols.append(np.tile(du[t], nu)); vals.append(Fb_hi.ravel())
         r = np.concatenate(rows); c_ = np.concatenate(cols); vv = np.concatenate(vals)
         A = sp.csr_matrix((vv, (r, c_)), shape=(S.ndof, S.ndof))
@@ -257,8 +269,9 @@ class Level:
         self.cvec[S.n_u::S.NB ** 3] = 1.0
 
     def rhs(self, f, g):
-        """F(v, q) = (f, v) + 2 mu sigma_h <g, v>_dOmega - mu <grad v n, g>_dOmega (eq. BCh);
-        f, g: callables (x, y, z arrays) -> (3, n) arrays.  Pressure rows are zero."""
+        """F(v, q) = (f, v) + 2 mu sigma_h <g, v>_G - mu <grad v n, g>_G (eq. BCh), G the
+        Dirichlet sides (g is never evaluated on an open side); f, g: callables (x, y,
+        z arrays) -> (3, n) arrays.  Pressure rows are zero."""
         S, rb, h, mu = self.sp, self.rb, self.h, self.mu
         q = self.k + 2
         X, W = cube_rule(q)
@@ -272,7 +285,9 @@ class Level:
             np.add.at(b, du[t], h ** 3 * np.einsum("iqa,aq,q->i", v, fv, W))
         pen = 2.0 * mu * self.sigma / h
         for d in range(3):
-            for xi, sgn in ((0.0, -1.0), (1.0, 1.0)):
+            for side, (xi, sgn) in enumerate(((0.0, -1.0), (1.0, 1.0))):
+                if S.bc[2 * d + side]:
+                    continue
                 Xb, Wf = face_rule(q, d, xi)
                 vb, gb = rb.vel(Xb)
                 dnb = sgn * gb[:, :, :, d] / h
@@ -298,7 +313,9 @@ class Level:
             d1, d2 = AXES[d]
             for t2 in range(N):
                 for t1 in range(N):
-                    for i in (0, N):
+                    for side, i in ((0, 0), (1, N)):
+                        if S.bc[2 * d + side]:
+                            continue
                         base = d * S.NF + ((t2 * N + t1) * (N + 1) + i) * NB * NB
                         for c in range(NB):
                             for b_ in range(NB):
@@ -388,10 +405,9 @@ class Smoother:
             for vy in range(N + 1):
                 for vx in range(N + 1):
                     dofs, cells = patch_dofs(S, vx, vy, vz)
-                    # the only dofs with a normal trace on the boundary are essential,
-                    # so no patch space has one: every patch has the constant patch
-                    # pressure in its kernel
-                    singular = True
+                    # without a free boundary normal dof (open sides only) the patch
+                    # space has the constant patch pressure in its kernel
+                    singular = not S.open_normal[dofs].any()
                     rows = A[dofs, :]
                     A_S = rows[:, dofs].toarray()
                     pinv = patch_pinv(A_S, S, dofs, cells, singular)
@@ -466,8 +482,9 @@ def prolongation(Sc: Space, Sf: Space):
 
 # ---------------------------------------------------------------- the solver
 class Oracle3D:
-    def __init__(self, n0, levels, k, mu, sigma, kappa, cycle=1, m_fine=2):
+    def __init__(self, n0, levels, k, mu, sigma, kappa, cycle=1, m_fine=2, bc=DIRICHLET):
         self.k, self.mu, self.sigma = k, mu, sigma
+        self.bc = tuple(int(v) for v in bc)
         self.J = levels - 1
         self.cycle, self.m_fine = cycle, m_fine
         Nf = n0 * 2 ** self.J
@@ -479,17 +496,21 @@ class Oracle3D:
                                   + K[0::2, 0::2, 1::2] + K[1::2, 0::2, 1::2] + K[0::2, 1::2, 1::2]
                                   + K[1::2, 1::2, 1::2])
         self.kap = kap
-        self.lev = [Level(n0 * 2 ** j, k, mu, sigma, kap[j].ravel()) for j in range(levels)]
+        self.lev = [Level(n0 * 2 ** j, k, mu, sigma, kap[j].ravel(), self.bc) for j in range(levels)]
         self.sm = [None] + [Smoother(L) for L in self.lev[1:]]
         self.P = [None] + [prolongation(self.lev[j - 1].sp, self.lev[j].sp) for j in range(1, levels)]
         A0 = self.lev[0].A.toarray()
-        c = self.lev[0].cvec / np.linalg.norm(self.lev[0].cvec)
-        n0d = A0.shape[0]
-        Bd = np.zeros((n0d + 1, n0d + 1))
-        Bd[:n0d, :n0d] = A0
-        Bd[:n0d, n0d] = c
-        Bd[n0d, :n0d] = c
-        self.A0inv = np.linalg.inv(Bd)[:n0d, :n0d]
+        if self.lev[0].sp.all_dirichlet:
+            # the constant pressure spans the kernel: bordered inverse
+            c = self.lev[0].cvec / np.linalg.norm(self.lev[0].cvec)
+            n0d = A0.shape[0]
+            Bd = np.zeros((n0d + 1, n0d + 1))
+            Bd[:n0d, :n0d] = A0
+            Bd[:n0d, n0d] = c
+            Bd[n0d, :n0d] = c
+            self.A0inv = np.linalg.inv(Bd)[:n0d, :n0d]
+        else:
+            self.A0inv = np.linalg.inv(A0)
 
     def m(self, j):
         return self.m_fine * (2 ** (self.J - j) if self.cycle == 1 else 1)
@@ -516,8 +537,11 @@ class Oracle3D:
         return self.lev[self.J if j is None else j].A @ x
 
     def direct_solve(self, b):
-        """Solution with zero pressure mean (bordered sparse system)."""
+        """The solution (with zero pressure mean when every side is Dirichlet: bordered
+        sparse system)."""
         L = self.lev[self.J]
+        if not L.sp.all_dirichlet:
+            return spla.spsolve(L.A.tocsc(), b)
         c = L.cvec / np.linalg.norm(L.cvec)
         Bd = sp.bmat([[L.A, sp.csr_matrix(c[:, None])], [sp.csr_matrix(c[None, :]), None]]).tocsc()
         return spla.spsolve(Bd, np.concatenate([b, [0.0]]))[:-1]

@@ -314,3 +314,112 @@ def test_darcy_convergence_rates_rt0_3d():
     rp = np.log2(errs[1][1] / errs[2][1])
     assert 0.85 < ru < 1.3, errs
     assert 0.85 < rp < 1.3, errs
+
+
+# ---------------------------------------------------------------------------------
+# Open sides (natural condition mu d_n u - p n = 0, no boundary data)
+# ---------------------------------------------------------------------------------
+OPEN_Z = (0, 0, 0, 0, 1, 1)  # open at z = 0 and z = 1
+OPEN_ONE = (0, 0, 0, 0, 0, 1)
+
+
+def _junk_on_open(g, bc):
+    """g plus a large perturbation on the open sides: the discretisation must not
+    evaluate boundary data there."""
+    def gj(x, y, z):
+        v = np.array(g(x, y, z), dtype=float)
+        for d, t in enumerate((x, y, z)):
+            for side, val in ((0, 0.0), (1, 1.0)):
+                if bc[2 * d + side]:
+                    v = v + 7.0 * (np.abs(np.asarray(t) - val) < 1e-14)
+        return v
+    return gj
+
+
+# P1 (open sides): u = (0, 0, x) flows through the open z sides (d_z u = 0 there, p =
+# 0): f = kappa u, g = u on the Dirichlet sides and junk on the open ones.  RT_1
+# holds u, so the discrete solution is exact, pressure included (no constant is free
+# with an open side).  Darcy (mu = 0): the same with p = 0 on the open sides.
+@pytest.mark.parametrize("mu", [1.0, 1e-2, 0.0])
+def test_flow_through_open_sides_is_reproduced_3d(mu):
+    n0, levels = 1, 3
+    n = n0 << (levels - 1)
+    kap = _kappa(n, 5)
+    o = o3.Oracle3D(n0, levels, 1, mu, 6.0, kap, bc=OPEN_Z)
+    lev = o.lev[-1]
+    k_at = lambda x, y, z: _cell_kappa(kap, n, x, y, z)
+    f = lambda x, y, z: np.array([0 * x, 0 * x, k_at(x, y, z) * x])
+    g = lambda x, y, z: np.array([0 * x, 0 * x, x])
+    b = lev.rhs(f, _junk_on_open(g, OPEN_Z))
+    P = np.random.default_rng(7).random((40, 3))
+    ue = np.stack([0 * P[:, 0], 0 * P[:, 0], P[:, 0]], 1)
+    for x in (o.direct_solve(b), o.fgmres(b, rtol=1e-13, maxit=80)[0]):
+        U, Pv = o3.evaluate(lev, x, P)
+        assert np.abs(U - ue).max() < 1e-10
+        assert np.abs(Pv).max() < 1e-10
+
+
+# P2 (open side): f = grad(phi), phi the trilinear hat at an interior vertex (zero on
+# the boundary, so the natural condition holds), g = 0: u_h = 0 and p_h = phi exactly,
+# with no constant removed -- an open side fixes the pressure level.
+@pytest.mark.parametrize("k", [0, 1])
+def test_hat_gradient_fixes_the_pressure_with_an_open_side_3d(k):
+    n = 4
+    h = 1.0 / n
+    lev = o3.Level(n, k, 1e-2, 2.0 if k == 0 else 6.0, _kappa(n, 9, -6.0, 0.0), OPEN_ONE)
+    v = np.array([2, 1, 3]) * h
+    hat1 = lambda t, c: np.maximum(0.0, 1.0 - np.abs(t - c) / h)
+    dhat1 = lambda t, c: np.where(np.abs(t - c) < h, -np.sign(t - c) / h, 0.0)
+    f = lambda x, y, z: np.array([dhat1(x, v[0]) * hat1(y, v[1]) * hat1(z, v[2]),
+                                  hat1(x, v[0]) * dhat1(y, v[1]) * hat1(z, v[2]),
+                                  hat1(x, v[0]) * hat1(y, v[1]) * dhat1(z, v[2])])
+    zero = lambda x, y, z: np.zeros((3,) + np.shape(x))
+    x = spla.spsolve(lev.A.tocsc(), lev.rhs(f, _junk_on_open(zero, OPEN_ONE)))
+    assert np.abs(x[:lev.sp.n_u]).max() < 1e-12
+    phi = lambda x_, y_, z_: hat1(x_, v[0]) * hat1(y_, v[1]) * hat1(z_, v[2])
+    if k == 1:  # the trilinear hat lies in dQ_1 cellwise
+        assert np.abs(x[lev.sp.n_u:] - lev.interpolate_pressure(phi)).max() < 1e-12
+    else:       # dQ_0: the cell means of phi
+        assert np.abs(x[lev.sp.n_u:] - lev.interpolate_pressure(phi)).max() < 1e-12
+
+
+def test_open_side_patches_and_operator_3d():
+    lev = o3.Level(4, 1, 0.3, 6.0, _kappa(4, 1), OPEN_Z)
+    S = lev.sp
+    # two open sides: their 2 x 16 faces x (k+1)^2 normal dofs are free
+    assert S.cons.sum() == 4 * 16 * 4 and S.open_normal.sum() == 2 * 16 * 4
+    assert abs(lev.A - lev.A.T).max() <= 1e-13 * abs(lev.A).max()
+    # no pressure constant in the kernel: the operator is nonsingular
+    assert np.abs(lev.A @ lev.cvec).max() > 1e-3
+    sm = o3.Smoother(lev)
+    kinds = {}
+    for (vx, vy, vz), dofs, rows, pinv, singular in sm.patches:
+        A_S = rows[:, dofs].toarray()
+        assert singular == (not S.open_normal[dofs].any())
+        kinds[singular] = True
+        if not singular:
+            assert np.abs(pinv @ A_S - np.eye(len(dofs))).max() < 1e-9
+        # only patches with a cell on the first or last layer in z touch an open side
+        assert (vz in (0, 1, 3, 4)) or singular
+    assert kinds == {True: True, False: True}
+
+
+@pytest.mark.parametrize("k,mu", [(1, 1e-2), (0, 1e-2), (0, 0.0)])
+def test_multigrid_matches_direct_solve_open_3d(k, mu):
+    kap = _kappa(8, 12) if mu == 0.0 else 10.0 ** np.clip(np.random.default_rng(12).normal(-3, 1.5, 512), -6, 0)
+    o = o3.Oracle3D(2, 3, k, mu, 2.0 if k == 0 else 6.0, kap, bc=OPEN_Z)
+    lev = o.lev[-1]
+    # a body force along z drives flow through the open sides (for Darcy the only data)
+    g = lambda x, y, z: np.array([0 * x, 0 * x, np.ones_like(x)])
+    b = lev.rhs(lambda x, y, z: np.array([0 * x, 0 * x, np.ones_like(x)]), g)
+    xm, its, tr = o.fgmres(b, rtol=1e-12, maxit=100)
+    xd = o.direct_solve(b)
+    assert tr < 1e-11 and its < 100
+    assert np.abs(xm - xd).max() < 1e-8 * np.abs(xd).max()
+    # the V-cycle is a symmetric operator
+    n = lev.sp.ndof
+    free = ~lev.sp.cons
+    rng = np.random.default_rng(2)
+    p_, q_ = rng.standard_normal(n) * free, rng.standard_normal(n) * free
+    a1, a2 = p_ @ o.vcycle(q_), q_ @ o.vcycle(p_)
+    assert abs(a1 - a2) < 1e-10 * abs(a1)
