@@ -4,16 +4,18 @@
  *
  * Problem (Section 2, d = 3): -mu Lap u + kappa u + grad p = f, div u = 0 on the unit
  * cube, mu >= 0 (mu = 0: the Darcy limit, eq. (Darcy-weak)), kappa >= 0 cellwise
- * constant, u = g on all six sides (for mu = 0 only the normal component counts).
+ * constant; on a Dirichlet side u = g (for mu = 0 only the normal component counts),
+ * on an open side the natural condition mu d_n u - p n = 0 (no boundary term, g not
+ * used there; for mu = 0: p = 0).
  * Discretisation (Section 2): RT_k velocity x discontinuous Q_k pressure, k = 0 (the
  * lowest order, Section 2.3: one normal-flux dof per face, one pressure per cell) or
  * k = 1, on a uniform
  * N x N x N hexahedral mesh, interior-penalty form a_h (eq. ipbrinkman) with face
  * penalty 2 mu sigma / h, saddle-point form (eq. Brinkman-weak).  The normal velocity
  * on the boundary is an essential condition (boundary normal face dofs fixed, identity
- * rows), the tangential one is imposed by the Nitsche terms of eq. (BCh), and the
- * pressure is determined up to a constant (solutions are returned as computed; compare
- * pressures after removing the mean).
+ * rows), the tangential one is imposed by the Nitsche terms of eq. (BCh); with every
+ * side Dirichlet the pressure is determined up to a constant (solutions are returned
+ * as computed; compare pressures after removing the mean), an open side fixes it.
  * Solver (Section 3): FGMRES preconditioned by the V-cycle over N_j = n0 2^j with the
  * symmetric multiplicative vertex-patch smoother over patches of up to eight cells
  * (27 colours (vx mod 3) + 3 (vy mod 3) + 9 (vz mod 3), order 0..26, 25..0), the exact
@@ -62,6 +64,7 @@ typedef struct {
   int32_t precond_prec; /* storage of the patch pseudo-inverses: 0 FP64, 1 FP32 (rounded to nearest;
                            vectors, residuals and arithmetic stay FP64; FGMRES absorbs the
                            perturbed V-cycle, as with the reduced-precision V-cycles of bmg.h) */
+  int32_t bc[6];   /* BMG_BC_DIRICHLET / BMG_BC_OPEN per side: 0 x=0, 1 x=1, 2 y=0, 3 y=1, 4 z=0, 5 z=1 */
 } bmg3_params;
 
 /* Assemble levels, transfers and patch pseudo-inverses for the fine-level kappa
@@ -101,7 +104,7 @@ bmg_status bmg3_vcycle(bmg3_handle h, const double* r_dev, double* z_dev);
  * produces one.  info may be NULL. */
 bmg_status bmg3_solve(bmg3_handle h, const double* b_dev, double* x_dev, double rtol, int32_t maxit,
                       bmg_solve_info* info);
-/* Dofs (ascending, *n of them, at most 208) and pseudo-inverse (n x n, column-major,
+/* Dofs (ascending, *n of them, at most 256) and pseudo-inverse (n x n, column-major,
  * symmetrised: the mean of the computed inverse and its transpose, as the smoother
  * applies it) of the patch of vertex (vx, vy, vz) on level >= 1 (host arrays;
  * pinv_host may be NULL). */

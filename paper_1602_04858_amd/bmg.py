@@ -489,7 +489,7 @@ def from_workload(w, prec=P_FP64, restart=100, device="cuda", dense_coarse_max=D
 class Params3(C.Structure):
     _fields_ = [("n0", C.c_int32), ("levels", C.c_int32), ("k", C.c_int32), ("mu", C.c_double),
                 ("sigma", C.c_double), ("cycle", C.c_int32), ("m_fine", C.c_int32), ("restart", C.c_int32),
-                ("precond_prec", C.c_int32)]
+                ("precond_prec", C.c_int32), ("bc", C.c_int32 * 6)]
 
 
 _sig3 = {
@@ -514,11 +514,17 @@ _lib.bmg3_last_error.argtypes = [_VP]
 _lib.bmg3_last_error.restype = C.c_char_p
 
 
-def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, restart=50, k=1, prec=P_FP64):
-    """prec: P_FP64, or P_FP32 for FP32-stored patch pseudo-inverses (FP64 arithmetic)."""
+def make_params3(n0, levels, mu, sigma=6.0, cycle=CYCLE_VARIABLE, m_fine=2, restart=50, k=1, prec=P_FP64,
+                 bc=(0, 0, 0, 0, 0, 0)):
+    """prec: P_FP64, or P_FP32 for FP32-stored patch pseudo-inverses (FP64 arithmetic);
+    bc: BC_DIRICHLET / BC_OPEN per side (x=0, x=1, y=0, y=1, z=0, z=1)."""
     p = Params3()
     p.n0, p.levels, p.k, p.mu, p.sigma = n0, levels, k, float(mu), float(sigma)
     p.cycle, p.m_fine, p.restart, p.precond_prec = cycle, m_fine, restart, prec
+    if len(bc) != 6:
+        raise ValueError("bc: six sides")
+    for i, v in enumerate(bc):
+        p.bc[i] = int(v)
     return p
 
 
@@ -616,8 +622,8 @@ class Solver3:
 
     def export_patch(self, level, vx, vy, vz):
         n = C.c_int32()
-        dofs = np.zeros(208, dtype=np.int32)
-        pinv = np.zeros(208 * 208)
+        dofs = np.zeros(256, dtype=np.int32)
+        pinv = np.zeros(256 * 256)
         self._check(_lib.bmg3_export_patch(self.h, level, vx, vy, vz, C.byref(n), dofs,
                                            pinv.ctypes.data_as(C.c_void_p)), "export_patch")
         m = n.value
@@ -645,8 +651,8 @@ def export_level_csr3(params: Params3, kappa, level):
 def export_patch_host3(params: Params3, kappa, level, vx, vy, vz):
     """(dofs, pseudo-inverse) of one vertex patch, assembled on the host by the library."""
     n = C.c_int32()
-    dofs = np.zeros(208, dtype=np.int32)
-    pinv = np.zeros(208 * 208)
+    dofs = np.zeros(256, dtype=np.int32)
+    pinv = np.zeros(256 * 256)
     st = _lib.bmg3_export_patch_host(C.byref(params), _kappa_host(kappa, _cells3(params)), level, vx, vy,
                                      vz, C.byref(n), dofs, pinv.ctypes.data_as(C.c_void_p))
     if st:

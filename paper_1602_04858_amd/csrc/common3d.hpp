@@ -6,9 +6,12 @@
 
 namespace bmg {
 
-// largest vertex-patch space of the 3-D RT_1 x dQ_1 discretisation: 12 inner faces x 4
-// + 8 cells x (12 interior velocity + 8 pressure) dofs
-constexpr int kMaxPatch3 = 208;
+// largest vertex-patch space the 3-D kernels take: an interior RT_1 x dQ_1 patch holds
+// 12 inner faces x 4 + 8 cells x (12 interior velocity + 8 pressure) = 208 dofs, and
+// each open side its patch touches adds 4 boundary faces x 4 normal dofs (three open
+// sides at a corner: 256; larger patches -- opposite open sides on a two-cell level --
+// are rejected at setup).  The colour kernel holds rows lane + 64 i, i < 4.
+constexpr int kMaxPatch3 = 256;
 
 // mode 0: y = A x; 1: y = b - A x; 2: y += A x (CSR, FP64, nrows rows)
 void launch3_csr(int mode, int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v, const double* x,

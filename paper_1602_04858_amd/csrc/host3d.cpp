@@ -45,8 +45,10 @@ inline int lu(int NA, int NB, int d, int a, int b, int c) { return (d * NA + a) 
 
 struct Num3 {  // global numbering of one level (the layout documented in bmg3.h), degree k
   int N, k, NA3, NB3, NU3, NP3, NL3;
+  int bcs[6];  // per side (2 d + 0 at x_d = 0, 2 d + 1 at x_d = 1): BMG_BC_DIRICHLET or BMG_BC_OPEN
   int64_t NF, NI, n_u, n_p, ndof;
-  Num3(int n, int deg) : N(n), k(deg), NA3(deg + 2), NB3(deg + 1) {
+  Num3(int n, int deg, const int32_t* bc = nullptr) : N(n), k(deg), NA3(deg + 2), NB3(deg + 1) {
+    for (int q = 0; q < 6; ++q) bcs[q] = bc ? bc[q] : BMG_BC_DIRICHLET;
     NU3 = 3 * NA3 * NB3 * NB3;
     NP3 = NB3 * NB3 * NB3;
     NL3 = NU3 + NP3;
@@ -71,12 +73,27 @@ struct Num3 {  // global numbering of one level (the layout documented in bmg3.h
     }
     return 3 * NF + cell(cc[0], cc[1], cc[2]) * NI + (d * k + a - 2) * NB3 * NB3 + bc;
   }
-  // essential: a normal face dof on a boundary face
+  // the boundary side of a normal face dof on the boundary, else -1
+  int side(int64_t gi) const {
+    if (gi >= 3 * NF) return -1;
+    const int d = (int)(gi / NF);
+    const int64_t i = ((gi % NF) / (NB3 * NB3)) % (N + 1);
+    return i == 0 ? 2 * d : i == N ? 2 * d + 1 : -1;
+  }
+  // essential: a normal face dof on a Dirichlet side
   bool essential(int64_t gi) const {
-    if (gi >= 3 * NF) return false;
-    const int64_t f = (gi % NF) / (NB3 * NB3);
-    const int64_t i = f % (N + 1);
-    return i == 0 || i == N;
+    const int q = side(gi);
+    return q >= 0 && bcs[q] == BMG_BC_DIRICHLET;
+  }
+  // a free normal face dof on an open side
+  bool open_normal(int64_t gi) const {
+    const int q = side(gi);
+    return q >= 0 && bcs[q] == BMG_BC_OPEN;
+  }
+  bool all_dirichlet() const {
+    for (int q = 0; q < 6; ++q)
+      if (bcs[q] != BMG_BC_DIRICHLET) return false;
+    return true;
   }
 };
 
@@ -388,6 +405,7 @@ Csr assemble_level_k(const Num3& S, double mu, double sigma, const std::vector<d
           }
           for (int s = 0; s < 2; ++s) {
             if ((s == 0 && cc[d] != 0) || (s == 1 && cc[d] != N - 1)) continue;
+            if (S.bcs[2 * d + s] != BMG_BC_DIRICHLET) continue;  // open side: no boundary term
             const auto& F = Fb[d][s];
             for (int i = 0; i < NU3; ++i)
               for (int j = 0; j < NU3; ++j) {
@@ -563,7 +581,7 @@ std::vector<double> rhs3_k(const Num3& S, double mu, double sigma, const std::ve
           double s = h * h * h * (Iv[i][0] * f[0] + Iv[i][1] * f[1] + Iv[i][2] * f[2]);
           for (int d = 0; d < 3; ++d)
             for (int sd = 0; sd < 2; ++sd)
-              if ((sd == 0 && cc[d] == 0) || (sd == 1 && cc[d] == N - 1))
+              if (((sd == 0 && cc[d] == 0) || (sd == 1 && cc[d] == N - 1)) && S.bcs[2 * d + sd] == BMG_BC_DIRICHLET)
                 s += Ib[d][sd][i][0] * g[0] + Ib[d][sd][i][1] * g[1] + Ib[d][sd][i][2] * g[2];
           b[gi] += s;
         }
@@ -573,7 +591,8 @@ std::vector<double> rhs3_k(const Num3& S, double mu, double sigma, const std::ve
   for (int d = 0; d < 3; ++d)
     for (int t2 = 0; t2 < N; ++t2)
       for (int t1 = 0; t1 < N; ++t1)
-        for (int i : {0, N}) ge[S.face(d, i, t1, t2, 0, 0)] = g[d];
+        for (int sd = 0; sd < 2; ++sd)
+          if (S.bcs[2 * d + sd] == BMG_BC_DIRICHLET) ge[S.face(d, sd ? N : 0, t1, t2, 0, 0)] = g[d];
   Csr Af;
   assemble_level_k<K>(S, mu, sigma, kap, &Af);
   for (int64_t i = 0; i < S.ndof; ++i) {
@@ -680,6 +699,8 @@ bmg_status check3(const bmg3_params* p) {
   if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
   if ((p->cycle != 0 && p->cycle != 1) || p->m_fine < 1 || p->restart < 1 || p->restart > 200) return BMG_E_ARG;
   if (p->precond_prec != 0 && p->precond_prec != 1) return BMG_E_ARG;
+  for (int q = 0; q < 6; ++q)
+    if (p->bc[q] != BMG_BC_DIRICHLET && p->bc[q] != BMG_BC_OPEN) return BMG_E_ARG;
   return BMG_OK;
 }
 
@@ -729,19 +750,25 @@ inline int colour3(int vx, int vy, int vz) { return (vx % 3) + 3 * (vy % 3) + 9 
 // in its kernel: no patch space holds a boundary normal dof).
 bool patch_pinv3(const Num3& S, const Csr& A, const std::vector<int64_t>& D, const std::vector<int>& cells,
                  double* dst) {
-  const int n = (int)D.size(), m = n + 1;
+  // a patch with a free normal dof on an open side has no pressure constant in its
+  // kernel: plain inverse; otherwise bordered with the normalised patch-constant pressure
+  bool singular = true;
+  for (int64_t gi : D) singular = singular && !S.open_normal(gi);
+  const int n = (int)D.size(), m = singular ? n + 1 : n;
   std::vector<double> a((size_t)m * m, 0.0), inv;
   for (int t = 0; t < n; ++t)
     for (int32_t e = A.rp[D[t]]; e < A.rp[D[t] + 1]; ++e) {
       const auto it = std::lower_bound(D.begin(), D.end(), (int64_t)A.ci[e]);
       if (it != D.end() && *it == A.ci[e]) a[(size_t)t * m + (it - D.begin())] = A.v[e];
     }
-  const double cv = 1.0 / std::sqrt((double)cells.size());
-  for (int cl : cells) {
-    const int64_t gpres = S.n_u + (int64_t)cl * S.NP3;
-    const int t = (int)(std::lower_bound(D.begin(), D.end(), gpres) - D.begin());
-    a[(size_t)t * m + n] = cv;
-    a[(size_t)n * m + t] = cv;
+  if (singular) {
+    const double cv = 1.0 / std::sqrt((double)cells.size());
+    for (int cl : cells) {
+      const int64_t gpres = S.n_u + (int64_t)cl * S.NP3;
+      const int t = (int)(std::lower_bound(D.begin(), D.end(), gpres) - D.begin());
+      a[(size_t)t * m + n] = cv;
+      a[(size_t)n * m + t] = cv;
+    }
   }
   if (!gj_inverse(m, a, inv)) return false;
   // the pseudo-inverse of the symmetric patch matrix is symmetric: the two rounded
@@ -769,7 +796,7 @@ void unrotate_sym3(int n, const double* R, double* F) {
 }
 
 // Patches of one level: dofs, pseudo-inverses (bordered with the normalised patch-
-// constant pressure: no patch space holds a boundary normal dof), colour ranges.
+// constant pressure unless the patch holds a normal dof of an open side), colour ranges.
 bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
   const Num3& S = L.S;
   const int N = S.N, nv = N + 1;
@@ -797,7 +824,9 @@ bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
   for (int64_t p = 0; p < nvert; ++p) {
     L.patch_of_vertex[order[p]] = p;
     const int64_t n = (int64_t)dofs[p].size();
-    if (n > kMaxPatch3 || n == 0) return fail3(c, BMG_E_ARG, "patch size out of range");
+    if (n == 0) return fail3(c, BMG_E_ARG, "empty patch");
+    if (n > kMaxPatch3)
+      return fail3(c, BMG_E_UNSUPPORTED, "a patch holds more than 256 dofs (opposite open sides on a 2-cell level)");
     L.hpoff[p + 1] = L.hpoff[p] + n;
     // FP64: rotated diagonals of the symmetric block; FP32: the full block
     L.hioff[p + 1] = L.hioff[p] + (c->p.precond_prec == 1 ? n * n : n * (n / 2 + 1));
@@ -909,7 +938,7 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
   c->lev.resize(p->levels);
   for (int j = 0; j <= J; ++j) {
     Level3& L = c->lev[j];
-    L.S = Num3(p->n0 << j, p->k);
+    L.S = Num3(p->n0 << j, p->k, p->bc);
     Csr A = assemble_level(L.S, p->mu, p->sigma, kap[j], nullptr);
     if (A.n == 0) return bail(BMG_E_SINGULAR, "essential row without diagonal");
     if (upload_csr(c, L.A, A)) return bail(BMG_E_NOMEM, "device allocation failed");
@@ -921,13 +950,15 @@ bmg_status bmg3_setup(const bmg3_params* p, const double* kappa_host, void* hip_
     if (dalloc(c, &L.x, L.S.ndof) || dalloc(c, &L.b, L.S.ndof) || dalloc(c, &L.r, L.S.ndof))
       return bail(BMG_E_NOMEM, "device allocation failed");
     if (j == 0) {
-      // bordered dense inverse (the constant pressure is in the kernel)
-      const int64_t n = L.S.ndof, m = n + 1;
+      // dense inverse, bordered when every side is Dirichlet (the constant pressure
+      // is then in the kernel; an open side fixes it)
+      const bool brd = L.S.all_dirichlet();
+      const int64_t n = L.S.ndof, m = brd ? n + 1 : n;
       std::vector<double> a((size_t)m * m, 0.0), inv;
       for (int64_t i = 0; i < n; ++i)
         for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) a[(size_t)i * m + A.ci[e]] = A.v[e];
       const double cv = 1.0 / std::sqrt((double)L.S.N * L.S.N * L.S.N);
-      for (int64_t cl = 0; cl < (int64_t)L.S.N * L.S.N * L.S.N; ++cl) {
+      for (int64_t cl = 0; brd && cl < (int64_t)L.S.N * L.S.N * L.S.N; ++cl) {
         a[(size_t)(L.S.n_u + cl * L.S.NP3) * m + n] = cv;
         a[(size_t)n * m + L.S.n_u + cl * L.S.NP3] = cv;
       }
@@ -994,7 +1025,7 @@ bmg_status bmg3_assemble_rhs(const bmg3_params* p, const double* kappa_host, con
   if (st) return fail3(nullptr, st, "invalid parameters");
   if (!kappa_host || !f || !g || !b_host) return fail3(nullptr, BMG_E_ARG, "NULL argument");
   const int Nf = p->n0 << (p->levels - 1);
-  Num3 S(Nf, p->k);
+  Num3 S(Nf, p->k, p->bc);
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   std::vector<double> b = rhs3(S, p->mu, p->sigma, kap, f, g);
   std::memcpy(b_host, b.data(), b.size() * sizeof(double));
@@ -1175,7 +1206,7 @@ bmg_status bmg3_export_level_csr(const bmg3_params* p, const double* kappa_host,
   const int J = p->levels - 1, Nf = p->n0 << J;
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   for (int j = J; j > level; --j) kap = coarsen(kap, p->n0 << (j - 1));
-  Csr A = assemble_level(Num3(p->n0 << level, p->k), p->mu, p->sigma, kap, nullptr);
+  Csr A = assemble_level(Num3(p->n0 << level, p->k, p->bc), p->mu, p->sigma, kap, nullptr);
   if (!rp_host) {
     *nnz = (int64_t)A.v.size();
     return BMG_OK;
@@ -1200,11 +1231,12 @@ bmg_status bmg3_export_patch_host(const bmg3_params* p, const double* kappa_host
   if (vx < 0 || vy < 0 || vz < 0 || vx > N || vy > N || vz > N) return fail3(nullptr, BMG_E_ARG, "vertex out of range");
   std::vector<double> kap(kappa_host, kappa_host + (size_t)Nf * Nf * Nf);
   for (int j = J; j > level; --j) kap = coarsen(kap, p->n0 << (j - 1));
-  const Num3 S(N, p->k);
+  const Num3 S(N, p->k, p->bc);
   Csr A = assemble_level(S, p->mu, p->sigma, kap, nullptr);
   std::vector<int64_t> D;
   std::vector<int> cells;
   patch_dofs3(S, vx, vy, vz, D, cells);
+  if ((int)D.size() > kMaxPatch3) return fail3(nullptr, BMG_E_UNSUPPORTED, "patch larger than 256 dofs");
   *n = (int32_t)D.size();
   for (size_t t = 0; t < D.size(); ++t) dofs_host[t] = (int32_t)D[t];
   if (pinv_host && !patch_pinv3(S, A, D, cells, pinv_host)) return fail3(nullptr, BMG_E_SINGULAR, "singular patch");

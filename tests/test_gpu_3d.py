@@ -297,3 +297,83 @@ def test_rt0_3d_at_n32_sampled():
     assert np.abs(y - lev.A @ xr).max() <= 1e-13 * np.abs(y).max()
     print(f"RT_0 3-D Darcy N=32: {info.iterations} iterations", flush=True)
     s.close()
+
+
+# ---------------------------------------------------------------------------------
+# Open sides (natural condition; an open side fixes the pressure level)
+# ---------------------------------------------------------------------------------
+OPEN_CASES = [(1, MU, (0, 0, 0, 0, 1, 1)), (0, MU, (0, 0, 1, 1, 0, 0)), (0, 0.0, (0, 0, 0, 0, 0, 1)),
+              (1, MU, (1, 0, 0, 0, 0, 0))]
+_ocache = {}
+
+
+def _open_pair(k, mu, bc, n0=1, levels=3):
+    key = (k, mu, bc, n0, levels)
+    if key not in _ocache:
+        N = n0 << (levels - 1)
+        kap = _kappa(N, 3)
+        sigma = (k + 1) * (k + 2)
+        print(f"3-D case k={k} mu={mu} bc={bc} n0={n0} levels={levels}", flush=True)
+        s = bmg.Solver3(bmg.make_params3(n0, levels, mu, sigma=sigma, k=k, bc=bc), kap)
+        o = o3.Oracle3D(n0, levels, k, mu, sigma, kap, bc=bc)
+        _ocache[key] = (s, o, kap)
+    return _ocache[key]
+
+
+@pytest.mark.parametrize("k,mu,bc", OPEN_CASES)
+def test_open_sides_steps_3d(k, mu, bc):
+    """Operator, one smoothing step and the V-cycle against the oracle."""
+    s, o, _ = _open_pair(k, mu, bc)
+    for level in (0, 1, 2):
+        L = o.lev[level]
+        x = np.random.default_rng(level).standard_normal(L.sp.ndof)
+        y = s.apply(_dev(x), level).cpu().numpy()
+        assert np.abs(y - L.A @ x).max() <= 1e-13 * np.abs(L.A @ x).max(), level
+    L = o.lev[2]
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(L.sp.ndof)
+    x[L.sp.cons] = 0.0
+    b = rng.standard_normal(L.sp.ndof)
+    xg = _dev(x)
+    s.smooth(2, 1, xg, _dev(b))
+    xo = x.copy()
+    o.sm[2].step(xo, b)
+    assert np.abs(xg.cpu().numpy() - xo).max() <= 1e-11 * np.abs(xo).max()
+    r = rng.standard_normal(L.sp.ndof)
+    r[L.sp.cons] = 0.0
+    z = s.vcycle(_dev(r)).cpu().numpy()
+    zo = o.vcycle(r)
+    assert np.abs(z - zo).max() <= 1e-10 * np.abs(zo).max()
+
+
+@pytest.mark.parametrize("k,mu,bc", OPEN_CASES)
+@pytest.mark.parametrize("n0,levels", [(1, 3), (2, 3)])
+def test_open_sides_solve_3d(k, mu, bc, n0, levels):
+    """FP64 solve with a body force through the open sides: iteration count within +-1
+    of the oracle's and the iterate after the same count within 1e-10 (max norm; the
+    pressure is determined, nothing removed)."""
+    s, o, kap = _open_pair(k, mu, bc, n0, levels)
+    lev = o.lev[-1]
+    f = lambda x, y, z: np.array([0.3 + 0 * x, -0.2 + 0 * x, np.ones_like(x)])
+    g = lambda x, y, z: np.array([np.ones_like(x), 0 * x, 0.5 + 0 * x])
+    b = lev.rhs(f, g)
+    b2 = bmg.assemble_rhs3(s.params, kap, (0.3, -0.2, 1.0), (1.0, 0.0, 0.5))
+    assert np.abs(b2 - b).max() <= 1e-13 * np.abs(b).max()
+    x, info = s.solve(_dev(b), rtol=1e-10, maxit=200)
+    xo, its, tr = o.fgmres(b, rtol=1e-10, maxit=200)
+    assert info.converged and info.rel_residual_true <= 1e-10
+    assert abs(info.iterations - its) <= 1, (info.iterations, its)
+    if info.iterations != its:
+        xo = _oracle_iterate(o, b, info.iterations)
+    xg = x.cpu().numpy()
+    print(f"open 3-D k={k} mu={mu} bc={bc} n0={n0}: {info.iterations} iterations (oracle {its}), max diff "
+          f"{np.abs(xg - xo).max() / np.abs(xo).max():.2e}")
+    assert np.abs(xg - xo).max() <= 1e-10 * np.abs(xo).max()
+
+
+def test_setup_rejects_patches_beyond_the_kernel_limit_3d():
+    """RT_1 with every side open on a two-cell level: the centre patch (304 dofs)
+    exceeds the colour kernel's 256 rows, and setup says so."""
+    with pytest.raises(bmg.BmgError) as e:
+        bmg.Solver3(bmg.make_params3(1, 2, MU, bc=(1, 1, 1, 1, 1, 1)), np.ones(8))
+    assert e.value.status == 2

@@ -112,3 +112,56 @@ def test_kappa_of_the_wrong_size_is_refused_by_the_binding_3d():
             bmg.export_level_csr3(p, np.ones(n), 1)
     with pytest.raises(ValueError):
         bmg.assemble_rhs3(p, np.ones(64), (1.0, 0.0), (0.0, 0.0, 0.0))
+
+
+# open sides: (k, mu, bc)
+OPEN_CASES = [(1, 1e-2, (0, 0, 0, 0, 1, 1)), (0, 1e-2, (0, 0, 1, 1, 0, 0)), (0, 0.0, (0, 0, 0, 0, 0, 1)),
+              (1, 0.3, (1, 0, 0, 0, 0, 0))]
+
+
+@pytest.mark.parametrize("k,mu,bc", OPEN_CASES)
+def test_open_sides_match_oracle(k, mu, bc):
+    sigma = 6.0 if k == 1 else 2.0
+    p = bmg.make_params3(1, 3, mu, sigma=sigma, k=k, bc=bc)
+    kap = _kappa(4, 1)
+    o = o3.Oracle3D(1, 3, k, mu, sigma, kap, bc=bc)
+    for level in (0, 1, 2):
+        rp, ci, v = bmg.export_level_csr3(p, kap, level)
+        n = len(rp) - 1
+        A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+        Ao = o.lev[level].A
+        assert A.shape == Ao.shape
+        assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max(), level
+    f, g = (0.5, -1.0, 0.25), (1.0, 0.3, -0.2)
+    b = bmg.assemble_rhs3(p, kap, f, g)
+    lev = o.lev[-1]
+    bo = lev.rhs(lambda x, y, z: np.array([c + 0 * x for c in f]), lambda x, y, z: np.array([c + 0 * x for c in g]))
+    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+    sm = o.sm[-1]
+    for vertex in [(2, 2, 2), (0, 0, 0), (4, 1, 2), (1, 4, 4), (3, 0, 1), (2, 2, 0), (2, 0, 4)]:
+        dofs, pinv = bmg.export_patch_host3(p, kap, 2, *vertex)
+        d_o, cells = o3.patch_dofs(lev.sp, *vertex)
+        assert np.array_equal(dofs, d_o)
+        singular = not lev.sp.open_normal[d_o].any()
+        po = o3.patch_pinv(lev.A[d_o][:, d_o].toarray(), lev.sp, d_o, cells, singular)
+        assert np.abs(pinv - po).max() <= 1e-9 * np.abs(po).max(), vertex
+
+
+def test_setup3_rejects_bad_side():
+    import ctypes as C
+    p = bmg.make_params3(1, 2, 1e-2)
+    p.bc[3] = 2
+    h = C.c_void_p()
+    assert bmg.lib().bmg3_setup(C.byref(p), np.ones(8), None, C.byref(h)) == 1 and not h.value
+
+
+def test_setup3_rejects_patches_beyond_the_kernel_limit():
+    """RT_1 on a two-cell level with every side open: the centre patch would hold
+    208 + 6 x 16 = 304 dofs, more than the colour kernel's 256 rows."""
+    p = bmg.make_params3(1, 2, 1e-2, bc=(1, 1, 1, 1, 1, 1))
+    with pytest.raises(bmg.BmgError) as e:
+        bmg.export_patch_host3(p, np.ones(8), 1, 1, 1, 1)
+    assert e.value.status == 2  # BMG_E_UNSUPPORTED, nothing written
+    # one open side pair is within the limit (208 + 2 x 16 = 240)
+    dofs, _ = bmg.export_patch_host3(bmg.make_params3(1, 2, 1e-2, bc=(0, 0, 0, 0, 1, 1)), np.ones(8), 1, 1, 1, 1)
+    assert len(dofs) == 240
