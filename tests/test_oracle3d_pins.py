@@ -423,3 +423,41 @@ def test_multigrid_matches_direct_solve_open_3d(k, mu):
     p_, q_ = rng.standard_normal(n) * free, rng.standard_normal(n) * free
     a1, a2 = p_ @ o.vcycle(q_), q_ @ o.vcycle(p_)
     assert abs(a1 - a2) < 1e-10 * abs(a1)
+
+
+# MAC / cell-centred equivalence of RT_0 (Section 2.3): with the kappa-mass lumped by
+# rows (the trapezoidal rule across each face's normal direction, exact for the
+# constant transverse factors), the Darcy Schur complement B M_lumped^-1 B^T of the
+# oracle's RT_0 blocks is the 7-point cell-centred (two-point flux) operator with face
+# transmissibility 2 h / (kappa_K + kappa_L) -- the harmonic mean of the permeabilities
+# 1 / kappa -- and no flux through the (essential, zero) boundary faces.  Built here
+# independently from kappa alone; a wrong divergence scaling, sign, face numbering or
+# boundary treatment in the oracle's RT_0 assembly breaks the equality.
+def test_rt0_darcy_lumped_schur_complement_is_the_cell_centred_scheme_3d():
+    n = 4
+    h = 1.0 / n
+    kap = _kappa(n, 21, -3.0, 1.0)
+    lev = o3.Level(n, 0, 0.0, 2.0, kap)
+    S = lev.sp
+    A = lev.A_full.tocsr()
+    free_u = np.flatnonzero(~S.cons[:S.n_u])
+    # row sums of the whole kappa-mass (the couplings to the essential faces included)
+    lumped = np.asarray(A[:S.n_u][:, :S.n_u].sum(axis=1)).ravel()[free_u]
+    B = A[S.n_u:][:, :S.n_u].toarray()[:, free_u]
+    Schur = B @ np.diag(1.0 / lumped) @ B.T
+    T = np.zeros((n ** 3, n ** 3))
+    for cz in range(n):
+        for cy in range(n):
+            for cx in range(n):
+                K = S.cell(cx, cy, cz)
+                for d in range(3):
+                    nb = [cx, cy, cz]
+                    nb[d] += 1
+                    if nb[d] < n:
+                        L = S.cell(*nb)
+                        t = 2.0 * h / (kap[K] + kap[L])
+                        T[K, L] -= t
+                        T[L, K] -= t
+                        T[K, K] += t
+                        T[L, L] += t
+    assert np.abs(Schur - T).max() < 1e-12 * np.abs(T).max()

@@ -777,3 +777,37 @@ def test_divergence_source_is_reproduced(k, mu, bc, src):
         worst = max(worst, np.abs(div - proj).max())
         scale = max(scale, np.abs(proj).max())
     assert worst <= 1e-10 * scale
+
+
+# MAC / cell-centred equivalence of RT_0 (Section 2.3): with the kappa-mass lumped by
+# rows (the trapezoidal rule across each edge's normal direction, exact for the
+# constant tangential factor), the Darcy Schur complement B M_lumped^-1 B^T of the
+# oracle's RT_0 blocks is the 5-point cell-centred (two-point flux) operator with edge
+# transmissibility 2 / (kappa_K + kappa_L) -- the harmonic mean of the permeabilities
+# 1 / kappa -- and no flux through the essential (zero) boundary edges.  Built here
+# from kappa alone; a wrong divergence scaling, sign, edge numbering or boundary
+# treatment in the oracle's RT_0 assembly breaks the equality.
+def test_rt0_darcy_lumped_schur_complement_is_the_cell_centred_scheme():
+    n0, J = 2, 2
+    N = n0 << J
+    kap = 10.0 ** np.random.default_rng(21).uniform(-3, 1, N * N)
+    o = Oracle(n0, J, 0, 0.0, 2.0, [0, 0, 0, 0], kap)
+    A = o.csr(full=True).tocsr()
+    nu, cons = o.n_u(), o.constrained()
+    free_u = np.flatnonzero(~cons[:nu])
+    lumped = np.asarray(A[:nu][:, :nu].sum(axis=1)).ravel()[free_u]
+    B = A[nu:][:, :nu].toarray()[:, free_u]
+    schur = B @ np.diag(1.0 / lumped) @ B.T
+    T = np.zeros((N * N, N * N))
+    for cy in range(N):
+        for cx in range(N):
+            K = cy * N + cx
+            for nx, ny in ((cx + 1, cy), (cx, cy + 1)):
+                if nx < N and ny < N:
+                    L = ny * N + nx
+                    t = 2.0 / (kap[K] + kap[L])
+                    T[K, L] -= t
+                    T[L, K] -= t
+                    T[K, K] += t
+                    T[L, L] += t
+    assert np.abs(schur - T).max() < 1e-12 * np.abs(T).max()
