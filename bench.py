@@ -299,14 +299,18 @@ def bench_c5(args, torch, bmg, inputs):
 
 
 def bench_d3(args, torch, bmg, inputs):
-    """3-D Brinkman (Section 4, SPE10-like layered kappa stand-in): RT_1 x dQ_1 on an
-    n^3 hexahedral mesh, mu = 1e-2, g = (1, 0, 0) on all sides, f = 0, FP64 V-cycle in
-    FP64 FGMRES to --rtol."""
+    """3-D Brinkman / Darcy (Section 4, SPE10-like layered kappa stand-in): RT_k x dQ_k
+    (--k3: 1, or 0 for the lowest order the paper's 128^3 SPE10 run uses) on an n^3
+    hexahedral mesh, mu = --mu3, g = (1, 0, 0) on the Dirichlet sides (--bc3 marks open
+    ones), f = 0, FP64 V-cycle in FP64 FGMRES to --rtol."""
     import numpy as np
     n = args.n3
-    levels = int(round(math.log2(n // 4))) + 1  # coarsest mesh 4^3 (2240 unknowns), solved densely
+    levels = int(round(math.log2(n // 4))) + 1  # coarsest mesh 4^3, solved densely
     kap = inputs.kappa_layered3(n, 6000)
-    p = bmg.make_params3(4, levels, 1e-2, restart=50)
+    k3, mu3 = args.k3, args.mu3
+    bc3 = tuple(int(v) for v in args.bc3.split(","))
+    sig3 = (k3 + 1) * (k3 + 2)
+    p = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, k=k3, bc=bc3)
     t0 = time.perf_counter()
     s = bmg.Solver3(p, kap)
     setup = time.perf_counter() - t0
@@ -340,7 +344,7 @@ def bench_d3(args, torch, bmg, inputs):
     # bandwidth-bound fine-level colour steps
     mixed = None
     if not args.no_mixed:
-        p32 = bmg.make_params3(4, levels, 1e-2, restart=50, prec=bmg.P_FP32)
+        p32 = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, prec=bmg.P_FP32, k=k3, bc=bc3)
         t0 = time.perf_counter()
         s32 = bmg.Solver3(p32, kap)
         setup32 = time.perf_counter() - t0
@@ -365,7 +369,7 @@ def bench_d3(args, torch, bmg, inputs):
     # one: the coarse levels (latency-bound launches) then smooth 4x / 2x less
     std = None
     if not args.no_mixed:
-        ps = bmg.make_params3(4, levels, 1e-2, restart=50, cycle=bmg.CYCLE_STANDARD)
+        ps = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, cycle=bmg.CYCLE_STANDARD, k=k3, bc=bc3)
         ss = bmg.Solver3(ps, kap)
         for _ in range(args.warmup):
             xs, infs = ss.solve(b, rtol=args.rtol, maxit=500)
@@ -382,12 +386,15 @@ def bench_d3(args, torch, bmg, inputs):
                "rel_diff_vs_variable": (torch.linalg.norm(xs - x64) / torch.linalg.norm(x64)).item()}
         log(f"bench: 3-D standard V-cycle {args.steps / dts:.3f} solves/s, iterations {itss}")
         ss.close()
-    out = {"metric": f"3-D Brinkman solves/s to {args.rtol:g} rel resid", "value": args.steps / dt,
+    model = "Darcy" if mu3 == 0 else "Brinkman"
+    sides = "all sides Dirichlet" if not any(bc3) else f"sides (x0,x1,y0,y1,z0,z1) {args.bc3} (1 = open)"
+    out = {"metric": f"3-D {model} solves/s to {args.rtol:g} rel resid", "value": args.steps / dt,
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"3-D Brinkman {n}^3 hexahedra, RT_1 x dQ_1, mu=1e-2, g=(1,0,0) on all sides, "
-                                  "f=0, 85-layer log-normal kappa (SPE10 stand-in), coarsest mesh 4^3, "
-                                  "variable V-cycle m=2, FP64 FGMRES(50)", "N": n, "levels": levels, "k": 1, "rtol": args.rtol},
+           "config": {"workload": f"3-D {model} {n}^3 hexahedra, RT_{k3} x dQ_{k3}, mu={mu3:g}, g=(1,0,0), "
+                                  f"{sides}, f=0, 85-layer log-normal kappa (SPE10 stand-in), coarsest mesh 4^3, "
+                                  "variable V-cycle m=2, FP64 FGMRES(50)", "N": n, "levels": levels, "k": k3,
+                      "mu": mu3, "bc": list(bc3), "rtol": args.rtol},
            "ndof": ndof, "iterations": its[-1], "dof_iters_per_s": ndof * sum(its) / dt,
            "true_rel_residual": info.rel_residual_true, "setup_s": setup, "vcycle_ms": vc_ms}
     if mixed:
@@ -461,6 +468,9 @@ def main():
                     help="C5: FGMRES restart (16 FP64 basis columns of 113 M unknowns: 7 fits in HBM)")
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--n3", type=int, default=32, help="D3: cells per side of the 3-D mesh (a power of two)")
+    ap.add_argument("--k3", type=int, default=1, choices=[0, 1], help="D3: Raviart-Thomas degree")
+    ap.add_argument("--mu3", type=float, default=1e-2, help="D3: viscosity (0: Darcy)")
+    ap.add_argument("--bc3", default="0,0,0,0,0,0", help="D3: per side x0,x1,y0,y1,z0,z1: 0 Dirichlet, 1 open")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,
                     help="levels up to this many dofs are applied as one precomputed dense matrix (0 = off)")
     ap.add_argument("--colouring", default="auto", choices=["S9", "L8", "auto"],

@@ -54,7 +54,7 @@ typedef struct bmg3_ctx* bmg3_handle;
 
 typedef struct {
   int32_t n0;      /* coarsest mesh n0^3 cells, 1 .. 8 */
-  int32_t levels;  /* >= 1; finest N = n0 2^(levels-1) <= 64 */
+  int32_t levels;  /* >= 1; finest N = n0 2^(levels-1) <= 64 (RT_1), <= 128 (RT_0) */
   int32_t k;       /* RT degree: 0 or 1 */
   double mu;       /* viscosity >= 0 (0: Darcy) */
   double sigma;    /* penalty parameter > 0 (sigma_h = sigma / h); Section 4.1 uses (k+1)(k+2) */

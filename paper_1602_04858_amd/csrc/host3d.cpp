@@ -695,7 +695,8 @@ bmg_status check3(const bmg3_params* p) {
   if (!p) return BMG_E_ARG;
   if (p->k != 0 && p->k != 1) return BMG_E_UNSUPPORTED;
   if (p->n0 < 1 || p->n0 > 8 || p->levels < 1 || p->levels > 8) return BMG_E_ARG;
-  if ((int64_t)p->n0 << (p->levels - 1) > 64) return BMG_E_ARG;
+  // finest mesh: 64^3 for RT_1 (65 GB of patch inverses), 128^3 for RT_0 (8.5 M unknowns)
+  if ((int64_t)p->n0 << (p->levels - 1) > (p->k == 0 ? 128 : 64)) return BMG_E_ARG;
   if (!(p->mu >= 0.0) || !std::isfinite(p->mu) || !(p->sigma > 0.0) || !std::isfinite(p->sigma)) return BMG_E_ARG;
   if ((p->cycle != 0 && p->cycle != 1) || p->m_fine < 1 || p->restart < 1 || p->restart > 200) return BMG_E_ARG;
   if (p->precond_prec != 0 && p->precond_prec != 1) return BMG_E_ARG;
