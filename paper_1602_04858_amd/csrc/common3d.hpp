@@ -17,10 +17,11 @@ constexpr int kMaxPatch3 = 256;
 void launch3_csr(int mode, int64_t nrows, const int32_t* rp, const int32_t* ci, const double* v, const double* x,
                  const double* b, double* y, hipStream_t s);
 // one colour step over patches p0 .. p0 + npatch - 1 of a level; pinv holds doubles
-// (sprec 0) or floats (sprec 1)
+// (sprec 0) or floats (sprec 1); maxn: the largest patch of the level (<= 32: one
+// wave per patch)
 void launch3_colour(int p0, int npatch, const int64_t* poff, const int32_t* pdofs, const int64_t* ioff,
                     const void* pinv, int sprec, const int32_t* rp, const int32_t* ci, const double* v, double* x,
-                    const double* b, hipStream_t s);
+                    const double* b, int maxn, hipStream_t s);
 // dst[idx[i]] = src[idx[i]], i < n
 void launch3_copy_idx(const int32_t* idx, int64_t n, const double* src, double* dst, hipStream_t s);
 

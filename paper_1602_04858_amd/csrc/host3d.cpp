@@ -638,6 +638,7 @@ struct Level3 {
   int32_t* pdofs = nullptr;
   void* pinv = nullptr;  // doubles or floats (bmg3_params.precond_prec)
   int cstart[28] = {0};
+  int maxn = 0;                          // largest patch of the level
   std::vector<int64_t> patch_of_vertex;  // vertex -> patch index
   std::vector<int64_t> hpoff, hioff;
   std::vector<int32_t> hpdofs;
@@ -829,6 +830,7 @@ bmg_status build_patches3(bmg3_ctx* c, Level3& L, const Csr& A) {
     if (n > kMaxPatch3)
       return fail3(c, BMG_E_UNSUPPORTED, "a patch holds more than 256 dofs (opposite open sides on a 2-cell level)");
     L.hpoff[p + 1] = L.hpoff[p] + n;
+    L.maxn = std::max(L.maxn, (int)n);
     // FP64: rotated diagonals of the symmetric block; FP32: the full block
     L.hioff[p + 1] = L.hioff[p] + (c->p.precond_prec == 1 ? n * n : n * (n / 2 + 1));
   }
@@ -882,7 +884,7 @@ void smooth_step3(bmg3_ctx* c, Level3& L, double* x, const double* b) {
   for (int k = 0; k < 53; ++k) {
     const int col = k < 27 ? k : 52 - k;
     launch3_colour(L.cstart[col], L.cstart[col + 1] - L.cstart[col], L.poff, L.pdofs, L.ioff, L.pinv,
-                   c->p.precond_prec, L.A.rp, L.A.ci, L.A.v, x, b, c->s);
+                   c->p.precond_prec, L.A.rp, L.A.ci, L.A.v, x, b, L.maxn, c->s);
   }
 }
 

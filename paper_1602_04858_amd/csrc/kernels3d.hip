@@ -173,6 +173,75 @@ __global__ __launch_bounds__(BS) void k3_colour(int p0, const int64_t* __restric
   }
 }
 
+// Small patches (n <= kSmallPatch3: every RT_0 patch, at most 12 inner faces + 12
+// open-side faces + 8 pressures) leave most of a 256-thread block idle, so here one
+// wave takes one patch and a block four patches of the colour (patch p0 + 4 blockIdx.x
+// + w): the wave's 64 lanes form the residual rows eight at a time (eight lanes per
+// row), then lanes (half, t) = (lane / 32, lane mod 32) sum the product for row t over
+// the diagonals (FP64 rotated) or columns (FP32 full) of parity `half`, and the two
+// halves meet by a cross-lane add.  Same-colour patches share no dof and no matrix
+// entry, so the four patches of a block do not interact.
+constexpr int kSmallPatch3 = 32;
+
+template <typename S>
+__global__ __launch_bounds__(256) void k3_colour_small(int p0, int npatch, const int64_t* __restrict__ poff,
+                                                       const int32_t* __restrict__ pdofs,
+                                                       const int64_t* __restrict__ ioff, const S* __restrict__ pinv,
+                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                       const double* __restrict__ v, double* __restrict__ x,
+                                                       const double* __restrict__ b) {
+  __shared__ double rs[4][2 * kSmallPatch3];
+  __shared__ int32_t gs[4][kSmallPatch3];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = 4 * (int)blockIdx.x + w;  // patch of the colour taken by this wave
+  const bool live = q < npatch;
+  int n = 0;
+  int64_t o = 0;
+  if (live) {
+    const int p = p0 + q;
+    o = poff[p];
+    n = (int)(poff[p + 1] - o);
+    if (lane < n) gs[w][lane] = pdofs[o + lane];
+  }
+  __syncthreads();
+  // residual rows: eight at a time, eight lanes each
+  const int sub = lane % kRowLanes, rl = lane / kRowLanes;
+  for (int t0 = 0; t0 < n; t0 += 64 / kRowLanes) {
+    const int t = t0 + rl;
+    double s = 0.0;
+    int gi = 0;
+    if (t < n) {
+      gi = gs[w][t];
+      const int e1 = rp[gi + 1];
+      for (int e = rp[gi] + sub; e < e1; e += kRowLanes) s += v[e] * x[ci[e]];
+    }
+    s = lane_group_sum(s);
+    if (t < n && sub == 0) rs[w][t] = rs[w][t + n] = b[gi] - s;
+  }
+  __syncthreads();
+  const int half = lane >> 5, t = lane & 31, tc = min(t, max(n - 1, 0));
+  double acc = 0.0;
+  if (live) {
+    const S* A = pinv + ioff[p0 + q];
+    if constexpr (sizeof(S) == 8) {
+      // y[t] = sum_d R[d][t] r[t + d] + sum_{1 <= d <= HL} R[d][(t - d) mod n] r[t - d]
+      const int H = n >> 1, HL = n - 1 - H;
+      for (int d = half; d <= H; d += 2) {
+        int sft = tc - d;
+        sft += sft < 0 ? n : 0;
+        const double au = t < n ? A[d * n + t] : 0.0;
+        const double al = (t < n && d >= 1 && d <= HL) ? A[d * n + sft] : 0.0;
+        acc += au * rs[w][tc + d] + al * rs[w][tc - d + n];
+      }
+    } else {
+      // full column-major block: y[t] = sum_u A[u n + t] r[u]
+      for (int u = half; u < n; u += 2) acc += (t < n ? (double)A[(int64_t)u * n + t] : 0.0) * rs[w][u];
+    }
+  }
+  acc += __shfl_xor(acc, 32);
+  if (live && half == 0 && t < n) x[gs[w][t]] += acc;
+}
+
 __global__ __launch_bounds__(256) void k3_copy_idx(const int32_t* __restrict__ idx, int64_t n,
                                                    const double* __restrict__ src, double* __restrict__ dst) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -206,8 +275,18 @@ static void colour_t(int p0, int npatch, const int64_t* poff, const int32_t* pdo
 
 void launch3_colour(int p0, int npatch, const int64_t* poff, const int32_t* pdofs, const int64_t* ioff,
                     const void* pinv, int sprec, const int32_t* rp, const int32_t* ci, const double* v, double* x,
-                    const double* b, hipStream_t s) {
+                    const double* b, int maxn, hipStream_t s) {
   if (npatch <= 0) return;
+  if (maxn <= kSmallPatch3) {
+    const dim3 g((unsigned)((npatch + 3) / 4)), bl(256);
+    if (sprec == 1)
+      hipLaunchKernelGGL(k3_colour_small<float>, g, bl, 0, s, p0, npatch, poff, pdofs, ioff, (const float*)pinv, rp,
+                         ci, v, x, b);
+    else
+      hipLaunchKernelGGL(k3_colour_small<double>, g, bl, 0, s, p0, npatch, poff, pdofs, ioff, (const double*)pinv,
+                         rp, ci, v, x, b);
+    return;
+  }
   if (sprec == 1) colour_t(p0, npatch, poff, pdofs, ioff, (const float*)pinv, rp, ci, v, x, b, s);
   else colour_t(p0, npatch, poff, pdofs, ioff, (const double*)pinv, rp, ci, v, x, b, s);
 }
