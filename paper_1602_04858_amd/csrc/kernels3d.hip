@@ -204,38 +204,58 @@ __global__ __launch_bounds__(256) void k3_colour_small(int p0, int npatch, const
     if (lane < n) gs[w][lane] = pdofs[o + lane];
   }
   __syncthreads();
+  // the pseudo-inverse entries of this lane, loaded before the residual's chain of
+  // dependent loads so the two overlap: lane (half, t) takes row t and the diagonals
+  // d = half, half + 2, ... (FP64 rotated) or columns u = half, half + 2, ... (FP32 full)
+  const int half = lane >> 5, t = lane & 31, tc = min(t, max(n - 1, 0));
+  const int H = n >> 1, HL = n - 1 - H;
+  constexpr int NJ = sizeof(S) == 8 ? kSmallPatch3 / 4 + 1 : kSmallPatch3 / 2;
+  double au[NJ], al[NJ];
+  if (live) {
+    const S* A = pinv + ioff[p0 + q];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if constexpr (sizeof(S) == 8) {
+        // y[t] = sum_d R[d][t] r[t + d] + sum_{1 <= d <= HL} R[d][(t - d) mod n] r[t - d]
+        const int d = half + 2 * j;
+        int sft = tc - d;
+        sft += sft < 0 ? n : 0;
+        au[j] = (t < n && d <= H) ? A[d * n + t] : 0.0;
+        al[j] = (t < n && d >= 1 && d <= HL) ? A[d * n + sft] : 0.0;
+      } else {
+        // full column-major block: y[t] = sum_u A[u n + t] r[u]
+        const int u = half + 2 * j;
+        au[j] = (t < n && u < n) ? (double)A[(int64_t)u * n + t] : 0.0;
+        al[j] = 0.0;
+      }
+    }
+  }
   // residual rows: eight at a time, eight lanes each
   const int sub = lane % kRowLanes, rl = lane / kRowLanes;
   for (int t0 = 0; t0 < n; t0 += 64 / kRowLanes) {
-    const int t = t0 + rl;
+    const int tr = t0 + rl;
     double s = 0.0;
     int gi = 0;
-    if (t < n) {
-      gi = gs[w][t];
+    if (tr < n) {
+      gi = gs[w][tr];
       const int e1 = rp[gi + 1];
       for (int e = rp[gi] + sub; e < e1; e += kRowLanes) s += v[e] * x[ci[e]];
     }
     s = lane_group_sum(s);
-    if (t < n && sub == 0) rs[w][t] = rs[w][t + n] = b[gi] - s;
+    if (tr < n && sub == 0) rs[w][tr] = rs[w][tr + n] = b[gi] - s;
   }
   __syncthreads();
-  const int half = lane >> 5, t = lane & 31, tc = min(t, max(n - 1, 0));
   double acc = 0.0;
   if (live) {
-    const S* A = pinv + ioff[p0 + q];
-    if constexpr (sizeof(S) == 8) {
-      // y[t] = sum_d R[d][t] r[t + d] + sum_{1 <= d <= HL} R[d][(t - d) mod n] r[t - d]
-      const int H = n >> 1, HL = n - 1 - H;
-      for (int d = half; d <= H; d += 2) {
-        int sft = tc - d;
-        sft += sft < 0 ? n : 0;
-        const double au = t < n ? A[d * n + t] : 0.0;
-        const double al = (t < n && d >= 1 && d <= HL) ? A[d * n + sft] : 0.0;
-        acc += au * rs[w][tc + d] + al * rs[w][tc - d + n];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int d = half + 2 * j;
+      if constexpr (sizeof(S) == 8) {
+        const int dd = min(d, H);  // entries beyond H are zero; keep the LDS index in range
+        acc += au[j] * rs[w][tc + dd] + al[j] * rs[w][tc - dd + n];
+      } else {
+        acc += au[j] * rs[w][min(d, max(n - 1, 0))];
       }
-    } else {
-      // full column-major block: y[t] = sum_u A[u n + t] r[u]
-      for (int u = half; u < n; u += 2) acc += (t < n ? (double)A[(int64_t)u * n + t] : 0.0) * rs[w][u];
     }
   }
   acc += __shfl_xor(acc, 32);
