@@ -509,7 +509,7 @@ template <int K>
 struct MrShared {
   using M = MrDims<K>;
   __attribute__((aligned(16))) float buf[16 * M::CS + 4];
-  __attribute__((aligned(16))) uint16_t apw[(M::NPR + 7) / 8 * 8];
+  __attribute__((aligned(16))) uint16_t apw[(M::NPR + 7) / 8 * 8 + 8];
   int sgi[Dims<K>::NSR], spa[Dims<K>::NSR], spb[Dims<K>::NSR];
 };
 
