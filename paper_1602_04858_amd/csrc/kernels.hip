@@ -510,7 +510,7 @@ struct MrShared {
   using M = MrDims<K>;
   __attribute__((aligned(16))) float buf[16 * M::CS + 4];
   __attribute__((aligned(16))) uint16_t apw[(M::NPR + 7) / 8 * 8 + 8];
-  int sgi[Dims<K>::NSR], spa[Dims<K>::NSR], spb[Dims<K>::NSR];
+  int sgi[Dims<K>::NSR + 1], spa[Dims<K>::NSR + 1], spb[Dims<K>::NSR + 1];
 };
 
 template <typename T, typename S, int K, bool PKD, bool MC>
