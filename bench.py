@@ -94,10 +94,21 @@ def cpu_baseline(w, iterations_full, sample_its, colouring=0):
     dt = time.perf_counter() - t0
     per_it = dt / abs(its)
     solve_s = per_it * iterations_full
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {abs(its)} FGMRES iterations of the same solve ({dt:.1f} s, setup {t_setup:.1f} s "
-                      f"untimed), scaled to the {iterations_full} iterations of the full solve",
-            "seconds_per_iteration": per_it}
+    out = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {abs(its)} FGMRES iterations of the same solve ({dt:.1f} s, setup {t_setup:.1f} s "
+                     f"untimed), scaled to the {iterations_full} iterations of the full solve",
+           "seconds_per_iteration": per_it, "host": host_info()}
+    omp_set = getattr(oracle_lib(), "omp_set_num_threads", None)
+    if omp_set is not None:
+        omp_set(1)
+        t0 = time.perf_counter()
+        _, its1, _, _ = o.fgmres(b, rtol=1e-10, maxit=2, restart=100)
+        dt1 = time.perf_counter() - t0
+        omp_set(threads)
+        out["single_thread"] = {"value": 1.0 / (dt1 / abs(its1) * iterations_full), "unit": "solves/s",
+                                "cores": 1, "sample": f"first {abs(its1)} iterations ({dt1:.1f} s)",
+                                "seconds_per_iteration": dt1 / abs(its1)}
+    return out
 
 
 def bench_c4(args, torch, bmg, inputs):
@@ -142,7 +153,7 @@ def bench_c4(args, torch, bmg, inputs):
     print(json.dumps(out), flush=True)
 
 
-def c5_cpu_baseline(nfull, its_full, n_sample=128, sample_its=10):
+def c5_cpu_baseline(nfull, its_full, n_sample=128, sample_its=10, single_its=2):
     """The oracle (plain FP64 CPU) on the C5 generator (RT_2, layered kappa, smooth
     source) at n_sample^2, one right-hand side: setup untimed, the first sample_its FGMRES
     iterations timed; the time per iteration and unknown is scaled to one right-hand side
@@ -161,11 +172,48 @@ def c5_cpu_baseline(nfull, its_full, n_sample=128, sample_its=10):
     dt = time.perf_counter() - t0
     per_it_dof = dt / abs(its) / o.ndof()
     solve_s = per_it_dof * nfull * its_full
-    return {"value": 1.0 / solve_s, "unit": "right-hand sides solved/s", "cores": threads, "kind": "oracle",
-            "sample": f"C5 generator at {n_sample}x{n_sample} ({o.ndof()} unknowns), first {abs(its)} FGMRES(8) "
-                      f"iterations ({dt:.1f} s; setup {t_setup:.1f} s untimed), time per iteration and unknown "
-                      f"scaled to {nfull} unknowns x {its_full} iterations",
-            "seconds_per_iteration_per_unknown": per_it_dof}
+    out = {"value": 1.0 / solve_s, "unit": "right-hand sides solved/s", "cores": threads, "kind": "oracle",
+           "sample": f"C5 generator at {n_sample}x{n_sample} ({o.ndof()} unknowns), first {abs(its)} FGMRES(8) "
+                     f"iterations ({dt:.1f} s; setup {t_setup:.1f} s untimed), time per iteration and unknown "
+                     f"scaled to {nfull} unknowns x {its_full} iterations",
+           "seconds_per_iteration_per_unknown": per_it_dof, "host": host_info()}
+    # the same sample on one thread (the oracle's OpenMP runtime, set through its library)
+    omp_set = getattr(oracle_lib(), "omp_set_num_threads", None)
+    if omp_set is not None and single_its > 0:
+        omp_set(1)
+        t0 = time.perf_counter()
+        _, its1, _, _ = o.fgmres(b, rtol=1e-10, maxit=single_its, restart=8)
+        dt1 = time.perf_counter() - t0
+        omp_set(threads)
+        per1 = dt1 / abs(its1) / o.ndof()
+        out["single_thread"] = {"value": 1.0 / (per1 * nfull * its_full), "unit": "right-hand sides solved/s",
+                                "cores": 1, "sample": f"first {abs(its1)} iterations ({dt1:.1f} s)",
+                                "seconds_per_iteration_per_unknown": per1}
+    return out
+
+
+def oracle_lib():
+    from oracle import lib
+    return lib()
+
+
+def host_info():
+    """nproc, CPU model and memory of the host the CPU baseline ran on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    info["mem_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
 
 
 def bench_c5(args, torch, bmg, inputs):
