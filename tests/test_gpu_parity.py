@@ -6,8 +6,11 @@ steps 2e-5 relative; full FP64 solves: iteration count within +-1 of the oracle'
 and the solution within 1e-10 of the oracle's iterate after the same number of
 iterations, in relative L2 and in the element-wise max norm; mixed-precision
 solves: true relative residual <= 1e-10, at most 2 iterations more than the
-oracle's FP64 solve, within 1e-8 (relative L2 and max norm) of the oracle solution
-converged to 1e-13.
+oracle's FP64 solve (scaled by the convergence rate where FGMRES is slow:
+_mixed_its_bound), within 1e-8 (relative L2 and max norm) of the oracle solution
+converged to 1e-13.  At 1024^2 (C3) the oracle's solves are stored samples
+(tests/golden/), and where rtol sits on the attainable-accuracy plateau the stopping
+count is checked to lie on it and the iterates are compared at fixed counts.
 """
 import json
 import math
