@@ -353,12 +353,15 @@ def bench_d3(args, torch, bmg, inputs):
     ones), f = 0, FP64 V-cycle in FP64 FGMRES to --rtol."""
     import numpy as np
     n = args.n3
-    levels = int(round(math.log2(n // 4))) + 1  # coarsest mesh 4^3, solved densely
+    # the coarsest mesh, inverted densely: 8^3 for RT_0 (2240 unknowns), 4^3 for RT_1
+    # (2240 unknowns; its 8^3 would be 17152)
+    n0 = args.coarse3 or (8 if args.k3 == 0 else 4)
+    levels = int(round(math.log2(n // n0))) + 1  # coarsest mesh n0^3, solved densely
     kap = inputs.kappa_layered3(n, 6000)
     k3, mu3 = args.k3, args.mu3
     bc3 = tuple(int(v) for v in args.bc3.split(","))
     sig3 = (k3 + 1) * (k3 + 2)
-    p = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, k=k3, bc=bc3)
+    p = bmg.make_params3(n0, levels, mu3, sigma=sig3, restart=50, k=k3, bc=bc3)
     t0 = time.perf_counter()
     s = bmg.Solver3(p, kap)
     setup = time.perf_counter() - t0
@@ -392,7 +395,7 @@ def bench_d3(args, torch, bmg, inputs):
     # bandwidth-bound fine-level colour steps
     mixed = None
     if not args.no_mixed:
-        p32 = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, prec=bmg.P_FP32, k=k3, bc=bc3)
+        p32 = bmg.make_params3(n0, levels, mu3, sigma=sig3, restart=50, prec=bmg.P_FP32, k=k3, bc=bc3)
         t0 = time.perf_counter()
         s32 = bmg.Solver3(p32, kap)
         setup32 = time.perf_counter() - t0
@@ -417,7 +420,7 @@ def bench_d3(args, torch, bmg, inputs):
     # one: the coarse levels (latency-bound launches) then smooth 4x / 2x less
     std = None
     if not args.no_mixed:
-        ps = bmg.make_params3(4, levels, mu3, sigma=sig3, restart=50, cycle=bmg.CYCLE_STANDARD, k=k3, bc=bc3)
+        ps = bmg.make_params3(n0, levels, mu3, sigma=sig3, restart=50, cycle=bmg.CYCLE_STANDARD, k=k3, bc=bc3)
         ss = bmg.Solver3(ps, kap)
         for _ in range(args.warmup):
             xs, infs = ss.solve(b, rtol=args.rtol, maxit=500)
@@ -440,7 +443,7 @@ def bench_d3(args, torch, bmg, inputs):
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"3-D {model} {n}^3 hexahedra, RT_{k3} x dQ_{k3}, mu={mu3:g}, g=(1,0,0), "
-                                  f"{sides}, f=0, 85-layer log-normal kappa (SPE10 stand-in), coarsest mesh 4^3, "
+                                  f"{sides}, f=0, 85-layer log-normal kappa (SPE10 stand-in), coarsest mesh {n0}^3, "
                                   "variable V-cycle m=2, FP64 FGMRES(50)", "N": n, "levels": levels, "k": k3,
                       "mu": mu3, "bc": list(bc3), "rtol": args.rtol},
            "ndof": ndof, "iterations": its[-1], "dof_iters_per_s": ndof * sum(its) / dt,
@@ -517,6 +520,8 @@ def main():
     ap.add_argument("--rhs", type=int, default=16, help="C5: right-hand sides solved together")
     ap.add_argument("--n3", type=int, default=32, help="D3: cells per side of the 3-D mesh (a power of two)")
     ap.add_argument("--k3", type=int, default=1, choices=[0, 1], help="D3: Raviart-Thomas degree")
+    ap.add_argument("--coarse3", type=int, default=0, choices=[0, 2, 4, 8],
+                    help="D3: cells per side of the coarsest mesh, solved densely (0: 8 for RT_0, 4 for RT_1)")
     ap.add_argument("--mu3", type=float, default=1e-2, help="D3: viscosity (0: Darcy)")
     ap.add_argument("--bc3", default="0,0,0,0,0,0", help="D3: per side x0,x1,y0,y1,z0,z1: 0 Dirichlet, 1 open")
     ap.add_argument("--dense-coarse-max", type=int, default=16384,

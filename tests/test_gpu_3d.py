@@ -381,3 +381,31 @@ def test_setup_rejects_patches_beyond_the_kernel_limit_3d():
     with pytest.raises(bmg.BmgError) as e:
         bmg.Solver3(bmg.make_params3(1, 2, MU, bc=(1, 1, 1, 1, 1, 1)), np.ones(8))
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("mu", [MU, 0.0])
+def test_rt0_coarsest_8_3d(mu):
+    """RT_0 with an 8^3 coarsest mesh (2240 unknowns inverted densely, the bench's
+    choice for RT_0) and 16^3 on top: V-cycle and solve against the oracle."""
+    s, o, kap = _pair(8, 2, k=0, mu=mu)
+    lev = o.lev[-1]
+    r = np.random.default_rng(6).standard_normal(lev.sp.ndof)
+    r[lev.sp.cons] = 0.0
+    z = s.vcycle(_dev(r)).cpu().numpy()
+    zo = o.vcycle(r)
+    assert np.abs(z - zo).max() <= 1e-10 * np.abs(zo).max()
+    g = lambda x, y, z_: np.array([np.ones_like(x), 0 * x, 0 * x])
+    f = lambda x, y, z_: np.array([0 * x, np.ones_like(x), 0 * x])
+    b = lev.rhs(f, g)
+    x, info = s.solve(_dev(b), rtol=1e-10, maxit=200)
+    xo, its, tr = o.fgmres(b, rtol=1e-10, maxit=200)
+    assert info.converged and info.rel_residual_true <= 1e-10
+    assert abs(info.iterations - its) <= 1, (info.iterations, its)
+    if info.iterations != its:
+        xo = _oracle_iterate(o, b, info.iterations)
+    xg = x.cpu().numpy()
+    d = xg - xo
+    d[lev.sp.n_u:] -= o.pressure_mean(xg) - o.pressure_mean(xo)
+    print(f"RT_0 3-D coarsest 8^3 mu={mu}: {info.iterations} iterations (oracle {its}), max diff "
+          f"{np.abs(d).max() / np.abs(xo).max():.2e}")
+    assert np.abs(d).max() <= 1e-10 * np.abs(xo).max()
